@@ -1,0 +1,251 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test pins the oracle to something other than itself: the dense generalized
+eigensolve of Eq. (2), closed forms for nu = 1, 2, Lanczos moment exactness for
+S = I, sum rules that follow from e_j being in L_nu^(j) and K^T S K = I (Sec. 2),
+an independent explicit-Krylov formulation, covariances and symmetry.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import mar_oracle as O
+from paper_1307_3218_amd import lattice
+
+KT = 0.1
+
+
+def _pattern_rows(H):
+    return np.repeat(np.arange(H.shape[0]), np.diff(H.indptr))
+
+
+@pytest.fixture(scope="module")
+def mu30(c1):
+    """Half-filling Fermi level bisected on the nu = 30 subspace electron count."""
+    r = O.solve(c1.H, c1.S, np.arange(c1.M), 30, 0.0, KT)
+    return O.fermi_level(r.eps, r.weight, c1.M, KT)
+
+
+# P1 / P12 -------------------------------------------------------------------
+def test_nu_equals_M_matches_dense_generalized_eigensolve(c1):
+    """At nu = M the subspace is the whole space: rho and E must be exact (Eq. 1, 2)."""
+    H, S, M = c1.H, c1.S, c1.M
+    mu = -0.448
+    r = O.solve(H, S, np.arange(M), M, mu, KT, workers=min(8, O.default_workers()))
+    rho_d, E_d, _ = O.dense(H, S, mu, KT)
+    ref = rho_d[H.indices, _pattern_rows(H)]      # slot (j, i) holds rho_ij
+    assert np.all(r.nu_eff == M)
+    assert np.linalg.norm(r.rho - ref) / np.linalg.norm(ref) < 1e-12
+    assert abs(r.e_band - E_d) / abs(E_d) < 1e-12
+    # P10: symmetric at nu = M
+    Rm = sp.csr_matrix((r.rho, H.indices, H.indptr), shape=H.shape)
+    assert abs(Rm - Rm.T).max() < 1e-12
+    # P11 at nu = M: Tr(S rho) over all columns is the exact electron count
+    n_exact = float(2.0 * O.fermi(O.dense(H, S, mu, KT)[2], mu, KT).sum())
+    assert abs(r.n_seed.sum() - n_exact) < 1e-9
+
+
+def test_nu_lt_M_differs_from_exact(c1, mu30):
+    """Sanity: nu = 30 is an approximation (not exact), with a nonsymmetric rho."""
+    H, S, M = c1.H, c1.S, c1.M
+    r = O.solve(H, S, np.arange(M), 30, mu30, KT)
+    _, E_d, _ = O.dense(H, S, mu30, KT)
+    assert abs(r.e_band - E_d) / abs(E_d) > 1e-4
+    Rm = sp.csr_matrix((r.rho, H.indices, H.indptr), shape=H.shape)
+    assert abs(Rm - Rm.T).max() > 1e-3
+
+
+# P2 -------------------------------------------------------------------------
+def test_identity_overlap_is_lanczos(c1):
+    """S = I: A is tridiagonal and reproduces e_j^T H^k e_j for k <= 2 nu - 1."""
+    H = c1.H
+    S = sp.identity(c1.M, format="csr")
+    nu, j = 12, 37
+    r = O.solve_seed(H, S, j, nu, 0.0, KT, keep=True)
+    A = r.A
+    off = np.abs(np.triu(A, 2)).max() / np.abs(A).max()
+    assert off < 1e-13
+    x = np.zeros(c1.M)
+    x[j] = 1.0
+    e1 = np.zeros(nu)
+    e1[0] = 1.0
+    y = e1.copy()
+    Hk = x.copy()
+    scale = np.abs(np.linalg.eigvalsh(H.toarray())).max()     # spectral radius of H
+    for k in range(1, 2 * nu):
+        Hk = H @ Hk
+        y = A @ y
+        ref = Hk[j]
+        assert abs(y[0] - ref) <= 1e-11 * scale ** k, k
+    # one beyond the exactness degree generally differs
+    Hk = H @ Hk
+    y = A @ y
+    assert abs(y[0] - Hk[j]) > 1e-8 * abs(Hk[j])
+
+
+# P3 -------------------------------------------------------------------------
+@pytest.mark.parametrize("j", [0, 5, 130, 255])
+def test_nu1_closed_form(c1, j):
+    H, S = c1.H, c1.S
+    Sd = S.toarray()
+    Hd = H.toarray()
+    mu = -0.3
+    r = O.solve_seed(H, S, j, 1, mu, KT)
+    f = 1.0 / (1.0 + math.exp((Hd[j, j] / Sd[j, j] - mu) / KT))
+    expect = np.where(r.cols == j, 2.0 * f / Sd[j, j], 0.0)
+    assert np.allclose(r.rho_row, expect, rtol=1e-14, atol=1e-300)
+    assert math.isclose(r.E, 2.0 * f / Sd[j, j] * Hd[j, j], rel_tol=1e-14)
+    assert math.isclose(r.N, 2.0 * f, rel_tol=1e-14)
+    assert r.nu_eff == 1 and math.isclose(r.eps[0], Hd[j, j] / Sd[j, j], rel_tol=1e-15)
+
+
+# P4 -------------------------------------------------------------------------
+@pytest.mark.parametrize("j", [3, 77, 200])
+def test_nu2_closed_form(c1, j):
+    """span{e_j, H e_j}: 2x2 generalized eigenproblem solved by the quadratic formula."""
+    H, S = c1.H.toarray(), c1.S.toarray()
+    mu = 0.4
+    ej = np.zeros(c1.M)
+    ej[j] = 1.0
+    g = H @ ej
+    a11, a12, a22 = ej @ H @ ej, ej @ H @ g, g @ H @ g
+    b11, b12, b22 = ej @ S @ ej, ej @ S @ g, g @ S @ g
+    qa = b11 * b22 - b12 ** 2
+    qb = -(a11 * b22 + a22 * b11 - 2 * a12 * b12)
+    qc = a11 * a22 - a12 ** 2
+    disc = math.sqrt(qb * qb - 4 * qa * qc)
+    lams = [(-qb - disc) / (2 * qa), (-qb + disc) / (2 * qa)]
+    rho = np.zeros(c1.M)
+    for lam in lams:
+        y = np.array([a12 - lam * b12, -(a11 - lam * b11)])
+        y /= math.sqrt(y @ np.array([[b11, b12], [b12, b22]]) @ y)
+        v = y[0] * ej + y[1] * g
+        f = 1.0 / (1.0 + math.exp((lam - mu) / KT))
+        rho += 2.0 * f * v * v[j]
+    r = O.solve_seed(c1.H, c1.S, j, 2, mu, KT)
+    assert np.allclose(np.sort(r.eps), lams, rtol=1e-12)
+    assert np.allclose(r.rho_row, rho[r.cols], rtol=1e-10, atol=1e-13 * np.abs(rho).max())
+    assert math.isclose(r.E, rho[r.cols] @ H[j, r.cols], rel_tol=1e-10)
+
+
+# P5 -------------------------------------------------------------------------
+@pytest.mark.parametrize("nu", [1, 3, 30])
+def test_full_and_empty_occupation(c1, nu):
+    seeds = np.arange(0, c1.M, 17)
+    full = O.solve(c1.H, c1.S, seeds, nu, 1e6, KT)
+    assert np.allclose(full.n_seed, 2.0, rtol=0, atol=1e-12)
+    empty = O.solve(c1.H, c1.S, seeds, nu, -1e6, KT)
+    assert np.all(empty.rho == 0.0) and empty.e_band == 0.0
+
+
+# P6 -------------------------------------------------------------------------
+@pytest.mark.parametrize("nu", [5, 30])
+def test_energy_count_weight_identities(c1, mu30, nu):
+    for j in [0, 9, 101, 254]:
+        r = O.solve_seed(c1.H, c1.S, j, nu, mu30, KT)
+        f = O.fermi(r.eps, mu30, KT)
+        assert math.isclose(r.weight.sum(), 1.0, rel_tol=1e-12)
+        assert math.isclose(r.E, 2.0 * np.sum(f * r.eps * r.weight), rel_tol=1e-11, abs_tol=1e-12)
+        assert math.isclose(r.N, 2.0 * np.sum(f * r.weight), rel_tol=1e-11, abs_tol=1e-12)
+
+
+# P7 -------------------------------------------------------------------------
+@pytest.mark.parametrize("nu", [30, 256])
+def test_basis_is_S_orthonormal(c1, nu):
+    for j in [0, 128]:
+        r = O.solve_seed(c1.H, c1.S, j, nu, 0.0, KT, keep=True)
+        G = r.K @ (c1.S @ r.K.T)
+        assert np.abs(G - np.eye(r.nu_eff)).max() < 1e-13
+
+
+# P8 -------------------------------------------------------------------------
+@pytest.mark.parametrize("nu", [2, 3, 5, 8])
+def test_cgs2_matches_explicit_krylov_cholesky(c1, nu):
+    mu = 0.02
+    for j in [1, 64, 250]:
+        r = O.solve_seed(c1.H, c1.S, j, nu, mu, KT)
+        eps_b, rho_b, E_b, N_b = O.brute_seed(c1.H, c1.S, j, nu, mu, KT)
+        # the explicit Krylov matrix loses ~10x accuracy per extra column; 1e-9 covers nu = 8
+        assert np.allclose(r.eps, eps_b, rtol=0, atol=1e-9)
+        assert np.abs(r.rho_row - rho_b).max() <= 1e-10 * np.abs(rho_b).max()
+        assert math.isclose(r.E, E_b, rel_tol=1e-10)
+
+
+# P9 -------------------------------------------------------------------------
+def test_energy_scale_covariance(c1):
+    a = 2.5
+    seeds = [0, 33, 199]
+    r1 = O.solve(c1.H, c1.S, seeds, 20, 0.1, KT)
+    r2 = O.solve(a * c1.H, c1.S, seeds, 20, a * 0.1, a * KT)
+    assert np.allclose(r2.rho, r1.rho, rtol=1e-10, atol=1e-12)
+    assert math.isclose(r2.e_band, a * r1.e_band, rel_tol=1e-11)
+
+
+def test_permutation_covariance(c1):
+    rng = np.random.default_rng(5)
+    perm_at = rng.permutation(c1.n_atoms)
+    perm = (4 * perm_at[:, None] + np.arange(4)).ravel()     # new index -> old index
+    inv = np.argsort(perm)                                   # old index -> new index
+
+    def relabel(A):
+        # keep the stored zeros of the 4x4 blocks: remap COO indices directly
+        c = A.tocoo()
+        B = sp.csr_matrix((c.data, (inv[c.row], inv[c.col])), shape=A.shape)
+        B.sort_indices()
+        return B
+
+    H2, S2 = relabel(c1.H), relabel(c1.S)
+    assert H2.nnz == c1.H.nnz
+    for j in [0, 42, 255]:
+        r1 = O.solve_seed(c1.H, c1.S, j, 25, 0.1, KT)
+        r2 = O.solve_seed(H2, S2, int(inv[j]), 25, 0.1, KT)
+        d1 = dict(zip(r1.cols, r1.rho_row))
+        d2 = dict(zip(perm[r2.cols], r2.rho_row))
+        assert set(d1) == set(d2)
+        for i in d1:
+            assert math.isclose(d1[i], d2[i], rel_tol=1e-9, abs_tol=1e-12)
+        assert math.isclose(r1.E, r2.E, rel_tol=1e-11)
+
+
+# P11 ------------------------------------------------------------------------
+def test_electron_count_at_bisected_mu(c1, mu30):
+    r = O.solve(c1.H, c1.S, np.arange(c1.M), 30, mu30, KT)
+    assert abs(r.n_seed.sum() - c1.M) < 1e-8
+    assert abs(O.electron_count(r.eps, r.weight, mu30, KT) - c1.M) < 1e-8
+
+
+# Breakdown and errors --------------------------------------------------------
+def test_breakdown_truncates_nu_eff():
+    """H block diagonal with S = I: the Krylov space of e_j is the 4-dim block."""
+    blocks = [np.array([[1.0, 0.3, 0.0, 0.2], [0.3, -1.0, 0.5, 0.0],
+                        [0.0, 0.5, 0.5, 0.1], [0.2, 0.0, 0.1, 2.0]]) * (k + 1) for k in range(3)]
+    H = sp.block_diag(blocks, format="csr")
+    S = sp.identity(12, format="csr")
+    r = O.solve_seed(H, S, 5, 8, 0.0, KT)
+    assert r.nu_eff == 4
+    ev = np.linalg.eigvalsh(blocks[1])
+    assert np.allclose(np.sort(r.eps), ev, rtol=1e-12)
+    assert math.isclose(r.weight.sum(), 1.0, rel_tol=1e-12)
+
+
+def test_indefinite_overlap_raises():
+    H = sp.csr_matrix(np.array([[0.0, 1.0, 0.0], [1.0, 0.0, 1.0], [0.0, 1.0, 0.0]]))
+    S = sp.csr_matrix(np.array([[1.0, 0.0, 0.0], [0.0, -1.0, 0.0], [0.0, 0.0, 1.0]]))
+    with pytest.raises(O.NotSPDError):
+        O.solve_seed(H, S, 0, 3, 0.0, KT)
+
+
+def test_zero_temperature_step():
+    assert np.array_equal(O.fermi([-1.0, 0.0, 1.0], 0.0, 0.0), [1.0, 0.5, 0.0])
+    assert np.allclose(O.fermi([-0.1, 0.0, 0.1], 0.0, 0.1),
+                       [1 / (1 + math.exp(-1)), 0.5, 1 / (1 + math.exp(1))], rtol=1e-15)
+
+
+def test_mixed_lattice_oracle_runs():
+    s = lattice.generate(2, 2, 2, mixed=True)
+    r = O.solve(s.H, s.S, [0, 100], 20, 0.0, KT)
+    assert np.all(r.nu_eff == 20)
+    full = O.solve(s.H, s.S, [0, 100], 20, 1e6, KT)
+    assert np.allclose(full.n_seed, 2.0, atol=1e-12)
