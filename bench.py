@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Throughput of the mArnoldi per-seed hot path on one MI355X.
+
+Workload: the 32768-atom mixed sp2/sp3 lattice (M = 131072, 4 orbitals per
+atom, seeded synthetic H and S), nu = 100, kT = 0.1 eV, mu at half filling.
+A step is one pass of the whole hot path (Krylov subspace + CGS2 + subspace
+eigensolve + Fermi-weighted assembly + band-energy sum) over one batch of
+seeds, in the batched FP32 form, with seeds, outputs and H/S resident in HBM.
+Reported: seed-subspaces/s of that form; beside it the plain FP64 form on the
+same GPU (one seed at a time), the per-kernel roofline from HIP events on the
+solve stream, and the FP64 CPU oracle on a bounded seed sample.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "seed-subspaces/s at ν=100, M=131072: FP32-batched vs FP64 plain; SpMM HBM %"
+HBM_PEAK_GBPS = 8000.0
+KT = 0.1
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(system, nu, mu, n_seeds, workers):
+    """The oracle as it stands, on a bounded seed sample, process-parallel over host cores."""
+    from oracle import mar_oracle as O
+    from paper_1307_3218_amd import lattice
+    seeds = lattice.sample_seeds(system.M, n_seeds, seed=99)
+    t0 = time.perf_counter()
+    O.solve(system.H, system.S, seeds, nu, mu, KT, workers=workers)
+    dt = time.perf_counter() - t0
+    return dict(value=n_seeds / dt, unit="seed-subspaces/s", cores=workers, kind="oracle",
+                sample=f"{n_seeds} uniformly sampled seeds of the same workload (nu={nu}), "
+                       f"FP64 NumPy/SciPy, one process per core, {dt:.1f} s wall")
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="mixed_16x16x16")
+    ap.add_argument("--nu", type=int, default=100)
+    ap.add_argument("--seeds-per-step", type=int, default=1024)
+    ap.add_argument("--plain-seeds", type=int, default=16)
+    ap.add_argument("--cpu-seeds", type=int, default=0, help="oracle sample size (0 = about 20 s of CPU work)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--seed-block", type=int, default=0)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the per-seed subspaces are independent, and a multi-GPU run "
+              "would shard the seed list (no collective on the hot path). Run with --gpus 1.", file=sys.stderr)
+        return 2
+
+    from paper_1307_3218_amd import fermi, lattice, mar
+    t = time.perf_counter()
+    system = lattice.workload(args.workload)
+    M, nu = system.M, args.nu
+    log(f"workload {system.name}: M={M} nnz={system.H.nnz} lambda_min(S)={system.lam_min_S:.3f} "
+        f"({time.perf_counter() - t:.1f} s)")
+
+    import torch
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ctx = mar.Context(system.H, system.S)
+    if args.seed_block:
+        ctx.set_tuning(args.seed_block)
+    B = ctx.seed_block(nu, "fp32")
+    S_step = args.seeds_per_step
+    stream = torch.cuda.current_stream().cuda_stream
+    order = np.random.default_rng(0).permutation(M).astype(np.int32)
+    n_steps = args.warmup + args.steps
+    d_order = torch.from_numpy(order).to(dev)
+
+    def seeds_for(k):
+        lo = (k * S_step) % M
+        return d_order[lo: lo + S_step]
+
+    d_rho = torch.zeros(system.H.nnz, dtype=torch.float64, device=dev)
+    d_eb = torch.zeros(1, dtype=torch.float64, device=dev)
+    d_e = torch.zeros(S_step, dtype=torch.float64, device=dev)
+    d_n = torch.zeros(S_step, dtype=torch.float64, device=dev)
+    d_nu = torch.zeros(S_step, dtype=torch.int32, device=dev)
+    d_eps = torch.zeros((S_step, nu), dtype=torch.float64, device=dev)
+    d_w = torch.zeros((S_step, nu), dtype=torch.float64, device=dev)
+
+    # warmup: the first pass also yields the subspace levels for the half-filling Fermi level
+    mu = 0.0
+    for k in range(args.warmup):
+        t = time.perf_counter()
+        ctx.solve_async(seeds_for(k), nu, mu, KT, "fp32", "batched", d_rho=d_rho, d_e_band=d_eb, d_e_seed=d_e,
+                        d_n_seed=d_n, d_nu_eff=d_nu, d_eps=d_eps, d_weight=d_w, stream=stream)
+        torch.cuda.synchronize()
+        log(f"warmup step {k}: {time.perf_counter() - t:.2f} s")
+        if k == 0:
+            nue = d_nu.cpu().numpy()
+            mu = fermi.fermi_level(d_eps.cpu().numpy(), d_w.cpu().numpy(), nue, float(S_step), KT)
+            log(f"half-filling Fermi level from {S_step} seeds: mu = {mu:.6f} eV; nu_eff min {nue.min()}")
+
+    # timed region: the batched FP32 form
+    if not args.no_profile:
+        ctx.profile(True)
+        ctx.profile_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.warmup, n_steps):
+        ctx.solve_async(seeds_for(k), nu, mu, KT, "fp32", "batched", d_rho=d_rho, d_e_band=d_eb, d_e_seed=d_e,
+                        d_n_seed=d_n, d_nu_eff=d_nu, stream=stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = args.steps * S_step / elapsed
+    log(f"timed {args.steps} steps x {S_step} seeds: {elapsed:.3f} s -> {value:.1f} seed-subspaces/s")
+    prof = ctx.profile_collect() if not args.no_profile else {}
+    ctx.profile(False)
+    nue = d_nu.cpu().numpy()
+    if (nue < 0).any():
+        log("error: a seed reported a non-positive-definite overlap")
+        return 1
+
+    kernels = {}
+    for name, e in prof.items():
+        if e["launches"] == 0:
+            continue
+        kernels[name] = dict(launches=int(e["launches"]), ms=round(e["ms"], 3),
+                             share=round(e["ms"] / (elapsed * 1e3), 4),
+                             GBps=round(e["bytes"] / (e["ms"] * 1e-3) / 1e9, 1) if e["ms"] > 0 else None)
+    roofline = None
+    spmm = None
+    if prof:
+        dom = max(prof, key=lambda n: prof[n]["ms"])
+        e = prof[dom]
+        ach = e["bytes"] / (e["ms"] * 1e-3) / 1e9
+        roofline = dict(kernel=dom, bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
+                        frac=round(ach / HBM_PEAK_GBPS, 4), traffic=None,
+                        bytes_per_launch=e["bytes"] / e["launches"], avg_launch_us=1e3 * e["ms"] / e["launches"])
+        s = prof.get("spmm")
+        if s and s["ms"] > 0:
+            sa = s["bytes"] / (s["ms"] * 1e-3) / 1e9
+            spmm = dict(achieved=round(sa, 1), peak=HBM_PEAK_GBPS, unit="GB/s", frac=round(sa / HBM_PEAK_GBPS, 4),
+                        avg_launch_us=1e3 * s["ms"] / s["launches"])
+
+    # the plain FP64 form on the same GPU (one seed per block, one launch per phase)
+    plain = None
+    if not args.no_plain and args.plain_seeds > 0:
+        n_p = args.plain_seeds
+        d_sp = d_order[-n_p:]
+        ctx.solve_async(d_sp[:1], nu, mu, KT, "fp64", "plain", d_rho=d_rho, d_e_band=d_eb, stream=stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ctx.solve_async(d_sp, nu, mu, KT, "fp64", "plain", d_rho=d_rho, d_e_band=d_eb, stream=stream)
+        torch.cuda.synchronize()
+        dtp = time.perf_counter() - t1
+        plain = dict(value=n_p / dtp, unit="seed-subspaces/s", seeds=n_p, seconds=round(dtp, 3))
+        log(f"plain FP64: {n_p} seeds in {dtp:.3f} s -> {n_p / dtp:.2f} seed-subspaces/s")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import mar_oracle as O
+        workers = min(16, O.default_workers())
+        n_cpu = args.cpu_seeds or max(workers, int(round(20.0 / 1.3)))
+        n_cpu = max(n_cpu, workers)
+        cpu = cpu_baseline(system, nu, mu, n_cpu, workers)
+        log(f"cpu oracle: {cpu['value']:.2f} seed-subspaces/s on {workers} cores")
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "seed-subspaces/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{system.name} mixed sp2/sp3 lattice, M={M}, nu={nu}, kT={KT}, FP32 batched",
+                   "M": M, "nnz": int(system.H.nnz), "nu": nu, "seeds_per_step": S_step, "seed_block": B,
+                   "precision": "fp32", "form": "batched", "mu": mu},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "fp64_plain": plain,
+        "ratio_fp32_batched_over_fp64_plain": round(value / plain["value"], 3) if plain else None,
+        "spmm_hbm": spmm,
+        "kernels": kernels,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

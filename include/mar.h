@@ -1,0 +1,161 @@
+/*
+ * mar.h - C ABI of the multiple-Arnoldi (mArnoldi) per-seed hot path, gfx950.
+ *
+ * The method (Sec. 2 of the paper): for the generalized shifted equations
+ * (zS - H) x = b of Eq. (1), with H and S sparse, real symmetric and S
+ * positive definite, the problem is reduced to one small nu x nu *standard*
+ * eigenproblem per basis index j, posed in a Krylov subspace L_nu^(j) that
+ * contains the unit vector e_j; the subspace eigen levels eps_alpha and
+ * vectors v_alpha determine the Green's function and from it the energy.
+ *
+ * This library computes, for each requested seed j (0-based here; the paper
+ * counts j = 1..M):
+ *   1. the S-orthonormal basis K = [u_1 .. u_nu] of span{e_j, He_j, ...,
+ *      H^(nu-1) e_j}, u_1 = e_j / sqrt(S_jj), by classical Gram-Schmidt with
+ *      two passes (CGS2) in the S-inner product, and A = K^T H K from the dot
+ *      products u_k . (H u_n) (k <= n), mirrored from its upper triangle;
+ *   2. the eigenpairs (eps_alpha, y_alpha) of A in FP64, v_alpha = K y_alpha;
+ *   3. the spin-summed density-matrix column on the pattern P(j) of H's row j,
+ *        rho_ij = 2 sum_alpha f((eps_alpha - mu)/kT) (e_i.v_alpha)(e_j.v_alpha),
+ *      f(x) = 1/(1+e^x) (kT = 0: step, 1/2 at eps = mu); the band-energy and
+ *      electron-count contributions E_j = sum_{i in P(j)} rho_ij H_ij and
+ *      N_j = sum_{i in P(j)} rho_ij S_ij; the weights
+ *      w_alpha = (e_j^T S v_alpha)(v_alpha^T e_j); E_band = sum_j E_j.
+ * Breakdown: when the S-norm beta of the new residual satisfies
+ * beta <= tau * eta (eta^2 = |c1|^2 + |c2|^2 + beta^2 from the two projection
+ * passes; tau = 1e-12 in FP64, 1e-5 in FP32) the subspace stops at
+ * nu_eff = n vectors. Breakdown is not an error.
+ *
+ * Precision forms: MAR_FP64 runs everything in FP64. MAR_FP32 stores the
+ * Krylov basis and runs the sparse products and the CGS2 projections/updates
+ * in FP32 with FP32 accumulation; the norms and breakdown test, the subspace
+ * eigensolve, the Fermi weighting and all energy sums stay FP64.
+ *
+ * Errors: every entry point returns a mar_status. Arguments are validated
+ * before any device work; on error the outputs are unspecified and
+ * mar_last_error() gives a message. No exception crosses this boundary.
+ * A context serves one solve at a time and is not thread-safe.
+ */
+#ifndef MAR_H
+#define MAR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mar_ctx mar_ctx;
+
+typedef enum {
+    MAR_OK = 0,
+    MAR_ERR_ARG = -1,      /* bad argument (sizes, nu, kT, seeds, NULL outputs) */
+    MAR_ERR_PATTERN = -2,  /* malformed CSR, asymmetric H or S, pattern(S) not in pattern(H) */
+    MAR_ERR_NOT_SPD = -3,  /* S_jj <= 0 at create, or w^T S w < 0 during a solve */
+    MAR_ERR_NOMEM = -4,    /* device allocation failed */
+    MAR_ERR_HIP = -5,      /* HIP runtime error (message in mar_last_error) */
+    MAR_ERR_STATE = -6     /* NULL context or use after an unrecoverable error */
+} mar_status;
+
+typedef enum { MAR_FP64 = 0, MAR_FP32 = 1 } mar_precision;
+
+/* MAR_FORM_PLAIN: one seed at a time (B = 1), one kernel launch per phase.
+ * MAR_FORM_BATCHED: B seeds per block with seed-interleaved vectors. */
+typedef enum { MAR_FORM_BATCHED = 0, MAR_FORM_PLAIN = 1 } mar_form;
+
+typedef struct {
+    int32_t seed_block;    /* B for the batched form: power of two, 1..256 (FP32) or 1..128
+                              (FP64); 0 = choose from the problem size */
+    int32_t proj_rows;     /* reserved (0 = default) */
+    int32_t upd_rows;      /* reserved (0 = default) */
+    int32_t reserved;
+} mar_tuning;
+
+/* Create a context from host CSR arrays of H and S (M x M, 0-based, columns
+ * sorted and unique in each row, rowptr[0] = 0). The arrays are copied to the
+ * device; the caller keeps ownership. Validation (MAR_ERR_PATTERN unless
+ * noted): rowptr monotone, columns in range, values finite (MAR_ERR_ARG), H and
+ * S symmetric in pattern and value (exact equality), every stored entry of S
+ * also stored in H, S_jj > 0 (MAR_ERR_NOT_SPD), at most 63 stored entries per
+ * row of H (MAR_ERR_ARG). Full positive definiteness of S is not checked here.
+ * A 4x4 block structure (identical patterns in rows 4I..4I+3 made of aligned
+ * 4-column groups) is detected and stored as BSR; otherwise CSR is used.
+ * Returns MAR_ERR_HIP if no GPU is usable. */
+mar_status mar_create(int64_t M,
+                      const int64_t* H_rowptr, const int32_t* H_col, const double* H_val,
+                      const int64_t* S_rowptr, const int32_t* S_col, const double* S_val,
+                      mar_ctx** out);
+
+void mar_destroy(mar_ctx* ctx);
+
+/* Host-side solve (blocking). seeds: n_seeds distinct indices in [0, M)
+ * (MAR_ERR_ARG otherwise); 1 <= nu <= M; mu finite; kT >= 0 and finite.
+ * Outputs (host, caller-allocated):
+ *   rho     [nnz(H)]   CSR row j slots of each listed seed j receive rho_ij for
+ *                      i in P(j) (slot (j,i) holds rho_ij); all other slots keep
+ *                      the caller's values. Required.
+ *   e_band  [1]        sum of E_j over the listed seeds (fixed-order FP64). Required.
+ *   e_seed  [n_seeds]  E_j, or NULL.
+ *   n_seed  [n_seeds]  N_j, or NULL.
+ *   nu_eff  [n_seeds]  subspace dimension reached, or NULL.
+ *   eps     [n_seeds * nu] subspace eigen levels of seed s at eps[s*nu + a],
+ *                      a < nu_eff (unsorted; remaining entries 0), or NULL.
+ *   weight  [n_seeds * nu] w_alpha in the same layout, or NULL.
+ * Returns MAR_ERR_NOT_SPD if some seed met w^T S w < 0. */
+mar_status mar_solve(mar_ctx* ctx, const int32_t* seeds, int64_t n_seeds, int32_t nu,
+                     double mu, double kT, mar_precision prec, mar_form form,
+                     double* rho, double* e_band, double* e_seed, double* n_seed,
+                     int32_t* nu_eff, double* eps, double* weight);
+
+/* Device-side solve, enqueued on hip_stream (a hipStream_t; NULL = the null
+ * stream) without host synchronization. All pointers are device pointers with
+ * the same meaning and layout as in mar_solve; d_seeds is read on the device,
+ * so range and uniqueness are not validated on the host: a seed outside
+ * [0, M) gets d_nu_eff = -2 and no other output, a seed that met w^T S w < 0
+ * gets d_nu_eff = -1 (d_nu_eff must then be non-NULL to see it). Scalar
+ * arguments are validated as in mar_solve. The device workspace is owned by
+ * the context and may be reallocated (hipMalloc) when nu, B, or the precision
+ * grows; call once with the largest shapes before capturing. */
+mar_status mar_solve_async(mar_ctx* ctx, const int32_t* d_seeds, int64_t n_seeds, int32_t nu,
+                           double mu, double kT, mar_precision prec, mar_form form,
+                           double* d_rho, double* d_e_band, double* d_e_seed, double* d_n_seed,
+                           int32_t* d_nu_eff, double* d_eps, double* d_weight, void* hip_stream);
+
+/* Set the tuning used by later solves (NULL restores the defaults). */
+mar_status mar_set_tuning(mar_ctx* ctx, const mar_tuning* t);
+mar_status mar_get_tuning(const mar_ctx* ctx, mar_tuning* t);
+
+/* Seeds per block the batched form would use for (nu, prec) with the current tuning. */
+int32_t mar_seed_block(const mar_ctx* ctx, int32_t nu, mar_precision prec);
+
+/* Last error message of ctx, or of the calling thread's last mar_create when
+ * ctx is NULL. Never NULL; valid until the next call on the same context. */
+const char* mar_last_error(const mar_ctx* ctx);
+
+/* ---- per-kernel timing (HIP events on the solve stream) ----
+ * While enabled, each kernel launch of a solve is bracketed by a pair of HIP
+ * events on the launch stream. mar_profile_collect synchronizes those events
+ * and accumulates, per kernel class, the launch count, the summed event time
+ * and the algorithmic bytes and flops (bytes: every operand read once and
+ * every result written once, as the method requires). */
+enum { MAR_PROF_CLASSES = 10 };
+typedef struct {
+    char name[24];
+    int64_t launches;
+    double ms;        /* summed launch durations */
+    double bytes;     /* summed algorithmic bytes */
+    double flops;     /* summed algorithmic flops */
+} mar_prof_entry;
+
+mar_status mar_profile_enable(mar_ctx* ctx, int32_t on);
+mar_status mar_profile_reset(mar_ctx* ctx);
+mar_status mar_profile_collect(mar_ctx* ctx, mar_prof_entry* out /* [MAR_PROF_CLASSES] */,
+                               int32_t* n_out);
+
+/* Library description: matrix storage actually used (1 = BSR 4x4 for H, 2 = for S). */
+int32_t mar_ctx_info(const mar_ctx* ctx, int64_t* M, int64_t* nnz_H, int64_t* nnz_S);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MAR_H */

@@ -1,0 +1,637 @@
+// Host side of the C ABI: argument validation, matrix upload (BSR 4x4 or CSR),
+// the per-block launch sequence of the hot path, and per-kernel timing.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mar.h"
+#include "mar_internal.h"
+
+using mar::DevMat;
+using mar::LaunchInfo;
+
+namespace {
+
+enum ProfClass { P_INIT = 0, P_SPMM, P_PROJ, P_UPD, P_REDUCE, P_NORM, P_APPEND, P_EIG, P_SUM, P_COUNT };
+const char* kProfNames[P_COUNT] = {"init", "spmm", "cgs_proj", "cgs_upd", "reduce", "norm", "append", "eig", "sum"};
+
+struct ProfRec {
+    int cls;
+    hipEvent_t a, b;
+    double bytes, flops;
+};
+
+thread_local std::string g_create_err;
+
+std::string fmt(const char* f, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, f);
+    vsnprintf(buf, sizeof buf, f, ap);
+    va_end(ap);
+    return buf;
+}
+
+}  // namespace
+
+struct mar_ctx {
+    int64_t M = 0;
+    int device = 0;
+    DevMat H, S;
+    int32_t* Hrp = nullptr;
+    int32_t* Hcol = nullptr;
+    double* Hval = nullptr;
+    double* SvalH = nullptr;  // S on H's pattern (zeros where S stores nothing)
+    double* diagS = nullptr;
+    int64_t nnzH = 0, nnzS = 0;
+    int max_row = 0;
+    mar_tuning tune{};
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    char* io = nullptr;
+    size_t io_bytes = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    bool prof = false;
+    std::vector<ProfRec> recs;
+    std::vector<hipEvent_t> evfree;
+    mar_prof_entry agg[MAR_PROF_CLASSES];
+    std::vector<void*> allocs;
+
+    ~mar_ctx() {
+        for (auto& r : recs) {
+            hipEventDestroy(r.a);
+            hipEventDestroy(r.b);
+        }
+        for (auto e : evfree) hipEventDestroy(e);
+        for (void* p : allocs) hipFree(p);
+        if (ws) hipFree(ws);
+        if (io) hipFree(io);
+        if (stream) hipStreamDestroy(stream);
+    }
+};
+
+namespace {
+
+mar_status set_err(mar_ctx* c, mar_status st, const std::string& m) {
+    if (c) c->err = m;
+    else g_create_err = m;
+    return st;
+}
+
+#define HIP_OR(c, call)                                                                              \
+    do {                                                                                             \
+        hipError_t e_ = (call);                                                                      \
+        if (e_ != hipSuccess)                                                                        \
+            return set_err(c, e_ == hipErrorOutOfMemory ? MAR_ERR_NOMEM : MAR_ERR_HIP,               \
+                           fmt("%s failed: %s", #call, hipGetErrorString(e_)));                      \
+    } while (0)
+
+// ---------------------------------------------------------------- validation
+mar_status check_csr(int64_t M, const int64_t* rp, const int32_t* col, const double* val, const char* nm,
+                     std::string& msg) {
+    if (!rp) return msg = fmt("%s: rowptr is NULL", nm), MAR_ERR_ARG;
+    if (rp[0] != 0) return msg = fmt("%s: rowptr[0] = %lld, expected 0", nm, (long long)rp[0]), MAR_ERR_PATTERN;
+    for (int64_t i = 0; i < M; ++i)
+        if (rp[i + 1] < rp[i]) return msg = fmt("%s: rowptr decreases at row %lld", nm, (long long)i), MAR_ERR_PATTERN;
+    const int64_t nnz = rp[M];
+    if (nnz >= (int64_t)INT32_MAX) return msg = fmt("%s: nnz %lld exceeds int32 range", nm, (long long)nnz), MAR_ERR_ARG;
+    if (nnz > 0 && (!col || !val)) return msg = fmt("%s: col or val is NULL", nm), MAR_ERR_ARG;
+    for (int64_t i = 0; i < M; ++i) {
+        for (int64_t t = rp[i]; t < rp[i + 1]; ++t) {
+            if (col[t] < 0 || col[t] >= M)
+                return msg = fmt("%s: column %d out of range in row %lld", nm, col[t], (long long)i), MAR_ERR_PATTERN;
+            if (t > rp[i] && col[t] <= col[t - 1])
+                return msg = fmt("%s: columns not sorted/unique in row %lld", nm, (long long)i), MAR_ERR_PATTERN;
+            if (!std::isfinite(val[t]))
+                return msg = fmt("%s: non-finite value at (%lld, %d)", nm, (long long)i, col[t]), MAR_ERR_ARG;
+        }
+    }
+    return MAR_OK;
+}
+
+int64_t find_slot(const int64_t* rp, const int32_t* col, int64_t i, int32_t j) {
+    const int32_t* lo = col + rp[i];
+    const int32_t* hi = col + rp[i + 1];
+    const int32_t* p = std::lower_bound(lo, hi, j);
+    return (p != hi && *p == j) ? (p - col) : -1;
+}
+
+mar_status check_sym(int64_t M, const int64_t* rp, const int32_t* col, const double* val, const char* nm,
+                     std::string& msg) {
+    for (int64_t i = 0; i < M; ++i)
+        for (int64_t t = rp[i]; t < rp[i + 1]; ++t) {
+            const int64_t u = find_slot(rp, col, col[t], (int32_t)i);
+            if (u < 0)
+                return msg = fmt("%s: pattern not symmetric at (%lld, %d)", nm, (long long)i, col[t]), MAR_ERR_PATTERN;
+            if (val[u] != val[t])
+                return msg = fmt("%s: values not symmetric at (%lld, %d)", nm, (long long)i, col[t]), MAR_ERR_PATTERN;
+        }
+    return MAR_OK;
+}
+
+// 4x4 block structure: rows 4I..4I+3 share one pattern made of aligned groups of 4.
+bool detect_bsr4(int64_t M, const int64_t* rp, const int32_t* col) {
+    if (M % 4 != 0) return false;
+    for (int64_t I = 0; I < M / 4; ++I) {
+        const int64_t L = rp[4 * I + 1] - rp[4 * I];
+        if (L % 4 != 0) return false;
+        for (int r = 1; r < 4; ++r) {
+            if (rp[4 * I + r + 1] - rp[4 * I + r] != L) return false;
+            if (std::memcmp(col + rp[4 * I], col + rp[4 * I + r], L * sizeof(int32_t)) != 0) return false;
+        }
+        for (int64_t t = 0; t < L; t += 4) {
+            const int32_t c0 = col[rp[4 * I] + t];
+            if (c0 % 4 != 0) return false;
+            for (int q = 1; q < 4; ++q)
+                if (col[rp[4 * I] + t + q] != c0 + q) return false;
+        }
+    }
+    return true;
+}
+
+template <typename X>
+mar_status upload(mar_ctx* c, X** dst, const X* src, size_t n) {
+    *dst = nullptr;
+    if (n == 0) n = 1;
+    void* p = nullptr;
+    HIP_OR(c, hipMalloc(&p, n * sizeof(X)));
+    c->allocs.push_back(p);
+    *dst = (X*)p;
+    if (src) HIP_OR(c, hipMemcpy(p, src, n * sizeof(X), hipMemcpyHostToDevice));
+    return MAR_OK;
+}
+
+mar_status build_devmat(mar_ctx* c, int64_t M, const int64_t* rp, const int32_t* col, const double* val, DevMat& D) {
+    mar_status st;
+    if (detect_bsr4(M, rp, col)) {
+        const int64_t nb = M / 4, nblk = rp[M] / 16;
+        std::vector<int32_t> brp(nb + 1), bcol(nblk);
+        std::vector<double> v64(nblk * 16);
+        std::vector<float> v32(nblk * 16);
+        for (int64_t I = 0; I <= nb; ++I) brp[I] = (int32_t)(rp[4 * std::min(I, nb)] / 16);
+        for (int64_t I = 0; I < nb; ++I) {
+            const int64_t L = rp[4 * I + 1] - rp[4 * I];
+            for (int64_t t = 0; t < L / 4; ++t) {
+                const int64_t blk = brp[I] + t;
+                bcol[blk] = col[rp[4 * I] + 4 * t] / 4;
+                for (int r = 0; r < 4; ++r)
+                    for (int q = 0; q < 4; ++q) {
+                        const double x = val[rp[4 * I + r] + 4 * t + q];
+                        v64[blk * 16 + r * 4 + q] = x;
+                        v32[blk * 16 + r * 4 + q] = (float)x;
+                    }
+            }
+        }
+        D.bsr = true;
+        D.n = nb;
+        D.nnz = nblk;
+        if ((st = upload(c, &D.ptr, brp.data(), brp.size())) != MAR_OK) return st;
+        if ((st = upload(c, &D.idx, bcol.data(), bcol.size())) != MAR_OK) return st;
+        if ((st = upload(c, &D.v64, v64.data(), v64.size())) != MAR_OK) return st;
+        if ((st = upload(c, &D.v32, v32.data(), v32.size())) != MAR_OK) return st;
+    } else {
+        const int64_t nnz = rp[M];
+        std::vector<int32_t> rp32(M + 1);
+        for (int64_t i = 0; i <= M; ++i) rp32[i] = (int32_t)rp[i];
+        std::vector<float> v32(nnz);
+        for (int64_t t = 0; t < nnz; ++t) v32[t] = (float)val[t];
+        D.bsr = false;
+        D.n = M;
+        D.nnz = nnz;
+        if ((st = upload(c, &D.ptr, rp32.data(), rp32.size())) != MAR_OK) return st;
+        if ((st = upload(c, &D.idx, col, (size_t)nnz)) != MAR_OK) return st;
+        if ((st = upload(c, &D.v64, val, (size_t)nnz)) != MAR_OK) return st;
+        if ((st = upload(c, &D.v32, v32.data(), v32.size())) != MAR_OK) return st;
+    }
+    return MAR_OK;
+}
+
+// ---------------------------------------------------------------- profiling
+hipEvent_t get_event(mar_ctx* c) {
+    if (!c->evfree.empty()) {
+        hipEvent_t e = c->evfree.back();
+        c->evfree.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    hipEventCreate(&e);
+    return e;
+}
+
+template <class F>
+void launch(mar_ctx* c, hipStream_t s, int cls, F&& f) {
+    if (!c->prof) {
+        f();
+        return;
+    }
+    hipEvent_t a = get_event(c), b = get_event(c);
+    hipEventRecord(a, s);
+    LaunchInfo li = f();
+    hipEventRecord(b, s);
+    c->recs.push_back({cls, a, b, li.bytes, li.flops});
+}
+
+// ---------------------------------------------------------------- block size
+int pow2_floor(int64_t x) {
+    int p = 1;
+    while ((int64_t)p * 2 <= x) p *= 2;
+    return p;
+}
+
+int choose_block(const mar_ctx* c, int nu, mar_precision prec, int64_t n_seeds) {
+    const int bmax = prec == MAR_FP32 ? mar::max_block<float>() : mar::max_block<double>();
+    const size_t p = prec == MAR_FP32 ? 4 : 8;
+    int B;
+    if (c->tune.seed_block > 0) {
+        B = std::min(c->tune.seed_block, bmax);
+    } else {
+        B = 64;
+        // small matrices: widen the block so one slab streams at least 4M elements
+        while ((int64_t)B < bmax && c->M * B < (int64_t)(1 << 22)) B *= 2;
+        // keep K and S*K within 96 GB
+        while (B > 1 && 2.0 * nu * (double)c->M * B * p > 96e9) B /= 2;
+        if (n_seeds > 0) B = std::min<int64_t>(B, pow2_floor(std::max<int64_t>(1, n_seeds)) * 2);
+        B = std::min(B, bmax);
+    }
+    return std::max(1, pow2_floor(B));
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+mar_status ensure_ws(mar_ctx* c, size_t bytes) {
+    if (bytes <= c->ws_bytes) return MAR_OK;
+    if (c->ws) {
+        HIP_OR(c, hipDeviceSynchronize());
+        HIP_OR(c, hipFree(c->ws));
+        c->ws = nullptr;
+        c->ws_bytes = 0;
+    }
+    void* p = nullptr;
+    HIP_OR(c, hipMalloc(&p, bytes));
+    c->ws = (char*)p;
+    c->ws_bytes = bytes;
+    return MAR_OK;
+}
+
+// ---------------------------------------------------------------- the solve
+template <typename T>
+mar_status run_solve(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds, int nu, double mu, double kT, int B,
+                     double* d_rho, double* d_e_band, double* d_e_seed, double* d_n_seed, int32_t* d_nu_eff,
+                     double* d_eps, double* d_w, hipStream_t s) {
+    constexpr int VEC = 16 / sizeof(T);
+    // vectors are stored with the row count padded to a multiple of 4, so that
+    // every [M][B] array is a whole number of 16-byte vectors; padded rows stay 0
+    const int64_t M = (c->M + 3) / 4 * 4;
+    const int64_t nvec = M * B / VEC;
+    const int64_t chunks = (nvec + mar::WG * mar::PROJ_Q - 1) / (mar::WG * mar::PROJ_Q);
+    const int P = B < VEC ? 1 : B / VEC;
+    const int64_t spmm_wgs = std::max((c->S.n * P + mar::WG - 1) / mar::WG, (c->H.n * P + mar::WG - 1) / mar::WG);
+    const size_t slab = (size_t)M * B * sizeof(T);
+
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align_up(bytes);
+        return o;
+    };
+    const size_t oK = take((size_t)nu * slab), oSK = take((size_t)nu * slab);
+    const size_t oW = take(slab), oZ = take(slab);
+    const size_t oPart = take(std::max<size_t>((size_t)chunks * 2 * nu * B, (size_t)spmm_wgs * B) * 8);
+    const size_t oRed1 = take((size_t)2 * nu * B * 8), oRed2 = take((size_t)nu * B * 8), oRedb = take((size_t)B * 8);
+    const size_t oH = take((size_t)B * nu * nu * 8), oBeta = take((size_t)B * 8);
+    const size_t oAct = take((size_t)B * 4), oNu = take((size_t)B * 4);
+    const bool own_e = d_e_seed == nullptr, own_n = d_n_seed == nullptr, own_nu = d_nu_eff == nullptr;
+    const size_t oE = take(own_e ? (size_t)n_seeds * 8 : 0), oN = take(own_n ? (size_t)n_seeds * 8 : 0);
+    const size_t oNuOut = take(own_nu ? (size_t)n_seeds * 4 : 0);
+    mar_status st = ensure_ws(c, off);
+    if (st != MAR_OK) return st;
+    char* w = c->ws;
+    mar::BlockWS<T> ws{(T*)(w + oK), (T*)(w + oSK), (T*)(w + oW), (T*)(w + oZ), (double*)(w + oPart),
+                       (double*)(w + oRed1), (double*)(w + oRed2), (double*)(w + oRedb), (double*)(w + oH),
+                       (double*)(w + oBeta), (int32_t*)(w + oAct), (int32_t*)(w + oNu)};
+    double* e_seed = own_e ? (double*)(w + oE) : d_e_seed;
+    double* n_seed = own_n ? (double*)(w + oN) : d_n_seed;
+    int32_t* nu_out = own_nu ? (int32_t*)(w + oNuOut) : d_nu_eff;
+    const double tau = sizeof(T) == 4 ? 1e-5 : 1e-12;
+    const int64_t slab_el = M * B;
+
+    for (int64_t blk0 = 0; blk0 < n_seeds; blk0 += B) {
+        const int ns = (int)std::min<int64_t>(B, n_seeds - blk0);
+        const int32_t* seeds = d_seeds + blk0;
+        if (M != c->M && blk0 == 0) {
+            // padded rows of W, Z and S K_1 must read as zero (spmm writes rows < M only)
+            launch(c, s, P_INIT, [&] { return mar::launch_zero(ws.W, (int64_t)slab, s); });
+            launch(c, s, P_INIT, [&] { return mar::launch_zero(ws.Z, (int64_t)slab, s); });
+            launch(c, s, P_INIT, [&] { return mar::launch_zero(ws.SK, (int64_t)slab, s); });
+        }
+        launch(c, s, P_INIT, [&] {
+            return mar::launch_init<T>(B, M, c->M, seeds, ns, c->diagS, nu, ws.K, ws.active, ws.nu_eff, s);
+        });
+        launch(c, s, P_SPMM, [&] { return mar::launch_spmm<T>(B, c->S, ws.K, ws.SK, nullptr, s); });
+        for (int n = 0; n < nu; ++n) {
+            const T* Kn = ws.K + (size_t)n * slab_el;
+            const int nk = n + 1;
+            const bool last = n + 1 == nu;
+            launch(c, s, P_SPMM, [&] { return mar::launch_spmm<T>(B, c->H, Kn, ws.W, nullptr, s); });
+            // h[:, n] = K^T w and c1 = (S K)^T w in one pass over K and S K
+            int64_t nch = 0;
+            launch(c, s, P_PROJ, [&] {
+                return mar::launch_proj<T>(B, last ? 1 : 2, ws.K, ws.SK, M, nk, ws.W, ws.part, &nch, s);
+            });
+            const int64_t L1 = (int64_t)(last ? 1 : 2) * nk * B;
+            launch(c, s, P_REDUCE, [&] { return mar::launch_reduce(ws.part, nch, L1, ws.red1, ws.h, B, nu, n, s); });
+            if (last) break;
+            const double* c1 = ws.red1 + (size_t)nk * B;
+            // CGS pass 1: w -= K c1
+            launch(c, s, P_UPD, [&] { return mar::launch_upd<T>(B, ws.K, M, nk, c1, ws.W, s); });
+            // CGS pass 2: c2 = (S K)^T w, w -= K c2
+            launch(c, s, P_PROJ, [&] {
+                return mar::launch_proj<T>(B, 1, ws.SK, nullptr, M, nk, ws.W, ws.part, &nch, s);
+            });
+            const int64_t L2 = (int64_t)nk * B;
+            launch(c, s, P_REDUCE, [&] { return mar::launch_reduce(ws.part, nch, L2, ws.red2, nullptr, B, nu, n, s); });
+            launch(c, s, P_UPD, [&] { return mar::launch_upd<T>(B, ws.K, M, nk, ws.red2, ws.W, s); });
+            // z = S w and w^T S w
+            int64_t swgs = 0;
+            launch(c, s, P_SPMM, [&] {
+                LaunchInfo li = mar::launch_spmm<T>(B, c->S, ws.W, ws.Z, ws.part, s);
+                swgs = li.wgs;
+                return li;
+            });
+            launch(c, s, P_REDUCE, [&] { return mar::launch_reduce(ws.part, swgs, B, ws.redb, nullptr, B, nu, n, s); });
+            launch(c, s, P_NORM, [&] {
+                return mar::launch_norm(B, nk, ws.redb, c1, ws.red2, tau, ws.active, ws.nu_eff, ws.beta, n, s);
+            });
+            launch(c, s, P_APPEND, [&] {
+                return mar::launch_append<T>(B, M, ws.W, ws.Z, ws.beta, ws.active, ws.K + (size_t)(n + 1) * slab_el,
+                                             ws.SK + (size_t)(n + 1) * slab_el, s);
+            });
+        }
+        launch(c, s, P_EIG, [&] {
+            return mar::launch_eig<T>(B, ns, seeds, nu, ws.h, ws.nu_eff, ws.K, M, c->Hrp, c->Hcol, c->Hval, c->SvalH,
+                                      c->diagS, c->max_row, mu, kT, d_rho, e_seed + blk0, n_seed + blk0,
+                                      nu_out + blk0, d_eps ? d_eps + blk0 * nu : nullptr,
+                                      d_w ? d_w + blk0 * nu : nullptr, s);
+        });
+    }
+    launch(c, s, P_SUM, [&] { return mar::launch_sum(e_seed, n_seeds, d_e_band, s); });
+    HIP_OR(c, hipGetLastError());
+    return MAR_OK;
+}
+
+mar_status check_scalars(mar_ctx* c, int64_t n_seeds, int32_t nu, double mu, double kT, mar_precision prec,
+                         mar_form form) {
+    if (n_seeds < 0) return set_err(c, MAR_ERR_ARG, "n_seeds < 0");
+    if (nu < 1 || nu > c->M) return set_err(c, MAR_ERR_ARG, fmt("nu = %d outside [1, M = %lld]", nu, (long long)c->M));
+    if (!std::isfinite(mu)) return set_err(c, MAR_ERR_ARG, "mu is not finite");
+    if (!(kT >= 0.0) || !std::isfinite(kT)) return set_err(c, MAR_ERR_ARG, "kT must be finite and >= 0");
+    if (prec != MAR_FP64 && prec != MAR_FP32) return set_err(c, MAR_ERR_ARG, "unknown precision");
+    if (form != MAR_FORM_BATCHED && form != MAR_FORM_PLAIN) return set_err(c, MAR_ERR_ARG, "unknown form");
+    if (mar::eig_lds_bytes(nu, c->max_row, false) > 160 * 1024)
+        return set_err(c, MAR_ERR_ARG, fmt("nu = %d too large for the subspace solver with rows of %d entries", nu,
+                                           c->max_row));
+    return MAR_OK;
+}
+
+}  // namespace
+
+// ======================================================================= ABI
+extern "C" {
+
+mar_status mar_create(int64_t M, const int64_t* H_rowptr, const int32_t* H_col, const double* H_val,
+                      const int64_t* S_rowptr, const int32_t* S_col, const double* S_val, mar_ctx** out) {
+    if (!out) return set_err(nullptr, MAR_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (M < 1 || M >= (int64_t)INT32_MAX) return set_err(nullptr, MAR_ERR_ARG, "M must be in [1, 2^31)");
+    std::string msg;
+    mar_status st;
+    if ((st = check_csr(M, H_rowptr, H_col, H_val, "H", msg)) != MAR_OK) return set_err(nullptr, st, msg);
+    if ((st = check_csr(M, S_rowptr, S_col, S_val, "S", msg)) != MAR_OK) return set_err(nullptr, st, msg);
+    if ((st = check_sym(M, H_rowptr, H_col, H_val, "H", msg)) != MAR_OK) return set_err(nullptr, st, msg);
+    if ((st = check_sym(M, S_rowptr, S_col, S_val, "S", msg)) != MAR_OK) return set_err(nullptr, st, msg);
+    int max_row = 0;
+    for (int64_t i = 0; i < M; ++i) max_row = std::max<int>(max_row, (int)(H_rowptr[i + 1] - H_rowptr[i]));
+    if (max_row > mar::MAX_ROW)
+        return set_err(nullptr, MAR_ERR_ARG, fmt("a row of H stores %d entries (at most %d supported)", max_row,
+                                                 mar::MAX_ROW));
+    std::vector<double> svalH(H_rowptr[M], 0.0), diag(M, 0.0);
+    for (int64_t i = 0; i < M; ++i)
+        for (int64_t t = S_rowptr[i]; t < S_rowptr[i + 1]; ++t) {
+            const int64_t u = find_slot(H_rowptr, H_col, i, S_col[t]);
+            if (u < 0)
+                return set_err(nullptr, MAR_ERR_PATTERN,
+                               fmt("S stores (%lld, %d) which H does not", (long long)i, S_col[t]));
+            svalH[u] = S_val[t];
+            if (S_col[t] == i) diag[i] = S_val[t];
+        }
+    for (int64_t i = 0; i < M; ++i)
+        if (!(diag[i] > 0.0))
+            return set_err(nullptr, MAR_ERR_NOT_SPD, fmt("S_jj = %g <= 0 at j = %lld", diag[i], (long long)i));
+
+    int ndev = 0;
+    hipError_t he = hipGetDeviceCount(&ndev);
+    if (he != hipSuccess || ndev < 1) return set_err(nullptr, MAR_ERR_HIP, "no HIP device available");
+    mar_ctx* c = new mar_ctx();
+    hipGetDevice(&c->device);
+    c->M = M;
+    c->nnzH = H_rowptr[M];
+    c->nnzS = S_rowptr[M];
+    c->max_row = max_row;
+    c->tune = mar_tuning{0, 0, 0, 0};
+    for (int k = 0; k < MAR_PROF_CLASSES; ++k) {
+        std::memset(&c->agg[k], 0, sizeof(mar_prof_entry));
+        if (k < P_COUNT) std::snprintf(c->agg[k].name, sizeof c->agg[k].name, "%s", kProfNames[k]);
+    }
+    auto fail = [&](mar_status s2) {
+        g_create_err = c->err;
+        delete c;
+        return s2;
+    };
+    if ((st = build_devmat(c, M, H_rowptr, H_col, H_val, c->H)) != MAR_OK) return fail(st);
+    if ((st = build_devmat(c, M, S_rowptr, S_col, S_val, c->S)) != MAR_OK) return fail(st);
+    std::vector<int32_t> rp32(M + 1);
+    for (int64_t i = 0; i <= M; ++i) rp32[i] = (int32_t)H_rowptr[i];
+    if ((st = upload(c, &c->Hrp, rp32.data(), rp32.size())) != MAR_OK) return fail(st);
+    if ((st = upload(c, &c->Hcol, H_col, (size_t)c->nnzH)) != MAR_OK) return fail(st);
+    if ((st = upload(c, &c->Hval, H_val, (size_t)c->nnzH)) != MAR_OK) return fail(st);
+    if ((st = upload(c, &c->SvalH, svalH.data(), svalH.size())) != MAR_OK) return fail(st);
+    if ((st = upload(c, &c->diagS, diag.data(), diag.size())) != MAR_OK) return fail(st);
+    he = hipStreamCreate(&c->stream);
+    if (he != hipSuccess) {
+        c->err = fmt("hipStreamCreate failed: %s", hipGetErrorString(he));
+        return fail(MAR_ERR_HIP);
+    }
+    *out = c;
+    return MAR_OK;
+}
+
+void mar_destroy(mar_ctx* ctx) {
+    if (!ctx) return;
+    hipDeviceSynchronize();
+    delete ctx;
+}
+
+mar_status mar_solve_async(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds, int32_t nu, double mu, double kT,
+                           mar_precision prec, mar_form form, double* d_rho, double* d_e_band, double* d_e_seed,
+                           double* d_n_seed, int32_t* d_nu_eff, double* d_eps, double* d_weight, void* hip_stream) {
+    if (!c) return MAR_ERR_STATE;
+    mar_status st = check_scalars(c, n_seeds, nu, mu, kT, prec, form);
+    if (st != MAR_OK) return st;
+    if (!d_e_band) return set_err(c, MAR_ERR_ARG, "e_band output is NULL");
+    if (n_seeds > 0 && (!d_seeds || !d_rho)) return set_err(c, MAR_ERR_ARG, "seeds or rho is NULL");
+    HIP_OR(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int B = form == MAR_FORM_PLAIN ? 1 : choose_block(c, nu, prec, n_seeds);
+    if (prec == MAR_FP32)
+        return run_solve<float>(c, d_seeds, n_seeds, nu, mu, kT, B, d_rho, d_e_band, d_e_seed, d_n_seed, d_nu_eff,
+                                d_eps, d_weight, s);
+    return run_solve<double>(c, d_seeds, n_seeds, nu, mu, kT, B, d_rho, d_e_band, d_e_seed, d_n_seed, d_nu_eff,
+                             d_eps, d_weight, s);
+}
+
+mar_status mar_solve(mar_ctx* c, const int32_t* seeds, int64_t n_seeds, int32_t nu, double mu, double kT,
+                     mar_precision prec, mar_form form, double* rho, double* e_band, double* e_seed,
+                     double* n_seed, int32_t* nu_eff, double* eps, double* weight) {
+    if (!c) return MAR_ERR_STATE;
+    mar_status st = check_scalars(c, n_seeds, nu, mu, kT, prec, form);
+    if (st != MAR_OK) return st;
+    if (!rho || !e_band) return set_err(c, MAR_ERR_ARG, "rho or e_band output is NULL");
+    if (n_seeds > 0 && !seeds) return set_err(c, MAR_ERR_ARG, "seeds is NULL");
+    {
+        std::vector<char> seen(c->M, 0);
+        for (int64_t i = 0; i < n_seeds; ++i) {
+            const int32_t j = seeds[i];
+            if (j < 0 || j >= c->M) return set_err(c, MAR_ERR_ARG, fmt("seed %d outside [0, M)", j));
+            if (seen[j]) return set_err(c, MAR_ERR_ARG, fmt("seed %d listed twice", j));
+            seen[j] = 1;
+        }
+    }
+    HIP_OR(c, hipSetDevice(c->device));
+    const size_t nl = (size_t)n_seeds * nu;
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        const size_t o = off;
+        off += align_up(b);
+        return o;
+    };
+    const size_t oSeeds = take(n_seeds * 4), oRho = take(c->nnzH * 8), oEb = take(8), oE = take(n_seeds * 8),
+                 oN = take(n_seeds * 8), oNu = take(n_seeds * 4), oEps = take(eps ? nl * 8 : 0),
+                 oW = take(weight ? nl * 8 : 0);
+    if (off > c->io_bytes) {
+        if (c->io) HIP_OR(c, hipFree(c->io));
+        c->io = nullptr;
+        c->io_bytes = 0;
+        void* p = nullptr;
+        HIP_OR(c, hipMalloc(&p, off));
+        c->io = (char*)p;
+        c->io_bytes = off;
+    }
+    char* b = c->io;
+    hipStream_t s = c->stream;
+    if (n_seeds > 0) HIP_OR(c, hipMemcpyAsync(b + oSeeds, seeds, n_seeds * 4, hipMemcpyHostToDevice, s));
+    HIP_OR(c, hipMemcpyAsync(b + oRho, rho, c->nnzH * 8, hipMemcpyHostToDevice, s));
+    st = mar_solve_async(c, (int32_t*)(b + oSeeds), n_seeds, nu, mu, kT, prec, form, (double*)(b + oRho),
+                         (double*)(b + oEb), (double*)(b + oE), (double*)(b + oN), (int32_t*)(b + oNu),
+                         eps ? (double*)(b + oEps) : nullptr, weight ? (double*)(b + oW) : nullptr, s);
+    if (st != MAR_OK) return st;
+    std::vector<int32_t> nuv(n_seeds);
+    HIP_OR(c, hipMemcpyAsync(rho, b + oRho, c->nnzH * 8, hipMemcpyDeviceToHost, s));
+    HIP_OR(c, hipMemcpyAsync(e_band, b + oEb, 8, hipMemcpyDeviceToHost, s));
+    if (n_seeds > 0) {
+        if (e_seed) HIP_OR(c, hipMemcpyAsync(e_seed, b + oE, n_seeds * 8, hipMemcpyDeviceToHost, s));
+        if (n_seed) HIP_OR(c, hipMemcpyAsync(n_seed, b + oN, n_seeds * 8, hipMemcpyDeviceToHost, s));
+        HIP_OR(c, hipMemcpyAsync(nuv.data(), b + oNu, n_seeds * 4, hipMemcpyDeviceToHost, s));
+        if (eps) HIP_OR(c, hipMemcpyAsync(eps, b + oEps, nl * 8, hipMemcpyDeviceToHost, s));
+        if (weight) HIP_OR(c, hipMemcpyAsync(weight, b + oW, nl * 8, hipMemcpyDeviceToHost, s));
+    }
+    HIP_OR(c, hipStreamSynchronize(s));
+    if (nu_eff && n_seeds > 0) std::memcpy(nu_eff, nuv.data(), n_seeds * 4);
+    for (int64_t i = 0; i < n_seeds; ++i)
+        if (nuv[i] == -1)
+            return set_err(c, MAR_ERR_NOT_SPD, fmt("w^T S w < 0 for seed %d: S is not positive definite", seeds[i]));
+    return MAR_OK;
+}
+
+mar_status mar_set_tuning(mar_ctx* c, const mar_tuning* t) {
+    if (!c) return MAR_ERR_STATE;
+    if (!t) {
+        c->tune = mar_tuning{0, 0, 0, 0};
+        return MAR_OK;
+    }
+    if (t->seed_block < 0 || t->seed_block > 256 || (t->seed_block & (t->seed_block - 1)) != 0)
+        return set_err(c, MAR_ERR_ARG, "seed_block must be 0 or a power of two <= 256");
+    c->tune = *t;
+    return MAR_OK;
+}
+
+mar_status mar_get_tuning(const mar_ctx* c, mar_tuning* t) {
+    if (!c) return MAR_ERR_STATE;
+    if (!t) return MAR_ERR_ARG;
+    *t = c->tune;
+    return MAR_OK;
+}
+
+int32_t mar_seed_block(const mar_ctx* c, int32_t nu, mar_precision prec) {
+    if (!c) return 0;
+    return choose_block(c, nu, prec, 0);
+}
+
+const char* mar_last_error(const mar_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+mar_status mar_profile_enable(mar_ctx* c, int32_t on) {
+    if (!c) return MAR_ERR_STATE;
+    c->prof = on != 0;
+    return MAR_OK;
+}
+
+mar_status mar_profile_reset(mar_ctx* c) {
+    if (!c) return MAR_ERR_STATE;
+    HIP_OR(c, hipDeviceSynchronize());
+    for (auto& r : c->recs) {
+        c->evfree.push_back(r.a);
+        c->evfree.push_back(r.b);
+    }
+    c->recs.clear();
+    for (int k = 0; k < MAR_PROF_CLASSES; ++k) {
+        c->agg[k].launches = 0;
+        c->agg[k].ms = c->agg[k].bytes = c->agg[k].flops = 0.0;
+    }
+    return MAR_OK;
+}
+
+mar_status mar_profile_collect(mar_ctx* c, mar_prof_entry* out, int32_t* n_out) {
+    if (!c) return MAR_ERR_STATE;
+    for (auto& r : c->recs) {
+        HIP_OR(c, hipEventSynchronize(r.b));
+        float ms = 0.f;
+        HIP_OR(c, hipEventElapsedTime(&ms, r.a, r.b));
+        mar_prof_entry& e = c->agg[r.cls];
+        e.launches += 1;
+        e.ms += ms;
+        e.bytes += r.bytes;
+        e.flops += r.flops;
+        c->evfree.push_back(r.a);
+        c->evfree.push_back(r.b);
+    }
+    c->recs.clear();
+    if (out) std::memcpy(out, c->agg, sizeof(mar_prof_entry) * MAR_PROF_CLASSES);
+    if (n_out) *n_out = P_COUNT;
+    return MAR_OK;
+}
+
+int32_t mar_ctx_info(const mar_ctx* c, int64_t* M, int64_t* nnz_H, int64_t* nnz_S) {
+    if (!c) return -1;
+    if (M) *M = c->M;
+    if (nnz_H) *nnz_H = c->nnzH;
+    if (nnz_S) *nnz_S = c->nnzS;
+    return (c->H.bsr ? 1 : 0) | (c->S.bsr ? 2 : 0);
+}
+
+}  // extern "C"

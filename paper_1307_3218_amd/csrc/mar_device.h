@@ -1,0 +1,76 @@
+// Device helpers shared by the streaming kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mar {
+
+// 16-byte vector of T: one global_load/store_dwordx4 per lane.
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { typedef float4 type; static constexpr int n = 4; };
+template <> struct Vec16<double> { typedef double2 type; static constexpr int n = 2; };
+
+__device__ __forceinline__ void unpack(const float4& v, float (&a)[4]) { a[0] = v.x; a[1] = v.y; a[2] = v.z; a[3] = v.w; }
+__device__ __forceinline__ void unpack(const double2& v, double (&a)[2]) { a[0] = v.x; a[1] = v.y; }
+__device__ __forceinline__ float4 pack(const float (&a)[4]) { return make_float4(a[0], a[1], a[2], a[3]); }
+__device__ __forceinline__ double2 pack(const double (&a)[2]) { return make_double2(a[0], a[1]); }
+
+// Seed-interleaved vectors: element e of an [M][B] array belongs to row e / B
+// and seed e % B. A lane owns one 16-byte vector of VEC elements:
+//   B >= VEC: the vector covers seeds (lane_vector_index % P) * VEC + [0, VEC),
+//             P = B / VEC lanes share a row;
+//   B <  VEC: the vector covers VEC / B rows of all B seeds; element i is seed i % B.
+template <typename T, int B>
+struct SeedMap {
+    static constexpr int VEC = Vec16<T>::n;
+    static constexpr int SW = B < VEC ? B : VEC;   // seeds per lane after folding
+    static constexpr int P = B < VEC ? 1 : B / VEC; // lanes per row (distinct seed groups)
+    static_assert(P <= 64, "B too large for one wavefront per row group");
+};
+
+// Map a hardware workgroup id to a logical one so that consecutive logical ids
+// run on the same XCD (the dispatcher deals workgroups round-robin over 8 XCDs,
+// each with its own L2). Bijective on [0, n).
+__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t n) {
+    constexpr int NX = 8;
+    const int64_t per = n / NX, rem = n % NX;
+    const int64_t x = bid % NX, local = bid / NX;
+    return x * per + (x < rem ? x : rem) + local;
+}
+
+// Workgroup reduction of per-seed partial sums (fixed order, deterministic).
+// Thread t holds vals[v][i] for seed (t % P) * SW + i. For every v and every
+// seed b in [0, P*SW) the sum over the workgroup's 256 threads is passed to
+// emit(v, b, sum) by exactly one thread. lds must hold 4 * NV * P * SW values.
+template <int P, int SW, int NV, typename A, typename F>
+__device__ __forceinline__ void wg_seed_reduce(A (&vals)[NV][SW], A* lds, F&& emit) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if constexpr (P < 64) {
+#pragma unroll
+        for (int off = P; off < 64; off <<= 1) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int i = 0; i < SW; ++i) vals[v][i] += __shfl_xor(vals[v][i], off);
+        }
+    }
+    constexpr int TOT = NV * P * SW;
+    if (lane < P) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int i = 0; i < SW; ++i) lds[wave * TOT + (v * P + lane) * SW + i] = vals[v][i];
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < TOT; o += 256) {
+        A s = lds[o];
+        s += lds[TOT + o];
+        s += lds[2 * TOT + o];
+        s += lds[3 * TOT + o];
+        emit(o / (P * SW), o % (P * SW), s);
+    }
+    __syncthreads();
+}
+
+}  // namespace mar

@@ -1,0 +1,356 @@
+// Subspace eigensolve and Fermi-weighted assembly, one workgroup per seed.
+//
+// For seed j with m = nu_eff vectors, A = K^T H K (m x m, FP64) is reduced to
+// tridiagonal form T = Q^T A Q by Householder reflections; the reflections are
+// applied on the fly to the m x (1 + |P(j)|) matrix R = [e_1 | K[P(j), :]^T],
+// so no m x m eigenvector matrix is ever formed. The implicit QL iteration
+// with Wilkinson shifts then diagonalizes T, applying each plane rotation to
+// the rows of R. At the end row alpha of R holds
+//     R[alpha][0]     = y_1alpha            (first component of y_alpha)
+//     R[alpha][1 + t] = e_i . v_alpha,  i = P(j)[t],  v_alpha = K y_alpha
+// which is all the Green's-function assembly needs (Sec. 2):
+//     rho_ij = 2 sum_alpha f_alpha (e_i.v_alpha)(e_j.v_alpha),
+//     w_alpha = (e_j^T S v_alpha)(v_alpha^T e_j) = sqrt(S_jj) y_1alpha (e_j.v_alpha)
+// (K^T S e_j = sqrt(S_jj) e_1 because u_1 = e_j / sqrt(S_jj) and K^T S K = I),
+//     E_j = sum_{i in P(j)} rho_ij H_ij,   N_j = sum_{i in P(j)} rho_ij S_ij.
+#include <cfloat>
+
+#include "mar_device.h"
+#include "mar_internal.h"
+
+namespace mar {
+
+__device__ __forceinline__ double fermi_occ(double eps, double mu, double kT) {
+    if (kT == 0.0) return eps < mu ? 1.0 : (eps > mu ? 0.0 : 0.5);
+    const double x = (eps - mu) / kT;
+    const double t = exp(-fabs(x));
+    return x >= 0.0 ? t / (1.0 + t) : 1.0 / (1.0 + t);
+}
+
+// Sum over the 256 threads; every thread gets the same value (butterfly
+// pairs add the same two operands, so all lanes agree bit for bit).
+__device__ __forceinline__ double block_sum(double v, double* red) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Implicit QL with Wilkinson shifts on the symmetric tridiagonal (d, e),
+// e[i] coupling d[i] and d[i+1], e[m-1] = 0 (Bowdler, Martin, Reinsch and
+// Wilkinson's tql2 scheme). Run by one wavefront: every lane carries the same
+// scalar recurrence, lane c < nr applies each rotation to column c of R.
+// Returns the number of eigenvalues left unconverged (0 on success).
+__device__ int ql_implicit(double* d, double* e, int m, double* R, int nr, int lane) {
+    int fails = 0;
+    for (int l = 0; l < m; ++l) {
+        int iter = 0;
+        for (;;) {
+            int mm = l;
+            for (; mm < m - 1; ++mm) {
+                const double dd = fabs(d[mm]) + fabs(d[mm + 1]);
+                if (fabs(e[mm]) <= DBL_EPSILON * dd) break;
+            }
+            if (mm == l) break;
+            if (++iter > 80) {
+                ++fails;
+                break;
+            }
+            double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+            double r = hypot(g, 1.0);
+            g = d[mm] - d[l] + e[l] / (g + copysign(r, g));
+            double s = 1.0, c = 1.0, p = 0.0;
+            bool split = false;
+            for (int i = mm - 1; i >= l; --i) {
+                const double f = s * e[i], bb = c * e[i];
+                r = hypot(f, g);
+                e[i + 1] = r;
+                if (r == 0.0) {
+                    d[i + 1] -= p;
+                    e[mm] = 0.0;
+                    split = true;
+                    break;
+                }
+                s = f / r;
+                c = g / r;
+                g = d[i + 1] - p;
+                r = (d[i] - g) * s + 2.0 * c * bb;
+                p = s * r;
+                d[i + 1] = g + p;
+                g = c * r - bb;
+                if (lane < nr) {
+                    const double a0 = R[i * nr + lane], a1 = R[(i + 1) * nr + lane];
+                    R[(i + 1) * nr + lane] = s * a0 + c * a1;
+                    R[i * nr + lane] = c * a0 - s * a1;
+                }
+            }
+            if (split) continue;
+            d[l] -= p;
+            e[l] = g;
+            e[mm] = 0.0;
+        }
+    }
+    return fails;
+}
+
+size_t eig_lds_bytes(int nu, int max_row, bool a_in_lds) {
+    size_t n = (a_in_lds ? (size_t)nu * nu : 0) + (size_t)nu * (max_row + 1) + 4 * (size_t)nu + 8 + 64 + 64 + 2;
+    return n * sizeof(double);
+}
+
+bool eig_a_fits_lds(int nu, int max_row) { return eig_lds_bytes(nu, max_row, true) <= 160 * 1024; }
+
+template <typename T, bool LDS_A>
+__global__ __launch_bounds__(WG) void k_eig(int nseeds, const int32_t* __restrict__ seeds, int B, int nu,
+                                            double* __restrict__ h, const int32_t* __restrict__ nu_eff_blk,
+                                            const T* __restrict__ K, int64_t M, const int32_t* __restrict__ Hrp,
+                                            const int32_t* __restrict__ Hcol, const double* __restrict__ Hval,
+                                            const double* __restrict__ SvalH, const double* __restrict__ diagS,
+                                            int max_row, double mu, double kT, double* __restrict__ rho,
+                                            double* __restrict__ e_seed, double* __restrict__ n_seed,
+                                            int32_t* __restrict__ nu_eff_out, double* __restrict__ eps_out,
+                                            double* __restrict__ w_out) {
+    extern __shared__ double smem[];
+    const int b = blockIdx.x;
+    if (b >= nseeds) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m = nu_eff_blk[b];
+    double* eps_b = eps_out ? eps_out + (int64_t)b * nu : nullptr;
+    double* w_b = w_out ? w_out + (int64_t)b * nu : nullptr;
+    if (m <= 0) {
+        if (tid == 0) {
+            nu_eff_out[b] = m;
+            e_seed[b] = 0.0;
+            n_seed[b] = 0.0;
+        }
+        for (int a = tid; a < nu; a += WG) {
+            if (eps_b) eps_b[a] = 0.0;
+            if (w_b) w_b[a] = 0.0;
+        }
+        return;
+    }
+    const int j = seeds[b];
+    const int rlo = Hrp[j];
+    const int nP = Hrp[j + 1] - rlo;
+    const int NR = nP + 1;
+
+    double* A;
+    int ld;
+    double* p = smem;
+    if constexpr (LDS_A) {
+        A = p;
+        ld = m;
+        p += (size_t)nu * nu;
+    } else {
+        A = h + (int64_t)b * nu * nu;
+        ld = nu;
+    }
+    double* R = p;
+    p += (size_t)nu * (max_row + 1);
+    double* d = p;
+    p += nu;
+    double* e = p;
+    p += nu;
+    double* v = p;
+    p += nu;
+    double* q = p;
+    p += nu;
+    double* red = p;
+    p += 8;
+    double* svec = p;
+    p += 64;
+    double* rhoL = p;
+    p += 64;
+    int* tjp = reinterpret_cast<int*>(p);
+
+    // A = K^T H K from its computed upper triangle (h[b][k][n], k <= n), mirrored.
+    const double* hb = h + (int64_t)b * nu * nu;
+    if constexpr (LDS_A) {
+        for (int r = wave; r < m; r += 4)
+            for (int c = lane; c < m; c += 64) A[r * ld + c] = r <= c ? hb[(int64_t)r * nu + c] : hb[(int64_t)c * nu + r];
+    } else {
+        for (int r = wave; r < m; r += 4)
+            for (int c = lane; c < r; c += 64) A[r * ld + c] = A[c * ld + r];
+    }
+    // R = [e_1 | K[P(j), :]^T]
+    for (int idx = tid; idx < m * NR; idx += WG) {
+        const int k = idx / NR, c = idx - k * NR;
+        R[idx] = c == 0 ? (k == 0 ? 1.0 : 0.0) : (double)K[((int64_t)k * M + Hcol[rlo + c - 1]) * B + b];
+    }
+    if (tid < nP && Hcol[rlo + tid] == j) *tjp = tid;
+    __syncthreads();
+
+    // Householder tridiagonalization, reflections also applied to R.
+    for (int k = 0; k < m - 2; ++k) {
+        const int len = m - k - 1;
+        const double* xr = A + k * ld + k + 1;  // row k right of the diagonal = column k below it
+        double part = 0.0;
+        for (int i = 1 + tid; i < len; i += WG) part += xr[i] * xr[i];
+        const double rest = block_sum(part, red);
+        const double x0 = xr[0];
+        if (rest == 0.0) {
+            if (tid == 0) {
+                d[k] = A[k * ld + k];
+                e[k] = x0;
+            }
+            continue;
+        }
+        const double xx = rest + x0 * x0;
+        const double alpha = -copysign(sqrt(xx), x0);
+        const double vn = 1.0 / sqrt(2.0 * (xx - alpha * x0));
+        for (int i = tid; i < len; i += WG) v[i] = (xr[i] - (i == 0 ? alpha : 0.0)) * vn;
+        __syncthreads();
+        // q = A22 v, then q = 2 (q - (v.q) v): A22 <- A22 - v q^T - q v^T
+        double pv = 0.0;
+        for (int i = tid; i < len; i += WG) {
+            const double* col = A + (k + 1) * ld + (k + 1) + i;
+            double s = 0.0;
+            for (int jj = 0; jj < len; ++jj) s += col[jj * ld] * v[jj];
+            q[i] = s;
+            pv += s * v[i];
+        }
+        const double kp = block_sum(pv, red);
+        for (int i = tid; i < len; i += WG) q[i] = 2.0 * (q[i] - kp * v[i]);
+        __syncthreads();
+        for (int r = wave; r < len; r += 4) {
+            const double vr = v[r], qr = q[r];
+            double* row = A + (k + 1 + r) * ld + (k + 1);
+            for (int c = lane; c < len; c += 64) row[c] -= vr * q[c] + qr * v[c];
+        }
+        for (int cb = 0; cb < NR; cb += WG / 8) {
+            const int c = cb + (tid >> 3), pi = tid & 7;
+            double s = 0.0;
+            if (c < NR)
+                for (int i = pi; i < len; i += 8) s += v[i] * R[(k + 1 + i) * NR + c];
+            s += __shfl_xor(s, 1);
+            s += __shfl_xor(s, 2);
+            s += __shfl_xor(s, 4);
+            if (c < NR && pi == 0) svec[c] = s;
+        }
+        __syncthreads();
+        for (int idx = tid; idx < len * NR; idx += WG) {
+            const int i = idx / NR, c = idx - i * NR;
+            R[(k + 1 + i) * NR + c] -= 2.0 * v[i] * svec[c];
+        }
+        if (tid == 0) {
+            d[k] = A[k * ld + k];
+            e[k] = alpha;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        if (m >= 2) {
+            d[m - 2] = A[(m - 2) * ld + (m - 2)];
+            e[m - 2] = A[(m - 2) * ld + (m - 1)];
+            d[m - 1] = A[(m - 1) * ld + (m - 1)];
+        } else {
+            d[0] = A[0];
+        }
+        e[m - 1] = 0.0;
+    }
+    __syncthreads();
+    if (wave == 0) ql_implicit(d, e, m, R, NR, lane);
+    __syncthreads();
+
+    // Fermi-weighted assembly.
+    const int tj = *tjp;
+    const double sq = sqrt(diagS[j]);
+    double* fz = q;
+    for (int a = tid; a < m; a += WG) {
+        const double ea = d[a];
+        const double zj = R[a * NR + 1 + tj];
+        fz[a] = fermi_occ(ea, mu, kT) * zj;
+        if (eps_b) eps_b[a] = ea;
+        if (w_b) w_b[a] = sq * R[a * NR] * zj;
+    }
+    for (int a = m + tid; a < nu; a += WG) {
+        if (eps_b) eps_b[a] = 0.0;
+        if (w_b) w_b[a] = 0.0;
+    }
+    __syncthreads();
+    for (int cb = 0; cb < nP; cb += WG / 8) {
+        const int t = cb + (tid >> 3), pi = tid & 7;
+        double s = 0.0;
+        if (t < nP)
+            for (int a = pi; a < m; a += 8) s += fz[a] * R[a * NR + 1 + t];
+        s += __shfl_xor(s, 1);
+        s += __shfl_xor(s, 2);
+        s += __shfl_xor(s, 4);
+        if (t < nP && pi == 0) {
+            const double r = 2.0 * s;
+            rho[rlo + t] = r;
+            rhoL[t] = r;
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double E = 0.0, N = 0.0;
+        for (int t = 0; t < nP; ++t) {
+            E += rhoL[t] * Hval[rlo + t];
+            N += rhoL[t] * SvalH[rlo + t];
+        }
+        e_seed[b] = E;
+        n_seed[b] = N;
+        nu_eff_out[b] = m;
+    }
+}
+
+template <typename T>
+static LaunchInfo launch_eig_t(int B, int nseeds, const int32_t* seeds, int nu, double* h, const int32_t* nu_eff_blk,
+                               const T* K, int64_t M, const int32_t* Hrp, const int32_t* Hcol, const double* Hval,
+                               const double* SvalH, const double* diagS, int max_row, double mu, double kT,
+                               double* rho, double* e_seed, double* n_seed, int32_t* nu_eff_out, double* eps_out,
+                               double* w_out, hipStream_t s) {
+    const bool lds_a = eig_a_fits_lds(nu, max_row);
+    const size_t lds = eig_lds_bytes(nu, max_row, lds_a);
+    if (lds_a) {
+        static bool attr = false;
+        if (!attr) {
+            hipFuncSetAttribute((const void*)k_eig<T, true>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            attr = true;
+        }
+        hipLaunchKernelGGL((k_eig<T, true>), dim3(nseeds), dim3(WG), lds, s, nseeds, seeds, B, nu, h, nu_eff_blk, K,
+                           M, Hrp, Hcol, Hval, SvalH, diagS, max_row, mu, kT, rho, e_seed, n_seed, nu_eff_out,
+                           eps_out, w_out);
+    } else {
+        static bool attr = false;
+        if (!attr) {
+            hipFuncSetAttribute((const void*)k_eig<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            attr = true;
+        }
+        hipLaunchKernelGGL((k_eig<T, false>), dim3(nseeds), dim3(WG), lds, s, nseeds, seeds, B, nu, h, nu_eff_blk, K,
+                           M, Hrp, Hcol, Hval, SvalH, diagS, max_row, mu, kT, rho, e_seed, n_seed, nu_eff_out,
+                           eps_out, w_out);
+    }
+    LaunchInfo li;
+    li.wgs = nseeds;
+    const double nv = (double)nu;
+    li.bytes = (double)nseeds * (nv * nv * 8.0 + nv * (max_row + 1) * sizeof(T) + (max_row + 3) * 8.0 * 3);
+    li.flops = (double)nseeds * ((4.0 / 3.0) * nv * nv * nv + 4.0 * nv * nv * (max_row + 1));
+    return li;
+}
+
+template <>
+LaunchInfo launch_eig<float>(int B, int nseeds, const int32_t* seeds, int nu, double* h, const int32_t* nu_eff_blk,
+                             const float* K, int64_t M, const int32_t* Hrp, const int32_t* Hcol, const double* Hval,
+                             const double* SvalH, const double* diagS, int max_row, double mu, double kT, double* rho,
+                             double* e_seed, double* n_seed, int32_t* nu_eff_out, double* eps_out, double* w_out,
+                             hipStream_t s) {
+    return launch_eig_t<float>(B, nseeds, seeds, nu, h, nu_eff_blk, K, M, Hrp, Hcol, Hval, SvalH, diagS, max_row, mu,
+                               kT, rho, e_seed, n_seed, nu_eff_out, eps_out, w_out, s);
+}
+
+template <>
+LaunchInfo launch_eig<double>(int B, int nseeds, const int32_t* seeds, int nu, double* h, const int32_t* nu_eff_blk,
+                              const double* K, int64_t M, const int32_t* Hrp, const int32_t* Hcol,
+                              const double* Hval, const double* SvalH, const double* diagS, int max_row, double mu,
+                              double kT, double* rho, double* e_seed, double* n_seed, int32_t* nu_eff_out,
+                              double* eps_out, double* w_out, hipStream_t s) {
+    return launch_eig_t<double>(B, nseeds, seeds, nu, h, nu_eff_blk, K, M, Hrp, Hcol, Hval, SvalH, diagS, max_row,
+                                mu, kT, rho, e_seed, n_seed, nu_eff_out, eps_out, w_out, s);
+}
+
+}  // namespace mar

@@ -1,0 +1,88 @@
+// Internal declarations shared by the host API and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+namespace mar {
+
+constexpr int WG = 256;            // threads per workgroup for every streaming kernel
+constexpr int PROJ_Q = 8;          // 16-byte vectors per thread in a projection chunk
+constexpr int PROJ_KG = 4;         // basis slabs reduced together in a projection
+constexpr int MAX_ROW = 63;        // max stored entries in a row of H (|P(j)| <= 63)
+
+// Device copy of one sparse matrix. BSR 4x4 (values [blk][r][c]) when the
+// pattern has that structure, else CSR. Values are kept in FP64 and FP32.
+struct DevMat {
+    bool bsr = false;
+    int64_t n = 0;          // block rows (BSR) or rows (CSR)
+    int64_t nnz = 0;        // blocks (BSR) or entries (CSR)
+    int32_t* ptr = nullptr; // n + 1
+    int32_t* idx = nullptr; // nnz
+    double* v64 = nullptr;  // nnz * (bsr ? 16 : 1)
+    float* v32 = nullptr;
+    double bytes_per_pass(size_t p) const {  // values + indices read once
+        return (double)nnz * ((bsr ? 16.0 : 1.0) * (double)p + 4.0) + (double)(n + 1) * 4.0;
+    }
+};
+
+// Pointers of one seed block's device workspace.
+template <typename T>
+struct BlockWS {
+    T* K;        // [nu][M][B]
+    T* SK;       // [nu][M][B]
+    T* W;        // [M][B]
+    T* Z;        // [M][B]
+    double* part;   // partial sums, [chunk][...]
+    double* red1;   // [2][nu][B]  (h column, c1)
+    double* red2;   // [nu][B]     (c2)
+    double* redb;   // [B]         (beta^2)
+    double* h;      // [B][nu][nu]
+    double* beta;   // [B]
+    int32_t* active;   // [B]
+    int32_t* nu_eff;   // [B]
+};
+
+// ---- launchers (defined per element type in mar_launch_*.hip) ----
+// Every launcher returns the number of workgroups it launched (for partials)
+// and sets *bytes / *flops to the algorithmic traffic of the launch.
+struct LaunchInfo {
+    int64_t wgs = 0;
+    double bytes = 0, flops = 0;
+};
+
+template <typename T>
+LaunchInfo launch_init(int B, int64_t Mp, int64_t M, const int32_t* seeds, int nseeds, const double* diagS,
+                       int nu, T* K0, int32_t* active, int32_t* nu_eff, hipStream_t s);
+template <typename T>
+LaunchInfo launch_spmm(int B, const DevMat& A, const T* X, T* Y, double* part, hipStream_t s);
+template <typename T>
+LaunchInfo launch_proj(int B, int ns, const T* b0, const T* b1, int64_t M, int nk, const T* x,
+                       double* part, int64_t* nchunks, hipStream_t s);
+template <typename T>
+LaunchInfo launch_upd(int B, const T* basis, int64_t M, int nk, const double* c, T* x, hipStream_t s);
+template <typename T>
+LaunchInfo launch_append(int B, int64_t M, const T* W, const T* Z, const double* beta,
+                         const int32_t* active, T* Kn, T* SKn, hipStream_t s);
+template <typename T>
+LaunchInfo launch_eig(int B, int nseeds, const int32_t* seeds, int nu, double* h, const int32_t* nu_eff_blk,
+                      const T* K, int64_t M, const int32_t* Hrp, const int32_t* Hcol, const double* Hval,
+                      const double* SvalH, const double* diagS, int max_row, double mu, double kT,
+                      double* rho, double* e_seed, double* n_seed, int32_t* nu_eff_out, double* eps_out,
+                      double* w_out, hipStream_t s);
+
+LaunchInfo launch_reduce(const double* part, int64_t nchunks, int64_t L, double* out, double* h, int B, int nu,
+                         int n, hipStream_t s);
+LaunchInfo launch_norm(int B, int nk, const double* beta2, const double* c1, const double* c2, double tau,
+                       int32_t* active, int32_t* nu_eff, double* beta, int n, hipStream_t s);
+LaunchInfo launch_sum(const double* x, int64_t n, double* out, hipStream_t s);
+LaunchInfo launch_zero(void* p, int64_t bytes, hipStream_t s);  // bytes: multiple of 16
+
+// Largest B accepted for an element type (P = B / vector width must fit one wavefront).
+template <typename T>
+constexpr int max_block() { return sizeof(T) == 4 ? 256 : 128; }
+
+size_t eig_lds_bytes(int nu, int max_row, bool a_in_lds);
+bool eig_a_fits_lds(int nu, int max_row);
+
+}  // namespace mar

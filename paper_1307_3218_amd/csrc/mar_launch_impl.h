@@ -1,0 +1,485 @@
+// Streaming kernels of the Krylov/CGS2 phase and their launchers, for one
+// element type MAR_T (float or double). Included once per type.
+//
+// Layout (all per seed block of B seeds): vectors are [M][B] with the seed
+// index fastest; the basis K and S*K are [nu][M][B] (slab k = k-th vector of
+// every seed). Each kernel streams whole slabs with 16-byte vector accesses.
+#include "mar_device.h"
+#include "mar_internal.h"
+
+#ifndef MAR_T
+#error "define MAR_T before including"
+#endif
+
+namespace mar {
+
+// ---------------------------------------------------------------------------
+// u_1 = e_j / sqrt(S_jj) for every seed of the block (the first basis vector,
+// which puts e_j in L_nu^(j)); flags seeds outside [0, M) as invalid.
+template <typename T, int B>
+__global__ __launch_bounds__(WG) void k_init(int64_t Mp, int64_t M, const int32_t* __restrict__ seeds, int nseeds,
+                                             const double* __restrict__ diagS, int nu, T* __restrict__ K0,
+                                             int32_t* __restrict__ active, int32_t* __restrict__ nu_eff) {
+    using SM = SeedMap<T, B>;
+    constexpr int VEC = SM::VEC;
+    using VT = typename Vec16<T>::type;
+    const int64_t nvec = Mp * B / VEC;
+    const int64_t vi = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (vi < B) {
+        const int b = (int)vi;
+        const int j = b < nseeds ? seeds[b] : -1;
+        const bool ok = j >= 0 && j < M;
+        active[b] = ok ? 1 : 0;
+        nu_eff[b] = ok ? nu : (b < nseeds ? -2 : 0);
+    }
+    if (vi >= nvec) return;
+    T a[VEC];
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) {
+        const int64_t e = vi * VEC + i;
+        const int64_t row = e / B;
+        const int b = (int)(e % B);
+        const int j = b < nseeds ? seeds[b] : -1;
+        a[i] = (j >= 0 && j < M && row == j) ? (T)(1.0 / sqrt(diagS[j])) : (T)0;
+    }
+    reinterpret_cast<VT*>(K0)[vi] = pack(a);
+}
+
+// ---------------------------------------------------------------------------
+// Y = A X over B seed-interleaved vectors, A in BSR 4x4. Thread = (block row,
+// seed group). The 16 block values are read once per thread and reused for
+// SW seeds; X rows of the block column are 16-byte vector loads.
+// DOT: also emit per-workgroup partial sums of X.Y per seed (FP64), the S-norm
+// of the residual (w^T S w).
+template <typename T, int B, bool DOT>
+__global__ __launch_bounds__(WG) void k_spmm_bsr4(int64_t nbrow, const int32_t* __restrict__ brp,
+                                                  const int32_t* __restrict__ bcol, const T* __restrict__ bval,
+                                                  const T* __restrict__ X, T* __restrict__ Y,
+                                                  double* __restrict__ part) {
+    using SM = SeedMap<T, B>;
+    constexpr int VEC = SM::VEC, SW = SM::SW, P = SM::P;
+    using VT = typename Vec16<T>::type;
+    const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t g = bid * WG + threadIdx.x;
+    const int64_t I = g / P;
+    const int grp = threadIdx.x % P;
+    const int s0 = (B < VEC) ? 0 : grp * VEC;
+    const VT* Xv = reinterpret_cast<const VT*>(X);
+    T acc[4][SW];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int i = 0; i < SW; ++i) acc[r][i] = (T)0;
+    if (I < nbrow) {
+        const int lo = brp[I], hi = brp[I + 1];
+        for (int blk = lo; blk < hi; ++blk) {
+            const int64_t J = bcol[blk];
+            T a[16];
+            const VT* av = reinterpret_cast<const VT*>(bval + (int64_t)blk * 16);
+#pragma unroll
+            for (int q = 0; q < 16 / VEC; ++q) {
+                T t[VEC];
+                unpack(av[q], t);
+#pragma unroll
+                for (int i = 0; i < VEC; ++i) a[q * VEC + i] = t[i];
+            }
+            T xv[4][SW];
+            if constexpr (B >= VEC) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    T t[VEC];
+                    unpack(Xv[((4 * J + c) * B + s0) / VEC], t);
+#pragma unroll
+                    for (int i = 0; i < VEC; ++i) xv[c][i] = t[i];
+                }
+            } else {
+                T t[4 * B];
+#pragma unroll
+                for (int q = 0; q < 4 * B / VEC; ++q) {
+                    T u[VEC];
+                    unpack(Xv[(4 * J * B) / VEC + q], u);
+#pragma unroll
+                    for (int i = 0; i < VEC; ++i) t[q * VEC + i] = u[i];
+                }
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+#pragma unroll
+                    for (int i = 0; i < SW; ++i) xv[c][i] = t[c * B + i];
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int i = 0; i < SW; ++i) {
+                    T s = acc[r][i];
+                    s = fma(a[r * 4 + 0], xv[0][i], s);
+                    s = fma(a[r * 4 + 1], xv[1][i], s);
+                    s = fma(a[r * 4 + 2], xv[2][i], s);
+                    s = fma(a[r * 4 + 3], xv[3][i], s);
+                    acc[r][i] = s;
+                }
+        }
+        VT* Yv = reinterpret_cast<VT*>(Y);
+        if constexpr (B >= VEC) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Yv[((4 * I + r) * B + s0) / VEC] = pack(acc[r]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4 * B / VEC; ++q) {
+                T u[VEC];
+#pragma unroll
+                for (int i = 0; i < VEC; ++i) u[i] = acc[(q * VEC + i) / B][(q * VEC + i) % B];
+                Yv[(4 * I * B) / VEC + q] = pack(u);
+            }
+        }
+    }
+    if constexpr (DOT) {
+        double d[1][SW];
+#pragma unroll
+        for (int i = 0; i < SW; ++i) d[0][i] = 0.0;
+        if (I < nbrow) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int i = 0; i < SW; ++i)
+                    d[0][i] += (double)X[(4 * I + r) * B + s0 + i] * (double)acc[r][i];
+        }
+        __shared__ double lds[4 * P * SW];
+        wg_seed_reduce<P, SW, 1>(d, lds, [&](int, int b, double s) { part[bid * B + b] = s; });
+    }
+}
+
+// Y = A X with A in CSR (patterns without 4x4 block structure). Thread = (row, seed group).
+template <typename T, int B, bool DOT>
+__global__ __launch_bounds__(WG) void k_spmm_csr(int64_t nrow, const int32_t* __restrict__ rp,
+                                                 const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                 const T* __restrict__ X, T* __restrict__ Y,
+                                                 double* __restrict__ part) {
+    using SM = SeedMap<T, B>;
+    constexpr int VEC = SM::VEC, SW = SM::SW, P = SM::P;
+    using VT = typename Vec16<T>::type;
+    const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t g = bid * WG + threadIdx.x;
+    const int64_t i0 = g / P;
+    const int grp = threadIdx.x % P;
+    const int s0 = (B < VEC) ? 0 : grp * VEC;
+    T acc[SW];
+#pragma unroll
+    for (int i = 0; i < SW; ++i) acc[i] = (T)0;
+    if (i0 < nrow) {
+        for (int t = rp[i0]; t < rp[i0 + 1]; ++t) {
+            const int64_t c = col[t];
+            const T a = val[t];
+            if constexpr (B >= VEC) {
+                T u[VEC];
+                unpack(reinterpret_cast<const VT*>(X)[(c * B + s0) / VEC], u);
+#pragma unroll
+                for (int i = 0; i < SW; ++i) acc[i] = fma(a, u[i], acc[i]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < SW; ++i) acc[i] = fma(a, X[c * B + i], acc[i]);
+            }
+        }
+        if constexpr (B >= VEC) {
+            reinterpret_cast<VT*>(Y)[(i0 * B + s0) / VEC] = pack(acc);
+        } else {
+#pragma unroll
+            for (int i = 0; i < SW; ++i) Y[i0 * B + i] = acc[i];
+        }
+    }
+    if constexpr (DOT) {
+        double d[1][SW];
+#pragma unroll
+        for (int i = 0; i < SW; ++i) d[0][i] = (i0 < nrow) ? (double)X[i0 * B + s0 + i] * (double)acc[i] : 0.0;
+        __shared__ double lds[4 * P * SW];
+        wg_seed_reduce<P, SW, 1>(d, lds, [&](int, int b, double s) { part[bid * B + b] = s; });
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Projection pass of CGS: for the basis slabs k in this workgroup's range,
+//   out[s][k][b] = sum over this chunk's rows of basis_s[k][row][b] * x[row][b]
+// (s = 0: K, s = 1: S K). Partial sums per chunk go to part[chunk][s][k][b];
+// a second kernel reduces over chunks in a fixed order. The chunk of x stays
+// in registers and is reused for every slab.
+template <typename T, int B, int NS, int Q, int KG>
+__global__ __launch_bounds__(WG) void k_proj(const T* __restrict__ b0, const T* __restrict__ b1, int64_t slab,
+                                             int nk, int kps, const T* __restrict__ x, int64_t nvec,
+                                             double* __restrict__ part) {
+    using SM = SeedMap<T, B>;
+    constexpr int VEC = SM::VEC, SW = SM::SW, P = SM::P;
+    using VT = typename Vec16<T>::type;
+    const int tid = threadIdx.x;
+    const int64_t chunk = blockIdx.x;
+    const int64_t vbase = chunk * (WG * Q) + tid;
+    const int64_t slabv = slab / VEC;
+    const VT* xv = reinterpret_cast<const VT*>(x);
+    const VT* bv0 = reinterpret_cast<const VT*>(b0);
+    const VT* bv1 = reinterpret_cast<const VT*>(b1);
+    T xr[Q][VEC];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int64_t vi = vbase + (int64_t)q * WG;
+        if (vi < nvec) unpack(xv[vi], xr[q]);
+        else {
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) xr[q][i] = (T)0;
+        }
+    }
+    const int k0 = blockIdx.y * kps;
+    const int k1 = min(nk, k0 + kps);
+    __shared__ T lds[4 * NS * KG * P * SW];
+    for (int kb = k0; kb < k1; kb += KG) {
+        T raw[NS][KG][VEC];
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int kk = 0; kk < KG; ++kk)
+#pragma unroll
+                for (int i = 0; i < VEC; ++i) raw[s][kk][i] = (T)0;
+#pragma unroll
+        for (int kk = 0; kk < KG; ++kk) {
+            const int k = kb + kk;
+            if (k < k1) {
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    const int64_t vi = vbase + (int64_t)q * WG;
+                    if (vi < nvec) {
+                        T a[VEC];
+                        unpack(bv0[(int64_t)k * slabv + vi], a);
+#pragma unroll
+                        for (int i = 0; i < VEC; ++i) raw[0][kk][i] = fma(a[i], xr[q][i], raw[0][kk][i]);
+                        if constexpr (NS == 2) {
+                            T c[VEC];
+                            unpack(bv1[(int64_t)k * slabv + vi], c);
+#pragma unroll
+                            for (int i = 0; i < VEC; ++i) raw[1][kk][i] = fma(c[i], xr[q][i], raw[1][kk][i]);
+                        }
+                    }
+                }
+            }
+        }
+        T acc[NS * KG][SW];
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int kk = 0; kk < KG; ++kk) {
+#pragma unroll
+                for (int i = 0; i < SW; ++i) acc[s * KG + kk][i] = (T)0;
+#pragma unroll
+                for (int i = 0; i < VEC; ++i) acc[s * KG + kk][i % SW] += raw[s][kk][i];
+            }
+        wg_seed_reduce<P, SW, NS * KG>(acc, lds, [&](int v, int b, T sum) {
+            const int s = v / KG, k = kb + v % KG;
+            if (k < k1) part[((chunk * NS + s) * nk + k) * B + b] = (double)sum;
+        });
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Update pass of CGS: x[row][b] -= sum_k basis[k][row][b] * c[k][b].
+template <typename T, int B, int Q>
+__global__ __launch_bounds__(WG) void k_upd(const T* __restrict__ basis, int64_t slab, int nk,
+                                            const double* __restrict__ c, T* __restrict__ x, int64_t nvec) {
+    using SM = SeedMap<T, B>;
+    constexpr int VEC = SM::VEC, P = SM::P;
+    using VT = typename Vec16<T>::type;
+    const int tid = threadIdx.x;
+    const int64_t vbase = (int64_t)blockIdx.x * (WG * Q) + tid;
+    const int64_t slabv = slab / VEC;
+    const int sb = (B < VEC) ? 0 : (tid % P) * VEC;
+    VT* xv = reinterpret_cast<VT*>(x);
+    const VT* bv = reinterpret_cast<const VT*>(basis);
+    T acc[Q][VEC];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int64_t vi = vbase + (int64_t)q * WG;
+        if (vi < nvec) unpack(xv[vi], acc[q]);
+        else {
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) acc[q][i] = (T)0;
+        }
+    }
+    for (int k = 0; k < nk; ++k) {
+        T cv[VEC];
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) cv[i] = (T)c[(int64_t)k * B + ((B < VEC) ? (i % B) : (sb + i))];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int64_t vi = vbase + (int64_t)q * WG;
+            if (vi < nvec) {
+                T a[VEC];
+                unpack(bv[(int64_t)k * slabv + vi], a);
+#pragma unroll
+                for (int i = 0; i < VEC; ++i) acc[q][i] = fma(-a[i], cv[i], acc[q][i]);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int64_t vi = vbase + (int64_t)q * WG;
+        if (vi < nvec) xv[vi] = pack(acc[q]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Append u_{n+1} = w / beta and s_{n+1} = (S w) / beta (zero for seeds that
+// stopped: breakdown, invalid seed or padding).
+template <typename T, int B>
+__global__ __launch_bounds__(WG) void k_append(const T* __restrict__ W, const T* __restrict__ Z,
+                                               const double* __restrict__ beta, const int32_t* __restrict__ active,
+                                               T* __restrict__ Kn, T* __restrict__ SKn, int64_t nvec) {
+    using SM = SeedMap<T, B>;
+    constexpr int VEC = SM::VEC, P = SM::P;
+    using VT = typename Vec16<T>::type;
+    const int64_t vi = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (vi >= nvec) return;
+    const int sb = (B < VEC) ? 0 : (threadIdx.x % P) * VEC;
+    T w[VEC], z[VEC];
+    unpack(reinterpret_cast<const VT*>(W)[vi], w);
+    unpack(reinterpret_cast<const VT*>(Z)[vi], z);
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) {
+        const int b = (B < VEC) ? (i % B) : (sb + i);
+        if (active[b]) {
+            const T bt = (T)beta[b];
+            w[i] = w[i] / bt;
+            z[i] = z[i] / bt;
+        } else {
+            w[i] = (T)0;
+            z[i] = (T)0;
+        }
+    }
+    reinterpret_cast<VT*>(Kn)[vi] = pack(w);
+    reinterpret_cast<VT*>(SKn)[vi] = pack(z);
+}
+
+// ---------------------------------------------------------------------------
+// Launchers: dispatch the runtime block size B to the compiled instance.
+#define MAR_DISPATCH_B(B, ...)                                   \
+    switch (B) {                                                 \
+        case 1: { constexpr int BB = 1; __VA_ARGS__; } break;    \
+        case 2: { constexpr int BB = 2; __VA_ARGS__; } break;    \
+        case 4: { constexpr int BB = 4; __VA_ARGS__; } break;    \
+        case 8: { constexpr int BB = 8; __VA_ARGS__; } break;    \
+        case 16: { constexpr int BB = 16; __VA_ARGS__; } break;  \
+        case 32: { constexpr int BB = 32; __VA_ARGS__; } break;  \
+        case 64: { constexpr int BB = 64; __VA_ARGS__; } break;  \
+        case 128: { constexpr int BB = 128; __VA_ARGS__; } break;\
+        default: MAR_DISPATCH_BIG(__VA_ARGS__);                  \
+    }
+
+template <>
+LaunchInfo launch_init<MAR_T>(int B, int64_t Mp, int64_t M, const int32_t* seeds, int nseeds, const double* diagS,
+                              int nu, MAR_T* K0, int32_t* active, int32_t* nu_eff, hipStream_t s) {
+    constexpr int VEC = Vec16<MAR_T>::n;
+    const int64_t nvec = Mp * B / VEC;
+    const int64_t wgs = (std::max<int64_t>(nvec, B) + WG - 1) / WG;
+    MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_init<MAR_T, BB>), dim3(wgs), dim3(WG), 0, s, Mp, M, seeds, nseeds,
+                                         diagS, nu, K0, active, nu_eff));
+    LaunchInfo li;
+    li.wgs = wgs;
+    li.bytes = (double)Mp * B * sizeof(MAR_T);
+    return li;
+}
+
+template <>
+LaunchInfo launch_spmm<MAR_T>(int B, const DevMat& A, const MAR_T* X, MAR_T* Y, double* part, hipStream_t s) {
+    constexpr int VEC = Vec16<MAR_T>::n;
+    const int P = B < VEC ? 1 : B / VEC;
+    const int64_t wgs = (A.n * P + WG - 1) / WG;
+    const MAR_T* val = std::is_same<MAR_T, float>::value ? (const MAR_T*)A.v32 : (const MAR_T*)A.v64;
+    const bool dot = part != nullptr;
+    if (A.bsr) {
+        if (dot) {
+            MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_spmm_bsr4<MAR_T, BB, true>), dim3(wgs), dim3(WG), 0, s, A.n,
+                                                 A.ptr, A.idx, val, X, Y, part));
+        } else {
+            MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_spmm_bsr4<MAR_T, BB, false>), dim3(wgs), dim3(WG), 0, s, A.n,
+                                                 A.ptr, A.idx, val, X, Y, part));
+        }
+    } else {
+        if (dot) {
+            MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_spmm_csr<MAR_T, BB, true>), dim3(wgs), dim3(WG), 0, s, A.n,
+                                                 A.ptr, A.idx, val, X, Y, part));
+        } else {
+            MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_spmm_csr<MAR_T, BB, false>), dim3(wgs), dim3(WG), 0, s, A.n,
+                                                 A.ptr, A.idx, val, X, Y, part));
+        }
+    }
+    const int64_t rows = A.bsr ? 4 * A.n : A.n;
+    LaunchInfo li;
+    li.wgs = wgs;
+    li.bytes = A.bytes_per_pass(sizeof(MAR_T)) + 2.0 * (double)rows * B * sizeof(MAR_T);
+    li.flops = 2.0 * (double)A.nnz * (A.bsr ? 16.0 : 1.0) * B;
+    return li;
+}
+
+template <>
+LaunchInfo launch_proj<MAR_T>(int B, int ns, const MAR_T* b0, const MAR_T* b1, int64_t M, int nk, const MAR_T* x,
+                              double* part, int64_t* nchunks, hipStream_t s) {
+    constexpr int VEC = Vec16<MAR_T>::n;
+    const int64_t nvec = M * B / VEC;
+    const int64_t chunks = (nvec + WG * PROJ_Q - 1) / (WG * PROJ_Q);
+    // split the slabs over more workgroups when the chunks alone cannot fill the GPU
+    const int64_t want = 2048;
+    int64_t nks = std::max<int64_t>(1, (want + chunks - 1) / chunks);
+    nks = std::min<int64_t>(nks, (nk + PROJ_KG - 1) / PROJ_KG);
+    int kps = (int)((nk + nks - 1) / nks);
+    kps = ((kps + PROJ_KG - 1) / PROJ_KG) * PROJ_KG;
+    nks = (nk + kps - 1) / kps;
+    const int64_t slab = M * B;
+    dim3 grid((unsigned)chunks, (unsigned)nks);
+    if (ns == 2) {
+        MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_proj<MAR_T, BB, 2, PROJ_Q, PROJ_KG>), grid, dim3(WG), 0, s, b0, b1,
+                                             slab, nk, kps, x, nvec, part));
+    } else {
+        MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_proj<MAR_T, BB, 1, PROJ_Q, PROJ_KG>), grid, dim3(WG), 0, s, b0, b1,
+                                             slab, nk, kps, x, nvec, part));
+    }
+    *nchunks = chunks;
+    LaunchInfo li;
+    li.wgs = chunks * nks;
+    li.bytes = ((double)ns * nk + 1.0) * (double)slab * sizeof(MAR_T);
+    li.flops = 2.0 * ns * nk * (double)slab;
+    return li;
+}
+
+template <>
+LaunchInfo launch_upd<MAR_T>(int B, const MAR_T* basis, int64_t M, int nk, const double* c, MAR_T* x,
+                             hipStream_t s) {
+    constexpr int VEC = Vec16<MAR_T>::n;
+    const int64_t nvec = M * B / VEC;
+    const int64_t slab = M * B;
+    const bool big = nvec >= (int64_t)WG * 4 * 1024;
+    LaunchInfo li;
+    if (big) {
+        const int64_t wgs = (nvec + WG * 4 - 1) / (WG * 4);
+        MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_upd<MAR_T, BB, 4>), dim3(wgs), dim3(WG), 0, s, basis, slab, nk, c,
+                                             x, nvec));
+        li.wgs = wgs;
+    } else {
+        const int64_t wgs = (nvec + WG - 1) / WG;
+        MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_upd<MAR_T, BB, 1>), dim3(wgs), dim3(WG), 0, s, basis, slab, nk, c,
+                                             x, nvec));
+        li.wgs = wgs;
+    }
+    li.bytes = ((double)nk + 2.0) * (double)slab * sizeof(MAR_T);
+    li.flops = 2.0 * nk * (double)slab;
+    return li;
+}
+
+template <>
+LaunchInfo launch_append<MAR_T>(int B, int64_t M, const MAR_T* W, const MAR_T* Z, const double* beta,
+                                const int32_t* active, MAR_T* Kn, MAR_T* SKn, hipStream_t s) {
+    constexpr int VEC = Vec16<MAR_T>::n;
+    const int64_t nvec = M * B / VEC;
+    const int64_t wgs = (nvec + WG - 1) / WG;
+    MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_append<MAR_T, BB>), dim3(wgs), dim3(WG), 0, s, W, Z, beta, active, Kn,
+                                         SKn, nvec));
+    LaunchInfo li;
+    li.wgs = wgs;
+    li.bytes = 4.0 * (double)M * B * sizeof(MAR_T);
+    return li;
+}
+
+}  // namespace mar

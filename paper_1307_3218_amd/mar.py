@@ -1,0 +1,244 @@
+"""Python binding of libmar.so (the C ABI declared in include/mar.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP
+library. The module-level functions carry the C names (mar_create,
+mar_solve, ...); ``Context`` is a small object wrapper around them. Device
+buffers for the asynchronous entry point are torch tensors (plumbing only).
+If libmar.so is missing this module raises on first use; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+
+import numpy as np
+import scipy.sparse as sp
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmar.so")
+
+MAR_OK, MAR_ERR_ARG, MAR_ERR_PATTERN, MAR_ERR_NOT_SPD, MAR_ERR_NOMEM, MAR_ERR_HIP, MAR_ERR_STATE = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "MAR_OK", -1: "MAR_ERR_ARG", -2: "MAR_ERR_PATTERN", -3: "MAR_ERR_NOT_SPD",
+                -4: "MAR_ERR_NOMEM", -5: "MAR_ERR_HIP", -6: "MAR_ERR_STATE"}
+PRECISION = {"fp64": 0, "fp32": 1}
+FORM = {"batched": 0, "plain": 1}
+PROF_CLASSES = 10
+
+
+class MarError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+class mar_tuning(C.Structure):
+    _fields_ = [("seed_block", C.c_int32), ("proj_rows", C.c_int32), ("upd_rows", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class mar_prof_entry(C.Structure):
+    _fields_ = [("name", C.c_char * 24), ("launches", C.c_int64), ("ms", C.c_double),
+                ("bytes", C.c_double), ("flops", C.c_double)]
+
+
+_lib = None
+_P = C.c_void_p
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_1307_3218_amd.build_lib`")
+    L = C.CDLL(LIB_PATH)
+    i32, i64, f64 = C.c_int32, C.c_int64, C.c_double
+    L.mar_create.argtypes = [i64, _P, _P, _P, _P, _P, _P, C.POINTER(_P)]
+    L.mar_create.restype = C.c_int
+    L.mar_destroy.argtypes = [_P]
+    L.mar_destroy.restype = None
+    L.mar_solve.argtypes = [_P, _P, i64, i32, f64, f64, C.c_int, C.c_int, _P, _P, _P, _P, _P, _P, _P]
+    L.mar_solve.restype = C.c_int
+    L.mar_solve_async.argtypes = [_P, _P, i64, i32, f64, f64, C.c_int, C.c_int, _P, _P, _P, _P, _P, _P, _P, _P]
+    L.mar_solve_async.restype = C.c_int
+    L.mar_set_tuning.argtypes = [_P, C.POINTER(mar_tuning)]
+    L.mar_set_tuning.restype = C.c_int
+    L.mar_get_tuning.argtypes = [_P, C.POINTER(mar_tuning)]
+    L.mar_get_tuning.restype = C.c_int
+    L.mar_seed_block.argtypes = [_P, i32, C.c_int]
+    L.mar_seed_block.restype = i32
+    L.mar_last_error.argtypes = [_P]
+    L.mar_last_error.restype = C.c_char_p
+    L.mar_profile_enable.argtypes = [_P, i32]
+    L.mar_profile_enable.restype = C.c_int
+    L.mar_profile_reset.argtypes = [_P]
+    L.mar_profile_reset.restype = C.c_int
+    L.mar_profile_collect.argtypes = [_P, C.POINTER(mar_prof_entry), C.POINTER(i32)]
+    L.mar_profile_collect.restype = C.c_int
+    L.mar_ctx_info.argtypes = [_P, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
+    L.mar_ctx_info.restype = i32
+    _lib = L
+    return L
+
+
+def _ptr(a) -> int | None:
+    return None if a is None else a.ctypes.data
+
+
+def _check(ctx, st: int):
+    if st != MAR_OK:
+        raise MarError(st, mar_last_error(ctx))
+
+
+# ---------------------------------------------------------------- C-named API
+def mar_last_error(ctx=None) -> str:
+    return (lib().mar_last_error(ctx) or b"").decode()
+
+
+def _csr(A) -> tuple:
+    A = sp.csr_matrix(A, dtype=np.float64)
+    A.sort_indices()
+    return (np.ascontiguousarray(A.indptr, dtype=np.int64), np.ascontiguousarray(A.indices, dtype=np.int32),
+            np.ascontiguousarray(A.data, dtype=np.float64), A)
+
+
+def mar_create(H, S):
+    """Create a context from scipy CSR H and S (copied to the device). Returns the handle."""
+    hp, hc, hv, H = _csr(H)
+    spp, sc, sv, S = _csr(S)
+    if H.shape != S.shape or H.shape[0] != H.shape[1]:
+        raise MarError(MAR_ERR_ARG, "H and S must be square and of one size")
+    out = _P()
+    st = lib().mar_create(H.shape[0], _ptr(hp), _ptr(hc), _ptr(hv), _ptr(spp), _ptr(sc), _ptr(sv), C.byref(out))
+    _check(None, st)
+    return out
+
+
+def mar_destroy(ctx) -> None:
+    lib().mar_destroy(ctx)
+
+
+def mar_solve(ctx, seeds, nu, mu, kT, prec, form, rho, e_band, e_seed=None, n_seed=None, nu_eff=None,
+              eps=None, weight=None) -> int:
+    """Blocking solve on host numpy arrays (rho is updated in place)."""
+    return lib().mar_solve(ctx, _ptr(seeds), len(seeds), int(nu), float(mu), float(kT), int(prec), int(form),
+                           _ptr(rho), _ptr(e_band), _ptr(e_seed), _ptr(n_seed), _ptr(nu_eff), _ptr(eps), _ptr(weight))
+
+
+def _tptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def mar_solve_async(ctx, d_seeds, n_seeds, nu, mu, kT, prec, form, d_rho, d_e_band, d_e_seed=None, d_n_seed=None,
+                    d_nu_eff=None, d_eps=None, d_weight=None, stream=None) -> int:
+    """Enqueue a solve on device tensors (torch) on ``stream`` (a hipStream_t handle as int)."""
+    return lib().mar_solve_async(ctx, _tptr(d_seeds), int(n_seeds), int(nu), float(mu), float(kT), int(prec),
+                                 int(form), _tptr(d_rho), _tptr(d_e_band), _tptr(d_e_seed), _tptr(d_n_seed),
+                                 _tptr(d_nu_eff), _tptr(d_eps), _tptr(d_weight), stream)
+
+
+def mar_set_tuning(ctx, seed_block: int = 0) -> int:
+    t = mar_tuning(seed_block, 0, 0, 0)
+    return lib().mar_set_tuning(ctx, C.byref(t))
+
+
+def mar_seed_block(ctx, nu: int, prec: int) -> int:
+    return lib().mar_seed_block(ctx, int(nu), int(prec))
+
+
+def mar_profile_enable(ctx, on: bool) -> int:
+    return lib().mar_profile_enable(ctx, 1 if on else 0)
+
+
+def mar_profile_reset(ctx) -> int:
+    return lib().mar_profile_reset(ctx)
+
+
+def mar_profile_collect(ctx) -> dict:
+    arr = (mar_prof_entry * PROF_CLASSES)()
+    n = C.c_int32(0)
+    _check(ctx, lib().mar_profile_collect(ctx, arr, C.byref(n)))
+    return {arr[k].name.decode(): dict(launches=arr[k].launches, ms=arr[k].ms, bytes=arr[k].bytes,
+                                       flops=arr[k].flops) for k in range(n.value)}
+
+
+def mar_ctx_info(ctx) -> dict:
+    M, nh, ns = C.c_int64(), C.c_int64(), C.c_int64()
+    flags = lib().mar_ctx_info(ctx, C.byref(M), C.byref(nh), C.byref(ns))
+    return dict(M=M.value, nnz_H=nh.value, nnz_S=ns.value, H_bsr=bool(flags & 1), S_bsr=bool(flags & 2))
+
+
+# ---------------------------------------------------------------- object wrapper
+@dataclasses.dataclass
+class SolveOutput:
+    rho: np.ndarray
+    e_band: float
+    e_seed: np.ndarray
+    n_seed: np.ndarray
+    nu_eff: np.ndarray
+    eps: np.ndarray | None       # (n_seeds, nu); entries >= nu_eff are 0
+    weight: np.ndarray | None
+
+
+class Context:
+    """One (H, S) pair resident on the GPU."""
+
+    def __init__(self, H, S):
+        self.H = sp.csr_matrix(H)
+        self.H.sort_indices()
+        self.M = self.H.shape[0]
+        self.handle = mar_create(self.H, S)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            mar_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, seeds, nu, mu, kT, precision="fp64", form="batched", rho=None, levels=False) -> SolveOutput:
+        seeds = np.ascontiguousarray(seeds, dtype=np.int32)
+        n = len(seeds)
+        rho = np.zeros(self.H.nnz) if rho is None else np.ascontiguousarray(rho, dtype=np.float64)
+        e_band = np.zeros(1)
+        e_seed, n_seed = np.zeros(n), np.zeros(n)
+        nu_eff = np.zeros(n, dtype=np.int32)
+        eps = np.zeros((n, nu)) if levels else None
+        weight = np.zeros((n, nu)) if levels else None
+        st = mar_solve(self.handle, seeds, nu, mu, kT, PRECISION[precision], FORM[form], rho, e_band, e_seed,
+                       n_seed, nu_eff, eps, weight)
+        _check(self.handle, st)
+        return SolveOutput(rho, float(e_band[0]), e_seed, n_seed, nu_eff, eps, weight)
+
+    def solve_async(self, d_seeds, nu, mu, kT, precision="fp64", form="batched", *, d_rho, d_e_band,
+                    d_e_seed=None, d_n_seed=None, d_nu_eff=None, d_eps=None, d_weight=None, stream=None):
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        st = mar_solve_async(self.handle, d_seeds, d_seeds.numel(), nu, mu, kT, PRECISION[precision], FORM[form],
+                             d_rho, d_e_band, d_e_seed, d_n_seed, d_nu_eff, d_eps, d_weight, stream)
+        _check(self.handle, st)
+
+    def set_tuning(self, seed_block: int = 0):
+        _check(self.handle, mar_set_tuning(self.handle, seed_block))
+
+    def seed_block(self, nu: int, precision: str = "fp32") -> int:
+        return mar_seed_block(self.handle, nu, PRECISION[precision])
+
+    def profile(self, on: bool = True):
+        _check(self.handle, mar_profile_enable(self.handle, on))
+
+    def profile_reset(self):
+        _check(self.handle, mar_profile_reset(self.handle))
+
+    def profile_collect(self) -> dict:
+        return mar_profile_collect(self.handle)
+
+    def info(self) -> dict:
+        return mar_ctx_info(self.handle)

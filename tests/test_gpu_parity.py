@@ -1,0 +1,319 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Bars (relative errors as defined for this study): FP64 form <= 1e-10 and FP32
+form <= 1e-5 on E_band and on the Frobenius norm of rho over the computed
+slots; nu_eff equal; sorted subspace levels equal within the same bar.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import mar_oracle as O
+from paper_1307_3218_amd import lattice, mar
+
+pytestmark = pytest.mark.gpu
+
+KT = 0.1
+TOL = {"fp64": 1e-10, "fp32": 1e-5}
+
+
+def _workers(n):
+    return max(1, min(16, O.default_workers(), n))
+
+
+def _slots(H, seeds):
+    return np.concatenate([np.arange(H.indptr[j], H.indptr[j + 1]) for j in seeds]) if len(seeds) else np.zeros(0, int)
+
+
+def compare(H, seeds, gpu, ref, prec, check_levels=True, label=""):
+    """Element-by-element comparison on the listed seeds' rows; returns the error record."""
+    tol = TOL[prec]
+    idx = _slots(H, seeds)
+    d = gpu.rho[idx] - ref.rho[idx]
+    rho_rel = np.linalg.norm(d) / np.linalg.norm(ref.rho[idx])
+    e_rel = abs(gpu.e_band - ref.e_band) / abs(ref.e_band)
+    col_rel = []
+    for s, j in enumerate(seeds):
+        sl = slice(H.indptr[j], H.indptr[j + 1])
+        col_rel.append(np.linalg.norm(gpu.rho[sl] - ref.rho[sl]) / max(np.linalg.norm(ref.rho[sl]), 1e-300))
+    rec = dict(rho_rel=rho_rel, e_rel=e_rel, col_rel_max=max(col_rel), label=label)
+    print(f"[parity {label} {prec}] rho {rho_rel:.2e} E_band {e_rel:.2e} worst column {max(col_rel):.2e}", flush=True)
+    assert np.array_equal(gpu.nu_eff, ref.nu_eff)
+    assert rho_rel <= tol, rec
+    assert e_rel <= tol, rec
+    assert max(col_rel) <= 100 * tol, rec
+    e_seed_err = np.abs(gpu.e_seed - ref.e_seed) / np.maximum(np.abs(ref.e_seed), 1e-3)
+    assert e_seed_err.max() <= 100 * tol
+    assert np.abs(gpu.n_seed - ref.n_seed).max() <= 100 * tol
+    if check_levels and gpu.eps is not None:
+        scale = max(np.abs(e).max() for e in ref.eps)
+        for s in range(len(seeds)):
+            m = gpu.nu_eff[s]
+            ge = np.sort(gpu.eps[s, :m])
+            assert np.abs(ge - ref.eps[s]).max() <= 10 * tol * scale
+    return rec
+
+
+def check_identities(gpu, mu, kT, prec):
+    """P6 on the GPU outputs: sum w = 1, N_j = 2 sum f w, E_j = 2 sum f eps w."""
+    tol = 100 * TOL[prec]
+    for s in range(len(gpu.nu_eff)):
+        m = gpu.nu_eff[s]
+        e, w = gpu.eps[s, :m], gpu.weight[s, :m]
+        f = O.fermi(e, mu, kT)
+        assert abs(w.sum() - 1.0) <= tol
+        assert abs(gpu.n_seed[s] - 2.0 * np.sum(f * w)) <= tol
+        assert abs(gpu.e_seed[s] - 2.0 * np.sum(f * e * w)) <= tol * max(1.0, abs(gpu.e_seed[s]))
+
+
+# ------------------------------------------------------------------ fixtures
+@pytest.fixture(scope="module")
+def c1_ctx(c1):
+    ctx = mar.Context(c1.H, c1.S)
+    info = ctx.info()
+    assert info["H_bsr"] and info["S_bsr"]
+    yield ctx
+    ctx.close()
+
+
+@pytest.fixture(scope="module")
+def c1_mu(c1):
+    r = O.solve(c1.H, c1.S, np.arange(c1.M), 30, 0.0, KT)
+    return O.fermi_level(r.eps, r.weight, c1.M, KT)
+
+
+@pytest.fixture(scope="module")
+def c1_ref30(c1, c1_mu):
+    return O.solve(c1.H, c1.S, np.arange(c1.M), 30, c1_mu, KT, workers=_workers(8))
+
+
+# ------------------------------------------------------------------ M = 256
+@pytest.mark.parametrize("prec,form", [("fp64", "batched"), ("fp64", "plain"), ("fp32", "batched"),
+                                       ("fp32", "plain")])
+def test_c1_all_seeds_nu30(c1, c1_ctx, c1_mu, c1_ref30, prec, form):
+    seeds = np.arange(c1.M, dtype=np.int32)
+    g = c1_ctx.solve(seeds, 30, c1_mu, KT, precision=prec, form=form, levels=True)
+    compare(c1.H, seeds, g, c1_ref30, prec, label=f"M=256 nu=30 {form}")
+    check_identities(g, c1_mu, KT, prec)
+    # electron-count sum rule at the bisected level
+    assert abs(g.n_seed.sum() - c1.M) <= 1e3 * TOL[prec] * c1.M
+
+
+@pytest.mark.parametrize("prec,B", [("fp64", b) for b in (1, 2, 4, 8, 16, 32, 64, 128)] +
+                         [("fp32", b) for b in (1, 2, 4, 8, 16, 32, 64, 128, 256)])
+def test_c1_every_block_size_ragged(c1, c1_ctx, c1_mu, prec, B):
+    seeds = lattice.sample_seeds(c1.M, 37, seed=B).astype(np.int32)    # 37: ragged last block
+    ref = O.solve(c1.H, c1.S, seeds, 24, c1_mu, KT)
+    c1_ctx.set_tuning(seed_block=B)
+    try:
+        g = c1_ctx.solve(seeds, 24, c1_mu, KT, precision=prec, form="batched", levels=True)
+    finally:
+        c1_ctx.set_tuning(0)
+    compare(c1.H, seeds, g, ref, prec, label=f"M=256 B={B}")
+
+
+def test_c1_nu_equals_M_exact(c1, c1_ctx):
+    """nu = M: the subspace result equals the dense generalized eigensolve (global-memory eigensolver path)."""
+    mu = -0.448
+    seeds = np.arange(c1.M, dtype=np.int32)
+    g = c1_ctx.solve(seeds, c1.M, mu, KT, precision="fp64", levels=True)
+    ref = O.solve(c1.H, c1.S, seeds, c1.M, mu, KT, workers=_workers(8))
+    compare(c1.H, seeds, g, ref, "fp64", label="M=256 nu=M")
+    rho_d, E_d, _ = O.dense(c1.H, c1.S, mu, KT)
+    rows = np.repeat(np.arange(c1.M), np.diff(c1.H.indptr))
+    exact = rho_d[c1.H.indices, rows]
+    assert np.linalg.norm(g.rho - exact) / np.linalg.norm(exact) < 1e-10
+    assert abs(g.e_band - E_d) / abs(E_d) < 1e-10
+
+
+def test_c1_determinism(c1, c1_ctx, c1_mu):
+    seeds = np.arange(0, c1.M, 3, dtype=np.int32)
+    a = c1_ctx.solve(seeds, 30, c1_mu, KT, precision="fp64")
+    b = c1_ctx.solve(seeds, 30, c1_mu, KT, precision="fp64")
+    assert np.array_equal(a.rho, b.rho) and a.e_band == b.e_band
+
+
+def test_small_nu_closed_forms(c1, c1_ctx):
+    seeds = np.array([0, 5, 130, 255], dtype=np.int32)
+    for nu in (1, 2, 3):
+        ref = O.solve(c1.H, c1.S, seeds, nu, -0.3, KT)
+        g = c1_ctx.solve(seeds, nu, -0.3, KT, precision="fp64", levels=True)
+        compare(c1.H, seeds, g, ref, "fp64", label=f"nu={nu}")
+    g = c1_ctx.solve(seeds, 1, -0.3, KT, precision="fp64")
+    Hd, Sd = c1.H.toarray(), c1.S.toarray()
+    for j in seeds:
+        f = 1.0 / (1.0 + math.exp((Hd[j, j] / Sd[j, j] + 0.3) / KT))
+        lo = c1.H.indptr[j]
+        t = list(c1.H.indices[lo:c1.H.indptr[j + 1]]).index(j)
+        assert math.isclose(g.rho[lo + t], 2 * f / Sd[j, j], rel_tol=1e-13)
+
+
+def test_full_occupation_and_zero_temperature(c1, c1_ctx):
+    seeds = np.arange(0, c1.M, 7, dtype=np.int32)
+    for prec in ("fp64", "fp32"):
+        g = c1_ctx.solve(seeds, 20, 1e3, 0.0, precision=prec)
+        assert np.allclose(g.n_seed, 2.0, atol=100 * TOL[prec])
+        g = c1_ctx.solve(seeds, 20, -1e3, 0.0, precision=prec)
+        assert np.all(g.rho == 0.0) and g.e_band == 0.0
+
+
+def test_rows_of_unlisted_seeds_untouched(c1, c1_ctx):
+    seeds = np.array([3, 9], dtype=np.int32)
+    rho0 = np.full(c1.H.nnz, 7.25)
+    g = c1_ctx.solve(seeds, 10, 0.0, KT, precision="fp64", rho=rho0)
+    mask = np.ones(c1.H.nnz, bool)
+    mask[_slots(c1.H, seeds)] = False
+    assert np.all(g.rho[mask] == 7.25)
+    assert np.all(g.rho[~mask] != 7.25)
+
+
+def test_empty_seed_list(c1, c1_ctx):
+    g = c1_ctx.solve(np.zeros(0, np.int32), 10, 0.0, KT, precision="fp32", rho=np.full(c1.H.nnz, 1.5))
+    assert g.e_band == 0.0 and np.all(g.rho == 1.5)
+
+
+def test_argument_errors(c1, c1_ctx):
+    with pytest.raises(mar.MarError) as e:
+        c1_ctx.solve(np.array([1, 1], np.int32), 5, 0.0, KT)
+    assert e.value.status == mar.MAR_ERR_ARG
+    with pytest.raises(mar.MarError):
+        c1_ctx.solve(np.array([c1.M], np.int32), 5, 0.0, KT)
+    with pytest.raises(mar.MarError):
+        c1_ctx.solve(np.array([0], np.int32), c1.M + 1, 0.0, KT)
+    with pytest.raises(mar.MarError):
+        c1_ctx.solve(np.array([0], np.int32), 5, 0.0, -1.0)
+    with pytest.raises(mar.MarError):
+        c1_ctx.solve(np.array([0], np.int32), 5, float("nan"), KT)
+
+
+def test_async_device_buffers_and_invalid_seed(c1, c1_ctx, c1_mu, c1_ref30):
+    import torch
+    dev = torch.device("cuda:0")
+    seeds = np.array([0, 17, c1.M + 5, 200], dtype=np.int32)          # one seed out of range
+    d_seeds = torch.from_numpy(seeds).to(dev)
+    d_rho = torch.zeros(c1.H.nnz, dtype=torch.float64, device=dev)
+    d_eb = torch.zeros(1, dtype=torch.float64, device=dev)
+    d_nu = torch.zeros(4, dtype=torch.int32, device=dev)
+    d_e = torch.zeros(4, dtype=torch.float64, device=dev)
+    c1_ctx.solve_async(d_seeds, 30, c1_mu, KT, "fp64", d_rho=d_rho, d_e_band=d_eb, d_nu_eff=d_nu, d_e_seed=d_e)
+    torch.cuda.synchronize()
+    nu = d_nu.cpu().numpy()
+    assert list(nu) == [30, 30, -2, 30]
+    e = d_e.cpu().numpy()
+    ref = {j: c1_ref30.e_seed[j] for j in (0, 17, 200)}
+    for s, j in ((0, 0), (1, 17), (3, 200)):
+        assert abs(e[s] - ref[j]) <= 1e-10 * abs(ref[j])
+    assert e[2] == 0.0
+
+
+# ------------------------------------------------------------------ other patterns
+def test_breakdown_truncates(c1):
+    blocks = [np.array([[1.0, 0.3, 0.0, 0.2], [0.3, -1.0, 0.5, 0.0],
+                        [0.0, 0.5, 0.5, 0.1], [0.2, 0.0, 0.1, 2.0]]) * (k + 1) for k in range(3)]
+    H = sp.block_diag(blocks, format="csr")
+    ctx = mar.Context(H, sp.identity(12, format="csr"))
+    seeds = np.array([1, 5, 11], dtype=np.int32)
+    for prec in ("fp64", "fp32"):
+        g = ctx.solve(seeds, 8, 0.0, KT, precision=prec, levels=True)
+        assert list(g.nu_eff) == [4, 4, 4]
+        ref = O.solve(H, sp.identity(12, format="csr"), seeds, 8, 0.0, KT)
+        compare(H, seeds, g, ref, prec, label="breakdown")
+    ctx.close()
+
+
+def test_indefinite_overlap_reports_not_spd():
+    H = sp.csr_matrix(np.array([[0.0, 1.0, 0.0], [1.0, 0.0, 1.0], [0.0, 1.0, 0.0]]))
+    S = sp.csr_matrix(np.array([[1.0, 0.0, 0.0], [0.0, 0.2, 0.9], [0.0, 0.9, 1.0]]))
+    ctx = mar.Context(H, S)
+    with pytest.raises(mar.MarError) as e:
+        ctx.solve(np.array([0], np.int32), 3, 0.0, KT, precision="fp64")
+    assert e.value.status == mar.MAR_ERR_NOT_SPD
+    ctx.close()
+
+
+def test_general_csr_pattern():
+    """A pattern without 4x4 blocks and M not a multiple of 4 takes the CSR kernels."""
+    rng = np.random.default_rng(3)
+    M = 203
+    A = sp.random(M, M, density=0.02, random_state=4, data_rvs=lambda n: rng.normal(size=n))
+    H = (A + A.T + sp.diags(rng.normal(size=M))).tocsr()
+    H.sort_indices()
+    Sn = (0.05 * (A + A.T)).tocsr()
+    S = (Sn + sp.identity(M)).tocsr()
+    S.sort_indices()
+    assert np.linalg.eigvalsh(S.toarray())[0] > 0.1
+    ctx = mar.Context(H, S)
+    assert not ctx.info()["H_bsr"]
+    seeds = lattice.sample_seeds(M, 41, seed=1).astype(np.int32)
+    for prec in ("fp64", "fp32"):
+        for B in (1, 8, 64):
+            ctx.set_tuning(B)
+            g = ctx.solve(seeds, 25, 0.1, KT, precision=prec, levels=True)
+            ref = O.solve(H, S, seeds, 25, 0.1, KT)
+            compare(H, seeds, g, ref, prec, label=f"csr B={B}")
+    ctx.close()
+
+
+def test_mixed_lattice_small():
+    s = lattice.generate(2, 2, 2, mixed=True)
+    ctx = mar.Context(s.H, s.S)
+    seeds = np.arange(s.M, dtype=np.int32)
+    ref = O.solve(s.H, s.S, seeds, 30, 0.0, KT, workers=_workers(8))
+    for prec in ("fp64", "fp32"):
+        g = ctx.solve(seeds, 30, 0.0, KT, precision=prec, levels=True)
+        compare(s.H, seeds, g, ref, prec, label="mixed M=256")
+    ctx.close()
+
+
+# ------------------------------------------------------------------ M = 16384
+@pytest.fixture(scope="module")
+def c2():
+    return lattice.workload("diamond_8x8x8")
+
+
+@pytest.fixture(scope="module")
+def c2_ctx(c2):
+    ctx = mar.Context(c2.H, c2.S)
+    yield ctx
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_c2_all_seeds_sampled_oracle(c2, c2_ctx, prec):
+    """All 16384 seeds on the GPU at nu = 30; the oracle checks a 300-seed sample element by element."""
+    seeds = np.arange(c2.M, dtype=np.int32)
+    mu = 0.0
+    g = c2_ctx.solve(seeds, 30, mu, KT, precision=prec, levels=True)
+    assert np.all(g.nu_eff == 30)
+    check_identities(g, mu, KT, prec)
+    sample = lattice.sample_seeds(c2.M, 300, seed=7)
+    ref = O.solve(c2.H, c2.S, sample, 30, mu, KT, workers=_workers(16))
+    sub = mar.SolveOutput(rho=g.rho, e_band=float(np.sum(g.e_seed[sample])), e_seed=g.e_seed[sample],
+                          n_seed=g.n_seed[sample], nu_eff=g.nu_eff[sample], eps=g.eps[sample], weight=None)
+    compare(c2.H, sample, sub, ref, prec, label="M=16384 nu=30")
+
+
+# ------------------------------------------------------------------ M = 131072 (bench shape)
+@pytest.fixture(scope="module")
+def c4():
+    return lattice.workload("mixed_16x16x16")
+
+
+def test_c4_bench_block_sampled_oracle(c4):
+    """The bench's launch configuration (FP32 batched, nu = 100) on one seed block; oracle on 4 of its seeds."""
+    ctx = mar.Context(c4.H, c4.S)
+    B = ctx.seed_block(100, "fp32")
+    seeds = lattice.sample_seeds(c4.M, B, seed=11)
+    mu = 0.0
+    g32 = ctx.solve(seeds, 100, mu, KT, precision="fp32", levels=True)
+    check_identities(g32, mu, KT, "fp32")
+    pick = np.array([0, B // 3, (2 * B) // 3, B - 1])
+    ref = O.solve(c4.H, c4.S, seeds[pick], 100, mu, KT, workers=_workers(4))
+    sub = mar.SolveOutput(rho=g32.rho, e_band=float(np.sum(g32.e_seed[pick])), e_seed=g32.e_seed[pick],
+                          n_seed=g32.n_seed[pick], nu_eff=g32.nu_eff[pick], eps=g32.eps[pick], weight=None)
+    compare(c4.H, seeds[pick], sub, ref, "fp32", label="M=131072 nu=100 fp32")
+    g64 = ctx.solve(seeds[pick], 100, mu, KT, precision="fp64", form="plain", levels=True)
+    compare(c4.H, seeds[pick], g64, ref, "fp64", label="M=131072 nu=100 fp64 plain")
+    ctx.close()
