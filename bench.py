@@ -62,6 +62,8 @@ def main() -> int:
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--seed-block", type=int, default=0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
+                    help="first run a plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -80,6 +82,14 @@ def main() -> int:
     import torch
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        c = torch.empty_like(a)
+        c.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {args.copy_calibration} MiB read + {args.copy_calibration} MiB written")
+        del a, c
     ctx = mar.Context(system.H, system.S)
     if args.seed_block:
         ctx.set_tuning(args.seed_block)

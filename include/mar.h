@@ -138,7 +138,7 @@ const char* mar_last_error(const mar_ctx* ctx);
  * and accumulates, per kernel class, the launch count, the summed event time
  * and the algorithmic bytes and flops (bytes: every operand read once and
  * every result written once, as the method requires). */
-enum { MAR_PROF_CLASSES = 10 };
+enum { MAR_PROF_CLASSES = 16 };
 typedef struct {
     char name[24];
     int64_t launches;

@@ -18,8 +18,12 @@ using mar::LaunchInfo;
 
 namespace {
 
-enum ProfClass { P_INIT = 0, P_SPMM, P_PROJ, P_UPD, P_REDUCE, P_NORM, P_APPEND, P_EIG, P_SUM, P_COUNT };
-const char* kProfNames[P_COUNT] = {"init", "spmm", "cgs_proj", "cgs_upd", "reduce", "norm", "append", "eig", "sum"};
+// One class per kernel variant, so that a class maps to one kernel symbol in a trace.
+enum ProfClass {
+    P_INIT = 0, P_SPMM, P_SPMM_DOT, P_PROJ2, P_PROJ1, P_UPD, P_REDUCE, P_NORM, P_APPEND, P_EIG, P_SUM, P_COUNT
+};
+const char* kProfNames[P_COUNT] = {"init",   "spmm",   "spmm_dot", "cgs_proj_KSK", "cgs_proj_1", "cgs_upd",
+                                   "reduce", "norm",   "append",   "eig",          "sum"};
 
 struct ProfRec {
     int cls;
@@ -342,7 +346,7 @@ mar_status run_solve(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds, int nu
             launch(c, s, P_SPMM, [&] { return mar::launch_spmm<T>(B, c->H, Kn, ws.W, nullptr, s); });
             // h[:, n] = K^T w and c1 = (S K)^T w in one pass over K and S K
             int64_t nch = 0;
-            launch(c, s, P_PROJ, [&] {
+            launch(c, s, last ? P_PROJ1 : P_PROJ2, [&] {
                 return mar::launch_proj<T>(B, last ? 1 : 2, ws.K, ws.SK, M, nk, ws.W, ws.part, &nch, s);
             });
             const int64_t L1 = (int64_t)(last ? 1 : 2) * nk * B;
@@ -352,7 +356,7 @@ mar_status run_solve(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds, int nu
             // CGS pass 1: w -= K c1
             launch(c, s, P_UPD, [&] { return mar::launch_upd<T>(B, ws.K, M, nk, c1, ws.W, s); });
             // CGS pass 2: c2 = (S K)^T w, w -= K c2
-            launch(c, s, P_PROJ, [&] {
+            launch(c, s, P_PROJ1, [&] {
                 return mar::launch_proj<T>(B, 1, ws.SK, nullptr, M, nk, ws.W, ws.part, &nch, s);
             });
             const int64_t L2 = (int64_t)nk * B;
@@ -360,7 +364,7 @@ mar_status run_solve(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds, int nu
             launch(c, s, P_UPD, [&] { return mar::launch_upd<T>(B, ws.K, M, nk, ws.red2, ws.W, s); });
             // z = S w and w^T S w
             int64_t swgs = 0;
-            launch(c, s, P_SPMM, [&] {
+            launch(c, s, P_SPMM_DOT, [&] {
                 LaunchInfo li = mar::launch_spmm<T>(B, c->S, ws.W, ws.Z, ws.part, s);
                 swgs = li.wgs;
                 return li;

@@ -67,19 +67,26 @@ __global__ __launch_bounds__(WG) void k_norm(int B, int nk, const double* __rest
                                              const double* __restrict__ c1, const double* __restrict__ c2,
                                              double tau, int32_t* __restrict__ active, int32_t* __restrict__ nu_eff,
                                              double* __restrict__ beta, int n) {
-    const int b = blockIdx.x * WG + threadIdx.x;
-    if (b >= B) return;
+    // thread (part, b): partial sums of |c1|^2 + |c2|^2 over k = part, part + np, ...
+    __shared__ double lds[WG];
+    const int np = WG / B;
+    const int b = threadIdx.x % B, part = threadIdx.x / B;
+    double s = 0.0;
+    if (part < np)
+        for (int k = part; k < nk; k += np) {
+            const double a1 = c1[(int64_t)k * B + b], a2 = c2[(int64_t)k * B + b];
+            s += a1 * a1 + a2 * a2;
+        }
+    lds[threadIdx.x] = s;
+    __syncthreads();
+    if ((int)threadIdx.x >= B) return;
+    double cc = 0.0;
+    for (int q = 0; q < np; ++q) cc += lds[q * B + b];
     if (!active[b]) {
         beta[b] = 0.0;
         return;
     }
     const double bb = beta2[b];
-    double s1 = 0.0, s2 = 0.0;
-    for (int k = 0; k < nk; ++k) {
-        const double a1 = c1[(int64_t)k * B + b], a2 = c2[(int64_t)k * B + b];
-        s1 += a1 * a1;
-        s2 += a2 * a2;
-    }
     if (!(bb >= 0.0) || !(bb < INFINITY)) {
         nu_eff[b] = -1;
         active[b] = 0;
@@ -87,7 +94,7 @@ __global__ __launch_bounds__(WG) void k_norm(int B, int nk, const double* __rest
         return;
     }
     const double bt = sqrt(bb);
-    const double eta = sqrt(s1 + s2 + bb);
+    const double eta = sqrt(cc + bb);
     if (bt <= tau * eta) {
         nu_eff[b] = n + 1;
         active[b] = 0;
@@ -99,10 +106,9 @@ __global__ __launch_bounds__(WG) void k_norm(int B, int nk, const double* __rest
 
 LaunchInfo launch_norm(int B, int nk, const double* beta2, const double* c1, const double* c2, double tau,
                        int32_t* active, int32_t* nu_eff, double* beta, int n, hipStream_t s) {
-    const int wgs = (B + WG - 1) / WG;
-    hipLaunchKernelGGL(k_norm, dim3(wgs), dim3(WG), 0, s, B, nk, beta2, c1, c2, tau, active, nu_eff, beta, n);
+    hipLaunchKernelGGL(k_norm, dim3(1), dim3(WG), 0, s, B, nk, beta2, c1, c2, tau, active, nu_eff, beta, n);
     LaunchInfo li;
-    li.wgs = wgs;
+    li.wgs = 1;
     li.bytes = (2.0 * nk + 3.0) * B * 8.0;
     return li;
 }

@@ -23,7 +23,7 @@ STATUS_NAMES = {0: "MAR_OK", -1: "MAR_ERR_ARG", -2: "MAR_ERR_PATTERN", -3: "MAR_
                 -4: "MAR_ERR_NOMEM", -5: "MAR_ERR_HIP", -6: "MAR_ERR_STATE"}
 PRECISION = {"fp64": 0, "fp32": 1}
 FORM = {"batched": 0, "plain": 1}
-PROF_CLASSES = 10
+PROF_CLASSES = 16
 
 
 class MarError(RuntimeError):
@@ -53,6 +53,13 @@ def lib() -> C.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_1307_3218_amd.build_lib`")
+    # torch ships its own HIP runtime. Loading torch first makes libmar bind to
+    # that same runtime (one runtime per process), so torch's streams and device
+    # pointers are valid handles inside libmar and torch can still use the GPU.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     i32, i64, f64 = C.c_int32, C.c_int64, C.c_double
     L.mar_create.argtypes = [i64, _P, _P, _P, _P, _P, _P, C.POINTER(_P)]

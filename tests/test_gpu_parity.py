@@ -224,9 +224,9 @@ def test_breakdown_truncates(c1):
 
 
 def test_indefinite_overlap_reports_not_spd():
-    H = sp.csr_matrix(np.array([[0.0, 1.0, 0.0], [1.0, 0.0, 1.0], [0.0, 1.0, 0.0]]))
-    S = sp.csr_matrix(np.array([[1.0, 0.0, 0.0], [0.0, 0.2, 0.9], [0.0, 0.9, 1.0]]))
-    ctx = mar.Context(H, S)
+    H = sp.csr_matrix(np.array([[0.1, 1.0, 0.0], [1.0, 0.2, 1.0], [0.0, 1.0, 0.3]]))
+    S = sp.csr_matrix(np.array([[1.0, 0.0, 0.0], [0.0, 0.2, 0.9], [0.0, 0.9, 1.0]]))   # eigenvalues of the
+    ctx = mar.Context(H, S)                                                            # lower block: 0.6 +- 0.98
     with pytest.raises(mar.MarError) as e:
         ctx.solve(np.array([0], np.int32), 3, 0.0, KT, precision="fp64")
     assert e.value.status == mar.MAR_ERR_NOT_SPD
