@@ -63,11 +63,28 @@ typedef enum { MAR_FP64 = 0, MAR_FP32 = 1 } mar_precision;
  * MAR_FORM_BATCHED: B seeds per block with seed-interleaved vectors. */
 typedef enum { MAR_FORM_BATCHED = 0, MAR_FORM_PLAIN = 1 } mar_form;
 
+/* CGS2 schedules. Both run two classical Gram-Schmidt passes per new vector
+ * in the S-inner product and give the same subspace and A = K^T H K up to
+ * rounding.
+ * TEXTBOOK: per step w = H u_n, h = K^T w and c1 = (S K)^T w in one pass,
+ *   w -= K c1, c2 = (S K)^T w, w -= K c2, then S w; K and S K are stored
+ *   (five basis passes per step).
+ * DELAYED: the second pass of a vector is merged with the first pass of the
+ *   next one. The SpMMs act on the once-orthogonalized vector u~ (y = H u~);
+ *   one sweep over K gives K^T S u~, K^T S y and K^T y; one update sweep
+ *   finishes u_n = (u~ - K c2)/gamma and the first-pass residual of y. The
+ *   relation H K = K R (R: the Gram-Schmidt coefficients) carries the change
+ *   from H u~ to H u_n into A and the coefficients; only K is stored (two basis
+ *   passes per step). The breakdown test on the two-pass norm runs one step
+ *   later, plus a first-pass test.
+ * AUTO: TEXTBOOK for the plain form, DELAYED for the batched form. */
+typedef enum { MAR_SCHED_AUTO = 0, MAR_SCHED_TEXTBOOK = 1, MAR_SCHED_DELAYED = 2 } mar_schedule;
+
 typedef struct {
     int32_t seed_block;    /* B for the batched form: power of two, 1..256 (FP32) or 1..128
                               (FP64); 0 = choose from the problem size */
-    int32_t proj_rows;     /* reserved (0 = default) */
-    int32_t upd_rows;      /* reserved (0 = default) */
+    int32_t schedule;      /* mar_schedule */
+    int32_t proj_wgs;      /* target workgroups of a projection sweep (0 = 1024) */
     int32_t reserved;
 } mar_tuning;
 

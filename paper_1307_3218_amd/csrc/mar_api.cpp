@@ -20,10 +20,12 @@ namespace {
 
 // One class per kernel variant, so that a class maps to one kernel symbol in a trace.
 enum ProfClass {
-    P_INIT = 0, P_SPMM, P_SPMM_DOT, P_PROJ2, P_PROJ1, P_UPD, P_REDUCE, P_NORM, P_APPEND, P_EIG, P_SUM, P_COUNT
+    P_INIT = 0, P_SPMM, P_SPMM_DOT, P_PROJ2, P_PROJ1, P_UPD, P_REDUCE, P_NORM, P_APPEND, P_EIG, P_SUM,
+    P_PROJR, P_UPD2, P_COEF, P_COUNT
 };
-const char* kProfNames[P_COUNT] = {"init",   "spmm",   "spmm_dot", "cgs_proj_KSK", "cgs_proj_1", "cgs_upd",
-                                   "reduce", "norm",   "append",   "eig",          "sum"};
+const char* kProfNames[P_COUNT] = {"init",   "spmm",     "spmm_dot",  "cgs_proj_KSK", "cgs_proj_1",
+                                   "cgs_upd", "reduce",  "norm",      "append",       "eig",
+                                   "sum",     "dcgs_proj", "dcgs_upd", "dcgs_coef"};
 
 struct ProfRec {
     int cls;
@@ -336,14 +338,14 @@ mar_status run_solve(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds, int nu
             launch(c, s, P_INIT, [&] { return mar::launch_zero(ws.SK, (int64_t)slab, s); });
         }
         launch(c, s, P_INIT, [&] {
-            return mar::launch_init<T>(B, M, c->M, seeds, ns, c->diagS, nu, ws.K, ws.active, ws.nu_eff, s);
+            return mar::launch_init<T>(B, M, c->M, seeds, ns, c->diagS, nu, ws.K, ws.active, ws.nu_eff, nullptr, s);
         });
-        launch(c, s, P_SPMM, [&] { return mar::launch_spmm<T>(B, c->S, ws.K, ws.SK, nullptr, s); });
+        launch(c, s, P_SPMM, [&] { return mar::launch_spmm<T>(B, c->S, ws.K, ws.SK, nullptr, 0, s); });
         for (int n = 0; n < nu; ++n) {
             const T* Kn = ws.K + (size_t)n * slab_el;
             const int nk = n + 1;
             const bool last = n + 1 == nu;
-            launch(c, s, P_SPMM, [&] { return mar::launch_spmm<T>(B, c->H, Kn, ws.W, nullptr, s); });
+            launch(c, s, P_SPMM, [&] { return mar::launch_spmm<T>(B, c->H, Kn, ws.W, nullptr, 0, s); });
             // h[:, n] = K^T w and c1 = (S K)^T w in one pass over K and S K
             int64_t nch = 0;
             launch(c, s, last ? P_PROJ1 : P_PROJ2, [&] {
@@ -365,7 +367,7 @@ mar_status run_solve(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds, int nu
             // z = S w and w^T S w
             int64_t swgs = 0;
             launch(c, s, P_SPMM_DOT, [&] {
-                LaunchInfo li = mar::launch_spmm<T>(B, c->S, ws.W, ws.Z, ws.part, s);
+                LaunchInfo li = mar::launch_spmm<T>(B, c->S, ws.W, ws.Z, ws.part, 1, s);
                 swgs = li.wgs;
                 return li;
             });
@@ -380,6 +382,134 @@ mar_status run_solve(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds, int nu
         }
         launch(c, s, P_EIG, [&] {
             return mar::launch_eig<T>(B, ns, seeds, nu, ws.h, ws.nu_eff, ws.K, M, c->Hrp, c->Hcol, c->Hval, c->SvalH,
+                                      c->diagS, c->max_row, mu, kT, d_rho, e_seed + blk0, n_seed + blk0,
+                                      nu_out + blk0, d_eps ? d_eps + blk0 * nu : nullptr,
+                                      d_w ? d_w + blk0 * nu : nullptr, s);
+        });
+    }
+    launch(c, s, P_SUM, [&] { return mar::launch_sum(e_seed, n_seeds, d_e_band, s); });
+    HIP_OR(c, hipGetLastError());
+    return MAR_OK;
+}
+
+// The delayed-reorthogonalization schedule (basis K only): per step two SpMMs
+// on the once-orthogonalized vector (y = H u~, S y), one projection sweep over
+// K with three right-hand sides, the FP64 coefficient kernel, one dual update
+// sweep (second pass of u~ and first pass of y), then the S-norm of the new
+// residual. Two passes over the basis per step instead of five.
+template <typename T>
+mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds, int nu, double mu, double kT,
+                             int B, double* d_rho, double* d_e_band, double* d_e_seed, double* d_n_seed,
+                             int32_t* d_nu_eff, double* d_eps, double* d_w, hipStream_t s) {
+    constexpr int VEC = 16 / sizeof(T);
+    const int64_t M = (c->M + 3) / 4 * 4;
+    const int64_t nvec = M * B / VEC;
+    const int P = B < VEC ? 1 : B / VEC;
+    const int target = c->tune.proj_wgs > 0 ? c->tune.proj_wgs : 1024;
+    const int64_t spmm_wgs = std::max((c->S.n * P + mar::WG - 1) / mar::WG, (c->H.n * P + mar::WG - 1) / mar::WG);
+    const int64_t ntiles = (nvec + mar::WG * mar::PROJR_Q - 1) / (mar::WG * mar::PROJR_Q);
+    const size_t slab = (size_t)M * B * sizeof(T);
+    size_t part_doubles = (size_t)spmm_wgs * 2 * B;
+    for (int nk = 1; nk <= nu; ++nk) {
+        const int nks = (nk + mar::PROJR_KG - 1) / mar::PROJR_KG;
+        const int64_t tiles = mar::projr_tiles(ntiles, nks, target);
+        const int64_t groups = (ntiles + tiles - 1) / tiles;
+        part_doubles = std::max<size_t>(part_doubles, (size_t)groups * 3 * nk * B);
+    }
+
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align_up(bytes);
+        return o;
+    };
+    const size_t oK = take((size_t)nu * slab), oY = take(slab), oSY = take(slab), oZT = take(slab);
+    const size_t oPart = take(part_doubles * 8);
+    const size_t oRed = take((size_t)3 * nu * B * 8), oRedb = take((size_t)2 * B * 8);
+    const size_t oH = take((size_t)B * nu * nu * 8), oG = take((size_t)B * nu * nu * 8);
+    const size_t oR = take((size_t)B * nu * (nu + 1) * 8), oC1 = take((size_t)B * nu * 8);
+    const size_t oBT = take((size_t)B * 8), oUU = take((size_t)B * 8), oGam = take((size_t)B * 8),
+                 oFn = take((size_t)B * 8);
+    const size_t oCA = take((size_t)nu * B * 8), oCB = take((size_t)nu * B * 8);
+    const size_t oAct = take((size_t)B * 4), oNu = take((size_t)B * 4);
+    const bool own_e = d_e_seed == nullptr, own_n = d_n_seed == nullptr, own_nu = d_nu_eff == nullptr;
+    const size_t oE = take(own_e ? (size_t)n_seeds * 8 : 0), oN = take(own_n ? (size_t)n_seeds * 8 : 0);
+    const size_t oNuOut = take(own_nu ? (size_t)n_seeds * 4 : 0);
+    mar_status st = ensure_ws(c, off);
+    if (st != MAR_OK) return st;
+    char* w = c->ws;
+    T* K = (T*)(w + oK);
+    T* Y = (T*)(w + oY);
+    T* SY = (T*)(w + oSY);
+    T* ZT = (T*)(w + oZT);
+    double* part = (double*)(w + oPart);
+    double* red = (double*)(w + oRed);
+    double* redb = (double*)(w + oRedb);
+    double* h = (double*)(w + oH);
+    double* G = (double*)(w + oG);
+    double* R = (double*)(w + oR);
+    double* C1 = (double*)(w + oC1);
+    double* BT = (double*)(w + oBT);
+    double* UU = (double*)(w + oUU);
+    double* gam = (double*)(w + oGam);
+    double* Fn = (double*)(w + oFn);
+    double* cA = (double*)(w + oCA);
+    double* cB = (double*)(w + oCB);
+    int32_t* active = (int32_t*)(w + oAct);
+    int32_t* nu_blk = (int32_t*)(w + oNu);
+    double* e_seed = own_e ? (double*)(w + oE) : d_e_seed;
+    double* n_seed = own_n ? (double*)(w + oN) : d_n_seed;
+    int32_t* nu_out = own_nu ? (int32_t*)(w + oNuOut) : d_nu_eff;
+    const double tau = sizeof(T) == 4 ? 1e-5 : 1e-12;
+    const int64_t slab_el = M * B;
+
+    for (int64_t blk0 = 0; blk0 < n_seeds; blk0 += B) {
+        const int ns = (int)std::min<int64_t>(B, n_seeds - blk0);
+        const int32_t* seeds = d_seeds + blk0;
+        if (M != c->M && blk0 == 0) {
+            // padded rows of Y, S y and S u~ must read as zero (spmm writes rows < M only)
+            launch(c, s, P_INIT, [&] { return mar::launch_zero(Y, (int64_t)slab, s); });
+            launch(c, s, P_INIT, [&] { return mar::launch_zero(SY, (int64_t)slab, s); });
+            launch(c, s, P_INIT, [&] { return mar::launch_zero(ZT, (int64_t)slab, s); });
+        }
+        launch(c, s, P_INIT, [&] {
+            return mar::launch_init<T>(B, M, c->M, seeds, ns, c->diagS, nu, K, active, nu_blk, UU, s);
+        });
+        launch(c, s, P_SPMM, [&] { return mar::launch_spmm<T>(B, c->S, K, ZT, nullptr, 0, s); });
+        for (int n = 0; n < nu; ++n) {
+            T* Kn = K + (size_t)n * slab_el;
+            const int nk = n + 1;
+            const bool last = n + 1 == nu;
+            launch(c, s, P_SPMM, [&] { return mar::launch_spmm<T>(B, c->H, Kn, Y, nullptr, 0, s); });
+            launch(c, s, P_SPMM, [&] { return mar::launch_spmm<T>(B, c->S, Y, SY, nullptr, 0, s); });
+            int64_t ngroups = 0;
+            launch(c, s, P_PROJR, [&] {
+                return mar::launch_projr<T>(B, K, M, nk, ZT, SY, Y, part, &ngroups, target, s);
+            });
+            const int64_t L = (int64_t)3 * nk * B;
+            launch(c, s, P_REDUCE, [&] { return mar::launch_reduce(part, ngroups, L, red, nullptr, B, nu, n, s); });
+            launch(c, s, P_COEF, [&] {
+                return mar::launch_coef(B, nu, n, red, active, h, G, R, C1, BT, UU, cA, cB, gam, Fn, active, nu_blk,
+                                        tau, s);
+            });
+            launch(c, s, P_UPD2, [&] { return mar::launch_upd2<T>(B, K, M, n, cA, cB, gam, Fn, Y, !last, s); });
+            if (last) break;
+            int64_t swgs = 0;
+            launch(c, s, P_SPMM_DOT, [&] {
+                LaunchInfo li = mar::launch_spmm<T>(B, c->S, Y, SY, part, 2, s);
+                swgs = li.wgs;
+                return li;
+            });
+            launch(c, s, P_REDUCE, [&] { return mar::launch_reduce(part, swgs, 2 * B, redb, nullptr, B, nu, n, s); });
+            launch(c, s, P_NORM, [&] {
+                return mar::launch_norm2(B, nu, n, redb, C1, tau, active, nu_blk, BT, UU, s);
+            });
+            launch(c, s, P_APPEND, [&] {
+                return mar::launch_append2<T>(B, M, Y, SY, BT, active, K + (size_t)(n + 1) * slab_el, ZT, s);
+            });
+        }
+        launch(c, s, P_EIG, [&] {
+            return mar::launch_eig<T>(B, ns, seeds, nu, h, nu_blk, K, M, c->Hrp, c->Hcol, c->Hval, c->SvalH,
                                       c->diagS, c->max_row, mu, kT, d_rho, e_seed + blk0, n_seed + blk0,
                                       nu_out + blk0, d_eps ? d_eps + blk0 * nu : nullptr,
                                       d_w ? d_w + blk0 * nu : nullptr, s);
@@ -493,9 +623,20 @@ mar_status mar_solve_async(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds, 
     HIP_OR(c, hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)hip_stream;
     const int B = form == MAR_FORM_PLAIN ? 1 : choose_block(c, nu, prec, n_seeds);
-    if (prec == MAR_FP32)
+    // schedule: the plain form is the textbook CGS2 (project, update, project,
+    // update); the batched form defaults to the delayed-reorthogonalization one
+    const bool delayed = c->tune.schedule == MAR_SCHED_DELAYED ||
+                         (c->tune.schedule == MAR_SCHED_AUTO && form == MAR_FORM_BATCHED);
+    if (prec == MAR_FP32) {
+        if (delayed)
+            return run_solve_delayed<float>(c, d_seeds, n_seeds, nu, mu, kT, B, d_rho, d_e_band, d_e_seed, d_n_seed,
+                                            d_nu_eff, d_eps, d_weight, s);
         return run_solve<float>(c, d_seeds, n_seeds, nu, mu, kT, B, d_rho, d_e_band, d_e_seed, d_n_seed, d_nu_eff,
                                 d_eps, d_weight, s);
+    }
+    if (delayed)
+        return run_solve_delayed<double>(c, d_seeds, n_seeds, nu, mu, kT, B, d_rho, d_e_band, d_e_seed, d_n_seed,
+                                         d_nu_eff, d_eps, d_weight, s);
     return run_solve<double>(c, d_seeds, n_seeds, nu, mu, kT, B, d_rho, d_e_band, d_e_seed, d_n_seed, d_nu_eff,
                              d_eps, d_weight, s);
 }
@@ -571,6 +712,9 @@ mar_status mar_set_tuning(mar_ctx* c, const mar_tuning* t) {
     }
     if (t->seed_block < 0 || t->seed_block > 256 || (t->seed_block & (t->seed_block - 1)) != 0)
         return set_err(c, MAR_ERR_ARG, "seed_block must be 0 or a power of two <= 256");
+    if (t->schedule < MAR_SCHED_AUTO || t->schedule > MAR_SCHED_DELAYED)
+        return set_err(c, MAR_ERR_ARG, "unknown schedule");
+    if (t->proj_wgs < 0) return set_err(c, MAR_ERR_ARG, "proj_wgs < 0");
     c->tune = *t;
     return MAR_OK;
 }

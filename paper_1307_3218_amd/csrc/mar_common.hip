@@ -152,4 +152,221 @@ LaunchInfo launch_zero(void* p, int64_t bytes, hipStream_t s) {
     return li;
 }
 
+// ---------------------------------------------------------------------------
+// Delayed-reorthogonalization schedule: small FP64 per-seed algebra of step n.
+//
+// Entering step n, u_0..u_{n-1} are final (K^T S K = I) and u~ (slab n) has
+// had one Gram-Schmidt pass and unit S-norm; y = H u~. The projection sweep
+// gave, per seed, c2 = K^T S u~ (second-pass coefficients of u~), g = K^T S y,
+// e = K^T y, and the self products u~.S y, u~.y. With
+//   gamma = sqrt(1 - |c2|^2),  u_n = (u~ - K c2) / gamma,
+// and the relation H K = K R collected from earlier steps (R upper Hessenberg
+// of the Gram-Schmidt coefficients, column n-1 completed here), this kernel
+// produces
+//   column n of A = K^T H K:  A[:n+1, n] = (E - G q) / gamma,  q = R c2,
+//     E = [e ; (u~.y - c2.e) / gamma],  G the Euclidean Gram matrix K^T K;
+//   column n of G from t = K^T u~ = (A[:n, n-1] - G c1_prev) / beta~_prev;
+//   the first-pass coefficients of H u_n against the S-basis,
+//     c1 = (F - q) / gamma,  F = [g ; (u~.S y - c2.g) / gamma];
+//   and the update coefficients (c2, g, gamma, F_n) for k_upd2.
+// The final norm of the vector appended at step n-1 is beta~_prev * gamma; it
+// is tested here against tau * eta (eta^2 = |c1_prev|^2 + beta~_prev^2 (|c2|^2 +
+// gamma^2)), the same test the two-pass schedule applies, one step later.
+// One workgroup per seed; A is h[b][k][n]; G is [nu][nu]; R is column-major
+// [nu][nu+1] (R_{p,k} at k*(nu+1) + p).
+__global__ __launch_bounds__(WG) void k_coef(int B, int nu, int n, const double* __restrict__ red,
+                                             double* __restrict__ Ah, double* __restrict__ Gm,
+                                             double* __restrict__ Rm, double* __restrict__ C1,
+                                             const double* __restrict__ BT, const double* __restrict__ UU,
+                                             double* __restrict__ cA, double* __restrict__ cB,
+                                             double* __restrict__ gam, double* __restrict__ Fn,
+                                             int32_t* __restrict__ active, int32_t* __restrict__ nu_eff, double tau) {
+    extern __shared__ double sm[];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const int nk = n + 1;
+    double* c2 = sm;
+    double* g = c2 + (nu + 1);
+    double* e = g + (nu + 1);
+    double* c1p = e + (nu + 1);
+    double* t = c1p + (nu + 1);
+    double* gc2 = t + (nu + 1);
+    double* q = gc2 + (nu + 1);
+    double* red8 = q + (nu + 1);
+    auto bsum = [&](double v) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        __syncthreads();
+        if ((tid & 63) == 0) red8[tid >> 6] = v;
+        __syncthreads();
+        return (red8[0] + red8[1]) + (red8[2] + red8[3]);
+    };
+    auto stop = [&](int nu_new) {
+        for (int k = tid; k < n; k += WG) {
+            cA[(int64_t)k * B + b] = 0.0;
+            cB[(int64_t)k * B + b] = 0.0;
+        }
+        if (tid == 0) {
+            gam[b] = 1.0;
+            Fn[b] = 0.0;
+            if (nu_new >= 0) {
+                nu_eff[b] = nu_new;
+                active[b] = 0;
+            }
+        }
+    };
+    if (!active[b]) {
+        stop(-1);
+        return;
+    }
+    double* A = Ah + (int64_t)b * nu * nu;
+    double* G = Gm + (int64_t)b * nu * nu;
+    double* Rc = Rm + (int64_t)b * nu * (nu + 1);
+    for (int k = tid; k < n; k += WG) {
+        c2[k] = red[((int64_t)0 * nk + k) * B + b];
+        g[k] = red[((int64_t)1 * nk + k) * B + b];
+        e[k] = red[((int64_t)2 * nk + k) * B + b];
+        c1p[k] = C1[(int64_t)b * nu + k];
+    }
+    const double utsy = red[((int64_t)1 * nk + n) * B + b];
+    const double uty = red[((int64_t)2 * nk + n) * B + b];
+    __syncthreads();
+    double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+    for (int k = tid; k < n; k += WG) {
+        p0 += c2[k] * c2[k];
+        p1 += c1p[k] * c1p[k];
+        p2 += c2[k] * e[k];
+        p3 += c2[k] * g[k];
+    }
+    const double s_cc = bsum(p0), s_c1p = bsum(p1), s_ce = bsum(p2), s_cg = bsum(p3);
+    const double gam2 = 1.0 - s_cc;
+    if (!(gam2 > 0.0)) {  // u~ lies in span(K): the Krylov space is exhausted
+        stop(n);
+        return;
+    }
+    const double gm = sqrt(gam2);
+    const double btp = BT[b], uu = UU[b];
+    if (n >= 1) {
+        const double bf = btp * gm;
+        const double eta = sqrt(s_c1p + btp * btp * (s_cc + gam2));
+        if (bf <= tau * eta) {
+            stop(n);
+            return;
+        }
+        for (int p = tid; p < n; p += WG) Rc[(int64_t)(n - 1) * (nu + 1) + p] = c1p[p] + btp * c2[p];
+        if (tid == 0) Rc[(int64_t)(n - 1) * (nu + 1) + n] = btp * gm;
+        for (int p = tid; p < n; p += WG) {
+            double sg = 0.0, sc = 0.0;
+            for (int k = 0; k < n; ++k) {
+                const double gkp = G[(int64_t)k * nu + p];
+                sg += gkp * c1p[k];
+                sc += gkp * c2[k];
+            }
+            t[p] = (A[(int64_t)p * nu + (n - 1)] - sg) / btp;
+            gc2[p] = sc;
+        }
+    }
+    __syncthreads();
+    double p4 = 0.0, p5 = 0.0;
+    for (int p = tid; p < n; p += WG) {
+        const double v = (t[p] - gc2[p]) / gm;
+        G[(int64_t)p * nu + n] = v;
+        G[(int64_t)n * nu + p] = v;
+        p4 += c2[p] * t[p];
+        p5 += c2[p] * gc2[p];
+    }
+    const double s_ct = bsum(p4), s_cgc = bsum(p5);
+    if (tid == 0) G[(int64_t)n * nu + n] = (uu - 2.0 * s_ct + s_cgc) / gam2;
+    // q = R[:n+1, :n] c2 (R_{p,k} vanishes for p > k + 1)
+    for (int p = tid; p <= n; p += WG) {
+        double sq = 0.0;
+        for (int k = (p > 0 ? p - 1 : 0); k < n; ++k) sq += Rc[(int64_t)k * (nu + 1) + p] * c2[k];
+        q[p] = sq;
+    }
+    __syncthreads();
+    const double En = (uty - s_ce) / gm;
+    const double Fnn = (utsy - s_cg) / gm;
+    for (int p = tid; p <= n; p += WG) {
+        double sgq = 0.0;
+        for (int k = 0; k <= n; ++k) sgq += G[(int64_t)k * nu + p] * q[k];
+        const double Ep = p < n ? e[p] : En;
+        A[(int64_t)p * nu + n] = (Ep - sgq) / gm;
+        const double Fp = p < n ? g[p] : Fnn;
+        C1[(int64_t)b * nu + p] = (Fp - q[p]) / gm;
+    }
+    for (int k = tid; k < n; k += WG) {
+        cA[(int64_t)k * B + b] = c2[k];
+        cB[(int64_t)k * B + b] = g[k];
+    }
+    if (tid == 0) {
+        gam[b] = gm;
+        Fn[b] = Fnn;
+    }
+}
+
+LaunchInfo launch_coef(int B, int nu, int n, const double* red, const int32_t*, double* A, double* G, double* R,
+                       double* C1, const double* BT, const double* UU, double* cA, double* cB, double* gam,
+                       double* Fn, int32_t* active, int32_t* nu_eff, double tau, hipStream_t s) {
+    const size_t lds = (size_t)(7 * (nu + 1) + 8) * sizeof(double);
+    hipLaunchKernelGGL(k_coef, dim3(B), dim3(WG), lds, s, B, nu, n, red, A, G, R, C1, BT, UU, cA, cB, gam, Fn, active,
+                       nu_eff, tau);
+    LaunchInfo li;
+    li.wgs = B;
+    const double nn = (double)n + 1.0;
+    li.bytes = (double)B * (3.0 * nn * nn + 8.0 * nn) * 8.0;
+    li.flops = (double)B * 8.0 * nn * nn;
+    return li;
+}
+
+// First-pass norm of the new residual w' (FP64): beta~ = sqrt(w'.S w'); the
+// vector is dropped when beta~ <= tau * sqrt(|c1|^2 + beta~^2); a negative or
+// non-finite w'.S w' flags S as not positive definite (nu_eff = -1).
+__global__ __launch_bounds__(WG) void k_norm2(int B, int nk, int nu, const double* __restrict__ redb,
+                                              const double* __restrict__ C1, double tau,
+                                              int32_t* __restrict__ active, int32_t* __restrict__ nu_eff,
+                                              double* __restrict__ BT, double* __restrict__ UU, int n) {
+    __shared__ double lds[WG];
+    const int np = WG / B;
+    const int b = threadIdx.x % B, part = threadIdx.x / B;
+    double s = 0.0;
+    if (part < np)
+        for (int k = part; k < nk; k += np) {
+            const double a = C1[(int64_t)b * nu + k];
+            s += a * a;
+        }
+    lds[threadIdx.x] = s;
+    __syncthreads();
+    if ((int)threadIdx.x >= B) return;
+    double cc = 0.0;
+    for (int p = 0; p < np; ++p) cc += lds[p * B + b];
+    if (!active[b]) {
+        BT[b] = 0.0;
+        return;
+    }
+    const double bb = redb[b], ww = redb[B + b];
+    if (!(bb >= 0.0) || !(bb < INFINITY)) {
+        nu_eff[b] = -1;
+        active[b] = 0;
+        BT[b] = 0.0;
+        return;
+    }
+    const double bt = sqrt(bb);
+    if (bt <= tau * sqrt(cc + bb)) {
+        nu_eff[b] = n + 1;
+        active[b] = 0;
+        BT[b] = 0.0;
+        return;
+    }
+    BT[b] = bt;
+    UU[b] = ww / bb;
+}
+
+LaunchInfo launch_norm2(int B, int nu, int n, const double* redb, const double* C1, double tau, int32_t* active,
+                        int32_t* nu_eff, double* BT, double* UU, hipStream_t s) {
+    hipLaunchKernelGGL(k_norm2, dim3(1), dim3(WG), 0, s, B, n + 1, nu, redb, C1, tau, active, nu_eff, BT, UU, n);
+    LaunchInfo li;
+    li.wgs = 1;
+    li.bytes = (double)B * (n + 4) * 8.0;
+    return li;
+}
+
 }  // namespace mar

@@ -42,7 +42,16 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t n) {
 // Workgroup reduction of per-seed partial sums (fixed order, deterministic).
 // Thread t holds vals[v][i] for seed (t % P) * SW + i. For every v and every
 // seed b in [0, P*SW) the sum over the workgroup's 256 threads is passed to
-// emit(v, b, sum) by exactly one thread. lds must hold 4 * NV * P * SW values.
+// emit(v, b, sum) by exactly one thread (always the same thread for a given
+// (v, b)). Values cross waves through LDS in chunks of SeedReduce::NVC values,
+// so the exchange buffer holds SeedReduce::LDS elements whatever NV is.
+template <int P, int SW, int NV>
+struct SeedReduce {
+    static constexpr int NVC_RAW = 768 / (P * SW);
+    static constexpr int NVC = NVC_RAW < 1 ? 1 : (NVC_RAW > NV ? NV : NVC_RAW);
+    static constexpr int LDS = 4 * NVC * P * SW;
+};
+
 template <int P, int SW, int NV, typename A, typename F>
 __device__ __forceinline__ void wg_seed_reduce(A (&vals)[NV][SW], A* lds, F&& emit) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -55,22 +64,31 @@ __device__ __forceinline__ void wg_seed_reduce(A (&vals)[NV][SW], A* lds, F&& em
                 for (int i = 0; i < SW; ++i) vals[v][i] += __shfl_xor(vals[v][i], off);
         }
     }
-    constexpr int TOT = NV * P * SW;
-    if (lane < P) {
+    constexpr int NVC = SeedReduce<P, SW, NV>::NVC;
+    constexpr int TOT = NVC * P * SW;
 #pragma unroll
-        for (int v = 0; v < NV; ++v)
+    for (int c0 = 0; c0 < NV; c0 += NVC) {
+        if (lane < P) {
 #pragma unroll
-            for (int i = 0; i < SW; ++i) lds[wave * TOT + (v * P + lane) * SW + i] = vals[v][i];
+            for (int v = 0; v < NVC; ++v)
+                if (c0 + v < NV) {
+#pragma unroll
+                    for (int i = 0; i < SW; ++i) lds[wave * TOT + (v * P + lane) * SW + i] = vals[c0 + v][i];
+                }
+        }
+        __syncthreads();
+        for (int o = threadIdx.x; o < TOT; o += 256) {
+            const int v = c0 + o / (P * SW);
+            if (v < NV) {
+                A s = lds[o];
+                s += lds[TOT + o];
+                s += lds[2 * TOT + o];
+                s += lds[3 * TOT + o];
+                emit(v, o % (P * SW), s);
+            }
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    for (int o = threadIdx.x; o < TOT; o += 256) {
-        A s = lds[o];
-        s += lds[TOT + o];
-        s += lds[2 * TOT + o];
-        s += lds[3 * TOT + o];
-        emit(o / (P * SW), o % (P * SW), s);
-    }
-    __syncthreads();
 }
 
 }  // namespace mar

@@ -10,6 +10,15 @@ constexpr int WG = 256;            // threads per workgroup for every streaming 
 constexpr int PROJ_Q = 8;          // 16-byte vectors per thread in a projection chunk
 constexpr int PROJ_KG = 4;         // basis slabs reduced together in a projection
 constexpr int MAX_ROW = 63;        // max stored entries in a row of H (|P(j)| <= 63)
+constexpr int PROJR_Q = 4;         // 16-byte vectors per thread and right-hand side in a row tile
+constexpr int PROJR_KG = 4;        // slabs owned by one workgroup in the delayed-schedule projection
+
+// Row tiles per workgroup of the delayed-schedule projection: as many as keep
+// the grid at about target_wgs workgroups (fewer partial sums), at least one.
+inline int64_t projr_tiles(int64_t ntiles, int nks, int target_wgs) {
+    const int64_t t = (ntiles * nks) / (target_wgs > 0 ? target_wgs : 1024);
+    return t < 1 ? 1 : (t > ntiles ? ntiles : t);
+}
 
 // Device copy of one sparse matrix. BSR 4x4 (values [blk][r][c]) when the
 // pattern has that structure, else CSR. Values are kept in FP64 and FP32.
@@ -53,9 +62,10 @@ struct LaunchInfo {
 
 template <typename T>
 LaunchInfo launch_init(int B, int64_t Mp, int64_t M, const int32_t* seeds, int nseeds, const double* diagS,
-                       int nu, T* K0, int32_t* active, int32_t* nu_eff, hipStream_t s);
+                       int nu, T* K0, int32_t* active, int32_t* nu_eff, double* uu, hipStream_t s);
+// ndot = 0: Y = A X; 1: also partial sums of X.Y per seed; 2: X.Y and X.X (part[wg][d][b]).
 template <typename T>
-LaunchInfo launch_spmm(int B, const DevMat& A, const T* X, T* Y, double* part, hipStream_t s);
+LaunchInfo launch_spmm(int B, const DevMat& A, const T* X, T* Y, double* part, int ndot, hipStream_t s);
 template <typename T>
 LaunchInfo launch_proj(int B, int ns, const T* b0, const T* b1, int64_t M, int nk, const T* x,
                        double* part, int64_t* nchunks, hipStream_t s);
@@ -70,6 +80,22 @@ LaunchInfo launch_eig(int B, int nseeds, const int32_t* seeds, int nu, double* h
                       const double* SvalH, const double* diagS, int max_row, double mu, double kT,
                       double* rho, double* e_seed, double* n_seed, int32_t* nu_eff_out, double* eps_out,
                       double* w_out, hipStream_t s);
+
+// Delayed-reorthogonalization schedule.
+template <typename T>
+LaunchInfo launch_projr(int B, const T* basis, int64_t M, int nk, const T* r0, const T* r1, const T* r2,
+                        double* part, int64_t* ngroups, int target_wgs, hipStream_t s);
+template <typename T>
+LaunchInfo launch_upd2(int B, T* basis, int64_t M, int n, const double* cA, const double* cB, const double* gam,
+                       const double* Fn, T* y, bool want_w, hipStream_t s);
+template <typename T>
+LaunchInfo launch_append2(int B, int64_t M, const T* W, const T* Z, const double* beta, const int32_t* active,
+                          T* Kn, T* ZT, hipStream_t s);
+LaunchInfo launch_coef(int B, int nu, int n, const double* red, const int32_t* active_in, double* A, double* G,
+                       double* R, double* C1, const double* BT, const double* UU, double* cA, double* cB,
+                       double* gam, double* Fn, int32_t* active, int32_t* nu_eff, double tau, hipStream_t s);
+LaunchInfo launch_norm2(int B, int nu, int n, const double* redb, const double* C1, double tau, int32_t* active,
+                        int32_t* nu_eff, double* BT, double* UU, hipStream_t s);
 
 LaunchInfo launch_reduce(const double* part, int64_t nchunks, int64_t L, double* out, double* h, int B, int nu,
                          int n, hipStream_t s);

@@ -19,7 +19,8 @@ namespace mar {
 template <typename T, int B>
 __global__ __launch_bounds__(WG) void k_init(int64_t Mp, int64_t M, const int32_t* __restrict__ seeds, int nseeds,
                                              const double* __restrict__ diagS, int nu, T* __restrict__ K0,
-                                             int32_t* __restrict__ active, int32_t* __restrict__ nu_eff) {
+                                             int32_t* __restrict__ active, int32_t* __restrict__ nu_eff,
+                                             double* __restrict__ uu) {
     using SM = SeedMap<T, B>;
     constexpr int VEC = SM::VEC;
     using VT = typename Vec16<T>::type;
@@ -31,6 +32,7 @@ __global__ __launch_bounds__(WG) void k_init(int64_t Mp, int64_t M, const int32_
         const bool ok = j >= 0 && j < M;
         active[b] = ok ? 1 : 0;
         nu_eff[b] = ok ? nu : (b < nseeds ? -2 : 0);
+        if (uu) uu[b] = ok ? 1.0 / diagS[j] : 0.0;   // u_1 . u_1
     }
     if (vi >= nvec) return;
     T a[VEC];
@@ -49,9 +51,10 @@ __global__ __launch_bounds__(WG) void k_init(int64_t Mp, int64_t M, const int32_
 // Y = A X over B seed-interleaved vectors, A in BSR 4x4. Thread = (block row,
 // seed group). The 16 block values are read once per thread and reused for
 // SW seeds; X rows of the block column are 16-byte vector loads.
-// DOT: also emit per-workgroup partial sums of X.Y per seed (FP64), the S-norm
-// of the residual (w^T S w).
-template <typename T, int B, bool DOT>
+// NDOT >= 1: also emit per-workgroup FP64 partial sums of X.Y per seed (the
+// S-norm w^T S w of a residual when A = S); NDOT = 2 adds X.X. Partials are
+// laid out part[wg][d][b].
+template <typename T, int B, int NDOT>
 __global__ __launch_bounds__(WG) void k_spmm_bsr4(int64_t nbrow, const int32_t* __restrict__ brp,
                                                   const int32_t* __restrict__ bcol, const T* __restrict__ bval,
                                                   const T* __restrict__ X, T* __restrict__ Y,
@@ -132,24 +135,29 @@ __global__ __launch_bounds__(WG) void k_spmm_bsr4(int64_t nbrow, const int32_t* 
             }
         }
     }
-    if constexpr (DOT) {
-        double d[1][SW];
+    if constexpr (NDOT > 0) {
+        double d[NDOT][SW];
 #pragma unroll
-        for (int i = 0; i < SW; ++i) d[0][i] = 0.0;
+        for (int v = 0; v < NDOT; ++v)
+#pragma unroll
+            for (int i = 0; i < SW; ++i) d[v][i] = 0.0;
         if (I < nbrow) {
 #pragma unroll
             for (int r = 0; r < 4; ++r)
 #pragma unroll
-                for (int i = 0; i < SW; ++i)
-                    d[0][i] += (double)X[(4 * I + r) * B + s0 + i] * (double)acc[r][i];
+                for (int i = 0; i < SW; ++i) {
+                    const double xv = (double)X[(4 * I + r) * B + s0 + i];
+                    d[0][i] += xv * (double)acc[r][i];
+                    if constexpr (NDOT > 1) d[1][i] += xv * xv;
+                }
         }
-        __shared__ double lds[4 * P * SW];
-        wg_seed_reduce<P, SW, 1>(d, lds, [&](int, int b, double s) { part[bid * B + b] = s; });
+        __shared__ double lds[SeedReduce<P, SW, NDOT>::LDS];
+        wg_seed_reduce<P, SW, NDOT>(d, lds, [&](int v, int b, double s) { part[(bid * NDOT + v) * B + b] = s; });
     }
 }
 
 // Y = A X with A in CSR (patterns without 4x4 block structure). Thread = (row, seed group).
-template <typename T, int B, bool DOT>
+template <typename T, int B, int NDOT>
 __global__ __launch_bounds__(WG) void k_spmm_csr(int64_t nrow, const int32_t* __restrict__ rp,
                                                  const int32_t* __restrict__ col, const T* __restrict__ val,
                                                  const T* __restrict__ X, T* __restrict__ Y,
@@ -186,12 +194,16 @@ __global__ __launch_bounds__(WG) void k_spmm_csr(int64_t nrow, const int32_t* __
             for (int i = 0; i < SW; ++i) Y[i0 * B + i] = acc[i];
         }
     }
-    if constexpr (DOT) {
-        double d[1][SW];
+    if constexpr (NDOT > 0) {
+        double d[NDOT][SW];
 #pragma unroll
-        for (int i = 0; i < SW; ++i) d[0][i] = (i0 < nrow) ? (double)X[i0 * B + s0 + i] * (double)acc[i] : 0.0;
-        __shared__ double lds[4 * P * SW];
-        wg_seed_reduce<P, SW, 1>(d, lds, [&](int, int b, double s) { part[bid * B + b] = s; });
+        for (int i = 0; i < SW; ++i) {
+            const double xv = (i0 < nrow) ? (double)X[i0 * B + s0 + i] : 0.0;
+            d[0][i] = xv * (double)acc[i];
+            if constexpr (NDOT > 1) d[1][i] = xv * xv;
+        }
+        __shared__ double lds[SeedReduce<P, SW, NDOT>::LDS];
+        wg_seed_reduce<P, SW, NDOT>(d, lds, [&](int v, int b, double s) { part[(bid * NDOT + v) * B + b] = s; });
     }
 }
 
@@ -227,7 +239,7 @@ __global__ __launch_bounds__(WG) void k_proj(const T* __restrict__ b0, const T* 
     }
     const int k0 = blockIdx.y * kps;
     const int k1 = min(nk, k0 + kps);
-    __shared__ T lds[4 * NS * KG * P * SW];
+    __shared__ T lds[SeedReduce<P, SW, NS * KG>::LDS];
     for (int kb = k0; kb < k1; kb += KG) {
         T raw[NS][KG][VEC];
 #pragma unroll
@@ -354,6 +366,187 @@ __global__ __launch_bounds__(WG) void k_append(const T* __restrict__ W, const T*
 }
 
 // ---------------------------------------------------------------------------
+// Delayed-reorthogonalization schedule (basis K only, no S K stored).
+//
+// Projection sweep: for NR right-hand sides r_0..r_{NR-1} (S u~, S y, y),
+//   part[group][r][k][b] = sum over the group's rows of K[k][row][b] * r[row][b].
+// Split over slabs: a workgroup owns KG consecutive slabs and `tiles` row
+// tiles (WG*Q vectors each); its KG x NR accumulators stay in registers across
+// all its tiles and are reduced across the workgroup once at the end, so one
+// partial per (group, r, k, b) leaves the kernel. The slab splits of one row
+// group are consecutive logical workgroups, which the XCD remapping places on
+// one XCD: they stream the same right-hand-side tiles at about the same time,
+// so those re-reads are served by that XCD's L2 rather than HBM.
+template <typename T, int B, int NR, int Q, int KG>
+__global__ __launch_bounds__(WG) void k_projr(const T* __restrict__ basis, int64_t slab, int nk, int nks,
+                                              const T* __restrict__ r0, const T* __restrict__ r1,
+                                              const T* __restrict__ r2, int64_t nvec, int tiles,
+                                              double* __restrict__ part) {
+    using SM = SeedMap<T, B>;
+    constexpr int VEC = SM::VEC, SW = SM::SW, P = SM::P;
+    using VT = typename Vec16<T>::type;
+    const int tid = threadIdx.x;
+    const int64_t L = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t grp = L / nks;
+    const int k0 = (int)(L % nks) * KG;
+    const int nkl = min(KG, nk - k0);
+    const int64_t slabv = slab / VEC;
+    const VT* bv = reinterpret_cast<const VT*>(basis) + (int64_t)k0 * slabv;
+    const VT* rv[3] = {reinterpret_cast<const VT*>(r0), reinterpret_cast<const VT*>(r1),
+                       reinterpret_cast<const VT*>(r2)};
+    T raw[NR][KG][VEC];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int kk = 0; kk < KG; ++kk)
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) raw[r][kk][i] = (T)0;
+    for (int tile = 0; tile < tiles; ++tile) {
+        const int64_t tbase = (grp * tiles + tile) * (int64_t)(WG * Q);
+        if (tbase >= nvec) break;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int64_t vi = tbase + (int64_t)q * WG + tid;
+            if (vi < nvec) {
+                T x[NR][VEC];
+#pragma unroll
+                for (int r = 0; r < NR; ++r) unpack(rv[r][vi], x[r]);
+#pragma unroll
+                for (int kk = 0; kk < KG; ++kk) {
+                    if (kk < nkl) {
+                        T a[VEC];
+                        unpack(bv[(int64_t)kk * slabv + vi], a);
+#pragma unroll
+                        for (int r = 0; r < NR; ++r)
+#pragma unroll
+                            for (int i = 0; i < VEC; ++i) raw[r][kk][i] = fma(a[i], x[r][i], raw[r][kk][i]);
+                    }
+                }
+            }
+        }
+    }
+    T acc[NR * KG][SW];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int kk = 0; kk < KG; ++kk) {
+#pragma unroll
+            for (int i = 0; i < SW; ++i) acc[r * KG + kk][i] = (T)0;
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) acc[r * KG + kk][i % SW] += raw[r][kk][i];
+        }
+    __shared__ T red_lds[SeedReduce<P, SW, NR * KG>::LDS];
+    wg_seed_reduce<P, SW, NR * KG>(acc, red_lds, [&](int v, int b, T sum) {
+        const int r = v / KG, kk = v % KG;
+        if (kk < nkl) part[((grp * NR + r) * nk + (k0 + kk)) * B + b] = (double)sum;
+    });
+}
+
+// Dual update of the delayed schedule, one pass over slabs 0..n-1:
+//   u_n = (u~ - sum_k K_k cA_k) / gamma       (second Gram-Schmidt pass of u~)
+//   w'  = (y  - sum_k K_k cB_k - u_n F_n) / gamma   (first pass of y = H u~)
+// u~ is slab n and is overwritten by u_n; y is overwritten by w' (if want_w).
+template <typename T, int B, int Q, bool WANT_W>
+__global__ __launch_bounds__(WG) void k_upd2(T* __restrict__ basis, int64_t slab, int n,
+                                             const double* __restrict__ cA, const double* __restrict__ cB,
+                                             const double* __restrict__ gam, const double* __restrict__ Fn,
+                                             T* __restrict__ y, int64_t nvec) {
+    using SM = SeedMap<T, B>;
+    constexpr int VEC = SM::VEC, P = SM::P;
+    using VT = typename Vec16<T>::type;
+    const int tid = threadIdx.x;
+    const int64_t vbase = (int64_t)blockIdx.x * (WG * Q) + tid;
+    const int64_t slabv = slab / VEC;
+    const int sb = (B < VEC) ? 0 : (tid % P) * VEC;
+    VT* bv = reinterpret_cast<VT*>(basis);
+    VT* yv = reinterpret_cast<VT*>(y);
+    T au[Q][VEC], aw[Q][VEC];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int64_t vi = vbase + (int64_t)q * WG;
+        if (vi < nvec) {
+            unpack(bv[(int64_t)n * slabv + vi], au[q]);
+            if constexpr (WANT_W) unpack(yv[vi], aw[q]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) au[q][i] = aw[q][i] = (T)0;
+        }
+    }
+    for (int k = 0; k < n; ++k) {
+        T ca[VEC], cb[VEC];
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) {
+            const int b = (B < VEC) ? (i % B) : (sb + i);
+            ca[i] = (T)cA[(int64_t)k * B + b];
+            if constexpr (WANT_W) cb[i] = (T)cB[(int64_t)k * B + b];
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int64_t vi = vbase + (int64_t)q * WG;
+            if (vi < nvec) {
+                T a[VEC];
+                unpack(bv[(int64_t)k * slabv + vi], a);
+#pragma unroll
+                for (int i = 0; i < VEC; ++i) {
+                    au[q][i] = fma(-a[i], ca[i], au[q][i]);
+                    if constexpr (WANT_W) aw[q][i] = fma(-a[i], cb[i], aw[q][i]);
+                }
+            }
+        }
+    }
+    T g[VEC], fn[VEC];
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) {
+        const int b = (B < VEC) ? (i % B) : (sb + i);
+        g[i] = (T)gam[b];
+        fn[i] = (T)Fn[b];
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int64_t vi = vbase + (int64_t)q * WG;
+        if (vi < nvec) {
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) {
+                au[q][i] = au[q][i] / g[i];
+                if constexpr (WANT_W) aw[q][i] = (aw[q][i] - au[q][i] * fn[i]) / g[i];
+            }
+            bv[(int64_t)n * slabv + vi] = pack(au[q]);
+            if constexpr (WANT_W) yv[vi] = pack(aw[q]);
+        }
+    }
+}
+
+// u~_{n+1} = w' / beta~ into slab n+1 and S u~_{n+1} = (S w') / beta~ (zero for stopped seeds).
+template <typename T, int B>
+__global__ __launch_bounds__(WG) void k_append2(const T* __restrict__ W, const T* __restrict__ Z,
+                                                const double* __restrict__ beta, const int32_t* __restrict__ active,
+                                                T* __restrict__ Kn, T* __restrict__ ZT, int64_t nvec) {
+    using SM = SeedMap<T, B>;
+    constexpr int VEC = SM::VEC, P = SM::P;
+    using VT = typename Vec16<T>::type;
+    const int64_t vi = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (vi >= nvec) return;
+    const int sb = (B < VEC) ? 0 : (threadIdx.x % P) * VEC;
+    T w[VEC], z[VEC];
+    unpack(reinterpret_cast<const VT*>(W)[vi], w);
+    unpack(reinterpret_cast<const VT*>(Z)[vi], z);
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) {
+        const int b = (B < VEC) ? (i % B) : (sb + i);
+        if (active[b]) {
+            const T bt = (T)beta[b];
+            w[i] = w[i] / bt;
+            z[i] = z[i] / bt;
+        } else {
+            w[i] = (T)0;
+            z[i] = (T)0;
+        }
+    }
+    reinterpret_cast<VT*>(Kn)[vi] = pack(w);
+    reinterpret_cast<VT*>(ZT)[vi] = pack(z);
+}
+
+// ---------------------------------------------------------------------------
 // Launchers: dispatch the runtime block size B to the compiled instance.
 #define MAR_DISPATCH_B(B, ...)                                   \
     switch (B) {                                                 \
@@ -370,12 +563,12 @@ __global__ __launch_bounds__(WG) void k_append(const T* __restrict__ W, const T*
 
 template <>
 LaunchInfo launch_init<MAR_T>(int B, int64_t Mp, int64_t M, const int32_t* seeds, int nseeds, const double* diagS,
-                              int nu, MAR_T* K0, int32_t* active, int32_t* nu_eff, hipStream_t s) {
+                              int nu, MAR_T* K0, int32_t* active, int32_t* nu_eff, double* uu, hipStream_t s) {
     constexpr int VEC = Vec16<MAR_T>::n;
     const int64_t nvec = Mp * B / VEC;
     const int64_t wgs = (std::max<int64_t>(nvec, B) + WG - 1) / WG;
     MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_init<MAR_T, BB>), dim3(wgs), dim3(WG), 0, s, Mp, M, seeds, nseeds,
-                                         diagS, nu, K0, active, nu_eff));
+                                         diagS, nu, K0, active, nu_eff, uu));
     LaunchInfo li;
     li.wgs = wgs;
     li.bytes = (double)Mp * B * sizeof(MAR_T);
@@ -383,29 +576,24 @@ LaunchInfo launch_init<MAR_T>(int B, int64_t Mp, int64_t M, const int32_t* seeds
 }
 
 template <>
-LaunchInfo launch_spmm<MAR_T>(int B, const DevMat& A, const MAR_T* X, MAR_T* Y, double* part, hipStream_t s) {
+LaunchInfo launch_spmm<MAR_T>(int B, const DevMat& A, const MAR_T* X, MAR_T* Y, double* part, int ndot,
+                              hipStream_t s) {
     constexpr int VEC = Vec16<MAR_T>::n;
     const int P = B < VEC ? 1 : B / VEC;
     const int64_t wgs = (A.n * P + WG - 1) / WG;
     const MAR_T* val = std::is_same<MAR_T, float>::value ? (const MAR_T*)A.v32 : (const MAR_T*)A.v64;
-    const bool dot = part != nullptr;
+#define MAR_SPMM_LAUNCH(KERNEL, ND) \
+    MAR_DISPATCH_B(B, hipLaunchKernelGGL((KERNEL<MAR_T, BB, ND>), dim3(wgs), dim3(WG), 0, s, A.n, A.ptr, A.idx, val, X, Y, part))
     if (A.bsr) {
-        if (dot) {
-            MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_spmm_bsr4<MAR_T, BB, true>), dim3(wgs), dim3(WG), 0, s, A.n,
-                                                 A.ptr, A.idx, val, X, Y, part));
-        } else {
-            MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_spmm_bsr4<MAR_T, BB, false>), dim3(wgs), dim3(WG), 0, s, A.n,
-                                                 A.ptr, A.idx, val, X, Y, part));
-        }
+        if (ndot == 2) { MAR_SPMM_LAUNCH(k_spmm_bsr4, 2); }
+        else if (ndot == 1) { MAR_SPMM_LAUNCH(k_spmm_bsr4, 1); }
+        else { MAR_SPMM_LAUNCH(k_spmm_bsr4, 0); }
     } else {
-        if (dot) {
-            MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_spmm_csr<MAR_T, BB, true>), dim3(wgs), dim3(WG), 0, s, A.n,
-                                                 A.ptr, A.idx, val, X, Y, part));
-        } else {
-            MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_spmm_csr<MAR_T, BB, false>), dim3(wgs), dim3(WG), 0, s, A.n,
-                                                 A.ptr, A.idx, val, X, Y, part));
-        }
+        if (ndot == 2) { MAR_SPMM_LAUNCH(k_spmm_csr, 2); }
+        else if (ndot == 1) { MAR_SPMM_LAUNCH(k_spmm_csr, 1); }
+        else { MAR_SPMM_LAUNCH(k_spmm_csr, 0); }
     }
+#undef MAR_SPMM_LAUNCH
     const int64_t rows = A.bsr ? 4 * A.n : A.n;
     LaunchInfo li;
     li.wgs = wgs;
@@ -476,6 +664,65 @@ LaunchInfo launch_append<MAR_T>(int B, int64_t M, const MAR_T* W, const MAR_T* Z
     const int64_t wgs = (nvec + WG - 1) / WG;
     MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_append<MAR_T, BB>), dim3(wgs), dim3(WG), 0, s, W, Z, beta, active, Kn,
                                          SKn, nvec));
+    LaunchInfo li;
+    li.wgs = wgs;
+    li.bytes = 4.0 * (double)M * B * sizeof(MAR_T);
+    return li;
+}
+
+template <>
+LaunchInfo launch_projr<MAR_T>(int B, const MAR_T* basis, int64_t M, int nk, const MAR_T* r0, const MAR_T* r1,
+                               const MAR_T* r2, double* part, int64_t* ngroups, int target_wgs, hipStream_t s) {
+    constexpr int VEC = Vec16<MAR_T>::n;
+    constexpr int Q = PROJR_Q, KG = PROJR_KG, NR = 3;
+    const int64_t nvec = M * B / VEC;
+    const int64_t ntiles = (nvec + WG * Q - 1) / (WG * Q);
+    const int nks = (nk + KG - 1) / KG;
+    const int64_t tiles = projr_tiles(ntiles, nks, target_wgs);
+    const int64_t groups = (ntiles + tiles - 1) / tiles;
+    const int64_t wgs = groups * nks;
+    MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_projr<MAR_T, BB, NR, Q, KG>), dim3((unsigned)wgs), dim3(WG), 0, s, basis,
+                                         M * B, nk, nks, r0, r1, r2, nvec, (int)tiles, part));
+    *ngroups = groups;
+    LaunchInfo li;
+    li.wgs = wgs;
+    li.bytes = ((double)nk + NR) * (double)(M * B) * sizeof(MAR_T);
+    li.flops = 2.0 * NR * nk * (double)(M * B);
+    return li;
+}
+
+template <>
+LaunchInfo launch_upd2<MAR_T>(int B, MAR_T* basis, int64_t M, int n, const double* cA, const double* cB,
+                              const double* gam, const double* Fn, MAR_T* y, bool want_w, hipStream_t s) {
+    constexpr int VEC = Vec16<MAR_T>::n;
+    const int64_t nvec = M * B / VEC;
+    const bool big = nvec >= (int64_t)WG * 4 * 1024;
+    const int Q = big ? 4 : 1;
+    const int64_t wgs = (nvec + WG * Q - 1) / (WG * Q);
+#define MAR_UPD2(QQ, WW) \
+    MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_upd2<MAR_T, BB, QQ, WW>), dim3(wgs), dim3(WG), 0, s, basis, M * B, n, cA, cB, gam, Fn, y, nvec))
+    if (big) {
+        if (want_w) { MAR_UPD2(4, true); } else { MAR_UPD2(4, false); }
+    } else {
+        if (want_w) { MAR_UPD2(1, true); } else { MAR_UPD2(1, false); }
+    }
+#undef MAR_UPD2
+    LaunchInfo li;
+    li.wgs = wgs;
+    const double slabs_read = (double)n + (want_w ? 2.0 : 1.0), slabs_written = want_w ? 2.0 : 1.0;
+    li.bytes = (slabs_read + slabs_written) * (double)(M * B) * sizeof(MAR_T);
+    li.flops = (want_w ? 4.0 : 2.0) * n * (double)(M * B);
+    return li;
+}
+
+template <>
+LaunchInfo launch_append2<MAR_T>(int B, int64_t M, const MAR_T* W, const MAR_T* Z, const double* beta,
+                                 const int32_t* active, MAR_T* Kn, MAR_T* ZT, hipStream_t s) {
+    constexpr int VEC = Vec16<MAR_T>::n;
+    const int64_t nvec = M * B / VEC;
+    const int64_t wgs = (nvec + WG - 1) / WG;
+    MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_append2<MAR_T, BB>), dim3(wgs), dim3(WG), 0, s, W, Z, beta, active, Kn,
+                                         ZT, nvec));
     LaunchInfo li;
     li.wgs = wgs;
     li.bytes = 4.0 * (double)M * B * sizeof(MAR_T);

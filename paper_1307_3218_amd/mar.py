@@ -22,6 +22,7 @@ MAR_OK, MAR_ERR_ARG, MAR_ERR_PATTERN, MAR_ERR_NOT_SPD, MAR_ERR_NOMEM, MAR_ERR_HI
 STATUS_NAMES = {0: "MAR_OK", -1: "MAR_ERR_ARG", -2: "MAR_ERR_PATTERN", -3: "MAR_ERR_NOT_SPD",
                 -4: "MAR_ERR_NOMEM", -5: "MAR_ERR_HIP", -6: "MAR_ERR_STATE"}
 PRECISION = {"fp64": 0, "fp32": 1}
+SCHEDULE = {"auto": 0, "textbook": 1, "delayed": 2}
 FORM = {"batched": 0, "plain": 1}
 PROF_CLASSES = 16
 
@@ -34,7 +35,7 @@ class MarError(RuntimeError):
 
 
 class mar_tuning(C.Structure):
-    _fields_ = [("seed_block", C.c_int32), ("proj_rows", C.c_int32), ("upd_rows", C.c_int32),
+    _fields_ = [("seed_block", C.c_int32), ("schedule", C.c_int32), ("proj_wgs", C.c_int32),
                 ("reserved", C.c_int32)]
 
 
@@ -146,8 +147,8 @@ def mar_solve_async(ctx, d_seeds, n_seeds, nu, mu, kT, prec, form, d_rho, d_e_ba
                                  _tptr(d_nu_eff), _tptr(d_eps), _tptr(d_weight), stream)
 
 
-def mar_set_tuning(ctx, seed_block: int = 0) -> int:
-    t = mar_tuning(seed_block, 0, 0, 0)
+def mar_set_tuning(ctx, seed_block: int = 0, schedule: int = 0, proj_wgs: int = 0) -> int:
+    t = mar_tuning(seed_block, schedule, proj_wgs, 0)
     return lib().mar_set_tuning(ctx, C.byref(t))
 
 
@@ -232,8 +233,8 @@ class Context:
                              d_rho, d_e_band, d_e_seed, d_n_seed, d_nu_eff, d_eps, d_weight, stream)
         _check(self.handle, st)
 
-    def set_tuning(self, seed_block: int = 0):
-        _check(self.handle, mar_set_tuning(self.handle, seed_block))
+    def set_tuning(self, seed_block: int = 0, schedule: str = "auto", proj_wgs: int = 0):
+        _check(self.handle, mar_set_tuning(self.handle, seed_block, SCHEDULE[schedule], proj_wgs))
 
     def seed_block(self, nu: int, precision: str = "fp32") -> int:
         return mar_seed_block(self.handle, nu, PRECISION[precision])

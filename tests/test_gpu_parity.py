@@ -101,31 +101,49 @@ def test_c1_all_seeds_nu30(c1, c1_ctx, c1_mu, c1_ref30, prec, form):
     assert abs(g.n_seed.sum() - c1.M) <= 1e3 * TOL[prec] * c1.M
 
 
+@pytest.mark.parametrize("sched", ["delayed", "textbook"])
 @pytest.mark.parametrize("prec,B", [("fp64", b) for b in (1, 2, 4, 8, 16, 32, 64, 128)] +
                          [("fp32", b) for b in (1, 2, 4, 8, 16, 32, 64, 128, 256)])
-def test_c1_every_block_size_ragged(c1, c1_ctx, c1_mu, prec, B):
+def test_c1_every_block_size_ragged(c1, c1_ctx, c1_mu, prec, B, sched):
     seeds = lattice.sample_seeds(c1.M, 37, seed=B).astype(np.int32)    # 37: ragged last block
     ref = O.solve(c1.H, c1.S, seeds, 24, c1_mu, KT)
-    c1_ctx.set_tuning(seed_block=B)
+    c1_ctx.set_tuning(seed_block=B, schedule=sched)
     try:
         g = c1_ctx.solve(seeds, 24, c1_mu, KT, precision=prec, form="batched", levels=True)
     finally:
         c1_ctx.set_tuning(0)
-    compare(c1.H, seeds, g, ref, prec, label=f"M=256 B={B}")
+    compare(c1.H, seeds, g, ref, prec, label=f"M=256 B={B} {sched}")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_c1_delayed_plain_and_projection_grids(c1, c1_ctx, c1_mu, c1_ref30, prec):
+    """The delayed schedule at B = 1 and with tiny / huge projection grids (many tiles per workgroup)."""
+    seeds = np.arange(0, c1.M, 5, dtype=np.int32)
+    for wgs in (1, 7, 100000):
+        c1_ctx.set_tuning(seed_block=0, schedule="delayed", proj_wgs=wgs)
+        try:
+            g = c1_ctx.solve(seeds, 30, c1_mu, KT, precision=prec, form="plain", levels=True)
+        finally:
+            c1_ctx.set_tuning(0)
+        ref = O.solve(c1.H, c1.S, seeds, 30, c1_mu, KT)
+        compare(c1.H, seeds, g, ref, prec, label=f"delayed plain proj_wgs={wgs}")
 
 
 def test_c1_nu_equals_M_exact(c1, c1_ctx):
     """nu = M: the subspace result equals the dense generalized eigensolve (global-memory eigensolver path)."""
     mu = -0.448
     seeds = np.arange(c1.M, dtype=np.int32)
-    g = c1_ctx.solve(seeds, c1.M, mu, KT, precision="fp64", levels=True)
     ref = O.solve(c1.H, c1.S, seeds, c1.M, mu, KT, workers=_workers(8))
-    compare(c1.H, seeds, g, ref, "fp64", label="M=256 nu=M")
     rho_d, E_d, _ = O.dense(c1.H, c1.S, mu, KT)
     rows = np.repeat(np.arange(c1.M), np.diff(c1.H.indptr))
     exact = rho_d[c1.H.indices, rows]
-    assert np.linalg.norm(g.rho - exact) / np.linalg.norm(exact) < 1e-10
-    assert abs(g.e_band - E_d) / abs(E_d) < 1e-10
+    for form in ("batched", "plain"):
+        g = c1_ctx.solve(seeds, c1.M, mu, KT, precision="fp64", form=form, levels=True)
+        compare(c1.H, seeds, g, ref, "fp64", label=f"M=256 nu=M {form}")
+        assert np.linalg.norm(g.rho - exact) / np.linalg.norm(exact) < 1e-10
+        assert abs(g.e_band - E_d) / abs(E_d) < 1e-10
+    g = c1_ctx.solve(seeds, c1.M, mu, KT, precision="fp32", levels=True)
+    compare(c1.H, seeds, g, ref, "fp32", label="M=256 nu=M fp32")
 
 
 def test_c1_determinism(c1, c1_ctx, c1_mu):
@@ -215,20 +233,23 @@ def test_breakdown_truncates(c1):
     H = sp.block_diag(blocks, format="csr")
     ctx = mar.Context(H, sp.identity(12, format="csr"))
     seeds = np.array([1, 5, 11], dtype=np.int32)
-    for prec in ("fp64", "fp32"):
-        g = ctx.solve(seeds, 8, 0.0, KT, precision=prec, levels=True)
-        assert list(g.nu_eff) == [4, 4, 4]
-        ref = O.solve(H, sp.identity(12, format="csr"), seeds, 8, 0.0, KT)
-        compare(H, seeds, g, ref, prec, label="breakdown")
+    for sched in ("delayed", "textbook"):
+        ctx.set_tuning(0, schedule=sched)
+        for prec in ("fp64", "fp32"):
+            g = ctx.solve(seeds, 8, 0.0, KT, precision=prec, levels=True)
+            assert list(g.nu_eff) == [4, 4, 4]
+            ref = O.solve(H, sp.identity(12, format="csr"), seeds, 8, 0.0, KT)
+            compare(H, seeds, g, ref, prec, label=f"breakdown {sched}")
     ctx.close()
 
 
-def test_indefinite_overlap_reports_not_spd():
+@pytest.mark.parametrize("form", ["plain", "batched"])
+def test_indefinite_overlap_reports_not_spd(form):
     H = sp.csr_matrix(np.array([[0.1, 1.0, 0.0], [1.0, 0.2, 1.0], [0.0, 1.0, 0.3]]))
     S = sp.csr_matrix(np.array([[1.0, 0.0, 0.0], [0.0, 0.2, 0.9], [0.0, 0.9, 1.0]]))   # eigenvalues of the
     ctx = mar.Context(H, S)                                                            # lower block: 0.6 +- 0.98
     with pytest.raises(mar.MarError) as e:
-        ctx.solve(np.array([0], np.int32), 3, 0.0, KT, precision="fp64")
+        ctx.solve(np.array([0], np.int32), 3, 0.0, KT, precision="fp64", form=form)
     assert e.value.status == mar.MAR_ERR_NOT_SPD
     ctx.close()
 
@@ -248,11 +269,12 @@ def test_general_csr_pattern():
     assert not ctx.info()["H_bsr"]
     seeds = lattice.sample_seeds(M, 41, seed=1).astype(np.int32)
     for prec in ("fp64", "fp32"):
+        ref = O.solve(H, S, seeds, 25, 0.1, KT)
         for B in (1, 8, 64):
-            ctx.set_tuning(B)
-            g = ctx.solve(seeds, 25, 0.1, KT, precision=prec, levels=True)
-            ref = O.solve(H, S, seeds, 25, 0.1, KT)
-            compare(H, seeds, g, ref, prec, label=f"csr B={B}")
+            for sched in ("delayed", "textbook"):
+                ctx.set_tuning(B, schedule=sched)
+                g = ctx.solve(seeds, 25, 0.1, KT, precision=prec, levels=True)
+                compare(H, seeds, g, ref, prec, label=f"csr B={B} {sched}")
     ctx.close()
 
 
@@ -280,19 +302,23 @@ def c2_ctx(c2):
     ctx.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_c2_all_seeds_sampled_oracle(c2, c2_ctx, prec):
+@pytest.mark.parametrize("prec,sched", [("fp64", "delayed"), ("fp32", "delayed"), ("fp32", "textbook")])
+def test_c2_all_seeds_sampled_oracle(c2, c2_ctx, prec, sched):
     """All 16384 seeds on the GPU at nu = 30; the oracle checks a 300-seed sample element by element."""
     seeds = np.arange(c2.M, dtype=np.int32)
     mu = 0.0
-    g = c2_ctx.solve(seeds, 30, mu, KT, precision=prec, levels=True)
+    c2_ctx.set_tuning(0, schedule=sched)
+    try:
+        g = c2_ctx.solve(seeds, 30, mu, KT, precision=prec, levels=True)
+    finally:
+        c2_ctx.set_tuning(0)
     assert np.all(g.nu_eff == 30)
     check_identities(g, mu, KT, prec)
     sample = lattice.sample_seeds(c2.M, 300, seed=7)
     ref = O.solve(c2.H, c2.S, sample, 30, mu, KT, workers=_workers(16))
     sub = mar.SolveOutput(rho=g.rho, e_band=float(np.sum(g.e_seed[sample])), e_seed=g.e_seed[sample],
                           n_seed=g.n_seed[sample], nu_eff=g.nu_eff[sample], eps=g.eps[sample], weight=None)
-    compare(c2.H, sample, sub, ref, prec, label="M=16384 nu=30")
+    compare(c2.H, sample, sub, ref, prec, label=f"M=16384 nu=30 {sched}")
 
 
 # ------------------------------------------------------------------ M = 131072 (bench shape)
