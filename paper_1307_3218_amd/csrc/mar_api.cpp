@@ -63,6 +63,8 @@ struct mar_ctx {
     char* io = nullptr;
     size_t io_bytes = 0;
     hipStream_t stream = nullptr;
+    hipStream_t side = nullptr;          // eigensolves of finished seed blocks overlap the next block here
+    hipEvent_t ev_rows[2] = {nullptr, nullptr}, ev_eig[2] = {nullptr, nullptr};
     std::string err;
     bool prof = false;
     std::vector<ProfRec> recs;
@@ -79,6 +81,11 @@ struct mar_ctx {
         for (void* p : allocs) hipFree(p);
         if (ws) hipFree(ws);
         if (io) hipFree(io);
+        for (int p = 0; p < 2; ++p) {
+            if (ev_rows[p]) hipEventDestroy(ev_rows[p]);
+            if (ev_eig[p]) hipEventDestroy(ev_eig[p]);
+        }
+        if (side) hipStreamDestroy(side);
         if (stream) hipStreamDestroy(stream);
     }
 };
@@ -313,6 +320,7 @@ mar_status run_solve(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds, int nu
     const size_t oRed1 = take((size_t)2 * nu * B * 8), oRed2 = take((size_t)nu * B * 8), oRedb = take((size_t)B * 8);
     const size_t oH = take((size_t)B * nu * nu * 8), oBeta = take((size_t)B * 8);
     const size_t oAct = take((size_t)B * 4), oNu = take((size_t)B * 4);
+    const size_t oKp = take((size_t)B * nu * std::max(1, c->max_row) * 8), oNuCp = take((size_t)B * 4);
     const bool own_e = d_e_seed == nullptr, own_n = d_n_seed == nullptr, own_nu = d_nu_eff == nullptr;
     const size_t oE = take(own_e ? (size_t)n_seeds * 8 : 0), oN = take(own_n ? (size_t)n_seeds * 8 : 0);
     const size_t oNuOut = take(own_nu ? (size_t)n_seeds * 4 : 0);
@@ -380,11 +388,16 @@ mar_status run_solve(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds, int nu
                                              ws.SK + (size_t)(n + 1) * slab_el, s);
             });
         }
+        double* Kp = (double*)(w + oKp);
+        int32_t* nucp = (int32_t*)(w + oNuCp);
         launch(c, s, P_EIG, [&] {
-            return mar::launch_eig<T>(B, ns, seeds, nu, ws.h, ws.nu_eff, ws.K, M, c->Hrp, c->Hcol, c->Hval, c->SvalH,
-                                      c->diagS, c->max_row, mu, kT, d_rho, e_seed + blk0, n_seed + blk0,
-                                      nu_out + blk0, d_eps ? d_eps + blk0 * nu : nullptr,
-                                      d_w ? d_w + blk0 * nu : nullptr, s);
+            return mar::launch_gather<T>(B, ns, seeds, nu, ws.nu_eff, ws.K, M, c->Hrp, c->Hcol, c->max_row, Kp, nucp,
+                                         s);
+        });
+        launch(c, s, P_EIG, [&] {
+            return mar::launch_eig(ns, seeds, nu, ws.h, nucp, Kp, c->Hrp, c->Hcol, c->Hval, c->SvalH, c->diagS,
+                                   c->max_row, mu, kT, d_rho, e_seed + blk0, n_seed + blk0, nu_out + blk0,
+                                   d_eps ? d_eps + blk0 * nu : nullptr, d_w ? d_w + blk0 * nu : nullptr, s);
         });
     }
     launch(c, s, P_SUM, [&] { return mar::launch_sum(e_seed, n_seeds, d_e_band, s); });
@@ -426,11 +439,15 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     const size_t oK = take((size_t)nu * slab), oY = take(slab), oSY = take(slab), oZT = take(slab);
     const size_t oPart = take(part_doubles * 8);
     const size_t oRed = take((size_t)3 * nu * B * 8), oRedb = take((size_t)2 * B * 8);
-    const size_t oH = take((size_t)B * nu * nu * 8), oG = take((size_t)B * nu * nu * 8);
+    const size_t oH0 = take((size_t)B * nu * nu * 8), oH1 = take((size_t)B * nu * nu * 8);
+    const size_t oG = take((size_t)B * nu * nu * 8);
+    const size_t kp_bytes = (size_t)B * nu * std::max(1, c->max_row) * 8;
+    const size_t oKp0 = take(kp_bytes), oKp1 = take(kp_bytes), oNc0 = take((size_t)B * 4), oNc1 = take((size_t)B * 4);
     const size_t oR = take((size_t)B * nu * (nu + 1) * 8), oC1 = take((size_t)B * nu * 8);
     const size_t oBT = take((size_t)B * 8), oUU = take((size_t)B * 8), oGam = take((size_t)B * 8),
                  oFn = take((size_t)B * 8);
     const size_t oCA = take((size_t)nu * B * 8), oCB = take((size_t)nu * B * 8);
+    const size_t oCAf = take((size_t)nu * B * 4), oCBf = take((size_t)nu * B * 4);
     const size_t oAct = take((size_t)B * 4), oNu = take((size_t)B * 4);
     const bool own_e = d_e_seed == nullptr, own_n = d_n_seed == nullptr, own_nu = d_nu_eff == nullptr;
     const size_t oE = take(own_e ? (size_t)n_seeds * 8 : 0), oN = take(own_n ? (size_t)n_seeds * 8 : 0);
@@ -445,7 +462,9 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     double* part = (double*)(w + oPart);
     double* red = (double*)(w + oRed);
     double* redb = (double*)(w + oRedb);
-    double* h = (double*)(w + oH);
+    double* hbuf[2] = {(double*)(w + oH0), (double*)(w + oH1)};
+    double* kpbuf[2] = {(double*)(w + oKp0), (double*)(w + oKp1)};
+    int32_t* ncbuf[2] = {(int32_t*)(w + oNc0), (int32_t*)(w + oNc1)};
     double* G = (double*)(w + oG);
     double* R = (double*)(w + oR);
     double* C1 = (double*)(w + oC1);
@@ -455,6 +474,10 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     double* Fn = (double*)(w + oFn);
     double* cA = (double*)(w + oCA);
     double* cB = (double*)(w + oCB);
+    float* cAf = sizeof(T) == 4 ? (float*)(w + oCAf) : nullptr;
+    float* cBf = sizeof(T) == 4 ? (float*)(w + oCBf) : nullptr;
+    const T* cAT = sizeof(T) == 4 ? (const T*)cAf : (const T*)cA;
+    const T* cBT = sizeof(T) == 4 ? (const T*)cBf : (const T*)cB;
     int32_t* active = (int32_t*)(w + oAct);
     int32_t* nu_blk = (int32_t*)(w + oNu);
     double* e_seed = own_e ? (double*)(w + oE) : d_e_seed;
@@ -466,6 +489,10 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     for (int64_t blk0 = 0; blk0 < n_seeds; blk0 += B) {
         const int ns = (int)std::min<int64_t>(B, n_seeds - blk0);
         const int32_t* seeds = d_seeds + blk0;
+        const int par = (int)((blk0 / B) & 1);
+        double* h = hbuf[par];
+        // the eigensolve of block i-2 (side stream) must be done with this parity's buffers
+        if (blk0 >= 2 * (int64_t)B) HIP_OR(c, hipStreamWaitEvent(s, c->ev_eig[par], 0));
         if (M != c->M && blk0 == 0) {
             // padded rows of Y, S y and S u~ must read as zero (spmm writes rows < M only)
             launch(c, s, P_INIT, [&] { return mar::launch_zero(Y, (int64_t)slab, s); });
@@ -489,10 +516,10 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
             const int64_t L = (int64_t)3 * nk * B;
             launch(c, s, P_REDUCE, [&] { return mar::launch_reduce(part, ngroups, L, red, nullptr, B, nu, n, s); });
             launch(c, s, P_COEF, [&] {
-                return mar::launch_coef(B, nu, n, red, active, h, G, R, C1, BT, UU, cA, cB, gam, Fn, active, nu_blk,
-                                        tau, s);
+                return mar::launch_coef(B, nu, n, red, h, G, R, C1, BT, UU, cA, cB, cAf, cBf, gam, Fn, active,
+                                        nu_blk, tau, s);
             });
-            launch(c, s, P_UPD2, [&] { return mar::launch_upd2<T>(B, K, M, n, cA, cB, gam, Fn, Y, !last, s); });
+            launch(c, s, P_UPD2, [&] { return mar::launch_upd2<T>(B, K, M, n, cAT, cBT, gam, Fn, Y, !last, s); });
             if (last) break;
             int64_t swgs = 0;
             launch(c, s, P_SPMM_DOT, [&] {
@@ -508,12 +535,24 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
                 return mar::launch_append2<T>(B, M, Y, SY, BT, active, K + (size_t)(n + 1) * slab_el, ZT, s);
             });
         }
+        // rows K[P(j), :] leave the basis here; the eigensolve runs on the side
+        // stream while the next block reuses the basis
         launch(c, s, P_EIG, [&] {
-            return mar::launch_eig<T>(B, ns, seeds, nu, h, nu_blk, K, M, c->Hrp, c->Hcol, c->Hval, c->SvalH,
-                                      c->diagS, c->max_row, mu, kT, d_rho, e_seed + blk0, n_seed + blk0,
-                                      nu_out + blk0, d_eps ? d_eps + blk0 * nu : nullptr,
-                                      d_w ? d_w + blk0 * nu : nullptr, s);
+            return mar::launch_gather<T>(B, ns, seeds, nu, nu_blk, K, M, c->Hrp, c->Hcol, c->max_row, kpbuf[par],
+                                         ncbuf[par], s);
         });
+        HIP_OR(c, hipEventRecord(c->ev_rows[par], s));
+        HIP_OR(c, hipStreamWaitEvent(c->side, c->ev_rows[par], 0));
+        launch(c, c->side, P_EIG, [&] {
+            return mar::launch_eig(ns, seeds, nu, h, ncbuf[par], kpbuf[par], c->Hrp, c->Hcol, c->Hval, c->SvalH,
+                                   c->diagS, c->max_row, mu, kT, d_rho, e_seed + blk0, n_seed + blk0, nu_out + blk0,
+                                   d_eps ? d_eps + blk0 * nu : nullptr, d_w ? d_w + blk0 * nu : nullptr, c->side);
+        });
+        HIP_OR(c, hipEventRecord(c->ev_eig[par], c->side));
+    }
+    if (n_seeds > 0) {
+        HIP_OR(c, hipStreamWaitEvent(s, c->ev_eig[0], 0));
+        HIP_OR(c, hipStreamWaitEvent(s, c->ev_eig[1], 0));
     }
     launch(c, s, P_SUM, [&] { return mar::launch_sum(e_seed, n_seeds, d_e_band, s); });
     HIP_OR(c, hipGetLastError());
@@ -598,8 +637,13 @@ mar_status mar_create(int64_t M, const int64_t* H_rowptr, const int32_t* H_col, 
     if ((st = upload(c, &c->SvalH, svalH.data(), svalH.size())) != MAR_OK) return fail(st);
     if ((st = upload(c, &c->diagS, diag.data(), diag.size())) != MAR_OK) return fail(st);
     he = hipStreamCreate(&c->stream);
+    if (he == hipSuccess) he = hipStreamCreate(&c->side);
+    for (int p = 0; p < 2 && he == hipSuccess; ++p) {
+        he = hipEventCreateWithFlags(&c->ev_rows[p], hipEventDisableTiming);
+        if (he == hipSuccess) he = hipEventCreateWithFlags(&c->ev_eig[p], hipEventDisableTiming);
+    }
     if (he != hipSuccess) {
-        c->err = fmt("hipStreamCreate failed: %s", hipGetErrorString(he));
+        c->err = fmt("stream/event creation failed: %s", hipGetErrorString(he));
         return fail(MAR_ERR_HIP);
     }
     *out = c;

@@ -179,6 +179,7 @@ __global__ __launch_bounds__(WG) void k_coef(int B, int nu, int n, const double*
                                              double* __restrict__ Rm, double* __restrict__ C1,
                                              const double* __restrict__ BT, const double* __restrict__ UU,
                                              double* __restrict__ cA, double* __restrict__ cB,
+                                             float* __restrict__ cAf, float* __restrict__ cBf,
                                              double* __restrict__ gam, double* __restrict__ Fn,
                                              int32_t* __restrict__ active, int32_t* __restrict__ nu_eff, double tau) {
     extern __shared__ double sm[];
@@ -204,6 +205,10 @@ __global__ __launch_bounds__(WG) void k_coef(int B, int nu, int n, const double*
         for (int k = tid; k < n; k += WG) {
             cA[(int64_t)k * B + b] = 0.0;
             cB[(int64_t)k * B + b] = 0.0;
+            if (cAf) {
+                cAf[(int64_t)k * B + b] = 0.0f;
+                cBf[(int64_t)k * B + b] = 0.0f;
+            }
         }
         if (tid == 0) {
             gam[b] = 1.0;
@@ -296,6 +301,10 @@ __global__ __launch_bounds__(WG) void k_coef(int B, int nu, int n, const double*
     for (int k = tid; k < n; k += WG) {
         cA[(int64_t)k * B + b] = c2[k];
         cB[(int64_t)k * B + b] = g[k];
+        if (cAf) {  // the same coefficients rounded once to the basis precision
+            cAf[(int64_t)k * B + b] = (float)c2[k];
+            cBf[(int64_t)k * B + b] = (float)g[k];
+        }
     }
     if (tid == 0) {
         gam[b] = gm;
@@ -303,12 +312,12 @@ __global__ __launch_bounds__(WG) void k_coef(int B, int nu, int n, const double*
     }
 }
 
-LaunchInfo launch_coef(int B, int nu, int n, const double* red, const int32_t*, double* A, double* G, double* R,
-                       double* C1, const double* BT, const double* UU, double* cA, double* cB, double* gam,
-                       double* Fn, int32_t* active, int32_t* nu_eff, double tau, hipStream_t s) {
+LaunchInfo launch_coef(int B, int nu, int n, const double* red, double* A, double* G, double* R, double* C1,
+                       const double* BT, const double* UU, double* cA, double* cB, float* cAf, float* cBf,
+                       double* gam, double* Fn, int32_t* active, int32_t* nu_eff, double tau, hipStream_t s) {
     const size_t lds = (size_t)(7 * (nu + 1) + 8) * sizeof(double);
-    hipLaunchKernelGGL(k_coef, dim3(B), dim3(WG), lds, s, B, nu, n, red, A, G, R, C1, BT, UU, cA, cB, gam, Fn, active,
-                       nu_eff, tau);
+    hipLaunchKernelGGL(k_coef, dim3(B), dim3(WG), lds, s, B, nu, n, red, A, G, R, C1, BT, UU, cA, cB, cAf, cBf, gam,
+                       Fn, active, nu_eff, tau);
     LaunchInfo li;
     li.wgs = B;
     const double nn = (double)n + 1.0;

@@ -103,10 +103,32 @@ size_t eig_lds_bytes(int nu, int max_row, bool a_in_lds) {
 
 bool eig_a_fits_lds(int nu, int max_row) { return eig_lds_bytes(nu, max_row, true) <= 160 * 1024; }
 
-template <typename T, bool LDS_A>
-__global__ __launch_bounds__(WG) void k_eig(int nseeds, const int32_t* __restrict__ seeds, int B, int nu,
+// Rows K[P(j), :] of each seed, gathered from the seed-interleaved basis into
+// Kp[(b * nu + k) * max_row + t] (FP64), with the seed's nu_eff copied beside
+// them, so that the eigensolve can run while the basis is reused.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_gather_rows(int nseeds, const int32_t* __restrict__ seeds, int B, int nu,
+                                                    const int32_t* __restrict__ nu_eff_blk, const T* __restrict__ K,
+                                                    int64_t M, const int32_t* __restrict__ Hrp,
+                                                    const int32_t* __restrict__ Hcol, int max_row,
+                                                    double* __restrict__ Kp, int32_t* __restrict__ nu_copy) {
+    const int b = blockIdx.x;
+    if (b >= nseeds) return;
+    const int m = nu_eff_blk[b];
+    if (threadIdx.x == 0) nu_copy[b] = m;
+    if (m <= 0) return;
+    const int j = seeds[b];
+    const int rlo = Hrp[j], nP = Hrp[j + 1] - rlo;
+    for (int idx = threadIdx.x; idx < m * nP; idx += WG) {
+        const int k = idx / nP, t = idx - k * nP;
+        Kp[((int64_t)b * nu + k) * max_row + t] = (double)K[((int64_t)k * M + Hcol[rlo + t]) * B + b];
+    }
+}
+
+template <bool LDS_A>
+__global__ __launch_bounds__(WG) void k_eig(int nseeds, const int32_t* __restrict__ seeds, int nu,
                                             double* __restrict__ h, const int32_t* __restrict__ nu_eff_blk,
-                                            const T* __restrict__ K, int64_t M, const int32_t* __restrict__ Hrp,
+                                            const double* __restrict__ Kp, const int32_t* __restrict__ Hrp,
                                             const int32_t* __restrict__ Hcol, const double* __restrict__ Hval,
                                             const double* __restrict__ SvalH, const double* __restrict__ diagS,
                                             int max_row, double mu, double kT, double* __restrict__ rho,
@@ -178,7 +200,7 @@ __global__ __launch_bounds__(WG) void k_eig(int nseeds, const int32_t* __restric
     // R = [e_1 | K[P(j), :]^T]
     for (int idx = tid; idx < m * NR; idx += WG) {
         const int k = idx / NR, c = idx - k * NR;
-        R[idx] = c == 0 ? (k == 0 ? 1.0 : 0.0) : (double)K[((int64_t)k * M + Hcol[rlo + c - 1]) * B + b];
+        R[idx] = c == 0 ? (k == 0 ? 1.0 : 0.0) : Kp[((int64_t)b * nu + k) * max_row + (c - 1)];
     }
     if (tid < nP && Hcol[rlo + tid] == j) *tjp = tid;
     __syncthreads();
@@ -298,59 +320,63 @@ __global__ __launch_bounds__(WG) void k_eig(int nseeds, const int32_t* __restric
     }
 }
 
-template <typename T>
-static LaunchInfo launch_eig_t(int B, int nseeds, const int32_t* seeds, int nu, double* h, const int32_t* nu_eff_blk,
-                               const T* K, int64_t M, const int32_t* Hrp, const int32_t* Hcol, const double* Hval,
-                               const double* SvalH, const double* diagS, int max_row, double mu, double kT,
-                               double* rho, double* e_seed, double* n_seed, int32_t* nu_eff_out, double* eps_out,
-                               double* w_out, hipStream_t s) {
+LaunchInfo launch_eig(int nseeds, const int32_t* seeds, int nu, double* h, const int32_t* nu_eff_blk,
+                      const double* Kp, const int32_t* Hrp, const int32_t* Hcol, const double* Hval,
+                      const double* SvalH, const double* diagS, int max_row, double mu, double kT, double* rho,
+                      double* e_seed, double* n_seed, int32_t* nu_eff_out, double* eps_out, double* w_out,
+                      hipStream_t s) {
     const bool lds_a = eig_a_fits_lds(nu, max_row);
     const size_t lds = eig_lds_bytes(nu, max_row, lds_a);
     if (lds_a) {
         static bool attr = false;
         if (!attr) {
-            hipFuncSetAttribute((const void*)k_eig<T, true>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            hipFuncSetAttribute((const void*)k_eig<true>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
             attr = true;
         }
-        hipLaunchKernelGGL((k_eig<T, true>), dim3(nseeds), dim3(WG), lds, s, nseeds, seeds, B, nu, h, nu_eff_blk, K,
-                           M, Hrp, Hcol, Hval, SvalH, diagS, max_row, mu, kT, rho, e_seed, n_seed, nu_eff_out,
-                           eps_out, w_out);
+        hipLaunchKernelGGL((k_eig<true>), dim3(nseeds), dim3(WG), lds, s, nseeds, seeds, nu, h, nu_eff_blk, Kp, Hrp,
+                           Hcol, Hval, SvalH, diagS, max_row, mu, kT, rho, e_seed, n_seed, nu_eff_out, eps_out, w_out);
     } else {
         static bool attr = false;
         if (!attr) {
-            hipFuncSetAttribute((const void*)k_eig<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            hipFuncSetAttribute((const void*)k_eig<false>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
             attr = true;
         }
-        hipLaunchKernelGGL((k_eig<T, false>), dim3(nseeds), dim3(WG), lds, s, nseeds, seeds, B, nu, h, nu_eff_blk, K,
-                           M, Hrp, Hcol, Hval, SvalH, diagS, max_row, mu, kT, rho, e_seed, n_seed, nu_eff_out,
-                           eps_out, w_out);
+        hipLaunchKernelGGL((k_eig<false>), dim3(nseeds), dim3(WG), lds, s, nseeds, seeds, nu, h, nu_eff_blk, Kp,
+                           Hrp, Hcol, Hval, SvalH, diagS, max_row, mu, kT, rho, e_seed, n_seed, nu_eff_out, eps_out,
+                           w_out);
     }
     LaunchInfo li;
     li.wgs = nseeds;
     const double nv = (double)nu;
-    li.bytes = (double)nseeds * (nv * nv * 8.0 + nv * (max_row + 1) * sizeof(T) + (max_row + 3) * 8.0 * 3);
+    li.bytes = (double)nseeds * (nv * nv * 8.0 + nv * max_row * 8.0 + (max_row + 3) * 8.0 * 3);
     li.flops = (double)nseeds * ((4.0 / 3.0) * nv * nv * nv + 4.0 * nv * nv * (max_row + 1));
     return li;
 }
 
-template <>
-LaunchInfo launch_eig<float>(int B, int nseeds, const int32_t* seeds, int nu, double* h, const int32_t* nu_eff_blk,
-                             const float* K, int64_t M, const int32_t* Hrp, const int32_t* Hcol, const double* Hval,
-                             const double* SvalH, const double* diagS, int max_row, double mu, double kT, double* rho,
-                             double* e_seed, double* n_seed, int32_t* nu_eff_out, double* eps_out, double* w_out,
-                             hipStream_t s) {
-    return launch_eig_t<float>(B, nseeds, seeds, nu, h, nu_eff_blk, K, M, Hrp, Hcol, Hval, SvalH, diagS, max_row, mu,
-                               kT, rho, e_seed, n_seed, nu_eff_out, eps_out, w_out, s);
+template <typename T>
+static LaunchInfo launch_gather_t(int B, int nseeds, const int32_t* seeds, int nu, const int32_t* nu_eff_blk,
+                                  const T* K, int64_t M, const int32_t* Hrp, const int32_t* Hcol, int max_row,
+                                  double* Kp, int32_t* nu_copy, hipStream_t s) {
+    hipLaunchKernelGGL((k_gather_rows<T>), dim3(nseeds), dim3(WG), 0, s, nseeds, seeds, B, nu, nu_eff_blk, K, M, Hrp,
+                       Hcol, max_row, Kp, nu_copy);
+    LaunchInfo li;
+    li.wgs = nseeds;
+    li.bytes = (double)nseeds * nu * max_row * (sizeof(T) + 8.0);
+    return li;
 }
 
 template <>
-LaunchInfo launch_eig<double>(int B, int nseeds, const int32_t* seeds, int nu, double* h, const int32_t* nu_eff_blk,
-                              const double* K, int64_t M, const int32_t* Hrp, const int32_t* Hcol,
-                              const double* Hval, const double* SvalH, const double* diagS, int max_row, double mu,
-                              double kT, double* rho, double* e_seed, double* n_seed, int32_t* nu_eff_out,
-                              double* eps_out, double* w_out, hipStream_t s) {
-    return launch_eig_t<double>(B, nseeds, seeds, nu, h, nu_eff_blk, K, M, Hrp, Hcol, Hval, SvalH, diagS, max_row,
-                                mu, kT, rho, e_seed, n_seed, nu_eff_out, eps_out, w_out, s);
+LaunchInfo launch_gather<float>(int B, int nseeds, const int32_t* seeds, int nu, const int32_t* nu_eff_blk,
+                                const float* K, int64_t M, const int32_t* Hrp, const int32_t* Hcol, int max_row,
+                                double* Kp, int32_t* nu_copy, hipStream_t s) {
+    return launch_gather_t<float>(B, nseeds, seeds, nu, nu_eff_blk, K, M, Hrp, Hcol, max_row, Kp, nu_copy, s);
+}
+
+template <>
+LaunchInfo launch_gather<double>(int B, int nseeds, const int32_t* seeds, int nu, const int32_t* nu_eff_blk,
+                                 const double* K, int64_t M, const int32_t* Hrp, const int32_t* Hcol, int max_row,
+                                 double* Kp, int32_t* nu_copy, hipStream_t s) {
+    return launch_gather_t<double>(B, nseeds, seeds, nu, nu_eff_blk, K, M, Hrp, Hcol, max_row, Kp, nu_copy, s);
 }
 
 }  // namespace mar

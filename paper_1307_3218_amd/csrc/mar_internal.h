@@ -74,25 +74,31 @@ LaunchInfo launch_upd(int B, const T* basis, int64_t M, int nk, const double* c,
 template <typename T>
 LaunchInfo launch_append(int B, int64_t M, const T* W, const T* Z, const double* beta,
                          const int32_t* active, T* Kn, T* SKn, hipStream_t s);
+// Rows K[P(j), :] of the block's seeds into Kp[(b * nu + k) * max_row + t] (FP64) and nu_eff into nu_copy.
 template <typename T>
-LaunchInfo launch_eig(int B, int nseeds, const int32_t* seeds, int nu, double* h, const int32_t* nu_eff_blk,
-                      const T* K, int64_t M, const int32_t* Hrp, const int32_t* Hcol, const double* Hval,
-                      const double* SvalH, const double* diagS, int max_row, double mu, double kT,
-                      double* rho, double* e_seed, double* n_seed, int32_t* nu_eff_out, double* eps_out,
-                      double* w_out, hipStream_t s);
+LaunchInfo launch_gather(int B, int nseeds, const int32_t* seeds, int nu, const int32_t* nu_eff_blk, const T* K,
+                         int64_t M, const int32_t* Hrp, const int32_t* Hcol, int max_row, double* Kp,
+                         int32_t* nu_copy, hipStream_t s);
+LaunchInfo launch_eig(int nseeds, const int32_t* seeds, int nu, double* h, const int32_t* nu_eff_blk,
+                      const double* Kp, const int32_t* Hrp, const int32_t* Hcol, const double* Hval,
+                      const double* SvalH, const double* diagS, int max_row, double mu, double kT, double* rho,
+                      double* e_seed, double* n_seed, int32_t* nu_eff_out, double* eps_out, double* w_out,
+                      hipStream_t s);
 
 // Delayed-reorthogonalization schedule.
 template <typename T>
 LaunchInfo launch_projr(int B, const T* basis, int64_t M, int nk, const T* r0, const T* r1, const T* r2,
                         double* part, int64_t* ngroups, int target_wgs, hipStream_t s);
+// cA/cB: [n][B] coefficients in the basis precision T.
 template <typename T>
-LaunchInfo launch_upd2(int B, T* basis, int64_t M, int n, const double* cA, const double* cB, const double* gam,
+LaunchInfo launch_upd2(int B, T* basis, int64_t M, int n, const T* cA, const T* cB, const double* gam,
                        const double* Fn, T* y, bool want_w, hipStream_t s);
 template <typename T>
 LaunchInfo launch_append2(int B, int64_t M, const T* W, const T* Z, const double* beta, const int32_t* active,
                           T* Kn, T* ZT, hipStream_t s);
-LaunchInfo launch_coef(int B, int nu, int n, const double* red, const int32_t* active_in, double* A, double* G,
-                       double* R, double* C1, const double* BT, const double* UU, double* cA, double* cB,
+// cAf/cBf (optional): the update coefficients rounded to FP32 for an FP32 basis.
+LaunchInfo launch_coef(int B, int nu, int n, const double* red, double* A, double* G, double* R, double* C1,
+                       const double* BT, const double* UU, double* cA, double* cB, float* cAf, float* cBf,
                        double* gam, double* Fn, int32_t* active, int32_t* nu_eff, double tau, hipStream_t s);
 LaunchInfo launch_norm2(int B, int nu, int n, const double* redb, const double* C1, double tau, int32_t* active,
                         int32_t* nu_eff, double* BT, double* UU, hipStream_t s);

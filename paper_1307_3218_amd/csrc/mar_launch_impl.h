@@ -445,12 +445,13 @@ __global__ __launch_bounds__(WG) void k_projr(const T* __restrict__ basis, int64
 // Dual update of the delayed schedule, one pass over slabs 0..n-1:
 //   u_n = (u~ - sum_k K_k cA_k) / gamma       (second Gram-Schmidt pass of u~)
 //   w'  = (y  - sum_k K_k cB_k - u_n F_n) / gamma   (first pass of y = H u~)
-// u~ is slab n and is overwritten by u_n; y is overwritten by w' (if want_w).
+// u~ is slab n and is overwritten by u_n; y is overwritten by w' (WANT_W).
+// The coefficients are [k][B] in the basis precision: one 16-byte load per
+// lane and slab for each of cA, cB when B >= VEC.
 template <typename T, int B, int Q, bool WANT_W>
-__global__ __launch_bounds__(WG) void k_upd2(T* __restrict__ basis, int64_t slab, int n,
-                                             const double* __restrict__ cA, const double* __restrict__ cB,
-                                             const double* __restrict__ gam, const double* __restrict__ Fn,
-                                             T* __restrict__ y, int64_t nvec) {
+__global__ __launch_bounds__(WG) void k_upd2(T* __restrict__ basis, int64_t slab, int n, const T* __restrict__ cA,
+                                             const T* __restrict__ cB, const double* __restrict__ gam,
+                                             const double* __restrict__ Fn, T* __restrict__ y, int64_t nvec) {
     using SM = SeedMap<T, B>;
     constexpr int VEC = SM::VEC, P = SM::P;
     using VT = typename Vec16<T>::type;
@@ -474,11 +475,15 @@ __global__ __launch_bounds__(WG) void k_upd2(T* __restrict__ basis, int64_t slab
     }
     for (int k = 0; k < n; ++k) {
         T ca[VEC], cb[VEC];
+        if constexpr (B >= VEC) {
+            unpack(reinterpret_cast<const VT*>(cA + (int64_t)k * B + sb)[0], ca);
+            if constexpr (WANT_W) unpack(reinterpret_cast<const VT*>(cB + (int64_t)k * B + sb)[0], cb);
+        } else {
 #pragma unroll
-        for (int i = 0; i < VEC; ++i) {
-            const int b = (B < VEC) ? (i % B) : (sb + i);
-            ca[i] = (T)cA[(int64_t)k * B + b];
-            if constexpr (WANT_W) cb[i] = (T)cB[(int64_t)k * B + b];
+            for (int i = 0; i < VEC; ++i) {
+                ca[i] = cA[(int64_t)k * B + i % B];
+                if constexpr (WANT_W) cb[i] = cB[(int64_t)k * B + i % B];
+            }
         }
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
@@ -692,17 +697,17 @@ LaunchInfo launch_projr<MAR_T>(int B, const MAR_T* basis, int64_t M, int nk, con
 }
 
 template <>
-LaunchInfo launch_upd2<MAR_T>(int B, MAR_T* basis, int64_t M, int n, const double* cA, const double* cB,
+LaunchInfo launch_upd2<MAR_T>(int B, MAR_T* basis, int64_t M, int n, const MAR_T* cA, const MAR_T* cB,
                               const double* gam, const double* Fn, MAR_T* y, bool want_w, hipStream_t s) {
     constexpr int VEC = Vec16<MAR_T>::n;
     const int64_t nvec = M * B / VEC;
-    const bool big = nvec >= (int64_t)WG * 4 * 1024;
-    const int Q = big ? 4 : 1;
+    const bool big = nvec >= (int64_t)WG * 8 * 1024;
+    const int Q = big ? 8 : 1;
     const int64_t wgs = (nvec + WG * Q - 1) / (WG * Q);
 #define MAR_UPD2(QQ, WW) \
     MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_upd2<MAR_T, BB, QQ, WW>), dim3(wgs), dim3(WG), 0, s, basis, M * B, n, cA, cB, gam, Fn, y, nvec))
     if (big) {
-        if (want_w) { MAR_UPD2(4, true); } else { MAR_UPD2(4, false); }
+        if (want_w) { MAR_UPD2(8, true); } else { MAR_UPD2(8, false); }
     } else {
         if (want_w) { MAR_UPD2(1, true); } else { MAR_UPD2(1, false); }
     }
