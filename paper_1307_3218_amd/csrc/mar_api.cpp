@@ -63,10 +63,9 @@ struct mar_ctx {
     char* io = nullptr;
     size_t io_bytes = 0;
     hipStream_t stream = nullptr;
-    hipStream_t side = nullptr;          // eigensolves of finished seed blocks overlap the next block here
-    hipEvent_t ev_rows[2] = {nullptr, nullptr}, ev_eig[2] = {nullptr, nullptr};
     std::string err;
     bool prof = false;
+    bool refused = false;   // a launcher refused to run in the current solve
     std::vector<ProfRec> recs;
     std::vector<hipEvent_t> evfree;
     mar_prof_entry agg[MAR_PROF_CLASSES];
@@ -81,11 +80,6 @@ struct mar_ctx {
         for (void* p : allocs) hipFree(p);
         if (ws) hipFree(ws);
         if (io) hipFree(io);
-        for (int p = 0; p < 2; ++p) {
-            if (ev_rows[p]) hipEventDestroy(ev_rows[p]);
-            if (ev_eig[p]) hipEventDestroy(ev_eig[p]);
-        }
-        if (side) hipStreamDestroy(side);
         if (stream) hipStreamDestroy(stream);
     }
 };
@@ -238,16 +232,20 @@ hipEvent_t get_event(mar_ctx* c) {
     return e;
 }
 
+// Runs one launcher; a launcher that refuses (partial-sum buffer too small)
+// marks the solve as failed, and no later kernel of the solve is enqueued.
 template <class F>
 void launch(mar_ctx* c, hipStream_t s, int cls, F&& f) {
+    if (c->refused) return;
     if (!c->prof) {
-        f();
+        if (f().wgs < 0) c->refused = true;
         return;
     }
     hipEvent_t a = get_event(c), b = get_event(c);
     hipEventRecord(a, s);
     LaunchInfo li = f();
     hipEventRecord(b, s);
+    if (li.wgs < 0) c->refused = true;
     c->recs.push_back({cls, a, b, li.bytes, li.flops});
 }
 
@@ -265,11 +263,10 @@ int choose_block(const mar_ctx* c, int nu, mar_precision prec, int64_t n_seeds) 
     if (c->tune.seed_block > 0) {
         B = std::min(c->tune.seed_block, bmax);
     } else {
-        B = 64;
-        // small matrices: widen the block so one slab streams at least 4M elements
-        while ((int64_t)B < bmax && c->M * B < (int64_t)(1 << 22)) B *= 2;
-        // keep K and S*K within 96 GB
-        while (B > 1 && 2.0 * nu * (double)c->M * B * p > 96e9) B /= 2;
+        // the widest block: one pass over a slab serves the most seeds and the
+        // matrix values are reused B times; keep the basis within 128 GB
+        B = bmax;
+        while (B > 1 && 2.0 * nu * (double)c->M * B * p > 128e9) B /= 2;
         if (n_seeds > 0) B = std::min<int64_t>(B, pow2_floor(std::max<int64_t>(1, n_seeds)) * 2);
         B = std::min(B, bmax);
     }
@@ -277,6 +274,13 @@ int choose_block(const mar_ctx* c, int nu, mar_precision prec, int64_t n_seeds) 
 }
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Elements between consecutive basis slabs: M*B plus a pad, so that the
+// same row of different slabs need not sit at a power-of-two distance.
+int64_t slab_stride(const mar_ctx* c, int64_t Mp, int B, size_t elem) {
+    const int64_t pad_bytes = (int64_t)(c->tune.slab_pad_kb > 0 ? c->tune.slab_pad_kb : 0) * 1024;
+    return Mp * B + pad_bytes / (int64_t)elem;
+}
 
 mar_status ensure_ws(mar_ctx* c, size_t bytes) {
     if (bytes <= c->ws_bytes) return MAR_OK;
@@ -307,6 +311,7 @@ mar_status run_solve(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds, int nu
     const int P = B < VEC ? 1 : B / VEC;
     const int64_t spmm_wgs = std::max((c->S.n * P + mar::WG - 1) / mar::WG, (c->H.n * P + mar::WG - 1) / mar::WG);
     const size_t slab = (size_t)M * B * sizeof(T);
+    const int64_t stride = slab_stride(c, M, B, sizeof(T));
 
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -314,9 +319,10 @@ mar_status run_solve(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds, int nu
         off += align_up(bytes);
         return o;
     };
-    const size_t oK = take((size_t)nu * slab), oSK = take((size_t)nu * slab);
+    const size_t oK = take((size_t)nu * stride * sizeof(T)), oSK = take((size_t)nu * stride * sizeof(T));
     const size_t oW = take(slab), oZ = take(slab);
-    const size_t oPart = take(std::max<size_t>((size_t)chunks * 2 * nu * B, (size_t)spmm_wgs * B) * 8);
+    const int64_t part_cap = (int64_t)std::max<size_t>((size_t)chunks * 2 * nu * B, (size_t)spmm_wgs * B);
+    const size_t oPart = take((size_t)part_cap * 8);
     const size_t oRed1 = take((size_t)2 * nu * B * 8), oRed2 = take((size_t)nu * B * 8), oRedb = take((size_t)B * 8);
     const size_t oH = take((size_t)B * nu * nu * 8), oBeta = take((size_t)B * 8);
     const size_t oAct = take((size_t)B * 4), oNu = take((size_t)B * 4);
@@ -334,7 +340,7 @@ mar_status run_solve(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds, int nu
     double* n_seed = own_n ? (double*)(w + oN) : d_n_seed;
     int32_t* nu_out = own_nu ? (int32_t*)(w + oNuOut) : d_nu_eff;
     const double tau = sizeof(T) == 4 ? 1e-5 : 1e-12;
-    const int64_t slab_el = M * B;
+    const int64_t slab_el = stride;
 
     for (int64_t blk0 = 0; blk0 < n_seeds; blk0 += B) {
         const int ns = (int)std::min<int64_t>(B, n_seeds - blk0);
@@ -348,34 +354,35 @@ mar_status run_solve(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds, int nu
         launch(c, s, P_INIT, [&] {
             return mar::launch_init<T>(B, M, c->M, seeds, ns, c->diagS, nu, ws.K, ws.active, ws.nu_eff, nullptr, s);
         });
-        launch(c, s, P_SPMM, [&] { return mar::launch_spmm<T>(B, c->S, ws.K, ws.SK, nullptr, 0, s); });
+        launch(c, s, P_SPMM, [&] { return mar::launch_spmm<T>(B, c->S, ws.K, ws.SK, nullptr, 0, 0, s); });
         for (int n = 0; n < nu; ++n) {
             const T* Kn = ws.K + (size_t)n * slab_el;
             const int nk = n + 1;
             const bool last = n + 1 == nu;
-            launch(c, s, P_SPMM, [&] { return mar::launch_spmm<T>(B, c->H, Kn, ws.W, nullptr, 0, s); });
+            launch(c, s, P_SPMM, [&] { return mar::launch_spmm<T>(B, c->H, Kn, ws.W, nullptr, 0, 0, s); });
             // h[:, n] = K^T w and c1 = (S K)^T w in one pass over K and S K
             int64_t nch = 0;
             launch(c, s, last ? P_PROJ1 : P_PROJ2, [&] {
-                return mar::launch_proj<T>(B, last ? 1 : 2, ws.K, ws.SK, M, nk, ws.W, ws.part, &nch, s);
+                return mar::launch_proj<T>(B, last ? 1 : 2, ws.K, ws.SK, M, stride, nk, ws.W, ws.part, part_cap,
+                                           &nch, s);
             });
             const int64_t L1 = (int64_t)(last ? 1 : 2) * nk * B;
             launch(c, s, P_REDUCE, [&] { return mar::launch_reduce(ws.part, nch, L1, ws.red1, ws.h, B, nu, n, s); });
             if (last) break;
             const double* c1 = ws.red1 + (size_t)nk * B;
             // CGS pass 1: w -= K c1
-            launch(c, s, P_UPD, [&] { return mar::launch_upd<T>(B, ws.K, M, nk, c1, ws.W, s); });
+            launch(c, s, P_UPD, [&] { return mar::launch_upd<T>(B, ws.K, M, stride, nk, c1, ws.W, s); });
             // CGS pass 2: c2 = (S K)^T w, w -= K c2
             launch(c, s, P_PROJ1, [&] {
-                return mar::launch_proj<T>(B, 1, ws.SK, nullptr, M, nk, ws.W, ws.part, &nch, s);
+                return mar::launch_proj<T>(B, 1, ws.SK, nullptr, M, stride, nk, ws.W, ws.part, part_cap, &nch, s);
             });
             const int64_t L2 = (int64_t)nk * B;
             launch(c, s, P_REDUCE, [&] { return mar::launch_reduce(ws.part, nch, L2, ws.red2, nullptr, B, nu, n, s); });
-            launch(c, s, P_UPD, [&] { return mar::launch_upd<T>(B, ws.K, M, nk, ws.red2, ws.W, s); });
+            launch(c, s, P_UPD, [&] { return mar::launch_upd<T>(B, ws.K, M, stride, nk, ws.red2, ws.W, s); });
             // z = S w and w^T S w
             int64_t swgs = 0;
             launch(c, s, P_SPMM_DOT, [&] {
-                LaunchInfo li = mar::launch_spmm<T>(B, c->S, ws.W, ws.Z, ws.part, 1, s);
+                LaunchInfo li = mar::launch_spmm<T>(B, c->S, ws.W, ws.Z, ws.part, 1, part_cap, s);
                 swgs = li.wgs;
                 return li;
             });
@@ -391,8 +398,8 @@ mar_status run_solve(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds, int nu
         double* Kp = (double*)(w + oKp);
         int32_t* nucp = (int32_t*)(w + oNuCp);
         launch(c, s, P_EIG, [&] {
-            return mar::launch_gather<T>(B, ns, seeds, nu, ws.nu_eff, ws.K, M, c->Hrp, c->Hcol, c->max_row, Kp, nucp,
-                                         s);
+            return mar::launch_gather<T>(B, ns, seeds, nu, ws.nu_eff, ws.K, stride, c->Hrp, c->Hcol, c->max_row, Kp,
+                                         nucp, s);
         });
         launch(c, s, P_EIG, [&] {
             return mar::launch_eig(ns, seeds, nu, ws.h, nucp, Kp, c->Hrp, c->Hcol, c->Hval, c->SvalH, c->diagS,
@@ -401,6 +408,10 @@ mar_status run_solve(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds, int nu
         });
     }
     launch(c, s, P_SUM, [&] { return mar::launch_sum(e_seed, n_seeds, d_e_band, s); });
+    if (c->refused) {
+        c->refused = false;
+        return set_err(c, MAR_ERR_STATE, "internal error: a partial-sum buffer was too small; solve not run");
+    }
     HIP_OR(c, hipGetLastError());
     return MAR_OK;
 }
@@ -418,17 +429,18 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     const int64_t M = (c->M + 3) / 4 * 4;
     const int64_t nvec = M * B / VEC;
     const int P = B < VEC ? 1 : B / VEC;
-    const int target = c->tune.proj_wgs > 0 ? c->tune.proj_wgs : 1024;
+    const int target = c->tune.proj_wgs > 0 ? c->tune.proj_wgs : mar::PROJR_WGS;
+    const int variant = c->tune.proj_variant;
     const int64_t spmm_wgs = std::max((c->S.n * P + mar::WG - 1) / mar::WG, (c->H.n * P + mar::WG - 1) / mar::WG);
     const int64_t ntiles = (nvec + mar::WG * mar::PROJR_Q - 1) / (mar::WG * mar::PROJR_Q);
     const size_t slab = (size_t)M * B * sizeof(T);
+    const int64_t stride = slab_stride(c, M, B, sizeof(T));
     size_t part_doubles = (size_t)spmm_wgs * 2 * B;
     for (int nk = 1; nk <= nu; ++nk) {
-        const int nks = (nk + mar::PROJR_KG - 1) / mar::PROJR_KG;
-        const int64_t tiles = mar::projr_tiles(ntiles, nks, target);
-        const int64_t groups = (ntiles + tiles - 1) / tiles;
-        part_doubles = std::max<size_t>(part_doubles, (size_t)groups * 3 * nk * B);
+        const mar::ProjrGeom gm = mar::projr_geometry(nvec, nk, variant, target);
+        part_doubles = std::max<size_t>(part_doubles, (size_t)gm.groups * 3 * nk * B);
     }
+    const int64_t part_cap = (int64_t)part_doubles;
 
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -436,13 +448,11 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
         off += align_up(bytes);
         return o;
     };
-    const size_t oK = take((size_t)nu * slab), oY = take(slab), oSY = take(slab), oZT = take(slab);
+    const size_t oK = take((size_t)nu * stride * sizeof(T)), oY = take(slab), oSY = take(slab), oZT = take(slab);
     const size_t oPart = take(part_doubles * 8);
     const size_t oRed = take((size_t)3 * nu * B * 8), oRedb = take((size_t)2 * B * 8);
-    const size_t oH0 = take((size_t)B * nu * nu * 8), oH1 = take((size_t)B * nu * nu * 8);
-    const size_t oG = take((size_t)B * nu * nu * 8);
-    const size_t kp_bytes = (size_t)B * nu * std::max(1, c->max_row) * 8;
-    const size_t oKp0 = take(kp_bytes), oKp1 = take(kp_bytes), oNc0 = take((size_t)B * 4), oNc1 = take((size_t)B * 4);
+    const size_t oH = take((size_t)B * nu * nu * 8), oG = take((size_t)B * nu * nu * 8);
+    const size_t oKp = take((size_t)B * nu * std::max(1, c->max_row) * 8), oNc = take((size_t)B * 4);
     const size_t oR = take((size_t)B * nu * (nu + 1) * 8), oC1 = take((size_t)B * nu * 8);
     const size_t oBT = take((size_t)B * 8), oUU = take((size_t)B * 8), oGam = take((size_t)B * 8),
                  oFn = take((size_t)B * 8);
@@ -462,9 +472,9 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     double* part = (double*)(w + oPart);
     double* red = (double*)(w + oRed);
     double* redb = (double*)(w + oRedb);
-    double* hbuf[2] = {(double*)(w + oH0), (double*)(w + oH1)};
-    double* kpbuf[2] = {(double*)(w + oKp0), (double*)(w + oKp1)};
-    int32_t* ncbuf[2] = {(int32_t*)(w + oNc0), (int32_t*)(w + oNc1)};
+    double* h = (double*)(w + oH);
+    double* Kp = (double*)(w + oKp);
+    int32_t* nucp = (int32_t*)(w + oNc);
     double* G = (double*)(w + oG);
     double* R = (double*)(w + oR);
     double* C1 = (double*)(w + oC1);
@@ -484,15 +494,11 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     double* n_seed = own_n ? (double*)(w + oN) : d_n_seed;
     int32_t* nu_out = own_nu ? (int32_t*)(w + oNuOut) : d_nu_eff;
     const double tau = sizeof(T) == 4 ? 1e-5 : 1e-12;
-    const int64_t slab_el = M * B;
+    const int64_t slab_el = stride;
 
     for (int64_t blk0 = 0; blk0 < n_seeds; blk0 += B) {
         const int ns = (int)std::min<int64_t>(B, n_seeds - blk0);
         const int32_t* seeds = d_seeds + blk0;
-        const int par = (int)((blk0 / B) & 1);
-        double* h = hbuf[par];
-        // the eigensolve of block i-2 (side stream) must be done with this parity's buffers
-        if (blk0 >= 2 * (int64_t)B) HIP_OR(c, hipStreamWaitEvent(s, c->ev_eig[par], 0));
         if (M != c->M && blk0 == 0) {
             // padded rows of Y, S y and S u~ must read as zero (spmm writes rows < M only)
             launch(c, s, P_INIT, [&] { return mar::launch_zero(Y, (int64_t)slab, s); });
@@ -502,16 +508,17 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
         launch(c, s, P_INIT, [&] {
             return mar::launch_init<T>(B, M, c->M, seeds, ns, c->diagS, nu, K, active, nu_blk, UU, s);
         });
-        launch(c, s, P_SPMM, [&] { return mar::launch_spmm<T>(B, c->S, K, ZT, nullptr, 0, s); });
+        launch(c, s, P_SPMM, [&] { return mar::launch_spmm<T>(B, c->S, K, ZT, nullptr, 0, 0, s); });
         for (int n = 0; n < nu; ++n) {
             T* Kn = K + (size_t)n * slab_el;
             const int nk = n + 1;
             const bool last = n + 1 == nu;
-            launch(c, s, P_SPMM, [&] { return mar::launch_spmm<T>(B, c->H, Kn, Y, nullptr, 0, s); });
-            launch(c, s, P_SPMM, [&] { return mar::launch_spmm<T>(B, c->S, Y, SY, nullptr, 0, s); });
+            launch(c, s, P_SPMM, [&] { return mar::launch_spmm<T>(B, c->H, Kn, Y, nullptr, 0, 0, s); });
+            launch(c, s, P_SPMM, [&] { return mar::launch_spmm<T>(B, c->S, Y, SY, nullptr, 0, 0, s); });
             int64_t ngroups = 0;
             launch(c, s, P_PROJR, [&] {
-                return mar::launch_projr<T>(B, K, M, nk, ZT, SY, Y, part, &ngroups, target, s);
+                return mar::launch_projr<T>(B, K, M, stride, nk, ZT, SY, Y, part, part_cap, &ngroups, target,
+                                            variant, s);
             });
             const int64_t L = (int64_t)3 * nk * B;
             launch(c, s, P_REDUCE, [&] { return mar::launch_reduce(part, ngroups, L, red, nullptr, B, nu, n, s); });
@@ -519,11 +526,13 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
                 return mar::launch_coef(B, nu, n, red, h, G, R, C1, BT, UU, cA, cB, cAf, cBf, gam, Fn, active,
                                         nu_blk, tau, s);
             });
-            launch(c, s, P_UPD2, [&] { return mar::launch_upd2<T>(B, K, M, n, cAT, cBT, gam, Fn, Y, !last, s); });
+            launch(c, s, P_UPD2, [&] {
+                return mar::launch_upd2<T>(B, K, M, stride, n, cAT, cBT, gam, Fn, Y, !last, s);
+            });
             if (last) break;
             int64_t swgs = 0;
             launch(c, s, P_SPMM_DOT, [&] {
-                LaunchInfo li = mar::launch_spmm<T>(B, c->S, Y, SY, part, 2, s);
+                LaunchInfo li = mar::launch_spmm<T>(B, c->S, Y, SY, part, 2, part_cap, s);
                 swgs = li.wgs;
                 return li;
             });
@@ -535,26 +544,22 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
                 return mar::launch_append2<T>(B, M, Y, SY, BT, active, K + (size_t)(n + 1) * slab_el, ZT, s);
             });
         }
-        // rows K[P(j), :] leave the basis here; the eigensolve runs on the side
-        // stream while the next block reuses the basis
+        // rows K[P(j), :] leave the basis, then the subspace eigensolve and assembly
         launch(c, s, P_EIG, [&] {
-            return mar::launch_gather<T>(B, ns, seeds, nu, nu_blk, K, M, c->Hrp, c->Hcol, c->max_row, kpbuf[par],
-                                         ncbuf[par], s);
+            return mar::launch_gather<T>(B, ns, seeds, nu, nu_blk, K, stride, c->Hrp, c->Hcol, c->max_row, Kp, nucp,
+                                         s);
         });
-        HIP_OR(c, hipEventRecord(c->ev_rows[par], s));
-        HIP_OR(c, hipStreamWaitEvent(c->side, c->ev_rows[par], 0));
-        launch(c, c->side, P_EIG, [&] {
-            return mar::launch_eig(ns, seeds, nu, h, ncbuf[par], kpbuf[par], c->Hrp, c->Hcol, c->Hval, c->SvalH,
-                                   c->diagS, c->max_row, mu, kT, d_rho, e_seed + blk0, n_seed + blk0, nu_out + blk0,
-                                   d_eps ? d_eps + blk0 * nu : nullptr, d_w ? d_w + blk0 * nu : nullptr, c->side);
+        launch(c, s, P_EIG, [&] {
+            return mar::launch_eig(ns, seeds, nu, h, nucp, Kp, c->Hrp, c->Hcol, c->Hval, c->SvalH, c->diagS,
+                                   c->max_row, mu, kT, d_rho, e_seed + blk0, n_seed + blk0, nu_out + blk0,
+                                   d_eps ? d_eps + blk0 * nu : nullptr, d_w ? d_w + blk0 * nu : nullptr, s);
         });
-        HIP_OR(c, hipEventRecord(c->ev_eig[par], c->side));
-    }
-    if (n_seeds > 0) {
-        HIP_OR(c, hipStreamWaitEvent(s, c->ev_eig[0], 0));
-        HIP_OR(c, hipStreamWaitEvent(s, c->ev_eig[1], 0));
     }
     launch(c, s, P_SUM, [&] { return mar::launch_sum(e_seed, n_seeds, d_e_band, s); });
+    if (c->refused) {
+        c->refused = false;
+        return set_err(c, MAR_ERR_STATE, "internal error: a partial-sum buffer was too small; solve not run");
+    }
     HIP_OR(c, hipGetLastError());
     return MAR_OK;
 }
@@ -617,7 +622,7 @@ mar_status mar_create(int64_t M, const int64_t* H_rowptr, const int32_t* H_col, 
     c->nnzH = H_rowptr[M];
     c->nnzS = S_rowptr[M];
     c->max_row = max_row;
-    c->tune = mar_tuning{0, 0, 0, 0};
+    c->tune = mar_tuning{0, 0, 0, 0, 0, 0, 0, 0};
     for (int k = 0; k < MAR_PROF_CLASSES; ++k) {
         std::memset(&c->agg[k], 0, sizeof(mar_prof_entry));
         if (k < P_COUNT) std::snprintf(c->agg[k].name, sizeof c->agg[k].name, "%s", kProfNames[k]);
@@ -637,13 +642,8 @@ mar_status mar_create(int64_t M, const int64_t* H_rowptr, const int32_t* H_col, 
     if ((st = upload(c, &c->SvalH, svalH.data(), svalH.size())) != MAR_OK) return fail(st);
     if ((st = upload(c, &c->diagS, diag.data(), diag.size())) != MAR_OK) return fail(st);
     he = hipStreamCreate(&c->stream);
-    if (he == hipSuccess) he = hipStreamCreate(&c->side);
-    for (int p = 0; p < 2 && he == hipSuccess; ++p) {
-        he = hipEventCreateWithFlags(&c->ev_rows[p], hipEventDisableTiming);
-        if (he == hipSuccess) he = hipEventCreateWithFlags(&c->ev_eig[p], hipEventDisableTiming);
-    }
     if (he != hipSuccess) {
-        c->err = fmt("stream/event creation failed: %s", hipGetErrorString(he));
+        c->err = fmt("stream creation failed: %s", hipGetErrorString(he));
         return fail(MAR_ERR_HIP);
     }
     *out = c;
@@ -665,6 +665,7 @@ mar_status mar_solve_async(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds, 
     if (!d_e_band) return set_err(c, MAR_ERR_ARG, "e_band output is NULL");
     if (n_seeds > 0 && (!d_seeds || !d_rho)) return set_err(c, MAR_ERR_ARG, "seeds or rho is NULL");
     HIP_OR(c, hipSetDevice(c->device));
+    c->refused = false;
     hipStream_t s = (hipStream_t)hip_stream;
     const int B = form == MAR_FORM_PLAIN ? 1 : choose_block(c, nu, prec, n_seeds);
     // schedule: the plain form is the textbook CGS2 (project, update, project,
@@ -751,7 +752,7 @@ mar_status mar_solve(mar_ctx* c, const int32_t* seeds, int64_t n_seeds, int32_t 
 mar_status mar_set_tuning(mar_ctx* c, const mar_tuning* t) {
     if (!c) return MAR_ERR_STATE;
     if (!t) {
-        c->tune = mar_tuning{0, 0, 0, 0};
+        c->tune = mar_tuning{0, 0, 0, 0, 0, 0, 0, 0};
         return MAR_OK;
     }
     if (t->seed_block < 0 || t->seed_block > 256 || (t->seed_block & (t->seed_block - 1)) != 0)
@@ -759,6 +760,8 @@ mar_status mar_set_tuning(mar_ctx* c, const mar_tuning* t) {
     if (t->schedule < MAR_SCHED_AUTO || t->schedule > MAR_SCHED_DELAYED)
         return set_err(c, MAR_ERR_ARG, "unknown schedule");
     if (t->proj_wgs < 0) return set_err(c, MAR_ERR_ARG, "proj_wgs < 0");
+    if (t->slab_pad_kb < 0 || t->slab_pad_kb > 65536) return set_err(c, MAR_ERR_ARG, "slab_pad_kb outside [0, 65536]");
+    if (t->proj_variant < 0 || t->proj_variant > 2) return set_err(c, MAR_ERR_ARG, "proj_variant outside [0, 2]");
     c->tune = *t;
     return MAR_OK;
 }

@@ -16,6 +16,18 @@ __device__ __forceinline__ void unpack(const double2& v, double (&a)[2]) { a[0] 
 __device__ __forceinline__ float4 pack(const float (&a)[4]) { return make_float4(a[0], a[1], a[2], a[3]); }
 __device__ __forceinline__ double2 pack(const double (&a)[2]) { return make_double2(a[0], a[1]); }
 
+// Non-temporal 16-byte loads (streamed data that should not displace reused lines in L2).
+typedef float nf4 __attribute__((ext_vector_type(4)));
+typedef double nd2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void unpack_nt(const float4* p, float (&a)[4]) {
+    const nf4 v = __builtin_nontemporal_load(reinterpret_cast<const nf4*>(p));
+    a[0] = v.x; a[1] = v.y; a[2] = v.z; a[3] = v.w;
+}
+__device__ __forceinline__ void unpack_nt(const double2* p, double (&a)[2]) {
+    const nd2 v = __builtin_nontemporal_load(reinterpret_cast<const nd2*>(p));
+    a[0] = v.x; a[1] = v.y;
+}
+
 // Seed-interleaved vectors: element e of an [M][B] array belongs to row e / B
 // and seed e % B. A lane owns one 16-byte vector of VEC elements:
 //   B >= VEC: the vector covers seeds (lane_vector_index % P) * VEC + [0, VEC),

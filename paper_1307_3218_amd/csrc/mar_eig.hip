@@ -109,7 +109,7 @@ bool eig_a_fits_lds(int nu, int max_row) { return eig_lds_bytes(nu, max_row, tru
 template <typename T>
 __global__ __launch_bounds__(WG) void k_gather_rows(int nseeds, const int32_t* __restrict__ seeds, int B, int nu,
                                                     const int32_t* __restrict__ nu_eff_blk, const T* __restrict__ K,
-                                                    int64_t M, const int32_t* __restrict__ Hrp,
+                                                    int64_t stride, const int32_t* __restrict__ Hrp,
                                                     const int32_t* __restrict__ Hcol, int max_row,
                                                     double* __restrict__ Kp, int32_t* __restrict__ nu_copy) {
     const int b = blockIdx.x;
@@ -121,7 +121,7 @@ __global__ __launch_bounds__(WG) void k_gather_rows(int nseeds, const int32_t* _
     const int rlo = Hrp[j], nP = Hrp[j + 1] - rlo;
     for (int idx = threadIdx.x; idx < m * nP; idx += WG) {
         const int k = idx / nP, t = idx - k * nP;
-        Kp[((int64_t)b * nu + k) * max_row + t] = (double)K[((int64_t)k * M + Hcol[rlo + t]) * B + b];
+        Kp[((int64_t)b * nu + k) * max_row + t] = (double)K[(int64_t)k * stride + (int64_t)Hcol[rlo + t] * B + b];
     }
 }
 
@@ -355,9 +355,9 @@ LaunchInfo launch_eig(int nseeds, const int32_t* seeds, int nu, double* h, const
 
 template <typename T>
 static LaunchInfo launch_gather_t(int B, int nseeds, const int32_t* seeds, int nu, const int32_t* nu_eff_blk,
-                                  const T* K, int64_t M, const int32_t* Hrp, const int32_t* Hcol, int max_row,
+                                  const T* K, int64_t stride, const int32_t* Hrp, const int32_t* Hcol, int max_row,
                                   double* Kp, int32_t* nu_copy, hipStream_t s) {
-    hipLaunchKernelGGL((k_gather_rows<T>), dim3(nseeds), dim3(WG), 0, s, nseeds, seeds, B, nu, nu_eff_blk, K, M, Hrp,
+    hipLaunchKernelGGL((k_gather_rows<T>), dim3(nseeds), dim3(WG), 0, s, nseeds, seeds, B, nu, nu_eff_blk, K, stride, Hrp,
                        Hcol, max_row, Kp, nu_copy);
     LaunchInfo li;
     li.wgs = nseeds;
@@ -367,16 +367,16 @@ static LaunchInfo launch_gather_t(int B, int nseeds, const int32_t* seeds, int n
 
 template <>
 LaunchInfo launch_gather<float>(int B, int nseeds, const int32_t* seeds, int nu, const int32_t* nu_eff_blk,
-                                const float* K, int64_t M, const int32_t* Hrp, const int32_t* Hcol, int max_row,
+                                const float* K, int64_t stride, const int32_t* Hrp, const int32_t* Hcol, int max_row,
                                 double* Kp, int32_t* nu_copy, hipStream_t s) {
-    return launch_gather_t<float>(B, nseeds, seeds, nu, nu_eff_blk, K, M, Hrp, Hcol, max_row, Kp, nu_copy, s);
+    return launch_gather_t<float>(B, nseeds, seeds, nu, nu_eff_blk, K, stride, Hrp, Hcol, max_row, Kp, nu_copy, s);
 }
 
 template <>
 LaunchInfo launch_gather<double>(int B, int nseeds, const int32_t* seeds, int nu, const int32_t* nu_eff_blk,
-                                 const double* K, int64_t M, const int32_t* Hrp, const int32_t* Hcol, int max_row,
+                                 const double* K, int64_t stride, const int32_t* Hrp, const int32_t* Hcol, int max_row,
                                  double* Kp, int32_t* nu_copy, hipStream_t s) {
-    return launch_gather_t<double>(B, nseeds, seeds, nu, nu_eff_blk, K, M, Hrp, Hcol, max_row, Kp, nu_copy, s);
+    return launch_gather_t<double>(B, nseeds, seeds, nu, nu_eff_blk, K, stride, Hrp, Hcol, max_row, Kp, nu_copy, s);
 }
 
 }  // namespace mar

@@ -15,9 +15,26 @@ constexpr int PROJR_KG = 4;        // slabs owned by one workgroup in the delaye
 
 // Row tiles per workgroup of the delayed-schedule projection: as many as keep
 // the grid at about target_wgs workgroups (fewer partial sums), at least one.
-inline int64_t projr_tiles(int64_t ntiles, int nks, int target_wgs) {
-    const int64_t t = (ntiles * nks) / (target_wgs > 0 ? target_wgs : 1024);
-    return t < 1 ? 1 : (t > ntiles ? ntiles : t);
+constexpr int PROJR_WGS = 4096;    // default target grid of the delayed-schedule projection
+
+// Grid of the delayed-schedule projection for nk slabs of nvec vectors: KG
+// slabs per workgroup (nks splits), `tiles` row tiles per workgroup (as many
+// as keep the grid near target_wgs), `groups` row groups. The partial-sum
+// buffer needs groups * 3 * nk * B doubles. Used by the launcher and by the
+// workspace sizing, so that both always agree.
+struct ProjrGeom {
+    int kg, nks;
+    int64_t ntiles, tiles, groups;
+};
+inline ProjrGeom projr_geometry(int64_t nvec, int nk, int variant, int target_wgs) {
+    ProjrGeom g;
+    g.kg = variant == 1 ? 8 : 4;
+    g.nks = (nk + g.kg - 1) / g.kg;
+    g.ntiles = (nvec + WG * PROJR_Q - 1) / (WG * PROJR_Q);
+    int64_t t = (g.ntiles * g.nks) / (target_wgs > 0 ? target_wgs : PROJR_WGS);
+    g.tiles = t < 1 ? 1 : (t > g.ntiles ? g.ntiles : t);
+    g.groups = (g.ntiles + g.tiles - 1) / g.tiles;
+    return g;
 }
 
 // Device copy of one sparse matrix. BSR 4x4 (values [blk][r][c]) when the
@@ -56,7 +73,7 @@ struct BlockWS {
 // Every launcher returns the number of workgroups it launched (for partials)
 // and sets *bytes / *flops to the algorithmic traffic of the launch.
 struct LaunchInfo {
-    int64_t wgs = 0;
+    int64_t wgs = 0;    // -1: not launched, the partial-sum buffer is too small
     double bytes = 0, flops = 0;
 };
 
@@ -64,20 +81,24 @@ template <typename T>
 LaunchInfo launch_init(int B, int64_t Mp, int64_t M, const int32_t* seeds, int nseeds, const double* diagS,
                        int nu, T* K0, int32_t* active, int32_t* nu_eff, double* uu, hipStream_t s);
 // ndot = 0: Y = A X; 1: also partial sums of X.Y per seed; 2: X.Y and X.X (part[wg][d][b]).
+// part_cap: doubles available at part (checked before launch).
 template <typename T>
-LaunchInfo launch_spmm(int B, const DevMat& A, const T* X, T* Y, double* part, int ndot, hipStream_t s);
+LaunchInfo launch_spmm(int B, const DevMat& A, const T* X, T* Y, double* part, int ndot, int64_t part_cap,
+                       hipStream_t s);
 template <typename T>
-LaunchInfo launch_proj(int B, int ns, const T* b0, const T* b1, int64_t M, int nk, const T* x,
-                       double* part, int64_t* nchunks, hipStream_t s);
+// stride: elements between consecutive basis slabs (>= M * B).
+LaunchInfo launch_proj(int B, int ns, const T* b0, const T* b1, int64_t M, int64_t stride, int nk, const T* x,
+                       double* part, int64_t part_cap, int64_t* nchunks, hipStream_t s);
 template <typename T>
-LaunchInfo launch_upd(int B, const T* basis, int64_t M, int nk, const double* c, T* x, hipStream_t s);
+LaunchInfo launch_upd(int B, const T* basis, int64_t M, int64_t stride, int nk, const double* c, T* x,
+                      hipStream_t s);
 template <typename T>
 LaunchInfo launch_append(int B, int64_t M, const T* W, const T* Z, const double* beta,
                          const int32_t* active, T* Kn, T* SKn, hipStream_t s);
 // Rows K[P(j), :] of the block's seeds into Kp[(b * nu + k) * max_row + t] (FP64) and nu_eff into nu_copy.
 template <typename T>
 LaunchInfo launch_gather(int B, int nseeds, const int32_t* seeds, int nu, const int32_t* nu_eff_blk, const T* K,
-                         int64_t M, const int32_t* Hrp, const int32_t* Hcol, int max_row, double* Kp,
+                         int64_t stride, const int32_t* Hrp, const int32_t* Hcol, int max_row, double* Kp,
                          int32_t* nu_copy, hipStream_t s);
 LaunchInfo launch_eig(int nseeds, const int32_t* seeds, int nu, double* h, const int32_t* nu_eff_blk,
                       const double* Kp, const int32_t* Hrp, const int32_t* Hcol, const double* Hval,
@@ -87,12 +108,14 @@ LaunchInfo launch_eig(int nseeds, const int32_t* seeds, int nu, double* h, const
 
 // Delayed-reorthogonalization schedule.
 template <typename T>
-LaunchInfo launch_projr(int B, const T* basis, int64_t M, int nk, const T* r0, const T* r1, const T* r2,
-                        double* part, int64_t* ngroups, int target_wgs, hipStream_t s);
+// variant 0: 4 slabs per workgroup; 1: 8 slabs; 2: 4 slabs with non-temporal basis loads.
+LaunchInfo launch_projr(int B, const T* basis, int64_t M, int64_t stride, int nk, const T* r0, const T* r1,
+                        const T* r2, double* part, int64_t part_cap, int64_t* ngroups, int target_wgs, int variant,
+                        hipStream_t s);
 // cA/cB: [n][B] coefficients in the basis precision T.
 template <typename T>
-LaunchInfo launch_upd2(int B, T* basis, int64_t M, int n, const T* cA, const T* cB, const double* gam,
-                       const double* Fn, T* y, bool want_w, hipStream_t s);
+LaunchInfo launch_upd2(int B, T* basis, int64_t M, int64_t stride, int n, const T* cA, const T* cB,
+                       const double* gam, const double* Fn, T* y, bool want_w, hipStream_t s);
 template <typename T>
 LaunchInfo launch_append2(int B, int64_t M, const T* W, const T* Z, const double* beta, const int32_t* active,
                           T* Kn, T* ZT, hipStream_t s);

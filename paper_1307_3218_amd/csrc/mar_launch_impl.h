@@ -377,7 +377,7 @@ __global__ __launch_bounds__(WG) void k_append(const T* __restrict__ W, const T*
 // group are consecutive logical workgroups, which the XCD remapping places on
 // one XCD: they stream the same right-hand-side tiles at about the same time,
 // so those re-reads are served by that XCD's L2 rather than HBM.
-template <typename T, int B, int NR, int Q, int KG>
+template <typename T, int B, int NR, int Q, int KG, bool NT>
 __global__ __launch_bounds__(WG) void k_projr(const T* __restrict__ basis, int64_t slab, int nk, int nks,
                                               const T* __restrict__ r0, const T* __restrict__ r1,
                                               const T* __restrict__ r2, int64_t nvec, int tiles,
@@ -415,7 +415,8 @@ __global__ __launch_bounds__(WG) void k_projr(const T* __restrict__ basis, int64
                 for (int kk = 0; kk < KG; ++kk) {
                     if (kk < nkl) {
                         T a[VEC];
-                        unpack(bv[(int64_t)kk * slabv + vi], a);
+                        if constexpr (NT) unpack_nt(bv + (int64_t)kk * slabv + vi, a);
+                        else unpack(bv[(int64_t)kk * slabv + vi], a);
 #pragma unroll
                         for (int r = 0; r < NR; ++r)
 #pragma unroll
@@ -582,10 +583,15 @@ LaunchInfo launch_init<MAR_T>(int B, int64_t Mp, int64_t M, const int32_t* seeds
 
 template <>
 LaunchInfo launch_spmm<MAR_T>(int B, const DevMat& A, const MAR_T* X, MAR_T* Y, double* part, int ndot,
-                              hipStream_t s) {
+                              int64_t part_cap, hipStream_t s) {
     constexpr int VEC = Vec16<MAR_T>::n;
     const int P = B < VEC ? 1 : B / VEC;
     const int64_t wgs = (A.n * P + WG - 1) / WG;
+    if (ndot > 0 && wgs * ndot * B > part_cap) {
+        LaunchInfo bad;
+        bad.wgs = -1;
+        return bad;
+    }
     const MAR_T* val = std::is_same<MAR_T, float>::value ? (const MAR_T*)A.v32 : (const MAR_T*)A.v64;
 #define MAR_SPMM_LAUNCH(KERNEL, ND) \
     MAR_DISPATCH_B(B, hipLaunchKernelGGL((KERNEL<MAR_T, BB, ND>), dim3(wgs), dim3(WG), 0, s, A.n, A.ptr, A.idx, val, X, Y, part))
@@ -608,8 +614,8 @@ LaunchInfo launch_spmm<MAR_T>(int B, const DevMat& A, const MAR_T* X, MAR_T* Y, 
 }
 
 template <>
-LaunchInfo launch_proj<MAR_T>(int B, int ns, const MAR_T* b0, const MAR_T* b1, int64_t M, int nk, const MAR_T* x,
-                              double* part, int64_t* nchunks, hipStream_t s) {
+LaunchInfo launch_proj<MAR_T>(int B, int ns, const MAR_T* b0, const MAR_T* b1, int64_t M, int64_t stride, int nk,
+                              const MAR_T* x, double* part, int64_t part_cap, int64_t* nchunks, hipStream_t s) {
     constexpr int VEC = Vec16<MAR_T>::n;
     const int64_t nvec = M * B / VEC;
     const int64_t chunks = (nvec + WG * PROJ_Q - 1) / (WG * PROJ_Q);
@@ -620,7 +626,12 @@ LaunchInfo launch_proj<MAR_T>(int B, int ns, const MAR_T* b0, const MAR_T* b1, i
     int kps = (int)((nk + nks - 1) / nks);
     kps = ((kps + PROJ_KG - 1) / PROJ_KG) * PROJ_KG;
     nks = (nk + kps - 1) / kps;
-    const int64_t slab = M * B;
+    const int64_t slab = stride;
+    if (chunks * ns * nk * B > part_cap) {
+        LaunchInfo bad;
+        bad.wgs = -1;
+        return bad;
+    }
     dim3 grid((unsigned)chunks, (unsigned)nks);
     if (ns == 2) {
         MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_proj<MAR_T, BB, 2, PROJ_Q, PROJ_KG>), grid, dim3(WG), 0, s, b0, b1,
@@ -632,17 +643,17 @@ LaunchInfo launch_proj<MAR_T>(int B, int ns, const MAR_T* b0, const MAR_T* b1, i
     *nchunks = chunks;
     LaunchInfo li;
     li.wgs = chunks * nks;
-    li.bytes = ((double)ns * nk + 1.0) * (double)slab * sizeof(MAR_T);
-    li.flops = 2.0 * ns * nk * (double)slab;
+    li.bytes = ((double)ns * nk + 1.0) * (double)(M * B) * sizeof(MAR_T);
+    li.flops = 2.0 * ns * nk * (double)(M * B);
     return li;
 }
 
 template <>
-LaunchInfo launch_upd<MAR_T>(int B, const MAR_T* basis, int64_t M, int nk, const double* c, MAR_T* x,
-                             hipStream_t s) {
+LaunchInfo launch_upd<MAR_T>(int B, const MAR_T* basis, int64_t M, int64_t stride, int nk, const double* c,
+                             MAR_T* x, hipStream_t s) {
     constexpr int VEC = Vec16<MAR_T>::n;
     const int64_t nvec = M * B / VEC;
-    const int64_t slab = M * B;
+    const int64_t slab = stride;
     const bool big = nvec >= (int64_t)WG * 4 * 1024;
     LaunchInfo li;
     if (big) {
@@ -656,8 +667,8 @@ LaunchInfo launch_upd<MAR_T>(int B, const MAR_T* basis, int64_t M, int nk, const
                                              x, nvec));
         li.wgs = wgs;
     }
-    li.bytes = ((double)nk + 2.0) * (double)slab * sizeof(MAR_T);
-    li.flops = 2.0 * nk * (double)slab;
+    li.bytes = ((double)nk + 2.0) * (double)(M * B) * sizeof(MAR_T);
+    li.flops = 2.0 * nk * (double)(M * B);
     return li;
 }
 
@@ -676,18 +687,27 @@ LaunchInfo launch_append<MAR_T>(int B, int64_t M, const MAR_T* W, const MAR_T* Z
 }
 
 template <>
-LaunchInfo launch_projr<MAR_T>(int B, const MAR_T* basis, int64_t M, int nk, const MAR_T* r0, const MAR_T* r1,
-                               const MAR_T* r2, double* part, int64_t* ngroups, int target_wgs, hipStream_t s) {
+LaunchInfo launch_projr<MAR_T>(int B, const MAR_T* basis, int64_t M, int64_t stride, int nk, const MAR_T* r0,
+                               const MAR_T* r1, const MAR_T* r2, double* part, int64_t part_cap, int64_t* ngroups,
+                               int target_wgs, int variant, hipStream_t s) {
     constexpr int VEC = Vec16<MAR_T>::n;
-    constexpr int Q = PROJR_Q, KG = PROJR_KG, NR = 3;
+    constexpr int Q = PROJR_Q, NR = 3;
     const int64_t nvec = M * B / VEC;
-    const int64_t ntiles = (nvec + WG * Q - 1) / (WG * Q);
-    const int nks = (nk + KG - 1) / KG;
-    const int64_t tiles = projr_tiles(ntiles, nks, target_wgs);
-    const int64_t groups = (ntiles + tiles - 1) / tiles;
+    const ProjrGeom gm = projr_geometry(nvec, nk, variant, target_wgs);
+    const int nks = gm.nks;
+    const int64_t tiles = gm.tiles, groups = gm.groups;
     const int64_t wgs = groups * nks;
-    MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_projr<MAR_T, BB, NR, Q, KG>), dim3((unsigned)wgs), dim3(WG), 0, s, basis,
-                                         M * B, nk, nks, r0, r1, r2, nvec, (int)tiles, part));
+    if (groups * NR * nk * B > part_cap) {
+        LaunchInfo bad;
+        bad.wgs = -1;
+        return bad;
+    }
+#define MAR_PROJR(KGV, NTV) \
+    MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_projr<MAR_T, BB, NR, Q, KGV, NTV>), dim3((unsigned)wgs), dim3(WG), 0, s, basis, stride, nk, nks, r0, r1, r2, nvec, (int)tiles, part))
+    if (variant == 1) { MAR_PROJR(8, false); }
+    else if (variant == 2) { MAR_PROJR(4, true); }
+    else { MAR_PROJR(4, false); }
+#undef MAR_PROJR
     *ngroups = groups;
     LaunchInfo li;
     li.wgs = wgs;
@@ -697,15 +717,16 @@ LaunchInfo launch_projr<MAR_T>(int B, const MAR_T* basis, int64_t M, int nk, con
 }
 
 template <>
-LaunchInfo launch_upd2<MAR_T>(int B, MAR_T* basis, int64_t M, int n, const MAR_T* cA, const MAR_T* cB,
-                              const double* gam, const double* Fn, MAR_T* y, bool want_w, hipStream_t s) {
+LaunchInfo launch_upd2<MAR_T>(int B, MAR_T* basis, int64_t M, int64_t stride, int n, const MAR_T* cA,
+                              const MAR_T* cB, const double* gam, const double* Fn, MAR_T* y, bool want_w,
+                              hipStream_t s) {
     constexpr int VEC = Vec16<MAR_T>::n;
     const int64_t nvec = M * B / VEC;
     const bool big = nvec >= (int64_t)WG * 8 * 1024;
     const int Q = big ? 8 : 1;
     const int64_t wgs = (nvec + WG * Q - 1) / (WG * Q);
 #define MAR_UPD2(QQ, WW) \
-    MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_upd2<MAR_T, BB, QQ, WW>), dim3(wgs), dim3(WG), 0, s, basis, M * B, n, cA, cB, gam, Fn, y, nvec))
+    MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_upd2<MAR_T, BB, QQ, WW>), dim3(wgs), dim3(WG), 0, s, basis, stride, n, cA, cB, gam, Fn, y, nvec))
     if (big) {
         if (want_w) { MAR_UPD2(8, true); } else { MAR_UPD2(8, false); }
     } else {
