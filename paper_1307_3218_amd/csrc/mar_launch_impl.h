@@ -248,25 +248,24 @@ __global__ __launch_bounds__(WG) void k_proj(const T* __restrict__ b0, const T* 
             for (int kk = 0; kk < KG; ++kk)
 #pragma unroll
                 for (int i = 0; i < VEC; ++i) raw[s][kk][i] = (T)0;
+        // branch-free: slab indices past the range repeat the last slab (sums
+        // never emitted); out-of-range vectors read vector 0 against x = 0
 #pragma unroll
         for (int kk = 0; kk < KG; ++kk) {
-            const int k = kb + kk;
-            if (k < k1) {
+            const int k = kb + kk < k1 ? kb + kk : k1 - 1;
 #pragma unroll
-                for (int q = 0; q < Q; ++q) {
-                    const int64_t vi = vbase + (int64_t)q * WG;
-                    if (vi < nvec) {
-                        T a[VEC];
-                        unpack(bv0[(int64_t)k * slabv + vi], a);
+            for (int q = 0; q < Q; ++q) {
+                const int64_t vi = vbase + (int64_t)q * WG;
+                const int64_t vs = vi < nvec ? vi : 0;
+                T a[VEC];
+                unpack(bv0[(int64_t)k * slabv + vs], a);
 #pragma unroll
-                        for (int i = 0; i < VEC; ++i) raw[0][kk][i] = fma(a[i], xr[q][i], raw[0][kk][i]);
-                        if constexpr (NS == 2) {
-                            T c[VEC];
-                            unpack(bv1[(int64_t)k * slabv + vi], c);
+                for (int i = 0; i < VEC; ++i) raw[0][kk][i] = fma(a[i], xr[q][i], raw[0][kk][i]);
+                if constexpr (NS == 2) {
+                    T c[VEC];
+                    unpack(bv1[(int64_t)k * slabv + vs], c);
 #pragma unroll
-                            for (int i = 0; i < VEC; ++i) raw[1][kk][i] = fma(c[i], xr[q][i], raw[1][kk][i]);
-                        }
-                    }
+                    for (int i = 0; i < VEC; ++i) raw[1][kk][i] = fma(c[i], xr[q][i], raw[1][kk][i]);
                 }
             }
         }
@@ -311,20 +310,23 @@ __global__ __launch_bounds__(WG) void k_upd(const T* __restrict__ basis, int64_t
             for (int i = 0; i < VEC; ++i) acc[q][i] = (T)0;
         }
     }
+    int64_t vsq[Q];  // always-valid load indices (out-of-range lanes read vector 0, never stored)
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int64_t vi = vbase + (int64_t)q * WG;
+        vsq[q] = vi < nvec ? vi : 0;
+    }
     for (int k = 0; k < nk; ++k) {
         T cv[VEC];
 #pragma unroll
         for (int i = 0; i < VEC; ++i) cv[i] = (T)c[(int64_t)k * B + ((B < VEC) ? (i % B) : (sb + i))];
+        T a[Q][VEC];
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int64_t vi = vbase + (int64_t)q * WG;
-            if (vi < nvec) {
-                T a[VEC];
-                unpack(bv[(int64_t)k * slabv + vi], a);
+        for (int q = 0; q < Q; ++q) unpack(bv[(int64_t)k * slabv + vsq[q]], a[q]);
 #pragma unroll
-                for (int i = 0; i < VEC; ++i) acc[q][i] = fma(-a[i], cv[i], acc[q][i]);
-            }
-        }
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) acc[q][i] = fma(-a[q][i], cv[i], acc[q][i]);
     }
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -401,29 +403,40 @@ __global__ __launch_bounds__(WG) void k_projr(const T* __restrict__ basis, int64
         for (int kk = 0; kk < KG; ++kk)
 #pragma unroll
             for (int i = 0; i < VEC; ++i) raw[r][kk][i] = (T)0;
+    // Branch-free inner loop (a guarded load makes the compiler wait for each
+    // load before the next): out-of-range vectors read vector 0 and contribute
+    // zero; slab indices past the range repeat the last slab and their sums
+    // are never emitted.
+    int koff[KG];
+#pragma unroll
+    for (int kk = 0; kk < KG; ++kk) koff[kk] = kk < nkl ? kk : nkl - 1;
     for (int tile = 0; tile < tiles; ++tile) {
         const int64_t tbase = (grp * tiles + tile) * (int64_t)(WG * Q);
         if (tbase >= nvec) break;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int64_t vi = tbase + (int64_t)q * WG + tid;
-            if (vi < nvec) {
-                T x[NR][VEC];
+            const bool ok = vi < nvec;
+            const int64_t vs = ok ? vi : 0;
+            T x[NR][VEC];
 #pragma unroll
-                for (int r = 0; r < NR; ++r) unpack(rv[r][vi], x[r]);
+            for (int r = 0; r < NR; ++r) {
+                unpack(rv[r][vs], x[r]);
 #pragma unroll
-                for (int kk = 0; kk < KG; ++kk) {
-                    if (kk < nkl) {
-                        T a[VEC];
-                        if constexpr (NT) unpack_nt(bv + (int64_t)kk * slabv + vi, a);
-                        else unpack(bv[(int64_t)kk * slabv + vi], a);
-#pragma unroll
-                        for (int r = 0; r < NR; ++r)
-#pragma unroll
-                            for (int i = 0; i < VEC; ++i) raw[r][kk][i] = fma(a[i], x[r][i], raw[r][kk][i]);
-                    }
-                }
+                for (int i = 0; i < VEC; ++i) x[r][i] = ok ? x[r][i] : (T)0;
             }
+            T a[KG][VEC];
+#pragma unroll
+            for (int kk = 0; kk < KG; ++kk) {
+                if constexpr (NT) unpack_nt(bv + (int64_t)koff[kk] * slabv + vs, a[kk]);
+                else unpack(bv[(int64_t)koff[kk] * slabv + vs], a[kk]);
+            }
+#pragma unroll
+            for (int kk = 0; kk < KG; ++kk)
+#pragma unroll
+                for (int r = 0; r < NR; ++r)
+#pragma unroll
+                    for (int i = 0; i < VEC; ++i) raw[r][kk][i] = fma(a[kk][i], x[r][i], raw[r][kk][i]);
         }
     }
     T acc[NR * KG][SW];
@@ -474,6 +487,12 @@ __global__ __launch_bounds__(WG) void k_upd2(T* __restrict__ basis, int64_t slab
             for (int i = 0; i < VEC; ++i) au[q][i] = aw[q][i] = (T)0;
         }
     }
+    int64_t vsq[Q];  // always-valid load indices (out-of-range lanes read vector 0, never stored)
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int64_t vi = vbase + (int64_t)q * WG;
+        vsq[q] = vi < nvec ? vi : 0;
+    }
     for (int k = 0; k < n; ++k) {
         T ca[VEC], cb[VEC];
         if constexpr (B >= VEC) {
@@ -486,19 +505,16 @@ __global__ __launch_bounds__(WG) void k_upd2(T* __restrict__ basis, int64_t slab
                 if constexpr (WANT_W) cb[i] = cB[(int64_t)k * B + i % B];
             }
         }
+        T a[Q][VEC];
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int64_t vi = vbase + (int64_t)q * WG;
-            if (vi < nvec) {
-                T a[VEC];
-                unpack(bv[(int64_t)k * slabv + vi], a);
+        for (int q = 0; q < Q; ++q) unpack(bv[(int64_t)k * slabv + vsq[q]], a[q]);
 #pragma unroll
-                for (int i = 0; i < VEC; ++i) {
-                    au[q][i] = fma(-a[i], ca[i], au[q][i]);
-                    if constexpr (WANT_W) aw[q][i] = fma(-a[i], cb[i], aw[q][i]);
-                }
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) {
+                au[q][i] = fma(-a[q][i], ca[i], au[q][i]);
+                if constexpr (WANT_W) aw[q][i] = fma(-a[q][i], cb[i], aw[q][i]);
             }
-        }
     }
     T g[VEC], fn[VEC];
 #pragma unroll
