@@ -84,11 +84,12 @@ typedef struct {
     int32_t seed_block;    /* B for the batched form: power of two, 1..256 (FP32) or 1..128
                               (FP64); 0 = choose from the problem size */
     int32_t schedule;      /* mar_schedule */
-    int32_t proj_wgs;      /* target workgroups of a delayed-schedule projection sweep (0 = 4096) */
+    int32_t proj_wgs;      /* target workgroups of a delayed-schedule projection sweep (0 = 2048) */
     int32_t slab_pad_kb;   /* extra KiB between consecutive basis slabs (0 = none) */
     int32_t proj_variant;  /* delayed-schedule projection: 0 = 4 slabs per workgroup, 1 = 8 slabs,
                               2 = 4 slabs with non-temporal basis loads */
-    int32_t reserved[3];
+    int32_t upd_q;         /* delayed-schedule update: 16-byte vectors per thread, 2/4/8 (0 = 8) */
+    int32_t reserved[2];
 } mar_tuning;
 
 /* Create a context from host CSR arrays of H and S (M x M, 0-based, columns

@@ -527,7 +527,7 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
                                         nu_blk, tau, s);
             });
             launch(c, s, P_UPD2, [&] {
-                return mar::launch_upd2<T>(B, K, M, stride, n, cAT, cBT, gam, Fn, Y, !last, s);
+                return mar::launch_upd2<T>(B, K, M, stride, n, cAT, cBT, gam, Fn, Y, !last, c->tune.upd_q, s);
             });
             if (last) break;
             int64_t swgs = 0;
@@ -762,6 +762,8 @@ mar_status mar_set_tuning(mar_ctx* c, const mar_tuning* t) {
     if (t->proj_wgs < 0) return set_err(c, MAR_ERR_ARG, "proj_wgs < 0");
     if (t->slab_pad_kb < 0 || t->slab_pad_kb > 65536) return set_err(c, MAR_ERR_ARG, "slab_pad_kb outside [0, 65536]");
     if (t->proj_variant < 0 || t->proj_variant > 2) return set_err(c, MAR_ERR_ARG, "proj_variant outside [0, 2]");
+    if (t->upd_q != 0 && t->upd_q != 2 && t->upd_q != 4 && t->upd_q != 8)
+        return set_err(c, MAR_ERR_ARG, "upd_q must be 0, 2, 4 or 8");
     c->tune = *t;
     return MAR_OK;
 }

@@ -15,7 +15,7 @@ constexpr int PROJR_KG = 4;        // slabs owned by one workgroup in the delaye
 
 // Row tiles per workgroup of the delayed-schedule projection: as many as keep
 // the grid at about target_wgs workgroups (fewer partial sums), at least one.
-constexpr int PROJR_WGS = 4096;    // default target grid of the delayed-schedule projection
+constexpr int PROJR_WGS = 2048;    // default target grid of the delayed-schedule projection
 
 // Grid of the delayed-schedule projection for nk slabs of nvec vectors: KG
 // slabs per workgroup (nks splits), `tiles` row tiles per workgroup (as many
@@ -114,8 +114,9 @@ LaunchInfo launch_projr(int B, const T* basis, int64_t M, int64_t stride, int nk
                         hipStream_t s);
 // cA/cB: [n][B] coefficients in the basis precision T.
 template <typename T>
+// upd_q: 16-byte vectors per thread (2, 4 or 8; 0 = 8), reduced for small grids.
 LaunchInfo launch_upd2(int B, T* basis, int64_t M, int64_t stride, int n, const T* cA, const T* cB,
-                       const double* gam, const double* Fn, T* y, bool want_w, hipStream_t s);
+                       const double* gam, const double* Fn, T* y, bool want_w, int upd_q, hipStream_t s);
 template <typename T>
 LaunchInfo launch_append2(int B, int64_t M, const T* W, const T* Z, const double* beta, const int32_t* active,
                           T* Kn, T* ZT, hipStream_t s);

@@ -735,19 +735,22 @@ LaunchInfo launch_projr<MAR_T>(int B, const MAR_T* basis, int64_t M, int64_t str
 template <>
 LaunchInfo launch_upd2<MAR_T>(int B, MAR_T* basis, int64_t M, int64_t stride, int n, const MAR_T* cA,
                               const MAR_T* cB, const double* gam, const double* Fn, MAR_T* y, bool want_w,
-                              hipStream_t s) {
+                              int upd_q, hipStream_t s) {
     constexpr int VEC = Vec16<MAR_T>::n;
     const int64_t nvec = M * B / VEC;
-    const bool big = nvec >= (int64_t)WG * 8 * 1024;
-    const int Q = big ? 8 : 1;
+    // vectors per thread: the requested depth when the grid still has >= 1024 workgroups
+    int Q = upd_q == 2 || upd_q == 4 || upd_q == 8 ? upd_q : 8;
+    while (Q > 1 && nvec < (int64_t)WG * Q * 1024) Q /= 2;
     const int64_t wgs = (nvec + WG * Q - 1) / (WG * Q);
 #define MAR_UPD2(QQ, WW) \
     MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_upd2<MAR_T, BB, QQ, WW>), dim3(wgs), dim3(WG), 0, s, basis, stride, n, cA, cB, gam, Fn, y, nvec))
-    if (big) {
-        if (want_w) { MAR_UPD2(8, true); } else { MAR_UPD2(8, false); }
-    } else {
-        if (want_w) { MAR_UPD2(1, true); } else { MAR_UPD2(1, false); }
-    }
+#define MAR_UPD2W(QQ) \
+    if (want_w) { MAR_UPD2(QQ, true); } else { MAR_UPD2(QQ, false); }
+    if (Q == 8) { MAR_UPD2W(8) }
+    else if (Q == 4) { MAR_UPD2W(4) }
+    else if (Q == 2) { MAR_UPD2W(2) }
+    else { MAR_UPD2W(1) }
+#undef MAR_UPD2W
 #undef MAR_UPD2
     LaunchInfo li;
     li.wgs = wgs;

@@ -36,7 +36,8 @@ class MarError(RuntimeError):
 
 class mar_tuning(C.Structure):
     _fields_ = [("seed_block", C.c_int32), ("schedule", C.c_int32), ("proj_wgs", C.c_int32),
-                ("slab_pad_kb", C.c_int32), ("proj_variant", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("slab_pad_kb", C.c_int32), ("proj_variant", C.c_int32), ("upd_q", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
 
 class mar_prof_entry(C.Structure):
@@ -148,8 +149,8 @@ def mar_solve_async(ctx, d_seeds, n_seeds, nu, mu, kT, prec, form, d_rho, d_e_ba
 
 
 def mar_set_tuning(ctx, seed_block: int = 0, schedule: int = 0, proj_wgs: int = 0, slab_pad_kb: int = 0,
-                   proj_variant: int = 0) -> int:
-    t = mar_tuning(seed_block, schedule, proj_wgs, slab_pad_kb, proj_variant)
+                   proj_variant: int = 0, upd_q: int = 0) -> int:
+    t = mar_tuning(seed_block, schedule, proj_wgs, slab_pad_kb, proj_variant, upd_q)
     return lib().mar_set_tuning(ctx, C.byref(t))
 
 
@@ -235,9 +236,9 @@ class Context:
         _check(self.handle, st)
 
     def set_tuning(self, seed_block: int = 0, schedule: str = "auto", proj_wgs: int = 0, slab_pad_kb: int = 0,
-                   proj_variant: int = 0):
+                   proj_variant: int = 0, upd_q: int = 0):
         _check(self.handle, mar_set_tuning(self.handle, seed_block, SCHEDULE[schedule], proj_wgs, slab_pad_kb,
-                                           proj_variant))
+                                           proj_variant, upd_q))
 
     def seed_block(self, nu: int, precision: str = "fp32") -> int:
         return mar_seed_block(self.handle, nu, PRECISION[precision])
