@@ -84,10 +84,12 @@ typedef struct {
     int32_t seed_block;    /* B for the batched form: power of two, 1..256 (FP32) or 1..128
                               (FP64); 0 = choose from the problem size */
     int32_t schedule;      /* mar_schedule */
-    int32_t proj_wgs;      /* target workgroups of a delayed-schedule projection sweep (0 = 2048) */
+    int32_t proj_wgs;      /* workgroup cap of a delayed-schedule projection sweep (0 = as many as
+                              the device holds at once) */
     int32_t slab_pad_kb;   /* extra KiB between consecutive basis slabs (0 = none) */
-    int32_t proj_variant;  /* delayed-schedule projection: 0 = 4 slabs per workgroup, 1 = 8 slabs,
-                              2 = 4 slabs with non-temporal basis loads */
+    int32_t proj_variant;  /* delayed-schedule projection, slabs x 16-byte vectors per thread and row
+                              tile: 0 = 4 x 4, 1 = 8 x 4, 2 = 4 x 4 with non-temporal basis loads,
+                              3 = 4 x 2, 4 = 8 x 2 */
     int32_t upd_q;         /* delayed-schedule update: 16-byte vectors per thread, 2/4/8 (0 = 8) */
     int32_t reserved[2];
 } mar_tuning;

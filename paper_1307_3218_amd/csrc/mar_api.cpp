@@ -57,6 +57,7 @@ struct mar_ctx {
     double* diagS = nullptr;
     int64_t nnzH = 0, nnzS = 0;
     int max_row = 0;
+    int n_cu = 1;             // compute units of the device
     mar_tuning tune{};
     char* ws = nullptr;
     size_t ws_bytes = 0;
@@ -429,10 +430,11 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     const int64_t M = (c->M + 3) / 4 * 4;
     const int64_t nvec = M * B / VEC;
     const int P = B < VEC ? 1 : B / VEC;
-    const int target = c->tune.proj_wgs > 0 ? c->tune.proj_wgs : mar::PROJR_WGS;
+    // default projection grid: the workgroups the device holds at once (one round, few partial sums)
+    const int64_t target = c->tune.proj_wgs > 0 ? (int64_t)c->tune.proj_wgs
+                                                 : (int64_t)mar::projr_blocks_per_cu<T>(B, c->tune.proj_variant) * c->n_cu;
     const int variant = c->tune.proj_variant;
     const int64_t spmm_wgs = std::max((c->S.n * P + mar::WG - 1) / mar::WG, (c->H.n * P + mar::WG - 1) / mar::WG);
-    const int64_t ntiles = (nvec + mar::WG * mar::PROJR_Q - 1) / (mar::WG * mar::PROJR_Q);
     const size_t slab = (size_t)M * B * sizeof(T);
     const int64_t stride = slab_stride(c, M, B, sizeof(T));
     size_t part_doubles = (size_t)spmm_wgs * 2 * B;
@@ -618,6 +620,9 @@ mar_status mar_create(int64_t M, const int64_t* H_rowptr, const int32_t* H_col, 
     if (he != hipSuccess || ndev < 1) return set_err(nullptr, MAR_ERR_HIP, "no HIP device available");
     mar_ctx* c = new mar_ctx();
     hipGetDevice(&c->device);
+    if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess ||
+        c->n_cu < 1)
+        c->n_cu = 1;
     c->M = M;
     c->nnzH = H_rowptr[M];
     c->nnzS = S_rowptr[M];
@@ -761,7 +766,7 @@ mar_status mar_set_tuning(mar_ctx* c, const mar_tuning* t) {
         return set_err(c, MAR_ERR_ARG, "unknown schedule");
     if (t->proj_wgs < 0) return set_err(c, MAR_ERR_ARG, "proj_wgs < 0");
     if (t->slab_pad_kb < 0 || t->slab_pad_kb > 65536) return set_err(c, MAR_ERR_ARG, "slab_pad_kb outside [0, 65536]");
-    if (t->proj_variant < 0 || t->proj_variant > 2) return set_err(c, MAR_ERR_ARG, "proj_variant outside [0, 2]");
+    if (t->proj_variant < 0 || t->proj_variant > 4) return set_err(c, MAR_ERR_ARG, "proj_variant outside [0, 4]");
     if (t->upd_q != 0 && t->upd_q != 2 && t->upd_q != 4 && t->upd_q != 8)
         return set_err(c, MAR_ERR_ARG, "upd_q must be 0, 2, 4 or 8");
     c->tune = *t;

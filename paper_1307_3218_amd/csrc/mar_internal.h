@@ -15,7 +15,6 @@ constexpr int PROJR_KG = 4;        // slabs owned by one workgroup in the delaye
 
 // Row tiles per workgroup of the delayed-schedule projection: as many as keep
 // the grid at about target_wgs workgroups (fewer partial sums), at least one.
-constexpr int PROJR_WGS = 2048;    // default target grid of the delayed-schedule projection
 
 // Grid of the delayed-schedule projection for nk slabs of nvec vectors: KG
 // slabs per workgroup (nks splits), `tiles` row tiles per workgroup (as many
@@ -23,16 +22,22 @@ constexpr int PROJR_WGS = 2048;    // default target grid of the delayed-schedul
 // buffer needs groups * 3 * nk * B doubles. Used by the launcher and by the
 // workspace sizing, so that both always agree.
 struct ProjrGeom {
-    int kg, nks;
+    int kg, q, nks;
     int64_t ntiles, tiles, groups;
 };
-inline ProjrGeom projr_geometry(int64_t nvec, int nk, int variant, int target_wgs) {
+// variant: 0 = 4 slabs x 4 vectors, 1 = 8 x 4, 2 = 4 x 4 non-temporal, 3 = 4 x 2, 4 = 8 x 2.
+// target_wgs (> 0) caps the grid: the row tiles are cut into target_wgs / nks
+// groups, so that a grid of the device's resident capacity runs in one round
+// and the partial sums stay few (groups * 3 * nk * B values).
+inline ProjrGeom projr_geometry(int64_t nvec, int nk, int variant, int64_t target_wgs) {
     ProjrGeom g;
-    g.kg = variant == 1 ? 8 : 4;
+    g.kg = variant == 1 || variant == 4 ? 8 : 4;
+    g.q = variant >= 3 ? 2 : PROJR_Q;
     g.nks = (nk + g.kg - 1) / g.kg;
-    g.ntiles = (nvec + WG * PROJR_Q - 1) / (WG * PROJR_Q);
-    int64_t t = (g.ntiles * g.nks) / (target_wgs > 0 ? target_wgs : PROJR_WGS);
-    g.tiles = t < 1 ? 1 : (t > g.ntiles ? g.ntiles : t);
+    g.ntiles = (nvec + WG * g.q - 1) / (WG * g.q);
+    int64_t groups = (target_wgs > 0 ? target_wgs : 1) / g.nks;
+    groups = groups < 1 ? 1 : (groups > g.ntiles ? g.ntiles : groups);
+    g.tiles = (g.ntiles + groups - 1) / groups;
     g.groups = (g.ntiles + g.tiles - 1) / g.tiles;
     return g;
 }
@@ -107,11 +112,14 @@ LaunchInfo launch_eig(int nseeds, const int32_t* seeds, int nu, double* h, const
                       hipStream_t s);
 
 // Delayed-reorthogonalization schedule.
+// Projection sweep (variants as in projr_geometry); target_wgs > 0.
 template <typename T>
-// variant 0: 4 slabs per workgroup; 1: 8 slabs; 2: 4 slabs with non-temporal basis loads.
 LaunchInfo launch_projr(int B, const T* basis, int64_t M, int64_t stride, int nk, const T* r0, const T* r1,
-                        const T* r2, double* part, int64_t part_cap, int64_t* ngroups, int target_wgs, int variant,
-                        hipStream_t s);
+                        const T* r2, double* part, int64_t part_cap, int64_t* ngroups, int64_t target_wgs,
+                        int variant, hipStream_t s);
+// Workgroups of that projection kernel one compute unit holds at once (>= 1).
+template <typename T>
+int projr_blocks_per_cu(int B, int variant);
 // cA/cB: [n][B] coefficients in the basis precision T.
 template <typename T>
 // upd_q: 16-byte vectors per thread (2, 4 or 8; 0 = 8), reduced for small grids.

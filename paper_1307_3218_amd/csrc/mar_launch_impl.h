@@ -470,28 +470,26 @@ __global__ __launch_bounds__(WG) void k_upd2(T* __restrict__ basis, int64_t slab
     constexpr int VEC = SM::VEC, P = SM::P;
     using VT = typename Vec16<T>::type;
     const int tid = threadIdx.x;
-    const int64_t vbase = (int64_t)blockIdx.x * (WG * Q) + tid;
     const int64_t slabv = slab / VEC;
     const int sb = (B < VEC) ? 0 : (tid % P) * VEC;
     VT* bv = reinterpret_cast<VT*>(basis);
     VT* yv = reinterpret_cast<VT*>(y);
-    T au[Q][VEC], aw[Q][VEC];
+    T g[VEC], fn[VEC];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        const int64_t vi = vbase + (int64_t)q * WG;
-        if (vi < nvec) {
-            unpack(bv[(int64_t)n * slabv + vi], au[q]);
-            if constexpr (WANT_W) unpack(yv[vi], aw[q]);
-        } else {
-#pragma unroll
-            for (int i = 0; i < VEC; ++i) au[q][i] = aw[q][i] = (T)0;
-        }
+    for (int i = 0; i < VEC; ++i) {
+        const int b = (B < VEC) ? (i % B) : (sb + i);
+        g[i] = (T)gam[b];
+        fn[i] = (T)Fn[b];
     }
-    int64_t vsq[Q];  // always-valid load indices (out-of-range lanes read vector 0, never stored)
+    const int64_t vbase = (int64_t)blockIdx.x * (WG * Q) + tid;
+    T au[Q][VEC], aw[Q][VEC];
+    int64_t vsq[Q];  // always-valid load indices (lanes past nvec read vector 0 and store nothing)
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const int64_t vi = vbase + (int64_t)q * WG;
         vsq[q] = vi < nvec ? vi : 0;
+        unpack(bv[(int64_t)n * slabv + vsq[q]], au[q]);
+        if constexpr (WANT_W) unpack(yv[vsq[q]], aw[q]);
     }
     for (int k = 0; k < n; ++k) {
         T ca[VEC], cb[VEC];
@@ -515,13 +513,6 @@ __global__ __launch_bounds__(WG) void k_upd2(T* __restrict__ basis, int64_t slab
                 au[q][i] = fma(-a[q][i], ca[i], au[q][i]);
                 if constexpr (WANT_W) aw[q][i] = fma(-a[q][i], cb[i], aw[q][i]);
             }
-    }
-    T g[VEC], fn[VEC];
-#pragma unroll
-    for (int i = 0; i < VEC; ++i) {
-        const int b = (B < VEC) ? (i % B) : (sb + i);
-        g[i] = (T)gam[b];
-        fn[i] = (T)Fn[b];
     }
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -705,9 +696,9 @@ LaunchInfo launch_append<MAR_T>(int B, int64_t M, const MAR_T* W, const MAR_T* Z
 template <>
 LaunchInfo launch_projr<MAR_T>(int B, const MAR_T* basis, int64_t M, int64_t stride, int nk, const MAR_T* r0,
                                const MAR_T* r1, const MAR_T* r2, double* part, int64_t part_cap, int64_t* ngroups,
-                               int target_wgs, int variant, hipStream_t s) {
+                               int64_t target_wgs, int variant, hipStream_t s) {
     constexpr int VEC = Vec16<MAR_T>::n;
-    constexpr int Q = PROJR_Q, NR = 3;
+    constexpr int NR = 3;
     const int64_t nvec = M * B / VEC;
     const ProjrGeom gm = projr_geometry(nvec, nk, variant, target_wgs);
     const int nks = gm.nks;
@@ -718,11 +709,13 @@ LaunchInfo launch_projr<MAR_T>(int B, const MAR_T* basis, int64_t M, int64_t str
         bad.wgs = -1;
         return bad;
     }
-#define MAR_PROJR(KGV, NTV) \
-    MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_projr<MAR_T, BB, NR, Q, KGV, NTV>), dim3((unsigned)wgs), dim3(WG), 0, s, basis, stride, nk, nks, r0, r1, r2, nvec, (int)tiles, part))
-    if (variant == 1) { MAR_PROJR(8, false); }
-    else if (variant == 2) { MAR_PROJR(4, true); }
-    else { MAR_PROJR(4, false); }
+#define MAR_PROJR(QV, KGV, NTV) \
+    MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_projr<MAR_T, BB, NR, QV, KGV, NTV>), dim3((unsigned)wgs), dim3(WG), 0, s, basis, stride, nk, nks, r0, r1, r2, nvec, (int)tiles, part))
+    if (variant == 1) { MAR_PROJR(PROJR_Q, 8, false); }
+    else if (variant == 2) { MAR_PROJR(PROJR_Q, 4, true); }
+    else if (variant == 3) { MAR_PROJR(2, 4, false); }
+    else if (variant == 4) { MAR_PROJR(2, 8, false); }
+    else { MAR_PROJR(PROJR_Q, 4, false); }
 #undef MAR_PROJR
     *ngroups = groups;
     LaunchInfo li;
@@ -730,6 +723,20 @@ LaunchInfo launch_projr<MAR_T>(int B, const MAR_T* basis, int64_t M, int64_t str
     li.bytes = ((double)nk + NR) * (double)(M * B) * sizeof(MAR_T);
     li.flops = 2.0 * NR * nk * (double)(M * B);
     return li;
+}
+
+template <>
+int projr_blocks_per_cu<MAR_T>(int B, int variant) {
+    int nb = 0;
+#define MAR_OCC(QV, KGV, NTV) \
+    MAR_DISPATCH_B(B, (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&k_projr<MAR_T, BB, 3, QV, KGV, NTV>), WG, 0))
+    if (variant == 1) { MAR_OCC(PROJR_Q, 8, false); }
+    else if (variant == 2) { MAR_OCC(PROJR_Q, 4, true); }
+    else if (variant == 3) { MAR_OCC(2, 4, false); }
+    else if (variant == 4) { MAR_OCC(2, 8, false); }
+    else { MAR_OCC(PROJR_Q, 4, false); }
+#undef MAR_OCC
+    return nb > 0 ? nb : 1;
 }
 
 template <>

@@ -115,10 +115,10 @@ def test_c1_every_block_size_ragged(c1, c1_ctx, c1_mu, prec, B, sched):
     compare(c1.H, seeds, g, ref, prec, label=f"M=256 B={B} {sched}")
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_c1_projection_variants(c1, c1_ctx, c1_mu, c1_ref30, prec, variant):
-    """Every projection variant (4 or 8 slabs per workgroup, non-temporal loads) at the widest block."""
+    """Every projection variant (4 or 8 slabs, 2 or 4 vectors per thread, non-temporal loads) at the widest block."""
     seeds = np.arange(c1.M, dtype=np.int32)
     c1_ctx.set_tuning(seed_block=0, schedule="delayed", proj_variant=variant)
     try:
