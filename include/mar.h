@@ -144,6 +144,50 @@ mar_status mar_solve_async(mar_ctx* ctx, const int32_t* d_seeds, int64_t n_seeds
                            double* d_rho, double* d_e_band, double* d_e_seed, double* d_n_seed,
                            int32_t* d_nu_eff, double* d_eps, double* d_weight, void* hip_stream);
 
+/* ---- several independent systems in one launch ----
+ * One request per context: the same arguments as mar_solve_async (device
+ * pointers, validated the same way). */
+typedef struct {
+    const int32_t* d_seeds;
+    int64_t n_seeds;
+    int32_t nu;
+    double mu, kT;
+    mar_precision prec;
+    mar_form form;
+    double* d_rho;
+    double* d_e_band;
+    double* d_e_seed;     /* or NULL */
+    double* d_n_seed;     /* or NULL */
+    int32_t* d_nu_eff;    /* or NULL */
+    double* d_eps;        /* or NULL */
+    double* d_weight;     /* or NULL */
+} mar_request;
+
+/* Solve n_sys independent systems (the Sec. 2 per-seed problem of each system,
+ * as in mar_solve_async) with one graph launch on hip_stream: the launch
+ * sequences of all systems are captured into one HIP graph as parallel
+ * branches, so systems of uneven size and nu overlap on the device. Contexts
+ * must be distinct and on the current device. The instantiated graph is cached
+ * under the exact request set (contexts, pointers, sizes, scalars and the
+ * resolved block sizes): calling again with identical requests replays it
+ * without capture, so a caller that refills the same seed buffers pays one
+ * capture. Workspaces are sized (and allocated) before the capture. Errors are
+ * reported on the context of the failing request (on ctx[0] for errors of the
+ * call itself). Cached graphs of a context are released by mar_destroy. */
+mar_status mar_solve_many(int32_t n_sys, mar_ctx* const* ctx, const mar_request* req, void* hip_stream);
+
+/* Autotuner: time the batched form on the first min(n_seeds, 256) of d_seeds
+ * (device) for every block size B (powers of two allowed by the precision and
+ * the 128 GB basis budget) and, for the delayed schedule, the projection tile
+ * variants 0 and 3; keep the fastest (B, variant) for (nu, prec) in the context.
+ * Later batched solves with seed_block = 0 and proj_variant = 0 in the tuning
+ * use it. Outputs of the probe solves go to a context-owned scratch buffer;
+ * the call synchronizes hip_stream. best_block (or NULL) receives B;
+ * best_rate (or NULL) the probe throughput in seed-subspaces/s. */
+mar_status mar_autotune(mar_ctx* ctx, int32_t nu, mar_precision prec, const int32_t* d_seeds, int64_t n_seeds,
+                        double mu, double kT, void* hip_stream, int32_t* best_block, int32_t* best_variant,
+                        double* best_rate);
+
 /* Set the tuning used by later solves (NULL restores the defaults). */
 mar_status mar_set_tuning(mar_ctx* ctx, const mar_tuning* t);
 mar_status mar_get_tuning(const mar_ctx* ctx, mar_tuning* t);

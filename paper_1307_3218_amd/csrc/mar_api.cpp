@@ -7,7 +7,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/mar.h"
@@ -58,6 +61,13 @@ struct mar_ctx {
     int64_t nnzH = 0, nnzS = 0;
     int max_row = 0;
     int n_cu = 1;             // compute units of the device
+    bool dry = false;         // size and allocate the workspace only; launch nothing
+    // projection workgroups per compute unit, by (element bytes, B, variant)
+    std::map<std::tuple<int, int, int>, int> occ;
+    // autotuned (B, projection variant) by (nu, precision)
+    std::map<std::pair<int, int>, std::pair<int, int>> tuned;
+    double* tune_buf = nullptr;   // probe outputs of the autotuner: rho [nnz(H)] + e_band
+
     mar_tuning tune{};
     char* ws = nullptr;
     size_t ws_bytes = 0;
@@ -237,7 +247,7 @@ hipEvent_t get_event(mar_ctx* c) {
 // marks the solve as failed, and no later kernel of the solve is enqueued.
 template <class F>
 void launch(mar_ctx* c, hipStream_t s, int cls, F&& f) {
-    if (c->refused) return;
+    if (c->refused || c->dry) return;
     if (!c->prof) {
         if (f().wgs < 0) c->refused = true;
         return;
@@ -257,21 +267,66 @@ int pow2_floor(int64_t x) {
     return p;
 }
 
-int choose_block(const mar_ctx* c, int nu, mar_precision prec, int64_t n_seeds) {
+// Widest block whose stored basis (K, plus S K in the textbook schedule) fits in 128 GB.
+int block_cap(const mar_ctx* c, int nu, mar_precision prec, bool delayed) {
     const int bmax = prec == MAR_FP32 ? mar::max_block<float>() : mar::max_block<double>();
-    const size_t p = prec == MAR_FP32 ? 4 : 8;
+    const double p = prec == MAR_FP32 ? 4.0 : 8.0, copies = delayed ? 1.0 : 2.0;
+    int B = bmax;
+    while (B > 1 && copies * nu * (double)c->M * B * p > 128e9) B /= 2;
+    return B;
+}
+
+int choose_block(const mar_ctx* c, int nu, mar_precision prec, int64_t n_seeds, bool delayed) {
+    const int bmax = prec == MAR_FP32 ? mar::max_block<float>() : mar::max_block<double>();
     int B;
     if (c->tune.seed_block > 0) {
         B = std::min(c->tune.seed_block, bmax);
     } else {
-        // the widest block: one pass over a slab serves the most seeds and the
-        // matrix values are reused B times; keep the basis within 128 GB
-        B = bmax;
-        while (B > 1 && 2.0 * nu * (double)c->M * B * p > 128e9) B /= 2;
+        auto t = c->tuned.find({nu, (int)prec});
+        if (t != c->tuned.end() && delayed) {
+            B = t->second.first;
+        } else {
+            // the widest block: one pass over a slab serves the most seeds and
+            // the matrix values are reused B times
+            B = block_cap(c, nu, prec, delayed);
+        }
         if (n_seeds > 0) B = std::min<int64_t>(B, pow2_floor(std::max<int64_t>(1, n_seeds)) * 2);
         B = std::min(B, bmax);
     }
     return std::max(1, pow2_floor(B));
+}
+
+// What a solve will run: block size, schedule and projection variant.
+struct Plan {
+    int B;
+    bool delayed;
+    int variant;
+};
+
+Plan plan_solve(const mar_ctx* c, int nu, mar_precision prec, mar_form form, int64_t n_seeds) {
+    Plan pl;
+    // the plain form is the textbook CGS2 (project, update, project, update);
+    // the batched form defaults to the delayed-reorthogonalization schedule
+    pl.delayed = c->tune.schedule == MAR_SCHED_DELAYED ||
+                 (c->tune.schedule == MAR_SCHED_AUTO && form == MAR_FORM_BATCHED);
+    pl.B = form == MAR_FORM_PLAIN ? 1 : choose_block(c, nu, prec, n_seeds, pl.delayed);
+    pl.variant = c->tune.proj_variant;
+    if (pl.variant == 0 && c->tune.seed_block == 0 && form == MAR_FORM_BATCHED) {
+        auto t = c->tuned.find({nu, (int)prec});
+        if (t != c->tuned.end()) pl.variant = t->second.second;
+    }
+    return pl;
+}
+
+// Projection workgroups one compute unit holds (cached per kernel instance).
+template <typename T>
+int projr_occupancy(mar_ctx* c, int B, int variant) {
+    const auto key = std::make_tuple((int)sizeof(T), B, variant);
+    auto it = c->occ.find(key);
+    if (it != c->occ.end()) return it->second;
+    const int nb = mar::projr_blocks_per_cu<T>(B, variant);
+    c->occ[key] = nb;
+    return nb;
 }
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -283,10 +338,13 @@ int64_t slab_stride(const mar_ctx* c, int64_t Mp, int B, size_t elem) {
     return Mp * B + pad_bytes / (int64_t)elem;
 }
 
+void drop_graphs_of(mar_ctx* c);
+
 mar_status ensure_ws(mar_ctx* c, size_t bytes) {
     if (bytes <= c->ws_bytes) return MAR_OK;
     if (c->ws) {
         HIP_OR(c, hipDeviceSynchronize());
+        drop_graphs_of(c);   // cached graphs hold pointers into the old workspace
         HIP_OR(c, hipFree(c->ws));
         c->ws = nullptr;
         c->ws_bytes = 0;
@@ -424,16 +482,15 @@ mar_status run_solve(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds, int nu
 // residual. Two passes over the basis per step instead of five.
 template <typename T>
 mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds, int nu, double mu, double kT,
-                             int B, double* d_rho, double* d_e_band, double* d_e_seed, double* d_n_seed,
-                             int32_t* d_nu_eff, double* d_eps, double* d_w, hipStream_t s) {
+                             int B, int variant, double* d_rho, double* d_e_band, double* d_e_seed,
+                             double* d_n_seed, int32_t* d_nu_eff, double* d_eps, double* d_w, hipStream_t s) {
     constexpr int VEC = 16 / sizeof(T);
     const int64_t M = (c->M + 3) / 4 * 4;
     const int64_t nvec = M * B / VEC;
     const int P = B < VEC ? 1 : B / VEC;
     // default projection grid: the workgroups the device holds at once (one round, few partial sums)
     const int64_t target = c->tune.proj_wgs > 0 ? (int64_t)c->tune.proj_wgs
-                                                 : (int64_t)mar::projr_blocks_per_cu<T>(B, c->tune.proj_variant) * c->n_cu;
-    const int variant = c->tune.proj_variant;
+                                                 : (int64_t)projr_occupancy<T>(c, B, variant) * c->n_cu;
     const int64_t spmm_wgs = std::max((c->S.n * P + mar::WG - 1) / mar::WG, (c->H.n * P + mar::WG - 1) / mar::WG);
     const size_t slab = (size_t)M * B * sizeof(T);
     const int64_t stride = slab_stride(c, M, B, sizeof(T));
@@ -580,6 +637,102 @@ mar_status check_scalars(mar_ctx* c, int64_t n_seeds, int32_t nu, double mu, dou
     return MAR_OK;
 }
 
+// Validation shared by the device-side entry points.
+mar_status check_request(mar_ctx* c, const mar_request& r) {
+    mar_status st = check_scalars(c, r.n_seeds, r.nu, r.mu, r.kT, r.prec, r.form);
+    if (st != MAR_OK) return st;
+    if (!r.d_e_band) return set_err(c, MAR_ERR_ARG, "e_band output is NULL");
+    if (r.n_seeds > 0 && (!r.d_seeds || !r.d_rho)) return set_err(c, MAR_ERR_ARG, "seeds or rho is NULL");
+    return MAR_OK;
+}
+
+// Enqueue one solve (validated) on stream s with a resolved plan.
+mar_status dispatch_solve(mar_ctx* c, const mar_request& r, const Plan& pl, hipStream_t s) {
+    c->refused = false;
+    mar_status st;
+    if (r.prec == MAR_FP32)
+        st = pl.delayed ? run_solve_delayed<float>(c, r.d_seeds, r.n_seeds, r.nu, r.mu, r.kT, pl.B, pl.variant,
+                                                   r.d_rho, r.d_e_band, r.d_e_seed, r.d_n_seed, r.d_nu_eff,
+                                                   r.d_eps, r.d_weight, s)
+                        : run_solve<float>(c, r.d_seeds, r.n_seeds, r.nu, r.mu, r.kT, pl.B, r.d_rho, r.d_e_band,
+                                           r.d_e_seed, r.d_n_seed, r.d_nu_eff, r.d_eps, r.d_weight, s);
+    else
+        st = pl.delayed ? run_solve_delayed<double>(c, r.d_seeds, r.n_seeds, r.nu, r.mu, r.kT, pl.B, pl.variant,
+                                                    r.d_rho, r.d_e_band, r.d_e_seed, r.d_n_seed, r.d_nu_eff,
+                                                    r.d_eps, r.d_weight, s)
+                        : run_solve<double>(c, r.d_seeds, r.n_seeds, r.nu, r.mu, r.kT, pl.B, r.d_rho, r.d_e_band,
+                                            r.d_e_seed, r.d_n_seed, r.d_nu_eff, r.d_eps, r.d_weight, s);
+    return st;
+}
+
+// ------------------------------------------------------------- graph cache
+// Instantiated graphs of mar_solve_many, keyed by the exact request set.
+struct GraphEntry {
+    std::vector<mar_ctx*> ctxs;
+    std::vector<char> key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap = nullptr;
+    std::vector<hipEvent_t> events;
+    void release() {
+        if (exec) hipGraphExecDestroy(exec);
+        if (graph) hipGraphDestroy(graph);
+        for (auto e : events) hipEventDestroy(e);
+        if (cap) hipStreamDestroy(cap);
+        exec = nullptr;
+        graph = nullptr;
+        cap = nullptr;
+        events.clear();
+    }
+};
+std::mutex g_graph_mu;
+std::vector<GraphEntry*> g_graphs;   // most recent last
+constexpr size_t kMaxGraphs = 16;
+
+void drop_graphs_of(mar_ctx* c) {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    for (size_t i = 0; i < g_graphs.size();) {
+        GraphEntry* g = g_graphs[i];
+        if (std::find(g->ctxs.begin(), g->ctxs.end(), c) != g->ctxs.end()) {
+            g->release();
+            delete g;
+            g_graphs.erase(g_graphs.begin() + i);
+        } else {
+            ++i;
+        }
+    }
+}
+
+template <class X>
+void put(std::vector<char>& k, const X& x) {
+    const char* p = reinterpret_cast<const char*>(&x);
+    k.insert(k.end(), p, p + sizeof(X));
+}
+
+// Field by field: padding bytes of the structs are not part of the key.
+void put_request(std::vector<char>& k, mar_ctx* c, const mar_request& r, const Plan& pl) {
+    put(k, c);
+    put(k, r.d_seeds);
+    put(k, r.n_seeds);
+    put(k, r.nu);
+    put(k, r.mu);
+    put(k, r.kT);
+    put(k, (int32_t)r.prec);
+    put(k, (int32_t)r.form);
+    put(k, r.d_rho);
+    put(k, r.d_e_band);
+    put(k, r.d_e_seed);
+    put(k, r.d_n_seed);
+    put(k, r.d_nu_eff);
+    put(k, r.d_eps);
+    put(k, r.d_weight);
+    put(k, pl.B);
+    put(k, (int32_t)pl.delayed);
+    put(k, pl.variant);
+    put(k, c->tune);
+    put(k, c->ws);
+}
+
 }  // namespace
 
 // ======================================================================= ABI
@@ -658,7 +811,173 @@ mar_status mar_create(int64_t M, const int64_t* H_rowptr, const int32_t* H_col, 
 void mar_destroy(mar_ctx* ctx) {
     if (!ctx) return;
     hipDeviceSynchronize();
+    drop_graphs_of(ctx);
     delete ctx;
+}
+
+mar_status mar_solve_many(int32_t n_sys, mar_ctx* const* ctx, const mar_request* req, void* hip_stream) {
+    if (n_sys < 1 || !ctx || !req) {
+        if (n_sys >= 1 && ctx && ctx[0]) return set_err(ctx[0], MAR_ERR_ARG, "ctx or req is NULL");
+        return MAR_ERR_ARG;
+    }
+    for (int i = 0; i < n_sys; ++i) {
+        if (!ctx[i]) return ctx[0] ? set_err(ctx[0], MAR_ERR_ARG, fmt("ctx[%d] is NULL", i)) : MAR_ERR_STATE;
+        for (int k = 0; k < i; ++k)
+            if (ctx[k] == ctx[i]) return set_err(ctx[0], MAR_ERR_ARG, fmt("ctx[%d] repeats ctx[%d]", i, k));
+        if (ctx[i]->device != ctx[0]->device)
+            return set_err(ctx[0], MAR_ERR_ARG, fmt("ctx[%d] is on another device", i));
+        mar_status st = check_request(ctx[i], req[i]);
+        if (st != MAR_OK) return st;
+    }
+    mar_ctx* c0 = ctx[0];
+    HIP_OR(c0, hipSetDevice(c0->device));
+    std::vector<Plan> plans(n_sys);
+    std::vector<char> key;
+    for (int i = 0; i < n_sys; ++i) {
+        plans[i] = plan_solve(ctx[i], req[i].nu, req[i].prec, req[i].form, req[i].n_seeds);
+        put_request(key, ctx[i], req[i], plans[i]);
+    }
+    GraphEntry* hit = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        for (size_t g = 0; g < g_graphs.size(); ++g)
+            if (g_graphs[g]->key == key) {
+                hit = g_graphs[g];
+                g_graphs.erase(g_graphs.begin() + g);
+                g_graphs.push_back(hit);   // most recently used last
+                break;
+            }
+    }
+    if (!hit) {
+        // size and allocate every workspace first: nothing may allocate under capture
+        for (int i = 0; i < n_sys; ++i) {
+            ctx[i]->dry = true;
+            mar_status st = dispatch_solve(ctx[i], req[i], plans[i], ctx[i]->stream);
+            ctx[i]->dry = false;
+            if (st != MAR_OK) return st;
+        }
+        HIP_OR(c0, hipDeviceSynchronize());
+        key.clear();   // the workspaces may have moved
+        for (int i = 0; i < n_sys; ++i) put_request(key, ctx[i], req[i], plans[i]);
+        auto* g = new GraphEntry();
+        g->ctxs.assign(ctx, ctx + n_sys);
+        g->key = key;
+        auto fail = [&](mar_ctx* c, mar_status st, const std::string& m) {
+            g->release();
+            delete g;
+            return set_err(c, st, m);
+        };
+        if (hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking) != hipSuccess)
+            return fail(c0, MAR_ERR_HIP, "hipStreamCreateWithFlags failed");
+        g->events.resize(n_sys + 1, nullptr);
+        for (auto& e : g->events)
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+                return fail(c0, MAR_ERR_HIP, "hipEventCreateWithFlags failed");
+        std::vector<bool> prof(n_sys);
+        for (int i = 0; i < n_sys; ++i) {
+            prof[i] = ctx[i]->prof;
+            ctx[i]->prof = false;   // no timing events inside a graph
+        }
+        hipError_t he = hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal);
+        mar_status st = MAR_OK;
+        int bad = 0;
+        if (he == hipSuccess) {
+            // fork: every system's launch sequence is a branch off one event
+            hipEventRecord(g->events[n_sys], g->cap);
+            for (int i = 0; i < n_sys && st == MAR_OK; ++i) {
+                hipStreamWaitEvent(ctx[i]->stream, g->events[n_sys], 0);
+                st = dispatch_solve(ctx[i], req[i], plans[i], ctx[i]->stream);
+                if (st != MAR_OK) bad = i;
+                hipEventRecord(g->events[i], ctx[i]->stream);
+                hipStreamWaitEvent(g->cap, g->events[i], 0);
+            }
+            he = hipStreamEndCapture(g->cap, &g->graph);
+        }
+        for (int i = 0; i < n_sys; ++i) ctx[i]->prof = prof[i];
+        if (st != MAR_OK) {
+            const std::string m = ctx[bad]->err;
+            return fail(ctx[bad], st, m);
+        }
+        if (he != hipSuccess) return fail(c0, MAR_ERR_HIP, fmt("graph capture failed: %s", hipGetErrorString(he)));
+        he = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+        if (he != hipSuccess)
+            return fail(c0, MAR_ERR_HIP, fmt("hipGraphInstantiate failed: %s", hipGetErrorString(he)));
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        if (g_graphs.size() >= kMaxGraphs) {
+            GraphEntry* old = g_graphs.front();
+            hipDeviceSynchronize();
+            old->release();
+            delete old;
+            g_graphs.erase(g_graphs.begin());
+        }
+        g_graphs.push_back(g);
+        hit = g;
+    }
+    HIP_OR(c0, hipGraphLaunch(hit->exec, (hipStream_t)hip_stream));
+    return MAR_OK;
+}
+
+mar_status mar_autotune(mar_ctx* c, int32_t nu, mar_precision prec, const int32_t* d_seeds, int64_t n_seeds,
+                        double mu, double kT, void* hip_stream, int32_t* best_block, int32_t* best_variant,
+                        double* best_rate) {
+    if (!c) return MAR_ERR_STATE;
+    mar_status st = check_scalars(c, n_seeds, nu, mu, kT, prec, MAR_FORM_BATCHED);
+    if (st != MAR_OK) return st;
+    if (n_seeds < 1 || !d_seeds) return set_err(c, MAR_ERR_ARG, "the autotuner needs at least one seed");
+    HIP_OR(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (!c->tune_buf) {
+        void* p = nullptr;
+        HIP_OR(c, hipMalloc(&p, (size_t)(c->nnzH + 1) * 8));
+        c->tune_buf = (double*)p;
+        c->allocs.push_back(p);
+    }
+    const int64_t n_probe = std::min<int64_t>(n_seeds, 256);
+    mar_request r{d_seeds, n_probe, nu, mu, kT, prec, MAR_FORM_BATCHED, c->tune_buf, c->tune_buf + c->nnzH,
+                  nullptr, nullptr, nullptr, nullptr, nullptr};
+    const mar_tuning saved = c->tune;
+    const bool delayed = saved.schedule != MAR_SCHED_TEXTBOOK;
+    const int cap = std::min<int64_t>(block_cap(c, nu, prec, delayed), pow2_floor(n_probe) * 2);
+    hipEvent_t e0, e1;
+    HIP_OR(c, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return set_err(c, MAR_ERR_HIP, "hipEventCreate failed");
+    }
+    int bestB = 0, bestV = 0;
+    double bestR = -1.0;
+    for (int B = std::min(cap, 16); B <= cap && st == MAR_OK; B *= 2) {
+        for (int v : {0, 3}) {
+            if (!delayed && v != 0) continue;
+            Plan pl{B, delayed, v};
+            st = dispatch_solve(c, r, pl, s);          // warm-up (sizes the workspace)
+            if (st != MAR_OK) break;
+            hipEventRecord(e0, s);
+            st = dispatch_solve(c, r, pl, s);
+            hipEventRecord(e1, s);
+            if (st != MAR_OK) break;
+            if (hipEventSynchronize(e1) != hipSuccess) {
+                st = set_err(c, MAR_ERR_HIP, "autotuner: hipEventSynchronize failed");
+                break;
+            }
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, e0, e1);
+            const double rate = ms > 0.f ? n_probe / (ms * 1e-3) : 0.0;
+            if (rate > bestR) {
+                bestR = rate;
+                bestB = B;
+                bestV = v;
+            }
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st != MAR_OK) return st;
+    c->tuned[{nu, (int)prec}] = {bestB, bestV};
+    if (best_block) *best_block = bestB;
+    if (best_variant) *best_variant = bestV;
+    if (best_rate) *best_rate = bestR;
+    return MAR_OK;
 }
 
 mar_status mar_solve_async(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds, int32_t nu, double mu, double kT,
@@ -670,25 +989,9 @@ mar_status mar_solve_async(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds, 
     if (!d_e_band) return set_err(c, MAR_ERR_ARG, "e_band output is NULL");
     if (n_seeds > 0 && (!d_seeds || !d_rho)) return set_err(c, MAR_ERR_ARG, "seeds or rho is NULL");
     HIP_OR(c, hipSetDevice(c->device));
-    c->refused = false;
-    hipStream_t s = (hipStream_t)hip_stream;
-    const int B = form == MAR_FORM_PLAIN ? 1 : choose_block(c, nu, prec, n_seeds);
-    // schedule: the plain form is the textbook CGS2 (project, update, project,
-    // update); the batched form defaults to the delayed-reorthogonalization one
-    const bool delayed = c->tune.schedule == MAR_SCHED_DELAYED ||
-                         (c->tune.schedule == MAR_SCHED_AUTO && form == MAR_FORM_BATCHED);
-    if (prec == MAR_FP32) {
-        if (delayed)
-            return run_solve_delayed<float>(c, d_seeds, n_seeds, nu, mu, kT, B, d_rho, d_e_band, d_e_seed, d_n_seed,
-                                            d_nu_eff, d_eps, d_weight, s);
-        return run_solve<float>(c, d_seeds, n_seeds, nu, mu, kT, B, d_rho, d_e_band, d_e_seed, d_n_seed, d_nu_eff,
-                                d_eps, d_weight, s);
-    }
-    if (delayed)
-        return run_solve_delayed<double>(c, d_seeds, n_seeds, nu, mu, kT, B, d_rho, d_e_band, d_e_seed, d_n_seed,
-                                         d_nu_eff, d_eps, d_weight, s);
-    return run_solve<double>(c, d_seeds, n_seeds, nu, mu, kT, B, d_rho, d_e_band, d_e_seed, d_n_seed, d_nu_eff,
-                             d_eps, d_weight, s);
+    mar_request r{d_seeds, n_seeds, nu, mu, kT, prec, form, d_rho, d_e_band, d_e_seed, d_n_seed, d_nu_eff, d_eps,
+                  d_weight};
+    return dispatch_solve(c, r, plan_solve(c, nu, prec, form, n_seeds), (hipStream_t)hip_stream);
 }
 
 mar_status mar_solve(mar_ctx* c, const int32_t* seeds, int64_t n_seeds, int32_t nu, double mu, double kT,
@@ -782,7 +1085,7 @@ mar_status mar_get_tuning(const mar_ctx* c, mar_tuning* t) {
 
 int32_t mar_seed_block(const mar_ctx* c, int32_t nu, mar_precision prec) {
     if (!c) return 0;
-    return choose_block(c, nu, prec, 0);
+    return plan_solve(c, nu, prec, MAR_FORM_BATCHED, 0).B;
 }
 
 const char* mar_last_error(const mar_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }

@@ -40,6 +40,13 @@ class mar_tuning(C.Structure):
                 ("reserved", C.c_int32 * 2)]
 
 
+class mar_request(C.Structure):
+    _fields_ = [("d_seeds", C.c_void_p), ("n_seeds", C.c_int64), ("nu", C.c_int32), ("mu", C.c_double),
+                ("kT", C.c_double), ("prec", C.c_int), ("form", C.c_int), ("d_rho", C.c_void_p),
+                ("d_e_band", C.c_void_p), ("d_e_seed", C.c_void_p), ("d_n_seed", C.c_void_p),
+                ("d_nu_eff", C.c_void_p), ("d_eps", C.c_void_p), ("d_weight", C.c_void_p)]
+
+
 class mar_prof_entry(C.Structure):
     _fields_ = [("name", C.c_char * 24), ("launches", C.c_int64), ("ms", C.c_double),
                 ("bytes", C.c_double), ("flops", C.c_double)]
@@ -72,6 +79,11 @@ def lib() -> C.CDLL:
     L.mar_solve.restype = C.c_int
     L.mar_solve_async.argtypes = [_P, _P, i64, i32, f64, f64, C.c_int, C.c_int, _P, _P, _P, _P, _P, _P, _P, _P]
     L.mar_solve_async.restype = C.c_int
+    L.mar_solve_many.argtypes = [i32, C.POINTER(_P), C.POINTER(mar_request), _P]
+    L.mar_solve_many.restype = C.c_int
+    L.mar_autotune.argtypes = [_P, i32, C.c_int, _P, i64, f64, f64, _P, C.POINTER(i32), C.POINTER(i32),
+                               C.POINTER(f64)]
+    L.mar_autotune.restype = C.c_int
     L.mar_set_tuning.argtypes = [_P, C.POINTER(mar_tuning)]
     L.mar_set_tuning.restype = C.c_int
     L.mar_get_tuning.argtypes = [_P, C.POINTER(mar_tuning)]
@@ -146,6 +158,30 @@ def mar_solve_async(ctx, d_seeds, n_seeds, nu, mu, kT, prec, form, d_rho, d_e_ba
     return lib().mar_solve_async(ctx, _tptr(d_seeds), int(n_seeds), int(nu), float(mu), float(kT), int(prec),
                                  int(form), _tptr(d_rho), _tptr(d_e_band), _tptr(d_e_seed), _tptr(d_n_seed),
                                  _tptr(d_nu_eff), _tptr(d_eps), _tptr(d_weight), stream)
+
+
+def mar_request_of(d_seeds, nu, mu, kT, prec, form, d_rho, d_e_band, d_e_seed=None, d_n_seed=None,
+                   d_nu_eff=None, d_eps=None, d_weight=None) -> mar_request:
+    """A request struct for mar_solve_many from device tensors (torch)."""
+    return mar_request(_tptr(d_seeds), int(d_seeds.numel()), int(nu), float(mu), float(kT), int(prec), int(form),
+                       _tptr(d_rho), _tptr(d_e_band), _tptr(d_e_seed), _tptr(d_n_seed), _tptr(d_nu_eff),
+                       _tptr(d_eps), _tptr(d_weight))
+
+
+def mar_solve_many(ctxs, requests, stream=None) -> int:
+    """One graph launch solving every (context, request) pair; returns the status."""
+    n = len(ctxs)
+    arr_c = (_P * n)(*[c.value if isinstance(c, _P) else c for c in ctxs])
+    arr_r = (mar_request * n)(*requests)
+    return lib().mar_solve_many(n, arr_c, arr_r, stream)
+
+
+def mar_autotune(ctx, nu, prec, d_seeds, mu, kT, stream=None) -> tuple:
+    """Returns (status, seed_block, proj_variant, probe seed-subspaces/s)."""
+    b, v, r = C.c_int32(), C.c_int32(), C.c_double()
+    st = lib().mar_autotune(ctx, int(nu), int(prec), _tptr(d_seeds), int(d_seeds.numel()), float(mu), float(kT),
+                            stream, C.byref(b), C.byref(v), C.byref(r))
+    return st, b.value, v.value, r.value
 
 
 def mar_set_tuning(ctx, seed_block: int = 0, schedule: int = 0, proj_wgs: int = 0, slab_pad_kb: int = 0,
@@ -240,6 +276,15 @@ class Context:
         _check(self.handle, mar_set_tuning(self.handle, seed_block, SCHEDULE[schedule], proj_wgs, slab_pad_kb,
                                            proj_variant, upd_q))
 
+    def autotune(self, d_seeds, nu, mu, kT, precision="fp32", stream=None) -> dict:
+        """Pick the seed block and projection tiles for (nu, precision) by timing probe solves."""
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        st, b, v, r = mar_autotune(self.handle, nu, PRECISION[precision], d_seeds, mu, kT, stream)
+        _check(self.handle, st)
+        return dict(seed_block=b, proj_variant=v, probe_rate=r)
+
     def seed_block(self, nu: int, precision: str = "fp32") -> int:
         return mar_seed_block(self.handle, nu, PRECISION[precision])
 
@@ -254,3 +299,25 @@ class Context:
 
     def info(self) -> dict:
         return mar_ctx_info(self.handle)
+
+
+def solve_many(contexts, requests, stream=None):
+    """Solve several systems with one graph launch.
+
+    contexts: Context objects (distinct); requests: dicts with the keyword
+    arguments of Context.solve_async (d_seeds, nu, mu, kT, precision, form,
+    d_rho, d_e_band, optional d_e_seed, d_n_seed, d_nu_eff, d_eps, d_weight).
+    """
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream().cuda_stream
+    reqs = []
+    for r in requests:
+        reqs.append(mar_request_of(r["d_seeds"], r["nu"], r["mu"], r["kT"], PRECISION[r.get("precision", "fp32")],
+                                   FORM[r.get("form", "batched")], r["d_rho"], r["d_e_band"], r.get("d_e_seed"),
+                                   r.get("d_n_seed"), r.get("d_nu_eff"), r.get("d_eps"), r.get("d_weight")))
+    handles = [c.handle for c in contexts]
+    st = mar_solve_many(handles, reqs, stream)
+    if st != MAR_OK:
+        msgs = "; ".join(m for m in (mar_last_error(h) for h in handles) if m)
+        raise MarError(st, msgs)
