@@ -11,6 +11,14 @@ same GPU (one seed at a time), the per-kernel roofline from HIP events on the
 solve stream, and the FP64 CPU oracle on a bounded seed sample.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+Other workloads (not the headline line):
+    --workload uneven8   the eight uneven diamond systems (M = 1024 ... 65536,
+                         nu alternating 30/100), every seed of every system,
+                         FP32 batched through mar_solve_many (one graph launch
+                         per call, autotuned block sizes), beside the same work
+                         issued eagerly system after system.
+    --workload mixed_32x32x32 --nu 300   the M = 1048576 lattice (seed blocks of 64).
 """
 from __future__ import annotations
 
@@ -48,6 +56,86 @@ def cpu_baseline(system, nu, mu, n_seeds, workers):
                        f"FP64 NumPy/SciPy, one process per core, {dt:.1f} s wall")
 
 
+def run_uneven(args) -> int:
+    """All seeds of the eight uneven systems: graph-launched batches vs eager per-system solves."""
+    import torch
+    from paper_1307_3218_amd import lattice, mar
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    calls = max(1, args.uneven_calls)
+    mu = -0.45
+    systems, ctxs, reqs, seeds_all = [], [], [], []
+    t = time.perf_counter()
+    for i, cells in enumerate(lattice.UNEVEN_SYSTEMS):
+        s = lattice.generate(*cells, mixed=False, seed=0)
+        nu = 30 if i % 2 == 0 else 100
+        systems.append((s, nu))
+        ctxs.append(mar.Context(s.H, s.S))
+    log(f"8 systems built ({time.perf_counter() - t:.1f} s): M = {[s.M for s, _ in systems]}")
+    tuned = []
+    for (s, nu), c in zip(systems, ctxs):
+        order = torch.from_numpy(np.random.default_rng(0).permutation(s.M).astype(np.int32)).to(dev)
+        seeds_all.append(order)
+        tuned.append(c.autotune(order[: min(256, s.M)], nu, mu, KT, "fp32"))
+        n = s.M // calls
+        reqs.append(dict(d_seeds=torch.empty(n, dtype=torch.int32, device=dev), nu=nu, mu=mu, kT=KT,
+                         precision="fp32", form="batched",
+                         d_rho=torch.zeros(s.H.nnz, dtype=torch.float64, device=dev),
+                         d_e_band=torch.zeros(1, dtype=torch.float64, device=dev)))
+    log("autotuned (B, variant): " + ", ".join(f"M={s.M}:{t_['seed_block']}/{t_['proj_variant']}"
+                                                for (s, _), t_ in zip(systems, tuned)))
+    total = sum(s.M for s, _ in systems)
+
+    def graph_pass():
+        e = 0.0
+        for k in range(calls):
+            for (s, _), r, order in zip(systems, reqs, seeds_all):
+                n = r["d_seeds"].numel()
+                r["d_seeds"].copy_(order[k * n:(k + 1) * n])
+            mar.solve_many(ctxs, reqs)
+            e += float(sum(r["d_e_band"] for r in reqs))   # synchronizes; E summed over calls
+        return e
+
+    def eager_pass():
+        e = 0.0
+        for (s, nu), c, r, order in zip(systems, ctxs, reqs, seeds_all):
+            c.solve_async(order, nu, mu, KT, "fp32", "batched", d_rho=r["d_rho"], d_e_band=r["d_e_band"])
+            e += float(r["d_e_band"])
+        return e
+
+    t = time.perf_counter()
+    graph_pass()            # captures the graph once (identical shapes on every call)
+    torch.cuda.synchronize()
+    log(f"warmup pass (with capture): {time.perf_counter() - t:.1f} s")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e_graph = graph_pass()
+    torch.cuda.synchronize()
+    dt_graph = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    e_eager = eager_pass()
+    torch.cuda.synchronize()
+    dt_eager = time.perf_counter() - t0
+    log(f"graph: {total} seeds in {dt_graph:.2f} s; eager: {dt_eager:.2f} s; E_band {e_graph:.6f} / {e_eager:.6f}")
+    out = {
+        "metric": "seed-subspaces/s, 8 uneven diamond systems, FP32 batched, graph-launched",
+        "value": round(total / dt_graph, 3), "unit": "seed-subspaces/s", "n_gpus": 1, "steps": calls, "warmup": calls,
+        "ms_per_step": round(1e3 * dt_graph / calls, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "8 diamond systems M=1024..65536, nu 30/100 alternating, all seeds",
+                   "M": [s.M for s, _ in systems], "nu": [nu for _, nu in systems], "seeds": total,
+                   "calls_per_pass": calls, "mu": mu,
+                   "autotuned": [dict(M=s.M, B=t_["seed_block"], variant=t_["proj_variant"])
+                                 for (s, _), t_ in zip(systems, tuned)]},
+        "eager_sequential": {"value": round(total / dt_eager, 3), "unit": "seed-subspaces/s"},
+        "e_band_graph_minus_eager": e_graph - e_eager,
+    }
+    print(json.dumps(out), flush=True)
+    for c in ctxs:
+        c.close()
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -62,6 +150,8 @@ def main() -> int:
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--seed-block", type=int, default=0)
+    ap.add_argument("--uneven-calls", type=int, default=8,
+                    help="uneven8: mar_solve_many calls per pass over all seeds (each takes M/calls seeds per system)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="first run a plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -72,6 +162,8 @@ def main() -> int:
               "would shard the seed list (no collective on the hot path). Run with --gpus 1.", file=sys.stderr)
         return 2
 
+    if args.workload == "uneven8":
+        return run_uneven(args)
     from paper_1307_3218_amd import fermi, lattice, mar
     t = time.perf_counter()
     system = lattice.workload(args.workload)
