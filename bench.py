@@ -145,6 +145,7 @@ def main() -> int:
     ap.add_argument("--nu", type=int, default=100)
     ap.add_argument("--seeds-per-step", type=int, default=1024)
     ap.add_argument("--plain-seeds", type=int, default=16)
+    ap.add_argument("--fp64-batched-seeds", type=int, default=256)
     ap.add_argument("--cpu-seeds", type=int, default=0, help="oracle sample size (0 = about 20 s of CPU work)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -273,6 +274,23 @@ def main() -> int:
         plain = dict(value=n_p / dtp, unit="seed-subspaces/s", seeds=n_p, seconds=round(dtp, 3))
         log(f"plain FP64: {n_p} seeds in {dtp:.3f} s -> {n_p / dtp:.2f} seed-subspaces/s")
 
+    # the two other corners, splitting the precision gain from the batching gain
+    split = {}
+    if not args.no_plain and args.plain_seeds > 0:
+        for prec, form, n_x in (("fp32", "plain", args.plain_seeds), ("fp64", "batched", args.fp64_batched_seeds)):
+            if n_x <= 0:
+                continue
+            d_sx = d_order[-n_x:]
+            ctx.solve_async(d_sx[: min(n_x, 4)], nu, mu, KT, prec, form, d_rho=d_rho, d_e_band=d_eb, stream=stream)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            ctx.solve_async(d_sx, nu, mu, KT, prec, form, d_rho=d_rho, d_e_band=d_eb, stream=stream)
+            torch.cuda.synchronize()
+            dtx = time.perf_counter() - t1
+            split[f"{prec}_{form}"] = dict(value=round(n_x / dtx, 3), unit="seed-subspaces/s", seeds=n_x,
+                                           seed_block=1 if form == "plain" else ctx.seed_block(nu, prec))
+            log(f"{prec} {form}: {n_x} seeds in {dtx:.3f} s -> {n_x / dtx:.2f} seed-subspaces/s")
+
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import mar_oracle as O
@@ -302,6 +320,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "fp64_plain": plain,
         "ratio_fp32_batched_over_fp64_plain": round(value / plain["value"], 3) if plain else None,
+        "precision_batching_split": split or None,
         "spmm_hbm": spmm,
         "kernels": kernels,
     }

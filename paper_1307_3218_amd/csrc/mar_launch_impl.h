@@ -51,6 +51,11 @@ __global__ __launch_bounds__(WG) void k_init(int64_t Mp, int64_t M, const int32_
 // Y = A X over B seed-interleaved vectors, A in BSR 4x4. Thread = (block row,
 // seed group). The 16 block values are read once per thread and reused for
 // SW seeds; X rows of the block column are 16-byte vector loads.
+// Blocks of a row are taken CH at a time: the CH column indices, then all
+// 4*CH X vectors and block values are requested before any is used, so one
+// memory latency covers CH blocks. When a wavefront holds one block row
+// (P = 64) the row index is made wavefront-uniform, so indices and block
+// values come through scalar loads.
 // NDOT >= 1: also emit per-workgroup FP64 partial sums of X.Y per seed (the
 // S-norm w^T S w of a residual when A = S); NDOT = 2 adds X.X. Partials are
 // laid out part[wg][d][b].
@@ -73,7 +78,59 @@ __global__ __launch_bounds__(WG) void k_spmm_bsr4(int64_t nbrow, const int32_t* 
     for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int i = 0; i < SW; ++i) acc[r][i] = (T)0;
-    if (I < nbrow) {
+    if constexpr (B >= VEC) {
+        constexpr int CH = P == 64 ? 4 : 2;   // blocks in flight per row
+        int64_t Iu = I;
+        if constexpr (P == 64) Iu = __builtin_amdgcn_readfirstlane((int)I);   // one row per wavefront
+        if (Iu < nbrow) {
+            const int lo = brp[Iu], hi = brp[Iu + 1];
+            for (int b0 = lo; b0 < hi; b0 += CH) {
+                int blk[CH];
+                int64_t J[CH];
+#pragma unroll
+                for (int t = 0; t < CH; ++t) {
+                    blk[t] = b0 + t < hi ? b0 + t : hi - 1;   // repeats the last block; its sum is skipped
+                    J[t] = bcol[blk[t]];
+                }
+                T xv[CH][4][VEC];
+#pragma unroll
+                for (int t = 0; t < CH; ++t)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) unpack(Xv[((4 * J[t] + c) * B + s0) / VEC], xv[t][c]);
+                T a[CH][16];
+#pragma unroll
+                for (int t = 0; t < CH; ++t) {
+                    const VT* av = reinterpret_cast<const VT*>(bval + (int64_t)blk[t] * 16);
+#pragma unroll
+                    for (int q = 0; q < 16 / VEC; ++q) {
+                        T u[VEC];
+                        unpack(av[q], u);
+#pragma unroll
+                        for (int i = 0; i < VEC; ++i) a[t][q * VEC + i] = u[i];
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < CH; ++t) {
+                    if (b0 + t < hi) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+#pragma unroll
+                            for (int i = 0; i < SW; ++i) {
+                                T sacc = acc[r][i];
+                                sacc = fma(a[t][r * 4 + 0], xv[t][0][i], sacc);
+                                sacc = fma(a[t][r * 4 + 1], xv[t][1][i], sacc);
+                                sacc = fma(a[t][r * 4 + 2], xv[t][2][i], sacc);
+                                sacc = fma(a[t][r * 4 + 3], xv[t][3][i], sacc);
+                                acc[r][i] = sacc;
+                            }
+                    }
+                }
+            }
+            VT* Yv = reinterpret_cast<VT*>(Y);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Yv[((4 * Iu + r) * B + s0) / VEC] = pack(acc[r]);
+        }
+    } else if (I < nbrow) {
         const int lo = brp[I], hi = brp[I + 1];
         for (int blk = lo; blk < hi; ++blk) {
             const int64_t J = bcol[blk];
@@ -86,29 +143,20 @@ __global__ __launch_bounds__(WG) void k_spmm_bsr4(int64_t nbrow, const int32_t* 
 #pragma unroll
                 for (int i = 0; i < VEC; ++i) a[q * VEC + i] = t[i];
             }
+            // B < VEC: one vector holds VEC / B rows of all B seeds
             T xv[4][SW];
-            if constexpr (B >= VEC) {
+            T t[4 * B];
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    T t[VEC];
-                    unpack(Xv[((4 * J + c) * B + s0) / VEC], t);
+            for (int q = 0; q < 4 * B / VEC; ++q) {
+                T u[VEC];
+                unpack(Xv[(4 * J * B) / VEC + q], u);
 #pragma unroll
-                    for (int i = 0; i < VEC; ++i) xv[c][i] = t[i];
-                }
-            } else {
-                T t[4 * B];
-#pragma unroll
-                for (int q = 0; q < 4 * B / VEC; ++q) {
-                    T u[VEC];
-                    unpack(Xv[(4 * J * B) / VEC + q], u);
-#pragma unroll
-                    for (int i = 0; i < VEC; ++i) t[q * VEC + i] = u[i];
-                }
-#pragma unroll
-                for (int c = 0; c < 4; ++c)
-#pragma unroll
-                    for (int i = 0; i < SW; ++i) xv[c][i] = t[c * B + i];
+                for (int i = 0; i < VEC; ++i) t[q * VEC + i] = u[i];
             }
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+#pragma unroll
+                for (int i = 0; i < SW; ++i) xv[c][i] = t[c * B + i];
 #pragma unroll
             for (int r = 0; r < 4; ++r)
 #pragma unroll
@@ -122,17 +170,12 @@ __global__ __launch_bounds__(WG) void k_spmm_bsr4(int64_t nbrow, const int32_t* 
                 }
         }
         VT* Yv = reinterpret_cast<VT*>(Y);
-        if constexpr (B >= VEC) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) Yv[((4 * I + r) * B + s0) / VEC] = pack(acc[r]);
-        } else {
+        for (int q = 0; q < 4 * B / VEC; ++q) {
+            T u[VEC];
 #pragma unroll
-            for (int q = 0; q < 4 * B / VEC; ++q) {
-                T u[VEC];
-#pragma unroll
-                for (int i = 0; i < VEC; ++i) u[i] = acc[(q * VEC + i) / B][(q * VEC + i) % B];
-                Yv[(4 * I * B) / VEC + q] = pack(u);
-            }
+            for (int i = 0; i < VEC; ++i) u[i] = acc[(q * VEC + i) / B][(q * VEC + i) % B];
+            Yv[(4 * I * B) / VEC + q] = pack(u);
         }
     }
     if constexpr (NDOT > 0) {
@@ -143,13 +186,21 @@ __global__ __launch_bounds__(WG) void k_spmm_bsr4(int64_t nbrow, const int32_t* 
             for (int i = 0; i < SW; ++i) d[v][i] = 0.0;
         if (I < nbrow) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
+            for (int r = 0; r < 4; ++r) {
+                T xr[SW];
+                if constexpr (B >= VEC) {
+                    unpack(Xv[((4 * I + r) * B + s0) / VEC], xr);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < SW; ++i) xr[i] = X[(4 * I + r) * B + s0 + i];
+                }
 #pragma unroll
                 for (int i = 0; i < SW; ++i) {
-                    const double xv = (double)X[(4 * I + r) * B + s0 + i];
+                    const double xv = (double)xr[i];
                     d[0][i] += xv * (double)acc[r][i];
                     if constexpr (NDOT > 1) d[1][i] += xv * xv;
                 }
+            }
         }
         __shared__ double lds[SeedReduce<P, SW, NDOT>::LDS];
         wg_seed_reduce<P, SW, NDOT>(d, lds, [&](int v, int b, double s) { part[(bid * NDOT + v) * B + b] = s; });
