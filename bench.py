@@ -43,6 +43,30 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of ``kernel`` from the committed rocprofv3 counter summary, or None.
+
+    The summary records a hash of the kernel sources it was measured on; when the
+    sources have changed since, the figure no longer describes this build (None).
+    """
+    import glob
+    import hashlib
+    src = b"".join(open(os.path.join(ROOT, "paper_1307_3218_amd", "csrc", f), "rb").read()
+                   for f in ("mar_launch_impl.h", "mar_device.h"))
+    sha = hashlib.sha256(src).hexdigest()[:16]
+    for path in glob.glob(os.path.join(ROOT, "profiles", "hbm_traffic_*.md")):
+        text = open(path).read()
+        for block in text.split("```json")[1:]:
+            try:
+                rec = json.loads(block.split("```")[0])
+            except ValueError:
+                continue
+            if rec.get("kernel") == kernel and rec.get("workload") == workload and \
+                    rec.get("kernel_source_sha256_16") == sha:
+                return float(rec["traffic_bytes_per_launch"])
+    return None
+
+
 def cpu_baseline(system, nu, mu, n_seeds, workers):
     """The oracle as it stands, on a bounded seed sample, process-parallel over host cores."""
     from oracle import mar_oracle as O
@@ -251,8 +275,11 @@ def main() -> int:
         dom = max(prof, key=lambda n: prof[n]["ms"])
         e = prof[dom]
         ach = e["bytes"] / (e["ms"] * 1e-3) / 1e9
+        kind, cells = system.name.split("_", 1)          # e.g. mixed, 16x16x16
+        wl = f"{kind}{cells.split('x')[0]}_nu{nu}_fp32_b{B}"
+        traffic = measured_traffic(dom, wl) if S_step % B == 0 else None
         roofline = dict(kernel=dom, bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
-                        frac=round(ach / HBM_PEAK_GBPS, 4), traffic=None,
+                        frac=round(ach / HBM_PEAK_GBPS, 4), traffic=traffic,
                         bytes_per_launch=e["bytes"] / e["launches"], avg_launch_us=1e3 * e["ms"] / e["launches"])
         s = prof.get("spmm")
         if s and s["ms"] > 0:
