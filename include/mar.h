@@ -144,6 +144,31 @@ mar_status mar_solve_async(mar_ctx* ctx, const int32_t* d_seeds, int64_t n_seeds
                            double* d_rho, double* d_e_band, double* d_e_seed, double* d_n_seed,
                            int32_t* d_nu_eff, double* d_eps, double* d_weight, void* hip_stream);
 
+/* ---- Fermi level found on the device ----
+ * The method takes the chemical potential mu as given (Sec. 2: the subspace
+ * levels give the Green's function, and from it the energy at mu). These
+ * entry points find it instead: the subspace eigenpairs of every listed seed
+ * are computed first (levels, weights and the rows e_i.v_alpha, i in P(j),
+ * kept on the device), then mu is bisected on the device, 200 halvings of
+ * [min eps - 40 kT, max eps + 40 kT] over all kept levels, so that
+ *     N(mu) = sum_j 2 sum_alpha f((eps_alpha^(j) - mu)/kT) w_alpha^(j) = n_target
+ * (half filling of a seed sample: n_target = n_seeds), and rho, E_j, N_j and
+ * E_band are assembled at that mu. No second Krylov pass. Where N(mu) is not
+ * monotone (some w_alpha < 0 when S != I) the bisection returns a root inside
+ * the bracket. Arguments and outputs as in mar_solve_async / mar_solve, plus
+ * n_target (finite, >= 0) and mu (one double, device or host) receiving the
+ * level. The kept rows take n_seeds * nu * (max row length of H) * 8 bytes of
+ * device memory, owned by the context. */
+mar_status mar_solve_fermi_async(mar_ctx* ctx, const int32_t* d_seeds, int64_t n_seeds, int32_t nu,
+                                 double n_target, double kT, mar_precision prec, mar_form form,
+                                 double* d_rho, double* d_e_band, double* d_e_seed, double* d_n_seed,
+                                 int32_t* d_nu_eff, double* d_eps, double* d_weight, double* d_mu,
+                                 void* hip_stream);
+mar_status mar_solve_fermi(mar_ctx* ctx, const int32_t* seeds, int64_t n_seeds, int32_t nu, double n_target,
+                           double kT, mar_precision prec, mar_form form, double* rho, double* e_band,
+                           double* mu, double* e_seed, double* n_seed, int32_t* nu_eff, double* eps,
+                           double* weight);
+
 /* ---- several independent systems in one launch ----
  * One request per context: the same arguments as mar_solve_async (device
  * pointers, validated the same way). */

@@ -24,11 +24,11 @@ namespace {
 // One class per kernel variant, so that a class maps to one kernel symbol in a trace.
 enum ProfClass {
     P_INIT = 0, P_SPMM, P_SPMM_DOT, P_PROJ2, P_PROJ1, P_UPD, P_REDUCE, P_NORM, P_APPEND, P_EIG, P_SUM,
-    P_PROJR, P_UPD2, P_COEF, P_COUNT
+    P_PROJR, P_UPD2, P_COEF, P_MU, P_COUNT
 };
 const char* kProfNames[P_COUNT] = {"init",   "spmm",     "spmm_dot",  "cgs_proj_KSK", "cgs_proj_1",
                                    "cgs_upd", "reduce",  "norm",      "append",       "eig",
-                                   "sum",     "dcgs_proj", "dcgs_upd", "dcgs_coef"};
+                                   "sum",     "dcgs_proj", "dcgs_upd", "dcgs_coef", "fermi_search"};
 
 struct ProfRec {
     int cls;
@@ -67,6 +67,9 @@ struct mar_ctx {
     // autotuned (B, projection variant) by (nu, precision)
     std::map<std::pair<int, int>, std::pair<int, int>> tuned;
     double* tune_buf = nullptr;   // probe outputs of the autotuner: rho [nnz(H)] + e_band
+    double* zc_defer = nullptr;   // set during a solve whose assembly waits for a device Fermi level
+    char* fws = nullptr;          // workspace of the device Fermi-level search
+    size_t fws_bytes = 0;
 
     mar_tuning tune{};
     char* ws = nullptr;
@@ -91,6 +94,7 @@ struct mar_ctx {
         for (void* p : allocs) hipFree(p);
         if (ws) hipFree(ws);
         if (io) hipFree(io);
+        if (fws) hipFree(fws);
         if (stream) hipStreamDestroy(stream);
     }
 };
@@ -463,10 +467,11 @@ mar_status run_solve(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds, int nu
         launch(c, s, P_EIG, [&] {
             return mar::launch_eig(ns, seeds, nu, ws.h, nucp, Kp, c->Hrp, c->Hcol, c->Hval, c->SvalH, c->diagS,
                                    c->max_row, mu, kT, d_rho, e_seed + blk0, n_seed + blk0, nu_out + blk0,
-                                   d_eps ? d_eps + blk0 * nu : nullptr, d_w ? d_w + blk0 * nu : nullptr, s);
+                                   d_eps ? d_eps + blk0 * nu : nullptr, d_w ? d_w + blk0 * nu : nullptr,
+                                   c->zc_defer ? c->zc_defer + (size_t)blk0 * nu * c->max_row : nullptr, s);
         });
     }
-    launch(c, s, P_SUM, [&] { return mar::launch_sum(e_seed, n_seeds, d_e_band, s); });
+    if (!c->zc_defer) launch(c, s, P_SUM, [&] { return mar::launch_sum(e_seed, n_seeds, d_e_band, s); });
     if (c->refused) {
         c->refused = false;
         return set_err(c, MAR_ERR_STATE, "internal error: a partial-sum buffer was too small; solve not run");
@@ -611,10 +616,11 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
         launch(c, s, P_EIG, [&] {
             return mar::launch_eig(ns, seeds, nu, h, nucp, Kp, c->Hrp, c->Hcol, c->Hval, c->SvalH, c->diagS,
                                    c->max_row, mu, kT, d_rho, e_seed + blk0, n_seed + blk0, nu_out + blk0,
-                                   d_eps ? d_eps + blk0 * nu : nullptr, d_w ? d_w + blk0 * nu : nullptr, s);
+                                   d_eps ? d_eps + blk0 * nu : nullptr, d_w ? d_w + blk0 * nu : nullptr,
+                                   c->zc_defer ? c->zc_defer + (size_t)blk0 * nu * c->max_row : nullptr, s);
         });
     }
-    launch(c, s, P_SUM, [&] { return mar::launch_sum(e_seed, n_seeds, d_e_band, s); });
+    if (!c->zc_defer) launch(c, s, P_SUM, [&] { return mar::launch_sum(e_seed, n_seeds, d_e_band, s); });
     if (c->refused) {
         c->refused = false;
         return set_err(c, MAR_ERR_STATE, "internal error: a partial-sum buffer was too small; solve not run");
@@ -992,6 +998,140 @@ mar_status mar_solve_async(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds, 
     mar_request r{d_seeds, n_seeds, nu, mu, kT, prec, form, d_rho, d_e_band, d_e_seed, d_n_seed, d_nu_eff, d_eps,
                   d_weight};
     return dispatch_solve(c, r, plan_solve(c, nu, prec, form, n_seeds), (hipStream_t)hip_stream);
+}
+
+mar_status mar_solve_fermi_async(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds, int32_t nu, double n_target,
+                                 double kT, mar_precision prec, mar_form form, double* d_rho, double* d_e_band,
+                                 double* d_e_seed, double* d_n_seed, int32_t* d_nu_eff, double* d_eps,
+                                 double* d_weight, double* d_mu, void* hip_stream) {
+    if (!c) return MAR_ERR_STATE;
+    mar_status st = check_scalars(c, n_seeds, nu, 0.0, kT, prec, form);
+    if (st != MAR_OK) return st;
+    if (!std::isfinite(n_target) || n_target < 0.0) return set_err(c, MAR_ERR_ARG, "n_target must be finite and >= 0");
+    if (!d_e_band || !d_mu) return set_err(c, MAR_ERR_ARG, "e_band or mu output is NULL");
+    if (n_seeds > 0 && (!d_seeds || !d_rho)) return set_err(c, MAR_ERR_ARG, "seeds or rho is NULL");
+    if ((size_t)nu > (size_t)mar::MAX_NU_ASSEMBLE) return set_err(c, MAR_ERR_ARG, "nu too large for the deferred assembly");
+    HIP_OR(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    // levels, weights, kept eigenvector rows and per-seed results for all listed seeds
+    const size_t n = (size_t)n_seeds, nl = n * nu;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align_up(bytes);
+        return o;
+    };
+    const size_t oZ = take(nl * c->max_row * 8), oEps = take(d_eps ? 0 : nl * 8), oW = take(d_weight ? 0 : nl * 8);
+    const size_t oE = take(d_e_seed ? 0 : n * 8), oN = take(d_n_seed ? 0 : n * 8), oNu = take(d_nu_eff ? 0 : n * 4);
+    const size_t oPart = take(2 * 512 * 8), oSt = take(4 * 8);
+    if (off > c->fws_bytes) {
+        if (c->fws) {
+            HIP_OR(c, hipDeviceSynchronize());
+            HIP_OR(c, hipFree(c->fws));
+        }
+        c->fws = nullptr;
+        c->fws_bytes = 0;
+        void* p = nullptr;
+        HIP_OR(c, hipMalloc(&p, off));
+        c->fws = (char*)p;
+        c->fws_bytes = off;
+    }
+    char* f = c->fws;
+    double* zc = (double*)(f + oZ);
+    double* eps = d_eps ? d_eps : (double*)(f + oEps);
+    double* wt = d_weight ? d_weight : (double*)(f + oW);
+    double* e_seed = d_e_seed ? d_e_seed : (double*)(f + oE);
+    double* n_seed = d_n_seed ? d_n_seed : (double*)(f + oN);
+    int32_t* nu_eff = d_nu_eff ? d_nu_eff : (int32_t*)(f + oNu);
+    double* part = (double*)(f + oPart);
+    double* stt = (double*)(f + oSt);
+    // 1. subspaces and eigenpairs of every seed, rows e_i.v_alpha kept
+    mar_request r{d_seeds, n_seeds, nu, 0.0, kT, prec, form, d_rho, d_e_band, e_seed, n_seed, nu_eff, eps, wt};
+    c->zc_defer = zc;
+    st = dispatch_solve(c, r, plan_solve(c, nu, prec, form, n_seeds), s);
+    c->zc_defer = nullptr;
+    if (st != MAR_OK) return st;
+    // 2. Fermi level by bisection on the device, 3. assembly at that level, 4. E_band
+    launch(c, s, P_MU, [&] {
+        return mar::launch_fermi_search(n_seeds, nu, nu_eff, eps, wt, n_target, kT, 200, part, stt, d_mu, s);
+    });
+    launch(c, s, P_EIG, [&] {
+        return mar::launch_assemble((int)n_seeds, d_seeds, nu, nu_eff, eps, zc, c->max_row, c->Hrp, c->Hcol, c->Hval,
+                                    c->SvalH, stt + 2, kT, d_rho, e_seed, n_seed, s);
+    });
+    launch(c, s, P_SUM, [&] { return mar::launch_sum(e_seed, n_seeds, d_e_band, s); });
+    if (c->refused) {
+        c->refused = false;
+        return set_err(c, MAR_ERR_STATE, "internal error: a launch was refused; solve not completed");
+    }
+    HIP_OR(c, hipGetLastError());
+    return MAR_OK;
+}
+
+mar_status mar_solve_fermi(mar_ctx* c, const int32_t* seeds, int64_t n_seeds, int32_t nu, double n_target,
+                           double kT, mar_precision prec, mar_form form, double* rho, double* e_band, double* mu,
+                           double* e_seed, double* n_seed, int32_t* nu_eff, double* eps, double* weight) {
+    if (!c) return MAR_ERR_STATE;
+    mar_status st = check_scalars(c, n_seeds, nu, 0.0, kT, prec, form);
+    if (st != MAR_OK) return st;
+    if (!rho || !e_band || !mu) return set_err(c, MAR_ERR_ARG, "rho, e_band or mu output is NULL");
+    if (n_seeds > 0 && !seeds) return set_err(c, MAR_ERR_ARG, "seeds is NULL");
+    {
+        std::vector<char> seen(c->M, 0);
+        for (int64_t i = 0; i < n_seeds; ++i) {
+            const int32_t j = seeds[i];
+            if (j < 0 || j >= c->M) return set_err(c, MAR_ERR_ARG, fmt("seed %d outside [0, M)", j));
+            if (seen[j]) return set_err(c, MAR_ERR_ARG, fmt("seed %d listed twice", j));
+            seen[j] = 1;
+        }
+    }
+    HIP_OR(c, hipSetDevice(c->device));
+    const size_t nl = (size_t)n_seeds * nu;
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        const size_t o = off;
+        off += align_up(b);
+        return o;
+    };
+    const size_t oSeeds = take(n_seeds * 4), oRho = take(c->nnzH * 8), oEb = take(8), oMu = take(8),
+                 oE = take(n_seeds * 8), oN = take(n_seeds * 8), oNu = take(n_seeds * 4), oEps = take(eps ? nl * 8 : 0),
+                 oW = take(weight ? nl * 8 : 0);
+    if (off > c->io_bytes) {
+        if (c->io) HIP_OR(c, hipFree(c->io));
+        c->io = nullptr;
+        c->io_bytes = 0;
+        void* p = nullptr;
+        HIP_OR(c, hipMalloc(&p, off));
+        c->io = (char*)p;
+        c->io_bytes = off;
+    }
+    char* b = c->io;
+    hipStream_t s = c->stream;
+    if (n_seeds > 0) HIP_OR(c, hipMemcpyAsync(b + oSeeds, seeds, n_seeds * 4, hipMemcpyHostToDevice, s));
+    HIP_OR(c, hipMemcpyAsync(b + oRho, rho, c->nnzH * 8, hipMemcpyHostToDevice, s));
+    st = mar_solve_fermi_async(c, (int32_t*)(b + oSeeds), n_seeds, nu, n_target, kT, prec, form, (double*)(b + oRho),
+                               (double*)(b + oEb), (double*)(b + oE), (double*)(b + oN), (int32_t*)(b + oNu),
+                               eps ? (double*)(b + oEps) : nullptr, weight ? (double*)(b + oW) : nullptr,
+                               (double*)(b + oMu), s);
+    if (st != MAR_OK) return st;
+    std::vector<int32_t> nuv(n_seeds);
+    HIP_OR(c, hipMemcpyAsync(rho, b + oRho, c->nnzH * 8, hipMemcpyDeviceToHost, s));
+    HIP_OR(c, hipMemcpyAsync(e_band, b + oEb, 8, hipMemcpyDeviceToHost, s));
+    HIP_OR(c, hipMemcpyAsync(mu, b + oMu, 8, hipMemcpyDeviceToHost, s));
+    if (n_seeds > 0) {
+        if (e_seed) HIP_OR(c, hipMemcpyAsync(e_seed, b + oE, n_seeds * 8, hipMemcpyDeviceToHost, s));
+        if (n_seed) HIP_OR(c, hipMemcpyAsync(n_seed, b + oN, n_seeds * 8, hipMemcpyDeviceToHost, s));
+        HIP_OR(c, hipMemcpyAsync(nuv.data(), b + oNu, n_seeds * 4, hipMemcpyDeviceToHost, s));
+        if (eps) HIP_OR(c, hipMemcpyAsync(eps, b + oEps, nl * 8, hipMemcpyDeviceToHost, s));
+        if (weight) HIP_OR(c, hipMemcpyAsync(weight, b + oW, nl * 8, hipMemcpyDeviceToHost, s));
+    }
+    HIP_OR(c, hipStreamSynchronize(s));
+    for (int64_t i = 0; i < n_seeds; ++i) {
+        if (nu_eff) nu_eff[i] = nuv[i];
+        if (nuv[i] == -1)
+            return set_err(c, MAR_ERR_NOT_SPD, fmt("w^T S w < 0 for seed %d: S is not positive definite", seeds[i]));
+    }
+    return MAR_OK;
 }
 
 mar_status mar_solve(mar_ctx* c, const int32_t* seeds, int64_t n_seeds, int32_t nu, double mu, double kT,

@@ -13,6 +13,7 @@
 //     w_alpha = (e_j^T S v_alpha)(v_alpha^T e_j) = sqrt(S_jj) y_1alpha (e_j.v_alpha)
 // (K^T S e_j = sqrt(S_jj) e_1 because u_1 = e_j / sqrt(S_jj) and K^T S K = I),
 //     E_j = sum_{i in P(j)} rho_ij H_ij,   N_j = sum_{i in P(j)} rho_ij S_ij.
+#include <algorithm>
 #include <cfloat>
 
 #include "mar_device.h"
@@ -134,7 +135,7 @@ __global__ __launch_bounds__(WG) void k_eig(int nseeds, const int32_t* __restric
                                             int max_row, double mu, double kT, double* __restrict__ rho,
                                             double* __restrict__ e_seed, double* __restrict__ n_seed,
                                             int32_t* __restrict__ nu_eff_out, double* __restrict__ eps_out,
-                                            double* __restrict__ w_out) {
+                                            double* __restrict__ w_out, double* __restrict__ zc) {
     extern __shared__ double smem[];
     const int b = blockIdx.x;
     if (b >= nseeds) return;
@@ -277,9 +278,27 @@ __global__ __launch_bounds__(WG) void k_eig(int nseeds, const int32_t* __restric
     if (wave == 0) ql_implicit(d, e, m, R, NR, lane);
     __syncthreads();
 
-    // Fermi-weighted assembly.
+    // Fermi-weighted assembly, or (zc != nullptr) keep the rows e_i.v_alpha,
+    // i in P(j), for an assembly at a Fermi level found later (k_assemble).
     const int tj = *tjp;
     const double sq = sqrt(diagS[j]);
+    if (zc != nullptr) {
+        double* zb = zc + (int64_t)b * nu * max_row;
+        for (int idx = tid; idx < m * nP; idx += WG) {
+            const int a = idx / nP, t = idx - a * nP;
+            zb[a * max_row + t] = R[a * NR + 1 + t];
+        }
+        for (int a = tid; a < m; a += WG) {
+            eps_b[a] = d[a];
+            w_b[a] = sq * R[a * NR] * R[a * NR + 1 + tj];
+        }
+        for (int a = m + tid; a < nu; a += WG) {
+            eps_b[a] = 0.0;
+            w_b[a] = 0.0;
+        }
+        if (tid == 0) nu_eff_out[b] = m;
+        return;
+    }
     double* fz = q;
     for (int a = tid; a < m; a += WG) {
         const double ea = d[a];
@@ -324,7 +343,7 @@ LaunchInfo launch_eig(int nseeds, const int32_t* seeds, int nu, double* h, const
                       const double* Kp, const int32_t* Hrp, const int32_t* Hcol, const double* Hval,
                       const double* SvalH, const double* diagS, int max_row, double mu, double kT, double* rho,
                       double* e_seed, double* n_seed, int32_t* nu_eff_out, double* eps_out, double* w_out,
-                      hipStream_t s) {
+                      double* zc, hipStream_t s) {
     const bool lds_a = eig_a_fits_lds(nu, max_row);
     const size_t lds = eig_lds_bytes(nu, max_row, lds_a);
     if (lds_a) {
@@ -334,7 +353,8 @@ LaunchInfo launch_eig(int nseeds, const int32_t* seeds, int nu, double* h, const
             attr = true;
         }
         hipLaunchKernelGGL((k_eig<true>), dim3(nseeds), dim3(WG), lds, s, nseeds, seeds, nu, h, nu_eff_blk, Kp, Hrp,
-                           Hcol, Hval, SvalH, diagS, max_row, mu, kT, rho, e_seed, n_seed, nu_eff_out, eps_out, w_out);
+                           Hcol, Hval, SvalH, diagS, max_row, mu, kT, rho, e_seed, n_seed, nu_eff_out, eps_out, w_out,
+                           zc);
     } else {
         static bool attr = false;
         if (!attr) {
@@ -343,13 +363,196 @@ LaunchInfo launch_eig(int nseeds, const int32_t* seeds, int nu, double* h, const
         }
         hipLaunchKernelGGL((k_eig<false>), dim3(nseeds), dim3(WG), lds, s, nseeds, seeds, nu, h, nu_eff_blk, Kp,
                            Hrp, Hcol, Hval, SvalH, diagS, max_row, mu, kT, rho, e_seed, n_seed, nu_eff_out, eps_out,
-                           w_out);
+                           w_out, zc);
     }
     LaunchInfo li;
     li.wgs = nseeds;
     const double nv = (double)nu;
     li.bytes = (double)nseeds * (nv * nv * 8.0 + nv * max_row * 8.0 + (max_row + 3) * 8.0 * 3);
     li.flops = (double)nseeds * ((4.0 / 3.0) * nv * nv * nv + 4.0 * nv * nv * (max_row + 1));
+    return li;
+}
+
+// ---------------------------------------------------------------------------
+// Assembly at a Fermi level held on the device (after k_eig with zc != nullptr):
+// the same sums, in the same order, as the fused epilogue of k_eig.
+__global__ __launch_bounds__(WG) void k_assemble(int nseeds, const int32_t* __restrict__ seeds, int nu,
+                                                 const int32_t* __restrict__ nu_eff, const double* __restrict__ eps,
+                                                 const double* __restrict__ zc, int max_row,
+                                                 const int32_t* __restrict__ Hrp, const int32_t* __restrict__ Hcol,
+                                                 const double* __restrict__ Hval, const double* __restrict__ SvalH,
+                                                 const double* __restrict__ mu_p, double kT, double* __restrict__ rho,
+                                                 double* __restrict__ e_seed, double* __restrict__ n_seed) {
+    __shared__ double fz[MAX_NU_ASSEMBLE];
+    __shared__ double rhoL[64];
+    __shared__ int tjs;
+    const int b = blockIdx.x, tid = threadIdx.x;
+    if (b >= nseeds) return;
+    const int m = nu_eff[b];
+    if (m <= 0) {
+        if (tid == 0) {
+            e_seed[b] = 0.0;
+            n_seed[b] = 0.0;
+        }
+        return;
+    }
+    const int j = seeds[b];
+    const int rlo = Hrp[j], nP = Hrp[j + 1] - rlo;
+    if (tid < nP && Hcol[rlo + tid] == j) tjs = tid;
+    __syncthreads();
+    const int tj = tjs;
+    const double mu = *mu_p;
+    const double* zb = zc + (int64_t)b * nu * max_row;
+    for (int a = tid; a < m; a += WG) fz[a] = fermi_occ(eps[(int64_t)b * nu + a], mu, kT) * zb[a * max_row + tj];
+    __syncthreads();
+    for (int cb = 0; cb < nP; cb += WG / 8) {
+        const int t = cb + (tid >> 3), pi = tid & 7;
+        double s = 0.0;
+        if (t < nP)
+            for (int a = pi; a < m; a += 8) s += fz[a] * zb[a * max_row + t];
+        s += __shfl_xor(s, 1);
+        s += __shfl_xor(s, 2);
+        s += __shfl_xor(s, 4);
+        if (t < nP && pi == 0) {
+            const double r = 2.0 * s;
+            rho[rlo + t] = r;
+            rhoL[t] = r;
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double E = 0.0, N = 0.0;
+        for (int t = 0; t < nP; ++t) {
+            E += rhoL[t] * Hval[rlo + t];
+            N += rhoL[t] * SvalH[rlo + t];
+        }
+        e_seed[b] = E;
+        n_seed[b] = N;
+    }
+}
+
+LaunchInfo launch_assemble(int nseeds, const int32_t* seeds, int nu, const int32_t* nu_eff, const double* eps,
+                           const double* zc, int max_row, const int32_t* Hrp, const int32_t* Hcol,
+                           const double* Hval, const double* SvalH, const double* mu, double kT, double* rho,
+                           double* e_seed, double* n_seed, hipStream_t s) {
+    LaunchInfo li;
+    if (nu > MAX_NU_ASSEMBLE || max_row > 64) {
+        li.wgs = -1;
+        return li;
+    }
+    if (nseeds > 0)
+        hipLaunchKernelGGL(k_assemble, dim3(nseeds), dim3(WG), 0, s, nseeds, seeds, nu, nu_eff, eps, zc, max_row, Hrp,
+                           Hcol, Hval, SvalH, mu, kT, rho, e_seed, n_seed);
+    li.wgs = nseeds;
+    li.bytes = (double)nseeds * ((double)nu * (max_row + 1) * 8.0 + 3.0 * max_row * 8.0);
+    li.flops = (double)nseeds * 2.0 * nu * (max_row + 1);
+    return li;
+}
+
+// ---------------------------------------------------------------------------
+// Fermi level on the device: mu with N(mu) = sum_j 2 sum_alpha f((eps_alpha^(j)
+// - mu)/kT) w_alpha^(j) equal to n_target, by bisection on [min eps - 40 kT,
+// max eps + 40 kT] over the listed seeds' subspace levels (alpha < nu_eff).
+// st = {lo, hi, mu}. Every sum runs in a fixed order.
+constexpr int MU_WGS = 512;   // workgroups of the counting kernel
+
+__device__ __forceinline__ void wg_minmax(double& lo, double& hi, double* red) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        lo = fmin(lo, __shfl_xor(lo, off));
+        hi = fmax(hi, __shfl_xor(hi, off));
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) {
+        red[wave] = lo;
+        red[4 + wave] = hi;
+    }
+    __syncthreads();
+    lo = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
+    hi = fmax(fmax(red[4], red[5]), fmax(red[6], red[7]));
+}
+
+__global__ __launch_bounds__(WG) void k_mu_bounds(int64_t nseeds, int nu, const int32_t* __restrict__ nu_eff,
+                                                  const double* __restrict__ eps, double* __restrict__ part) {
+    __shared__ double red[8];
+    double lo = INFINITY, hi = -INFINITY;
+    const int64_t npair = nseeds * nu;
+    for (int64_t p = (int64_t)blockIdx.x * WG + threadIdx.x; p < npair; p += (int64_t)gridDim.x * WG) {
+        const int64_t b = p / nu;
+        const int a = (int)(p - b * nu);
+        if (a < nu_eff[b]) {
+            lo = fmin(lo, eps[p]);
+            hi = fmax(hi, eps[p]);
+        }
+    }
+    wg_minmax(lo, hi, red);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = lo;
+        part[2 * blockIdx.x + 1] = hi;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_mu_init(int nwg, const double* __restrict__ part, double kT,
+                                                double* __restrict__ st) {
+    if (threadIdx.x != 0) return;
+    double lo = INFINITY, hi = -INFINITY;
+    for (int g = 0; g < nwg; ++g) {
+        lo = fmin(lo, part[2 * g]);
+        hi = fmax(hi, part[2 * g + 1]);
+    }
+    if (!(lo <= hi)) lo = hi = 0.0;   // no levels at all
+    st[0] = lo - 40.0 * kT;
+    st[1] = hi + 40.0 * kT;
+    st[2] = 0.5 * (st[0] + st[1]);
+}
+
+__global__ __launch_bounds__(WG) void k_mu_count(int64_t nseeds, int nu, const int32_t* __restrict__ nu_eff,
+                                                 const double* __restrict__ eps, const double* __restrict__ w,
+                                                 double kT, const double* __restrict__ st, double* __restrict__ part) {
+    __shared__ double red[8];
+    const double mid = 0.5 * (st[0] + st[1]);
+    double s = 0.0;
+    const int64_t npair = nseeds * nu;
+    for (int64_t p = (int64_t)blockIdx.x * WG + threadIdx.x; p < npair; p += (int64_t)gridDim.x * WG) {
+        const int64_t b = p / nu;
+        const int a = (int)(p - b * nu);
+        if (a < nu_eff[b]) s += 2.0 * fermi_occ(eps[p], mid, kT) * w[p];
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(64) void k_mu_step(int nwg, const double* __restrict__ part, double n_target,
+                                                double* __restrict__ st, int last, double* __restrict__ mu_out) {
+    if (threadIdx.x != 0) return;
+    double n = 0.0;
+    for (int g = 0; g < nwg; ++g) n += part[g];
+    const double mid = 0.5 * (st[0] + st[1]);
+    if (n < n_target) st[0] = mid;
+    else st[1] = mid;
+    if (last) {
+        st[2] = 0.5 * (st[0] + st[1]);
+        if (mu_out) *mu_out = st[2];
+    }
+}
+
+LaunchInfo launch_fermi_search(int64_t nseeds, int nu, const int32_t* nu_eff, const double* eps, const double* w,
+                               double n_target, double kT, int iters, double* part, double* st, double* mu_out,
+                               hipStream_t s) {
+    const int64_t npair = nseeds * nu;
+    int nwg = (int)std::min<int64_t>(MU_WGS, std::max<int64_t>(1, (npair + WG - 1) / WG));
+    hipLaunchKernelGGL(k_mu_bounds, dim3(nwg), dim3(WG), 0, s, nseeds, nu, nu_eff, eps, part);
+    hipLaunchKernelGGL(k_mu_init, dim3(1), dim3(64), 0, s, nwg, part, kT, st);
+    for (int it = 0; it < iters; ++it) {
+        hipLaunchKernelGGL(k_mu_count, dim3(nwg), dim3(WG), 0, s, nseeds, nu, nu_eff, eps, w, kT, st, part);
+        hipLaunchKernelGGL(k_mu_step, dim3(1), dim3(64), 0, s, nwg, part, n_target, st, it + 1 == iters ? 1 : 0,
+                           mu_out);
+    }
+    LaunchInfo li;
+    li.wgs = nwg;
+    li.bytes = (double)(iters + 1) * npair * 20.0;
+    li.flops = (double)iters * npair * 30.0;
     return li;
 }
 

@@ -109,7 +109,19 @@ LaunchInfo launch_eig(int nseeds, const int32_t* seeds, int nu, double* h, const
                       const double* Kp, const int32_t* Hrp, const int32_t* Hcol, const double* Hval,
                       const double* SvalH, const double* diagS, int max_row, double mu, double kT, double* rho,
                       double* e_seed, double* n_seed, int32_t* nu_eff_out, double* eps_out, double* w_out,
-                      hipStream_t s);
+                      double* zc, hipStream_t s);
+// zc != nullptr: k_eig keeps zc[(b*nu + alpha)*max_row + t] = e_i.v_alpha (i = P(j)[t]) and writes levels
+// and weights (eps_out, w_out required) instead of assembling; k_assemble finishes at mu = *mu.
+constexpr int MAX_NU_ASSEMBLE = 4096;
+LaunchInfo launch_assemble(int nseeds, const int32_t* seeds, int nu, const int32_t* nu_eff, const double* eps,
+                           const double* zc, int max_row, const int32_t* Hrp, const int32_t* Hcol,
+                           const double* Hval, const double* SvalH, const double* mu, double kT, double* rho,
+                           double* e_seed, double* n_seed, hipStream_t s);
+// Bisection for the Fermi level over the levels of nseeds seeds; part >= 2 * 512 doubles, st = {lo, hi, mu};
+// the final mu is also written to *mu_out when mu_out != nullptr.
+LaunchInfo launch_fermi_search(int64_t nseeds, int nu, const int32_t* nu_eff, const double* eps, const double* w,
+                               double n_target, double kT, int iters, double* part, double* st, double* mu_out,
+                               hipStream_t s);
 
 // Delayed-reorthogonalization schedule.
 // Projection sweep (variants as in projr_geometry); target_wgs > 0.

@@ -79,6 +79,11 @@ def lib() -> C.CDLL:
     L.mar_solve.restype = C.c_int
     L.mar_solve_async.argtypes = [_P, _P, i64, i32, f64, f64, C.c_int, C.c_int, _P, _P, _P, _P, _P, _P, _P, _P]
     L.mar_solve_async.restype = C.c_int
+    L.mar_solve_fermi.argtypes = [_P, _P, i64, i32, f64, f64, C.c_int, C.c_int, _P, _P, _P, _P, _P, _P, _P, _P]
+    L.mar_solve_fermi.restype = C.c_int
+    L.mar_solve_fermi_async.argtypes = [_P, _P, i64, i32, f64, f64, C.c_int, C.c_int, _P, _P, _P, _P, _P, _P, _P,
+                                        _P, _P]
+    L.mar_solve_fermi_async.restype = C.c_int
     L.mar_solve_many.argtypes = [i32, C.POINTER(_P), C.POINTER(mar_request), _P]
     L.mar_solve_many.restype = C.c_int
     L.mar_autotune.argtypes = [_P, i32, C.c_int, _P, i64, f64, f64, _P, C.POINTER(i32), C.POINTER(i32),
@@ -158,6 +163,22 @@ def mar_solve_async(ctx, d_seeds, n_seeds, nu, mu, kT, prec, form, d_rho, d_e_ba
     return lib().mar_solve_async(ctx, _tptr(d_seeds), int(n_seeds), int(nu), float(mu), float(kT), int(prec),
                                  int(form), _tptr(d_rho), _tptr(d_e_band), _tptr(d_e_seed), _tptr(d_n_seed),
                                  _tptr(d_nu_eff), _tptr(d_eps), _tptr(d_weight), stream)
+
+
+def mar_solve_fermi(ctx, seeds, nu, n_target, kT, prec, form, rho, e_band, mu, e_seed=None, n_seed=None,
+                    nu_eff=None, eps=None, weight=None) -> int:
+    """Blocking solve with the Fermi level found on the device (mu: 1-element array, output)."""
+    return lib().mar_solve_fermi(ctx, _ptr(seeds), len(seeds), int(nu), float(n_target), float(kT), int(prec),
+                                 int(form), _ptr(rho), _ptr(e_band), _ptr(mu), _ptr(e_seed), _ptr(n_seed),
+                                 _ptr(nu_eff), _ptr(eps), _ptr(weight))
+
+
+def mar_solve_fermi_async(ctx, d_seeds, n_seeds, nu, n_target, kT, prec, form, d_rho, d_e_band, d_e_seed=None,
+                          d_n_seed=None, d_nu_eff=None, d_eps=None, d_weight=None, d_mu=None, stream=None) -> int:
+    return lib().mar_solve_fermi_async(ctx, _tptr(d_seeds), int(n_seeds), int(nu), float(n_target), float(kT),
+                                       int(prec), int(form), _tptr(d_rho), _tptr(d_e_band), _tptr(d_e_seed),
+                                       _tptr(d_n_seed), _tptr(d_nu_eff), _tptr(d_eps), _tptr(d_weight), _tptr(d_mu),
+                                       stream)
 
 
 def mar_request_of(d_seeds, nu, mu, kT, prec, form, d_rho, d_e_band, d_e_seed=None, d_n_seed=None,
@@ -261,6 +282,31 @@ class Context:
                        n_seed, nu_eff, eps, weight)
         _check(self.handle, st)
         return SolveOutput(rho, float(e_band[0]), e_seed, n_seed, nu_eff, eps, weight)
+
+    def solve_fermi(self, seeds, nu, n_target, kT, precision="fp64", form="batched", rho=None, levels=False):
+        """Solve with mu bisected on the device so that N(mu) = n_target; returns (SolveOutput, mu)."""
+        seeds = np.ascontiguousarray(seeds, dtype=np.int32)
+        n = len(seeds)
+        rho = np.zeros(self.H.nnz) if rho is None else np.ascontiguousarray(rho, dtype=np.float64)
+        e_band, mu = np.zeros(1), np.zeros(1)
+        e_seed, n_seed = np.zeros(n), np.zeros(n)
+        nu_eff = np.zeros(n, dtype=np.int32)
+        eps = np.zeros((n, nu)) if levels else None
+        weight = np.zeros((n, nu)) if levels else None
+        st = mar_solve_fermi(self.handle, seeds, nu, n_target, kT, PRECISION[precision], FORM[form], rho, e_band, mu,
+                             e_seed, n_seed, nu_eff, eps, weight)
+        _check(self.handle, st)
+        return SolveOutput(rho, float(e_band[0]), e_seed, n_seed, nu_eff, eps, weight), float(mu[0])
+
+    def solve_fermi_async(self, d_seeds, nu, n_target, kT, precision="fp32", form="batched", *, d_rho, d_e_band,
+                          d_mu, d_e_seed=None, d_n_seed=None, d_nu_eff=None, d_eps=None, d_weight=None, stream=None):
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        st = mar_solve_fermi_async(self.handle, d_seeds, d_seeds.numel(), nu, n_target, kT, PRECISION[precision],
+                                   FORM[form], d_rho, d_e_band, d_e_seed, d_n_seed, d_nu_eff, d_eps, d_weight, d_mu,
+                                   stream)
+        _check(self.handle, st)
 
     def solve_async(self, d_seeds, nu, mu, kT, precision="fp64", form="batched", *, d_rho, d_e_band,
                     d_e_seed=None, d_n_seed=None, d_nu_eff=None, d_eps=None, d_weight=None, stream=None):
