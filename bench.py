@@ -229,18 +229,34 @@ def main() -> int:
     d_eps = torch.zeros((S_step, nu), dtype=torch.float64, device=dev)
     d_w = torch.zeros((S_step, nu), dtype=torch.float64, device=dev)
 
-    # warmup: the first pass also yields the subspace levels for the half-filling Fermi level
+    # warmup: the first pass finds the half-filling Fermi level of its seeds on the device
+    # (levels kept, mu bisected, then assembled); later passes reuse that mu
     mu = 0.0
+    fermi_info = None
+    d_mu = torch.zeros(1, dtype=torch.float64, device=dev)
     for k in range(args.warmup):
         t = time.perf_counter()
-        ctx.solve_async(seeds_for(k), nu, mu, KT, "fp32", "batched", d_rho=d_rho, d_e_band=d_eb, d_e_seed=d_e,
-                        d_n_seed=d_n, d_nu_eff=d_nu, d_eps=d_eps, d_weight=d_w, stream=stream)
-        torch.cuda.synchronize()
-        log(f"warmup step {k}: {time.perf_counter() - t:.2f} s")
         if k == 0:
+            ctx.profile(True)
+            ctx.profile_reset()
+            ctx.solve_fermi_async(seeds_for(k), nu, float(S_step), KT, "fp32", "batched", d_rho=d_rho, d_e_band=d_eb,
+                                  d_mu=d_mu, d_e_seed=d_e, d_n_seed=d_n, d_nu_eff=d_nu, d_eps=d_eps, d_weight=d_w,
+                                  stream=stream)
+            torch.cuda.synchronize()
+            fs = ctx.profile_collect().get("fermi_search")
+            ctx.profile(False)
+            mu = float(d_mu.cpu()[0])
             nue = d_nu.cpu().numpy()
-            mu = fermi.fermi_level(d_eps.cpu().numpy(), d_w.cpu().numpy(), nue, float(S_step), KT)
-            log(f"half-filling Fermi level from {S_step} seeds: mu = {mu:.6f} eV; nu_eff min {nue.min()}")
+            mu_host = fermi.fermi_level(d_eps.cpu().numpy(), d_w.cpu().numpy(), nue, float(S_step), KT)
+            fermi_info = dict(mu=mu, seeds=S_step, search_ms=round(fs["ms"], 3) if fs else None,
+                              host_bisection_mu=mu_host)
+            log(f"half-filling Fermi level from {S_step} seeds on the device: mu = {mu:.6f} eV "
+                f"(host bisection {mu_host:.6f}); search {fermi_info['search_ms']} ms; nu_eff min {nue.min()}")
+        else:
+            ctx.solve_async(seeds_for(k), nu, mu, KT, "fp32", "batched", d_rho=d_rho, d_e_band=d_eb, d_e_seed=d_e,
+                            d_n_seed=d_n, d_nu_eff=d_nu, stream=stream)
+            torch.cuda.synchronize()
+        log(f"warmup step {k}: {time.perf_counter() - t:.2f} s")
 
     # timed region: the batched FP32 form
     if not args.no_profile:
@@ -348,6 +364,7 @@ def main() -> int:
         "fp64_plain": plain,
         "ratio_fp32_batched_over_fp64_plain": round(value / plain["value"], 3) if plain else None,
         "precision_batching_split": split or None,
+        "fermi_level": fermi_info,
         "spmm_hbm": spmm,
         "kernels": kernels,
     }
