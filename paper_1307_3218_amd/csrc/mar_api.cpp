@@ -591,21 +591,21 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
                                         nu_blk, tau, s);
             });
             launch(c, s, P_UPD2, [&] {
-                return mar::launch_upd2<T>(B, K, M, stride, n, cAT, cBT, gam, Fn, Y, !last, c->tune.upd_q, s);
+                // w' goes straight into slab n + 1, unnormalized (its scale is handled by k_coef)
+                return mar::launch_upd2<T>(B, K, M, stride, n, cAT, cBT, gam, Fn, Y,
+                                           last ? nullptr : K + (size_t)(n + 1) * slab_el, !last, c->tune.upd_q, s);
             });
             if (last) break;
+            // S w' and its norms; S w' is the next sweep's right-hand side, scaled like the slab
             int64_t swgs = 0;
             launch(c, s, P_SPMM_DOT, [&] {
-                LaunchInfo li = mar::launch_spmm<T>(B, c->S, Y, SY, part, 2, part_cap, s);
+                LaunchInfo li = mar::launch_spmm<T>(B, c->S, K + (size_t)(n + 1) * slab_el, ZT, part, 2, part_cap, s);
                 swgs = li.wgs;
                 return li;
             });
             launch(c, s, P_REDUCE, [&] { return mar::launch_reduce(part, swgs, 2 * B, redb, nullptr, B, nu, n, s); });
             launch(c, s, P_NORM, [&] {
                 return mar::launch_norm2(B, nu, n, redb, C1, tau, active, nu_blk, BT, UU, s);
-            });
-            launch(c, s, P_APPEND, [&] {
-                return mar::launch_append2<T>(B, M, Y, SY, BT, active, K + (size_t)(n + 1) * slab_el, ZT, s);
             });
         }
         // rows K[P(j), :] leave the basis, then the subspace eigensolve and assembly

@@ -172,6 +172,10 @@ LaunchInfo launch_zero(void* p, int64_t bytes, hipStream_t s) {
 // The final norm of the vector appended at step n-1 is beta~_prev * gamma; it
 // is tested here against tau * eta (eta^2 = |c1_prev|^2 + beta~_prev^2 (|c2|^2 +
 // gamma^2)), the same test the two-pass schedule applies, one step later.
+// Slab n holds u~ unnormalized, s u~ with s = beta~_prev (1 at n = 0), and so
+// do the sweep's right-hand sides; the products are rescaled here, and the
+// update coefficients go out multiplied by s (k_upd2 divides by s gamma).
+// A stopped seed gets gamma = inf, so that its slabs become zero.
 // One workgroup per seed; A is h[b][k][n]; G is [nu][nu]; R is column-major
 // [nu][nu+1] (R_{p,k} at k*(nu+1) + p).
 __global__ __launch_bounds__(WG) void k_coef(int B, int nu, int n, const double* __restrict__ red,
@@ -211,7 +215,7 @@ __global__ __launch_bounds__(WG) void k_coef(int B, int nu, int n, const double*
             }
         }
         if (tid == 0) {
-            gam[b] = 1.0;
+            gam[b] = INFINITY;
             Fn[b] = 0.0;
             if (nu_new >= 0) {
                 nu_eff[b] = nu_new;
@@ -226,14 +230,15 @@ __global__ __launch_bounds__(WG) void k_coef(int B, int nu, int n, const double*
     double* A = Ah + (int64_t)b * nu * nu;
     double* G = Gm + (int64_t)b * nu * nu;
     double* Rc = Rm + (int64_t)b * nu * (nu + 1);
+    const double sc = n >= 1 ? BT[b] : 1.0;   // scale of slab n
     for (int k = tid; k < n; k += WG) {
-        c2[k] = red[((int64_t)0 * nk + k) * B + b];
-        g[k] = red[((int64_t)1 * nk + k) * B + b];
-        e[k] = red[((int64_t)2 * nk + k) * B + b];
+        c2[k] = red[((int64_t)0 * nk + k) * B + b] / sc;
+        g[k] = red[((int64_t)1 * nk + k) * B + b] / sc;
+        e[k] = red[((int64_t)2 * nk + k) * B + b] / sc;
         c1p[k] = C1[(int64_t)b * nu + k];
     }
-    const double utsy = red[((int64_t)1 * nk + n) * B + b];
-    const double uty = red[((int64_t)2 * nk + n) * B + b];
+    const double utsy = red[((int64_t)1 * nk + n) * B + b] / sc / sc;
+    const double uty = red[((int64_t)2 * nk + n) * B + b] / sc / sc;
     __syncthreads();
     double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
     for (int k = tid; k < n; k += WG) {
@@ -299,16 +304,16 @@ __global__ __launch_bounds__(WG) void k_coef(int B, int nu, int n, const double*
         C1[(int64_t)b * nu + p] = (Fp - q[p]) / gm;
     }
     for (int k = tid; k < n; k += WG) {
-        cA[(int64_t)k * B + b] = c2[k];
-        cB[(int64_t)k * B + b] = g[k];
+        cA[(int64_t)k * B + b] = sc * c2[k];
+        cB[(int64_t)k * B + b] = sc * g[k];
         if (cAf) {  // the same coefficients rounded once to the basis precision
-            cAf[(int64_t)k * B + b] = (float)c2[k];
-            cBf[(int64_t)k * B + b] = (float)g[k];
+            cAf[(int64_t)k * B + b] = (float)(sc * c2[k]);
+            cBf[(int64_t)k * B + b] = (float)(sc * g[k]);
         }
     }
     if (tid == 0) {
-        gam[b] = gm;
-        Fn[b] = Fnn;
+        gam[b] = sc * gm;
+        Fn[b] = sc * Fnn;
     }
 }
 

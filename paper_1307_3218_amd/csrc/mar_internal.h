@@ -136,10 +136,8 @@ int projr_blocks_per_cu(int B, int variant);
 template <typename T>
 // upd_q: 16-byte vectors per thread (2, 4 or 8; 0 = 8), reduced for small grids.
 LaunchInfo launch_upd2(int B, T* basis, int64_t M, int64_t stride, int n, const T* cA, const T* cB,
-                       const double* gam, const double* Fn, T* y, bool want_w, int upd_q, hipStream_t s);
-template <typename T>
-LaunchInfo launch_append2(int B, int64_t M, const T* W, const T* Z, const double* beta, const int32_t* active,
-                          T* Kn, T* ZT, hipStream_t s);
+                       const double* gam, const double* Fn, const T* y, T* wout, bool want_w, int upd_q,
+                       hipStream_t s);
 // cAf/cBf (optional): the update coefficients rounded to FP32 for an FP32 basis.
 LaunchInfo launch_coef(int B, int nu, int n, const double* red, double* A, double* G, double* R, double* C1,
                        const double* BT, const double* UU, double* cA, double* cB, float* cAf, float* cBf,

@@ -510,13 +510,16 @@ __global__ __launch_bounds__(WG) void k_projr(const T* __restrict__ basis, int64
 // Dual update of the delayed schedule, one pass over slabs 0..n-1:
 //   u_n = (u~ - sum_k K_k cA_k) / gamma       (second Gram-Schmidt pass of u~)
 //   w'  = (y  - sum_k K_k cB_k - u_n F_n) / gamma   (first pass of y = H u~)
-// u~ is slab n and is overwritten by u_n; y is overwritten by w' (WANT_W).
+// u~ is slab n and is overwritten by u_n; w' goes to wout (WANT_W), the next
+// slab, unnormalized. The slab may hold u~ times a per-seed scale s and y
+// times the same s: the caller passes s cA, s cB, s F_n and s gamma.
 // The coefficients are [k][B] in the basis precision: one 16-byte load per
 // lane and slab for each of cA, cB when B >= VEC.
 template <typename T, int B, int Q, bool WANT_W>
 __global__ __launch_bounds__(WG) void k_upd2(T* __restrict__ basis, int64_t slab, int n, const T* __restrict__ cA,
                                              const T* __restrict__ cB, const double* __restrict__ gam,
-                                             const double* __restrict__ Fn, T* __restrict__ y, int64_t nvec) {
+                                             const double* __restrict__ Fn, const T* __restrict__ y,
+                                             T* __restrict__ wout, int64_t nvec) {
     using SM = SeedMap<T, B>;
     constexpr int VEC = SM::VEC, P = SM::P;
     using VT = typename Vec16<T>::type;
@@ -524,7 +527,8 @@ __global__ __launch_bounds__(WG) void k_upd2(T* __restrict__ basis, int64_t slab
     const int64_t slabv = slab / VEC;
     const int sb = (B < VEC) ? 0 : (tid % P) * VEC;
     VT* bv = reinterpret_cast<VT*>(basis);
-    VT* yv = reinterpret_cast<VT*>(y);
+    const VT* yv = reinterpret_cast<const VT*>(y);
+    VT* wv = reinterpret_cast<VT*>(wout);
     T g[VEC], fn[VEC];
 #pragma unroll
     for (int i = 0; i < VEC; ++i) {
@@ -575,39 +579,9 @@ __global__ __launch_bounds__(WG) void k_upd2(T* __restrict__ basis, int64_t slab
                 if constexpr (WANT_W) aw[q][i] = (aw[q][i] - au[q][i] * fn[i]) / g[i];
             }
             bv[(int64_t)n * slabv + vi] = pack(au[q]);
-            if constexpr (WANT_W) yv[vi] = pack(aw[q]);
+            if constexpr (WANT_W) wv[vi] = pack(aw[q]);
         }
     }
-}
-
-// u~_{n+1} = w' / beta~ into slab n+1 and S u~_{n+1} = (S w') / beta~ (zero for stopped seeds).
-template <typename T, int B>
-__global__ __launch_bounds__(WG) void k_append2(const T* __restrict__ W, const T* __restrict__ Z,
-                                                const double* __restrict__ beta, const int32_t* __restrict__ active,
-                                                T* __restrict__ Kn, T* __restrict__ ZT, int64_t nvec) {
-    using SM = SeedMap<T, B>;
-    constexpr int VEC = SM::VEC, P = SM::P;
-    using VT = typename Vec16<T>::type;
-    const int64_t vi = (int64_t)blockIdx.x * WG + threadIdx.x;
-    if (vi >= nvec) return;
-    const int sb = (B < VEC) ? 0 : (threadIdx.x % P) * VEC;
-    T w[VEC], z[VEC];
-    unpack(reinterpret_cast<const VT*>(W)[vi], w);
-    unpack(reinterpret_cast<const VT*>(Z)[vi], z);
-#pragma unroll
-    for (int i = 0; i < VEC; ++i) {
-        const int b = (B < VEC) ? (i % B) : (sb + i);
-        if (active[b]) {
-            const T bt = (T)beta[b];
-            w[i] = w[i] / bt;
-            z[i] = z[i] / bt;
-        } else {
-            w[i] = (T)0;
-            z[i] = (T)0;
-        }
-    }
-    reinterpret_cast<VT*>(Kn)[vi] = pack(w);
-    reinterpret_cast<VT*>(ZT)[vi] = pack(z);
 }
 
 // ---------------------------------------------------------------------------
@@ -792,8 +766,8 @@ int projr_blocks_per_cu<MAR_T>(int B, int variant) {
 
 template <>
 LaunchInfo launch_upd2<MAR_T>(int B, MAR_T* basis, int64_t M, int64_t stride, int n, const MAR_T* cA,
-                              const MAR_T* cB, const double* gam, const double* Fn, MAR_T* y, bool want_w,
-                              int upd_q, hipStream_t s) {
+                              const MAR_T* cB, const double* gam, const double* Fn, const MAR_T* y, MAR_T* wout,
+                              bool want_w, int upd_q, hipStream_t s) {
     constexpr int VEC = Vec16<MAR_T>::n;
     const int64_t nvec = M * B / VEC;
     // vectors per thread: the requested depth when the grid still has >= 1024 workgroups
@@ -801,7 +775,7 @@ LaunchInfo launch_upd2<MAR_T>(int B, MAR_T* basis, int64_t M, int64_t stride, in
     while (Q > 1 && nvec < (int64_t)WG * Q * 1024) Q /= 2;
     const int64_t wgs = (nvec + WG * Q - 1) / (WG * Q);
 #define MAR_UPD2(QQ, WW) \
-    MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_upd2<MAR_T, BB, QQ, WW>), dim3(wgs), dim3(WG), 0, s, basis, stride, n, cA, cB, gam, Fn, y, nvec))
+    MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_upd2<MAR_T, BB, QQ, WW>), dim3(wgs), dim3(WG), 0, s, basis, stride, n, cA, cB, gam, Fn, y, wout, nvec))
 #define MAR_UPD2W(QQ) \
     if (want_w) { MAR_UPD2(QQ, true); } else { MAR_UPD2(QQ, false); }
     if (Q == 8) { MAR_UPD2W(8) }
@@ -815,20 +789,6 @@ LaunchInfo launch_upd2<MAR_T>(int B, MAR_T* basis, int64_t M, int64_t stride, in
     const double slabs_read = (double)n + (want_w ? 2.0 : 1.0), slabs_written = want_w ? 2.0 : 1.0;
     li.bytes = (slabs_read + slabs_written) * (double)(M * B) * sizeof(MAR_T);
     li.flops = (want_w ? 4.0 : 2.0) * n * (double)(M * B);
-    return li;
-}
-
-template <>
-LaunchInfo launch_append2<MAR_T>(int B, int64_t M, const MAR_T* W, const MAR_T* Z, const double* beta,
-                                 const int32_t* active, MAR_T* Kn, MAR_T* ZT, hipStream_t s) {
-    constexpr int VEC = Vec16<MAR_T>::n;
-    const int64_t nvec = M * B / VEC;
-    const int64_t wgs = (nvec + WG - 1) / WG;
-    MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_append2<MAR_T, BB>), dim3(wgs), dim3(WG), 0, s, W, Z, beta, active, Kn,
-                                         ZT, nvec));
-    LaunchInfo li;
-    li.wgs = wgs;
-    li.bytes = 4.0 * (double)M * B * sizeof(MAR_T);
     return li;
 }
 
