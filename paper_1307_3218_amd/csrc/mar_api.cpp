@@ -53,6 +53,7 @@ struct mar_ctx {
     int64_t M = 0;
     int device = 0;
     DevMat H, S;
+    DevMat SH;                // S's values on H's BSR pattern (for the fused H/S product), if H is BSR
     int32_t* Hrp = nullptr;
     int32_t* Hcol = nullptr;
     double* Hval = nullptr;
@@ -572,12 +573,36 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
         launch(c, s, P_INIT, [&] {
             return mar::launch_init<T>(B, M, c->M, seeds, ns, c->diagS, nu, K, active, nu_blk, UU, s);
         });
-        launch(c, s, P_SPMM, [&] { return mar::launch_spmm<T>(B, c->S, K, ZT, nullptr, 0, 0, s); });
+        // H u and S u of the same vector in one pass when H is BSR (S on H's pattern); at steps n >= 1 that
+        // pass also gives the norms of slab n (the unnormalized residual of step n - 1)
+        const bool dual = c->H.bsr && c->SH.nnz == c->H.nnz && B >= VEC;
+        if (!dual) launch(c, s, P_SPMM, [&] { return mar::launch_spmm<T>(B, c->S, K, ZT, nullptr, 0, 0, s); });
         for (int n = 0; n < nu; ++n) {
             T* Kn = K + (size_t)n * slab_el;
             const int nk = n + 1;
             const bool last = n + 1 == nu;
-            launch(c, s, P_SPMM, [&] { return mar::launch_spmm<T>(B, c->H, Kn, Y, nullptr, 0, 0, s); });
+            int64_t swgs = 0;
+            if (dual) {
+                launch(c, s, n == 0 ? P_SPMM : P_SPMM_DOT, [&] {
+                    LaunchInfo li = mar::launch_spmm2<T>(B, c->H, c->SH, Kn, Y, ZT, n == 0 ? nullptr : part,
+                                                         n == 0 ? 0 : 2, part_cap, s);
+                    swgs = li.wgs;
+                    return li;
+                });
+            } else if (n >= 1) {
+                launch(c, s, P_SPMM_DOT, [&] {
+                    LaunchInfo li = mar::launch_spmm<T>(B, c->S, Kn, ZT, part, 2, part_cap, s);
+                    swgs = li.wgs;
+                    return li;
+                });
+            }
+            if (n >= 1) {
+                launch(c, s, P_REDUCE, [&] { return mar::launch_reduce(part, swgs, 2 * B, redb, nullptr, B, nu, n, s); });
+                launch(c, s, P_NORM, [&] {
+                    return mar::launch_norm2(B, nu, n - 1, redb, C1, tau, active, nu_blk, BT, UU, s);
+                });
+            }
+            if (!dual) launch(c, s, P_SPMM, [&] { return mar::launch_spmm<T>(B, c->H, Kn, Y, nullptr, 0, 0, s); });
             launch(c, s, P_SPMM, [&] { return mar::launch_spmm<T>(B, c->S, Y, SY, nullptr, 0, 0, s); });
             int64_t ngroups = 0;
             launch(c, s, P_PROJR, [&] {
@@ -596,17 +621,6 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
                                            last ? nullptr : K + (size_t)(n + 1) * slab_el, !last, c->tune.upd_q, s);
             });
             if (last) break;
-            // S w' and its norms; S w' is the next sweep's right-hand side, scaled like the slab
-            int64_t swgs = 0;
-            launch(c, s, P_SPMM_DOT, [&] {
-                LaunchInfo li = mar::launch_spmm<T>(B, c->S, K + (size_t)(n + 1) * slab_el, ZT, part, 2, part_cap, s);
-                swgs = li.wgs;
-                return li;
-            });
-            launch(c, s, P_REDUCE, [&] { return mar::launch_reduce(part, swgs, 2 * B, redb, nullptr, B, nu, n, s); });
-            launch(c, s, P_NORM, [&] {
-                return mar::launch_norm2(B, nu, n, redb, C1, tau, active, nu_blk, BT, UU, s);
-            });
         }
         // rows K[P(j), :] leave the basis, then the subspace eigensolve and assembly
         launch(c, s, P_EIG, [&] {
@@ -798,6 +812,7 @@ mar_status mar_create(int64_t M, const int64_t* H_rowptr, const int32_t* H_col, 
     };
     if ((st = build_devmat(c, M, H_rowptr, H_col, H_val, c->H)) != MAR_OK) return fail(st);
     if ((st = build_devmat(c, M, S_rowptr, S_col, S_val, c->S)) != MAR_OK) return fail(st);
+    if (c->H.bsr && (st = build_devmat(c, M, H_rowptr, H_col, svalH.data(), c->SH)) != MAR_OK) return fail(st);
     std::vector<int32_t> rp32(M + 1);
     for (int64_t i = 0; i <= M; ++i) rp32[i] = (int32_t)H_rowptr[i];
     if ((st = upload(c, &c->Hrp, rp32.data(), rp32.size())) != MAR_OK) return fail(st);

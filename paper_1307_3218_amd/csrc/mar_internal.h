@@ -123,6 +123,11 @@ LaunchInfo launch_fermi_search(int64_t nseeds, int nu, const int32_t* nu_eff, co
                                double n_target, double kT, int iters, double* part, double* st, double* mu_out,
                                hipStream_t s);
 
+// Y = H X and Z = S X in one pass (SH: S's values on H's BSR pattern); refused (wgs = -1) unless H is BSR
+// and B >= the vector width. ndot as in launch_spmm, against Z.
+template <typename T>
+LaunchInfo launch_spmm2(int B, const DevMat& H, const DevMat& SH, const T* X, T* Y, T* Z, double* part, int ndot,
+                        int64_t part_cap, hipStream_t s);
 // Delayed-reorthogonalization schedule.
 // Projection sweep (variants as in projr_geometry); target_wgs > 0.
 template <typename T>

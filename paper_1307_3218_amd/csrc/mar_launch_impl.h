@@ -208,6 +208,114 @@ __global__ __launch_bounds__(WG) void k_spmm_bsr4(int64_t nbrow, const int32_t* 
 }
 
 // Y = A X with A in CSR (patterns without 4x4 block structure). Thread = (row, seed group).
+// Y = H X and Z = S X in one pass over X, for S stored on H's block pattern
+// (zero blocks where S has none); B >= VEC only. NDOT as in k_spmm_bsr4, with
+// the products taken against Z: X.(S X) and X.X per seed.
+template <typename T, int B, int NDOT>
+__global__ __launch_bounds__(WG) void k_spmm2_bsr4(int64_t nbrow, const int32_t* __restrict__ brp,
+                                                   const int32_t* __restrict__ bcol, const T* __restrict__ hval,
+                                                   const T* __restrict__ sval, const T* __restrict__ X,
+                                                   T* __restrict__ Y, T* __restrict__ Z, double* __restrict__ part) {
+    using SM = SeedMap<T, B>;
+    constexpr int VEC = SM::VEC, SW = SM::SW, P = SM::P;
+    static_assert(B >= VEC, "dual product needs one seed group per lane");
+    using VT = typename Vec16<T>::type;
+    constexpr int CH = 2;   // blocks in flight per row (two value sets per block)
+    const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t g = bid * WG + threadIdx.x;
+    const int64_t I = g / P;
+    const int s0 = (threadIdx.x % P) * VEC;
+    const VT* Xv = reinterpret_cast<const VT*>(X);
+    T ah[4][SW], as[4][SW];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int i = 0; i < SW; ++i) ah[r][i] = as[r][i] = (T)0;
+    int64_t Iu = I;
+    if constexpr (P == 64) Iu = __builtin_amdgcn_readfirstlane((int)I);   // one row per wavefront
+    if (Iu < nbrow) {
+        const int lo = brp[Iu], hi = brp[Iu + 1];
+        for (int b0 = lo; b0 < hi; b0 += CH) {
+            int blk[CH];
+            int64_t J[CH];
+#pragma unroll
+            for (int t = 0; t < CH; ++t) {
+                blk[t] = b0 + t < hi ? b0 + t : hi - 1;   // repeats the last block; its sum is skipped
+                J[t] = bcol[blk[t]];
+            }
+            T xv[CH][4][VEC];
+#pragma unroll
+            for (int t = 0; t < CH; ++t)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) unpack(Xv[((4 * J[t] + c) * B + s0) / VEC], xv[t][c]);
+            T hv[CH][16], sv[CH][16];
+#pragma unroll
+            for (int t = 0; t < CH; ++t) {
+                const VT* hp = reinterpret_cast<const VT*>(hval + (int64_t)blk[t] * 16);
+                const VT* sp = reinterpret_cast<const VT*>(sval + (int64_t)blk[t] * 16);
+#pragma unroll
+                for (int q = 0; q < 16 / VEC; ++q) {
+                    T u[VEC], w[VEC];
+                    unpack(hp[q], u);
+                    unpack(sp[q], w);
+#pragma unroll
+                    for (int i = 0; i < VEC; ++i) {
+                        hv[t][q * VEC + i] = u[i];
+                        sv[t][q * VEC + i] = w[i];
+                    }
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < CH; ++t) {
+                if (b0 + t < hi) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int i = 0; i < SW; ++i) {
+                            T h = ah[r][i], z = as[r][i];
+#pragma unroll
+                            for (int c = 0; c < 4; ++c) {
+                                h = fma(hv[t][r * 4 + c], xv[t][c][i], h);
+                                z = fma(sv[t][r * 4 + c], xv[t][c][i], z);
+                            }
+                            ah[r][i] = h;
+                            as[r][i] = z;
+                        }
+                }
+            }
+        }
+        VT* Yv = reinterpret_cast<VT*>(Y);
+        VT* Zv = reinterpret_cast<VT*>(Z);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            Yv[((4 * Iu + r) * B + s0) / VEC] = pack(ah[r]);
+            Zv[((4 * Iu + r) * B + s0) / VEC] = pack(as[r]);
+        }
+    }
+    if constexpr (NDOT > 0) {
+        double d[NDOT][SW];
+#pragma unroll
+        for (int v = 0; v < NDOT; ++v)
+#pragma unroll
+            for (int i = 0; i < SW; ++i) d[v][i] = 0.0;
+        if (I < nbrow) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                T xr[SW];
+                unpack(Xv[((4 * I + r) * B + s0) / VEC], xr);
+#pragma unroll
+                for (int i = 0; i < SW; ++i) {
+                    const double xd = (double)xr[i];
+                    d[0][i] += xd * (double)as[r][i];
+                    if constexpr (NDOT > 1) d[1][i] += xd * xd;
+                }
+            }
+        }
+        __shared__ double lds[SeedReduce<P, SW, NDOT>::LDS];
+        wg_seed_reduce<P, SW, NDOT>(d, lds, [&](int v, int b, double sdot) { part[(bid * NDOT + v) * B + b] = sdot; });
+    }
+}
+
 template <typename T, int B, int NDOT>
 __global__ __launch_bounds__(WG) void k_spmm_csr(int64_t nrow, const int32_t* __restrict__ rp,
                                                  const int32_t* __restrict__ col, const T* __restrict__ val,
@@ -642,6 +750,37 @@ LaunchInfo launch_spmm<MAR_T>(int B, const DevMat& A, const MAR_T* X, MAR_T* Y, 
     li.wgs = wgs;
     li.bytes = A.bytes_per_pass(sizeof(MAR_T)) + 2.0 * (double)rows * B * sizeof(MAR_T);
     li.flops = 2.0 * (double)A.nnz * (A.bsr ? 16.0 : 1.0) * B;
+    return li;
+}
+
+template <>
+LaunchInfo launch_spmm2<MAR_T>(int B, const DevMat& H, const DevMat& SH, const MAR_T* X, MAR_T* Y, MAR_T* Z,
+                               double* part, int ndot, int64_t part_cap, hipStream_t s) {
+    constexpr int VEC = Vec16<MAR_T>::n;
+    LaunchInfo li;
+    if (!H.bsr || B < VEC || SH.nnz != H.nnz) {
+        li.wgs = -1;
+        return li;
+    }
+    const int P = B / VEC;
+    const int64_t wgs = (H.n * P + WG - 1) / WG;
+    if (ndot > 0 && wgs * ndot * B > part_cap) {
+        li.wgs = -1;
+        return li;
+    }
+    const bool f32 = std::is_same<MAR_T, float>::value;
+    const MAR_T* hv = f32 ? (const MAR_T*)H.v32 : (const MAR_T*)H.v64;
+    const MAR_T* sv = f32 ? (const MAR_T*)SH.v32 : (const MAR_T*)SH.v64;
+#define MAR_SPMM2(ND) \
+    MAR_DISPATCH_B(B, if constexpr (BB >= VEC) hipLaunchKernelGGL((k_spmm2_bsr4<MAR_T, BB, ND>), dim3(wgs), dim3(WG), 0, s, H.n, H.ptr, H.idx, hv, sv, X, Y, Z, part))
+    if (ndot == 2) { MAR_SPMM2(2); }
+    else if (ndot == 1) { MAR_SPMM2(1); }
+    else { MAR_SPMM2(0); }
+#undef MAR_SPMM2
+    li.wgs = wgs;
+    li.bytes = (double)H.nnz * (2.0 * 16.0 * sizeof(MAR_T) + 4.0) + (double)(H.n + 1) * 4.0 +
+               3.0 * (double)(4 * H.n) * B * sizeof(MAR_T);
+    li.flops = 4.0 * (double)H.nnz * 16.0 * B;
     return li;
 }
 
