@@ -169,6 +169,34 @@ mar_status mar_solve_fermi(mar_ctx* ctx, const int32_t* seeds, int64_t n_seeds, 
                            double* mu, double* e_seed, double* n_seed, int32_t* nu_eff, double* eps,
                            double* weight);
 
+/* ---- eigen states (Sec. 3, Eq. 3; Appendix) ----
+ * The k-th eigen level and the components of its eigenvector over the listed
+ * seeds, from the same subspaces. With the weights w_alpha^(j) of every listed
+ * seed, the integrated density of states is
+ *     n(eta) = sum_j sum_alpha w_alpha^(j) F((eta - eps_alpha^(j)) / sigma)
+ * (F the logistic step 1/(1+e^-x); sigma = 0: the unit step, 1/2 at 0), so that
+ * n(+inf) = n_seeds; eta(n) is its inverse, found by 200 halvings of
+ * [min eps - 1, max eps + 1]. The level is eps_k = eta(k - 1/2), and (Eq. 3,
+ * with the delta smoothed to the derivative of F(x/sigma))
+ *     e_j^T phi_k = sum_alpha s_alpha^(j) (e_j^T v_alpha^(j))
+ *                   [F((eta(k) - eps_alpha^(j))/sigma) - F((eta(k-1) - eps_alpha^(j))/sigma)],
+ * where s_alpha^(j) = +1 or -1 makes v_ref . v_alpha^(j) >= 0 (inner-product
+ * method), v_ref being the subspace eigenvector with the largest
+ * |(e_j^T v_alpha^(j)) x window| over all listed seeds. Cost: every listed seed
+ * is solved twice (levels and reference first, signs second) plus the
+ * reference seed alone in the plain form. With all M seeds listed and
+ * nu = M the result is the exact S-normalized generalized eigenvector up to one
+ * global sign. Arguments: 1 <= k <= n_seeds, sigma finite and >= 0, the rest as
+ * in mar_solve_async. Outputs: phi [n_seeds] (component of each listed seed, in
+ * list order), levels [3] = {eps_k, eta(k-1), eta(k)}, ref [3] = {position in
+ * the list, alpha, seed} of the reference (or NULL). Host variant: host arrays. */
+mar_status mar_eigen_state_async(mar_ctx* ctx, const int32_t* d_seeds, int64_t n_seeds, int32_t nu, int32_t k,
+                                 double sigma, mar_precision prec, mar_form form, double* d_phi,
+                                 double* d_levels, int32_t* d_ref, void* hip_stream);
+mar_status mar_eigen_state(mar_ctx* ctx, const int32_t* seeds, int64_t n_seeds, int32_t nu, int32_t k,
+                           double sigma, mar_precision prec, mar_form form, double* phi, double* levels,
+                           int32_t* ref);
+
 /* ---- several independent systems in one launch ----
  * One request per context: the same arguments as mar_solve_async (device
  * pointers, validated the same way). */

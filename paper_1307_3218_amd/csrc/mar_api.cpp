@@ -69,6 +69,14 @@ struct mar_ctx {
     std::map<std::pair<int, int>, std::pair<int, int>> tuned;
     double* tune_buf = nullptr;   // probe outputs of the autotuner: rho [nnz(H)] + e_band
     double* zc_defer = nullptr;   // set during a solve whose assembly waits for a device Fermi level
+    struct EsHook {               // eigen-state passes (mode 1: reference seed, 2: signed components)
+        int mode = 0;
+        double *Rg = nullptr, *Y = nullptr, *eps1 = nullptr, *yref = nullptr, *vref = nullptr;
+        const double* lv = nullptr;
+        double sigma = 0.0;
+        double *pdot = nullptr, *pred = nullptr, *phi = nullptr;
+        int groups = 64;
+    } es;
     char* fws = nullptr;          // workspace of the device Fermi-level search
     size_t fws_bytes = 0;
 
@@ -362,6 +370,44 @@ mar_status ensure_ws(mar_ctx* c, size_t bytes) {
 }
 
 // ---------------------------------------------------------------- the solve
+// The eigensolve and assembly of one seed block, or one of the eigen-state passes.
+template <typename T>
+void eig_stage(mar_ctx* c, hipStream_t s, int B, int ns, const int32_t* seeds, int nu, double* h, const int32_t* nucp,
+               const double* Kp, const T* K, int64_t stride, int64_t Mp, double mu, double kT, double* rho,
+               double* e_seed, double* n_seed, int32_t* nu_out, double* eps, double* w, int64_t blk0) {
+    mar::EigExtra ex;
+    if (c->es.mode == 2) {   // v_ref . v_alpha^(j) through K^T v_ref, then the signed Eq. 3 component
+        launch(c, s, P_EIG, [&] {
+            return mar::launch_es_pdot<T>(B, K, stride, c->M, Mp, nu, c->es.vref, c->es.pdot, c->es.groups, s);
+        });
+        launch(c, s, P_REDUCE, [&] {
+            return mar::launch_reduce(c->es.pdot, c->es.groups, (int64_t)nu * B, c->es.pred, nullptr, B, nu, 0, s);
+        });
+        ex.mode = 2;
+        ex.pref = c->es.pred;
+        ex.pB = B;
+        ex.win = c->es.lv;
+        ex.sigma = c->es.sigma;
+        ex.phi = c->es.phi + blk0;
+    } else if (c->es.mode == 1) {   // the reference seed's full subspace eigenvectors
+        ex.mode = 1;
+        ex.Rg = c->es.Rg;
+        ex.Y = c->es.Y;
+        eps = c->es.eps1;
+        w = nullptr;
+    }
+    launch(c, s, P_EIG, [&] {
+        return mar::launch_eig(ns, seeds, nu, h, nucp, Kp, c->Hrp, c->Hcol, c->Hval, c->SvalH, c->diagS, c->max_row,
+                               mu, kT, rho, e_seed, n_seed, nu_out, eps, w,
+                               c->zc_defer ? c->zc_defer + (size_t)blk0 * nu * c->max_row : nullptr, ex, s);
+    });
+    if (c->es.mode == 1)
+        launch(c, s, P_EIG, [&] {
+            return mar::launch_es_refvec<T>(K, stride, c->M, seeds, nu, nucp, c->es.Y, c->es.eps1, c->es.lv,
+                                            c->es.sigma, c->es.yref, c->es.vref, s);
+        });
+}
+
 template <typename T>
 mar_status run_solve(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds, int nu, double mu, double kT, int B,
                      double* d_rho, double* d_e_band, double* d_e_seed, double* d_n_seed, int32_t* d_nu_eff,
@@ -465,14 +511,11 @@ mar_status run_solve(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds, int nu
             return mar::launch_gather<T>(B, ns, seeds, nu, ws.nu_eff, ws.K, stride, c->Hrp, c->Hcol, c->max_row, Kp,
                                          nucp, s);
         });
-        launch(c, s, P_EIG, [&] {
-            return mar::launch_eig(ns, seeds, nu, ws.h, nucp, Kp, c->Hrp, c->Hcol, c->Hval, c->SvalH, c->diagS,
-                                   c->max_row, mu, kT, d_rho, e_seed + blk0, n_seed + blk0, nu_out + blk0,
-                                   d_eps ? d_eps + blk0 * nu : nullptr, d_w ? d_w + blk0 * nu : nullptr,
-                                   c->zc_defer ? c->zc_defer + (size_t)blk0 * nu * c->max_row : nullptr, s);
-        });
+        eig_stage<T>(c, s, B, ns, seeds, nu, ws.h, nucp, Kp, ws.K, stride, M, mu, kT, d_rho, e_seed + blk0,
+                     n_seed + blk0, nu_out + blk0, d_eps ? d_eps + blk0 * nu : nullptr,
+                     d_w ? d_w + blk0 * nu : nullptr, blk0);
     }
-    if (!c->zc_defer) launch(c, s, P_SUM, [&] { return mar::launch_sum(e_seed, n_seeds, d_e_band, s); });
+    if (!c->zc_defer && !c->es.mode) launch(c, s, P_SUM, [&] { return mar::launch_sum(e_seed, n_seeds, d_e_band, s); });
     if (c->refused) {
         c->refused = false;
         return set_err(c, MAR_ERR_STATE, "internal error: a partial-sum buffer was too small; solve not run");
@@ -627,14 +670,10 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
             return mar::launch_gather<T>(B, ns, seeds, nu, nu_blk, K, stride, c->Hrp, c->Hcol, c->max_row, Kp, nucp,
                                          s);
         });
-        launch(c, s, P_EIG, [&] {
-            return mar::launch_eig(ns, seeds, nu, h, nucp, Kp, c->Hrp, c->Hcol, c->Hval, c->SvalH, c->diagS,
-                                   c->max_row, mu, kT, d_rho, e_seed + blk0, n_seed + blk0, nu_out + blk0,
-                                   d_eps ? d_eps + blk0 * nu : nullptr, d_w ? d_w + blk0 * nu : nullptr,
-                                   c->zc_defer ? c->zc_defer + (size_t)blk0 * nu * c->max_row : nullptr, s);
-        });
+        eig_stage<T>(c, s, B, ns, seeds, nu, h, nucp, Kp, K, stride, M, mu, kT, d_rho, e_seed + blk0, n_seed + blk0,
+                     nu_out + blk0, d_eps ? d_eps + blk0 * nu : nullptr, d_w ? d_w + blk0 * nu : nullptr, blk0);
     }
-    if (!c->zc_defer) launch(c, s, P_SUM, [&] { return mar::launch_sum(e_seed, n_seeds, d_e_band, s); });
+    if (!c->zc_defer && !c->es.mode) launch(c, s, P_SUM, [&] { return mar::launch_sum(e_seed, n_seeds, d_e_band, s); });
     if (c->refused) {
         c->refused = false;
         return set_err(c, MAR_ERR_STATE, "internal error: a partial-sum buffer was too small; solve not run");
@@ -1080,6 +1119,149 @@ mar_status mar_solve_fermi_async(mar_ctx* c, const int32_t* d_seeds, int64_t n_s
         return set_err(c, MAR_ERR_STATE, "internal error: a launch was refused; solve not completed");
     }
     HIP_OR(c, hipGetLastError());
+    return MAR_OK;
+}
+
+mar_status mar_eigen_state_async(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds, int32_t nu, int32_t k,
+                                 double sigma, mar_precision prec, mar_form form, double* d_phi, double* d_levels,
+                                 int32_t* d_ref, void* hip_stream) {
+    if (!c) return MAR_ERR_STATE;
+    mar_status st = check_scalars(c, n_seeds, nu, 0.0, 0.0, prec, form);
+    if (st != MAR_OK) return st;
+    if (n_seeds < 1 || !d_seeds) return set_err(c, MAR_ERR_ARG, "eigen states need at least one seed");
+    if (k < 1 || k > n_seeds) return set_err(c, MAR_ERR_ARG, fmt("k = %d outside [1, n_seeds = %lld]", k, (long long)n_seeds));
+    if (!(sigma >= 0.0) || !std::isfinite(sigma)) return set_err(c, MAR_ERR_ARG, "sigma must be finite and >= 0");
+    if (!d_phi || !d_levels) return set_err(c, MAR_ERR_ARG, "phi or levels output is NULL");
+    if ((size_t)nu > (size_t)mar::MAX_NU_ASSEMBLE) return set_err(c, MAR_ERR_ARG, "nu too large for the eigen states");
+    HIP_OR(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    const Plan pl = plan_solve(c, nu, prec, form, n_seeds);
+    const size_t n = (size_t)n_seeds, nl = n * nu, Mp = (size_t)(c->M + 3) / 4 * 4;
+    const int groups = 64;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align_up(bytes);
+        return o;
+    };
+    const size_t oZ = take(nl * c->max_row * 8), oEps = take(nl * 8), oW = take(nl * 8), oE = take(n * 8),
+                 oN = take(n * 8), oNu = take(n * 4), oPart = take(3 * 512 * 8), oSt = take(8 * 8),
+                 oCm = take(n * 8), oAm = take(n * 4), oRef = take(4 * 4), oRs = take(4), oRg = take((size_t)nu * (nu + 1) * 8),
+                 oY = take((size_t)nu * nu * 8), oE1 = take((size_t)nu * 8), oYr = take((size_t)nu * 8),
+                 oVr = take(Mp * 8), oPd = take((size_t)groups * nu * pl.B * 8), oPr = take((size_t)nu * pl.B * 8),
+                 o1 = take(4 * 8);
+    if (off > c->fws_bytes) {
+        if (c->fws) {
+            HIP_OR(c, hipDeviceSynchronize());
+            HIP_OR(c, hipFree(c->fws));
+        }
+        c->fws = nullptr;
+        c->fws_bytes = 0;
+        void* p = nullptr;
+        HIP_OR(c, hipMalloc(&p, off));
+        c->fws = (char*)p;
+        c->fws_bytes = off;
+    }
+    char* f = c->fws;
+    double* zc = (double*)(f + oZ);
+    double* eps = (double*)(f + oEps);
+    double* wt = (double*)(f + oW);
+    int32_t* nu_eff = (int32_t*)(f + oNu);
+    int32_t* ref = d_ref ? d_ref : (int32_t*)(f + oRef);
+    int32_t* refseed = (int32_t*)(f + oRs);
+    double* one = (double*)(f + o1);   // per-seed outputs of the one-seed reference solve
+    // pass 1: levels, weights and rows e_i.v_alpha of every seed (Sec. 3: the Green's function of all seeds)
+    mar_request r{d_seeds, n_seeds, nu, 0.0, 0.0, prec, form, nullptr, nullptr, (double*)(f + oE), (double*)(f + oN),
+                  nu_eff, eps, wt};
+    c->zc_defer = zc;
+    st = dispatch_solve(c, r, pl, s);
+    c->zc_defer = nullptr;
+    if (st != MAR_OK) return st;
+    // eta(k - 1), eps_k = eta(k - 1/2), eta(k) from the integrated density of states
+    launch(c, s, P_MU, [&] {
+        return mar::launch_dos_search(n_seeds, nu, nu_eff, eps, wt, sigma, k, 200, (double*)(f + oPart),
+                                      (double*)(f + oSt), d_levels, s);
+    });
+    // the reference subspace eigenvector: largest weight contribution to phi_k (Appendix)
+    launch(c, s, P_EIG, [&] {
+        return mar::launch_es_reference((int)n_seeds, d_seeds, nu, nu_eff, eps, zc, c->max_row, c->Hrp, c->Hcol,
+                                        d_levels, sigma, (double*)(f + oCm), (int32_t*)(f + oAm), ref, refseed, s);
+    });
+    if (c->refused) {
+        c->refused = false;
+        return set_err(c, MAR_ERR_STATE, "internal error: a launch was refused; eigen state not computed");
+    }
+    // pass 1': the reference seed alone (B = 1), its eigenvector formed over all rows as v_ref
+    c->es = mar_ctx::EsHook{};
+    c->es.mode = 1;
+    c->es.Rg = (double*)(f + oRg);
+    c->es.Y = (double*)(f + oY);
+    c->es.eps1 = (double*)(f + oE1);
+    c->es.yref = (double*)(f + oYr);
+    c->es.vref = (double*)(f + oVr);
+    c->es.lv = d_levels;
+    c->es.sigma = sigma;
+    mar_request r1{refseed, 1, nu, 0.0, 0.0, prec, MAR_FORM_PLAIN, nullptr, nullptr, one, one + 1, (int32_t*)(one + 2),
+                   nullptr, nullptr};
+    st = dispatch_solve(c, r1, plan_solve(c, nu, prec, MAR_FORM_PLAIN, 1), s);
+    if (st != MAR_OK) {
+        c->es = mar_ctx::EsHook{};
+        return st;
+    }
+    // pass 2: every seed again, with v_ref . v_alpha^(j) from K^T v_ref, then Eq. 3 with those signs
+    c->es.mode = 2;
+    c->es.pdot = (double*)(f + oPd);
+    c->es.pred = (double*)(f + oPr);
+    c->es.groups = groups;
+    c->es.phi = d_phi;
+    st = dispatch_solve(c, r, pl, s);
+    c->es = mar_ctx::EsHook{};
+    if (st != MAR_OK) return st;
+    HIP_OR(c, hipGetLastError());
+    return MAR_OK;
+}
+
+mar_status mar_eigen_state(mar_ctx* c, const int32_t* seeds, int64_t n_seeds, int32_t nu, int32_t k, double sigma,
+                           mar_precision prec, mar_form form, double* phi, double* levels, int32_t* ref) {
+    if (!c) return MAR_ERR_STATE;
+    if (!phi || !levels) return set_err(c, MAR_ERR_ARG, "phi or levels output is NULL");
+    if (n_seeds > 0 && !seeds) return set_err(c, MAR_ERR_ARG, "seeds is NULL");
+    {
+        std::vector<char> seen(c->M, 0);
+        for (int64_t i = 0; i < n_seeds; ++i) {
+            const int32_t j = seeds[i];
+            if (j < 0 || j >= c->M) return set_err(c, MAR_ERR_ARG, fmt("seed %d outside [0, M)", j));
+            if (seen[j]) return set_err(c, MAR_ERR_ARG, fmt("seed %d listed twice", j));
+            seen[j] = 1;
+        }
+    }
+    HIP_OR(c, hipSetDevice(c->device));
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        const size_t o = off;
+        off += align_up(b);
+        return o;
+    };
+    const size_t oSeeds = take(n_seeds * 4), oPhi = take(n_seeds * 8), oLv = take(3 * 8), oRef = take(3 * 4);
+    if (off > c->io_bytes) {
+        if (c->io) HIP_OR(c, hipFree(c->io));
+        c->io = nullptr;
+        c->io_bytes = 0;
+        void* p = nullptr;
+        HIP_OR(c, hipMalloc(&p, off));
+        c->io = (char*)p;
+        c->io_bytes = off;
+    }
+    char* b = c->io;
+    hipStream_t s = c->stream;
+    if (n_seeds > 0) HIP_OR(c, hipMemcpyAsync(b + oSeeds, seeds, n_seeds * 4, hipMemcpyHostToDevice, s));
+    mar_status st = mar_eigen_state_async(c, (int32_t*)(b + oSeeds), n_seeds, nu, k, sigma, prec, form,
+                                          (double*)(b + oPhi), (double*)(b + oLv), (int32_t*)(b + oRef), s);
+    if (st != MAR_OK) return st;
+    HIP_OR(c, hipMemcpyAsync(phi, b + oPhi, n_seeds * 8, hipMemcpyDeviceToHost, s));
+    HIP_OR(c, hipMemcpyAsync(levels, b + oLv, 3 * 8, hipMemcpyDeviceToHost, s));
+    if (ref) HIP_OR(c, hipMemcpyAsync(ref, b + oRef, 3 * 4, hipMemcpyDeviceToHost, s));
+    HIP_OR(c, hipStreamSynchronize(s));
     return MAR_OK;
 }
 

@@ -28,6 +28,20 @@ __device__ __forceinline__ double fermi_occ(double eps, double mu, double kT) {
     return x >= 0.0 ? t / (1.0 + t) : 1.0 / (1.0 + t);
 }
 
+// Logistic step F(x) = 1/(1+e^-x), and the window of a smoothed delta of width
+// sigma over [a, b] (sigma = 0: sharp, 1/2 at an endpoint) for Eq. 3.
+__device__ __forceinline__ double logistic_step(double x) {
+    const double t = exp(-fabs(x));
+    return x >= 0.0 ? 1.0 / (1.0 + t) : t / (1.0 + t);
+}
+__device__ __forceinline__ double smooth_step(double x, double sigma) {
+    if (sigma == 0.0) return x > 0.0 ? 1.0 : (x < 0.0 ? 0.0 : 0.5);
+    return logistic_step(x / sigma);
+}
+__device__ __forceinline__ double level_window(double eps, double a, double b, double sigma) {
+    return smooth_step(b - eps, sigma) - smooth_step(a - eps, sigma);
+}
+
 // Sum over the 256 threads; every thread gets the same value (butterfly
 // pairs add the same two operands, so all lanes agree bit for bit).
 __device__ __forceinline__ double block_sum(double v, double* red) {
@@ -43,7 +57,7 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // Implicit QL with Wilkinson shifts on the symmetric tridiagonal (d, e),
 // e[i] coupling d[i] and d[i+1], e[m-1] = 0 (Bowdler, Martin, Reinsch and
 // Wilkinson's tql2 scheme). Run by one wavefront: every lane carries the same
-// scalar recurrence, lane c < nr applies each rotation to column c of R.
+// scalar recurrence, lane l applies each rotation to columns l, l + 64, ... of R.
 // Returns the number of eigenvalues left unconverged (0 on success).
 __device__ int ql_implicit(double* d, double* e, int m, double* R, int nr, int lane) {
     int fails = 0;
@@ -82,10 +96,10 @@ __device__ int ql_implicit(double* d, double* e, int m, double* R, int nr, int l
                 p = s * r;
                 d[i + 1] = g + p;
                 g = c * r - bb;
-                if (lane < nr) {
-                    const double a0 = R[i * nr + lane], a1 = R[(i + 1) * nr + lane];
-                    R[(i + 1) * nr + lane] = s * a0 + c * a1;
-                    R[i * nr + lane] = c * a0 - s * a1;
+                for (int col = lane; col < nr; col += 64) {
+                    const double a0 = R[i * nr + col], a1 = R[(i + 1) * nr + col];
+                    R[(i + 1) * nr + col] = s * a0 + c * a1;
+                    R[i * nr + col] = c * a0 - s * a1;
                 }
             }
             if (split) continue;
@@ -98,7 +112,7 @@ __device__ int ql_implicit(double* d, double* e, int m, double* R, int nr, int l
 }
 
 size_t eig_lds_bytes(int nu, int max_row, bool a_in_lds) {
-    size_t n = (a_in_lds ? (size_t)nu * nu : 0) + (size_t)nu * (max_row + 1) + 4 * (size_t)nu + 8 + 64 + 64 + 2;
+    size_t n = (a_in_lds ? (size_t)nu * nu : 0) + (size_t)nu * (max_row + 1) + 4 * (size_t)nu + 8 + 72 + 64 + 2;
     return n * sizeof(double);
 }
 
@@ -127,7 +141,7 @@ __global__ __launch_bounds__(WG) void k_gather_rows(int nseeds, const int32_t* _
 }
 
 template <bool LDS_A>
-__global__ __launch_bounds__(WG) void k_eig(int nseeds, const int32_t* __restrict__ seeds, int nu,
+__global__ __launch_bounds__(WG) void k_eig(EigExtra ex, int nseeds, const int32_t* __restrict__ seeds, int nu,
                                             double* __restrict__ h, const int32_t* __restrict__ nu_eff_blk,
                                             const double* __restrict__ Kp, const int32_t* __restrict__ Hrp,
                                             const int32_t* __restrict__ Hcol, const double* __restrict__ Hval,
@@ -158,7 +172,8 @@ __global__ __launch_bounds__(WG) void k_eig(int nseeds, const int32_t* __restric
     const int j = seeds[b];
     const int rlo = Hrp[j];
     const int nP = Hrp[j + 1] - rlo;
-    const int NR = nP + 1;
+    // columns of R: [e_1 | K[P(j),:]^T] (+ [K^T v_ref] in mode 2), or [e_1 | I_m] in mode 1
+    const int NR = ex.mode == 1 ? m + 1 : (ex.mode == 2 ? nP + 2 : nP + 1);
 
     double* A;
     int ld;
@@ -171,8 +186,9 @@ __global__ __launch_bounds__(WG) void k_eig(int nseeds, const int32_t* __restric
         A = h + (int64_t)b * nu * nu;
         ld = nu;
     }
-    double* R = p;
-    p += (size_t)nu * (max_row + 1);
+    double* Rl = p;
+    double* R = ex.mode == 1 ? ex.Rg + (int64_t)b * nu * (nu + 1) : Rl;
+    p += (size_t)nu * (max_row + (ex.mode == 2 ? 2 : 1));
     double* d = p;
     p += nu;
     double* e = p;
@@ -183,8 +199,8 @@ __global__ __launch_bounds__(WG) void k_eig(int nseeds, const int32_t* __restric
     p += nu;
     double* red = p;
     p += 8;
-    double* svec = p;
-    p += 64;
+    double* svec = ex.mode == 1 ? Rl : p;   // one value per column of R (mode 1: up to nu + 1, in R's unused LDS)
+    p += 72;
     double* rhoL = p;
     p += 64;
     int* tjp = reinterpret_cast<int*>(p);
@@ -198,10 +214,14 @@ __global__ __launch_bounds__(WG) void k_eig(int nseeds, const int32_t* __restric
         for (int r = wave; r < m; r += 4)
             for (int c = lane; c < r; c += 64) A[r * ld + c] = A[c * ld + r];
     }
-    // R = [e_1 | K[P(j), :]^T]
     for (int idx = tid; idx < m * NR; idx += WG) {
         const int k = idx / NR, c = idx - k * NR;
-        R[idx] = c == 0 ? (k == 0 ? 1.0 : 0.0) : Kp[((int64_t)b * nu + k) * max_row + (c - 1)];
+        double r0;
+        if (c == 0) r0 = k == 0 ? 1.0 : 0.0;
+        else if (ex.mode == 1) r0 = k == c - 1 ? 1.0 : 0.0;
+        else if (c <= nP) r0 = Kp[((int64_t)b * nu + k) * max_row + (c - 1)];
+        else r0 = ex.pref[(int64_t)k * ex.pB + b];
+        R[idx] = r0;
     }
     if (tid < nP && Hcol[rlo + tid] == j) *tjp = tid;
     __syncthreads();
@@ -282,6 +302,28 @@ __global__ __launch_bounds__(WG) void k_eig(int nseeds, const int32_t* __restric
     // i in P(j), for an assembly at a Fermi level found later (k_assemble).
     const int tj = *tjp;
     const double sq = sqrt(diagS[j]);
+    if (ex.mode == 1) {   // the full subspace eigenvectors y_alpha and levels
+        for (int idx = tid; idx < m * m; idx += WG) {
+            const int a = idx / m, c = idx - a * m;
+            ex.Y[((int64_t)b * nu + a) * nu + c] = R[a * NR + 1 + c];
+        }
+        for (int a = tid; a < nu; a += WG) eps_b[a] = a < m ? d[a] : 0.0;
+        if (tid == 0) nu_eff_out[b] = m;
+        return;
+    }
+    if (ex.mode == 2) {   // Eq. 3 with the inner-product signs: sum_alpha s_alpha (e_j.v_alpha) window_alpha
+        if (tid == 0) {
+            const double lo = ex.win[1], hi = ex.win[2];
+            double phi = 0.0;
+            for (int a = 0; a < m; ++a) {
+                const double c = R[a * NR + 1 + tj] * level_window(d[a], lo, hi, ex.sigma);
+                phi += R[a * NR + NR - 1] >= 0.0 ? c : -c;
+            }
+            ex.phi[b] = phi;
+            nu_eff_out[b] = m;
+        }
+        return;
+    }
     if (zc != nullptr) {
         double* zb = zc + (int64_t)b * nu * max_row;
         for (int idx = tid; idx < m * nP; idx += WG) {
@@ -343,16 +385,17 @@ LaunchInfo launch_eig(int nseeds, const int32_t* seeds, int nu, double* h, const
                       const double* Kp, const int32_t* Hrp, const int32_t* Hcol, const double* Hval,
                       const double* SvalH, const double* diagS, int max_row, double mu, double kT, double* rho,
                       double* e_seed, double* n_seed, int32_t* nu_eff_out, double* eps_out, double* w_out,
-                      double* zc, hipStream_t s) {
-    const bool lds_a = eig_a_fits_lds(nu, max_row);
-    const size_t lds = eig_lds_bytes(nu, max_row, lds_a);
+                      double* zc, const EigExtra& ex, hipStream_t s) {
+    const int rcols = max_row + (ex.mode == 2 ? 1 : 0);   // R's LDS share (mode 1 keeps R in global memory)
+    const bool lds_a = eig_a_fits_lds(nu, rcols);
+    const size_t lds = eig_lds_bytes(nu, rcols, lds_a);
     if (lds_a) {
         static bool attr = false;
         if (!attr) {
             hipFuncSetAttribute((const void*)k_eig<true>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
             attr = true;
         }
-        hipLaunchKernelGGL((k_eig<true>), dim3(nseeds), dim3(WG), lds, s, nseeds, seeds, nu, h, nu_eff_blk, Kp, Hrp,
+        hipLaunchKernelGGL((k_eig<true>), dim3(nseeds), dim3(WG), lds, s, ex, nseeds, seeds, nu, h, nu_eff_blk, Kp, Hrp,
                            Hcol, Hval, SvalH, diagS, max_row, mu, kT, rho, e_seed, n_seed, nu_eff_out, eps_out, w_out,
                            zc);
     } else {
@@ -361,7 +404,7 @@ LaunchInfo launch_eig(int nseeds, const int32_t* seeds, int nu, double* h, const
             hipFuncSetAttribute((const void*)k_eig<false>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
             attr = true;
         }
-        hipLaunchKernelGGL((k_eig<false>), dim3(nseeds), dim3(WG), lds, s, nseeds, seeds, nu, h, nu_eff_blk, Kp,
+        hipLaunchKernelGGL((k_eig<false>), dim3(nseeds), dim3(WG), lds, s, ex, nseeds, seeds, nu, h, nu_eff_blk, Kp,
                            Hrp, Hcol, Hval, SvalH, diagS, max_row, mu, kT, rho, e_seed, n_seed, nu_eff_out, eps_out,
                            w_out, zc);
     }
@@ -555,6 +598,222 @@ LaunchInfo launch_fermi_search(int64_t nseeds, int nu, const int32_t* nu_eff, co
     li.flops = (double)iters * npair * 30.0;
     return li;
 }
+
+// ---------------------------------------------------------------------------
+// Eigen states (Sec. 3, Eq. 3; Appendix): integrated density of states
+//   n(eta) = sum_j sum_alpha w_alpha^(j) F((eta - eps_alpha^(j)) / sigma)
+// (F the logistic step; sigma = 0: the unit step, 1/2 at 0), bisected for the
+// three counts k - 1, k - 1/2 and k at once on [min eps - 1, max eps + 1].
+// st = {lo, hi} x 3; lv = {eta(k - 1/2), eta(k - 1), eta(k)}.
+__global__ __launch_bounds__(64) void k_dos_init(int nwg, const double* __restrict__ part, double* __restrict__ st) {
+    if (threadIdx.x != 0) return;
+    double lo = INFINITY, hi = -INFINITY;
+    for (int g = 0; g < nwg; ++g) {
+        lo = fmin(lo, part[2 * g]);
+        hi = fmax(hi, part[2 * g + 1]);
+    }
+    if (!(lo <= hi)) lo = hi = 0.0;
+    for (int t = 0; t < 3; ++t) {
+        st[2 * t] = lo - 1.0;
+        st[2 * t + 1] = hi + 1.0;
+    }
+}
+
+__global__ __launch_bounds__(WG) void k_dos_count(int64_t nseeds, int nu, const int32_t* __restrict__ nu_eff,
+                                                  const double* __restrict__ eps, const double* __restrict__ w,
+                                                  double sigma, const double* __restrict__ st,
+                                                  double* __restrict__ part) {
+    __shared__ double red[8];
+    double mid[3], c[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < 3; ++t) mid[t] = 0.5 * (st[2 * t] + st[2 * t + 1]);
+    const int64_t npair = nseeds * nu;
+    for (int64_t p = (int64_t)blockIdx.x * WG + threadIdx.x; p < npair; p += (int64_t)gridDim.x * WG) {
+        const int64_t b = p / nu;
+        const int a = (int)(p - b * nu);
+        if (a < nu_eff[b]) {
+#pragma unroll
+            for (int t = 0; t < 3; ++t) c[t] += w[p] * smooth_step(mid[t] - eps[p], sigma);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        const double v = block_sum(c[t], red);
+        if (threadIdx.x == 0) part[3 * blockIdx.x + t] = v;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_dos_step(int nwg, const double* __restrict__ part, int k,
+                                                 double* __restrict__ st, int last, double* __restrict__ lv) {
+    if (threadIdx.x != 0) return;
+    const double target[3] = {k - 1.0, k - 0.5, (double)k};
+    for (int t = 0; t < 3; ++t) {
+        double n = 0.0;
+        for (int g = 0; g < nwg; ++g) n += part[3 * g + t];
+        const double mid = 0.5 * (st[2 * t] + st[2 * t + 1]);
+        if (n < target[t]) st[2 * t] = mid;
+        else st[2 * t + 1] = mid;
+    }
+    if (last) {
+        lv[0] = 0.5 * (st[2] + st[3]);   // eps_k = eta(k - 1/2)
+        lv[1] = 0.5 * (st[0] + st[1]);   // eta(k - 1)
+        lv[2] = 0.5 * (st[4] + st[5]);   // eta(k)
+    }
+}
+
+LaunchInfo launch_dos_search(int64_t nseeds, int nu, const int32_t* nu_eff, const double* eps, const double* w,
+                             double sigma, int k, int iters, double* part, double* st, double* lv, hipStream_t s) {
+    const int64_t npair = nseeds * nu;
+    const int nwg = (int)std::min<int64_t>(MU_WGS, std::max<int64_t>(1, (npair + WG - 1) / WG));
+    hipLaunchKernelGGL(k_mu_bounds, dim3(nwg), dim3(WG), 0, s, nseeds, nu, nu_eff, eps, part);
+    hipLaunchKernelGGL(k_dos_init, dim3(1), dim3(64), 0, s, nwg, part, st);
+    for (int it = 0; it < iters; ++it) {
+        hipLaunchKernelGGL(k_dos_count, dim3(nwg), dim3(WG), 0, s, nseeds, nu, nu_eff, eps, w, sigma, st, part);
+        hipLaunchKernelGGL(k_dos_step, dim3(1), dim3(64), 0, s, nwg, part, k, st, it + 1 == iters ? 1 : 0, lv);
+    }
+    LaunchInfo li;
+    li.wgs = nwg;
+    li.bytes = (double)(iters + 1) * npair * 20.0;
+    li.flops = (double)iters * npair * 90.0;
+    return li;
+}
+
+// Contributions c_alpha^(j) = (e_j . v_alpha^(j)) window_alpha of every seed
+// (kept rows zc, levels eps) and the reference: the largest |c| (first seed,
+// then first alpha, on ties). ref = {position b, alpha, seed j}; refseed[0] = j.
+__global__ __launch_bounds__(WG) void k_es_contrib(int nseeds, const int32_t* __restrict__ seeds, int nu,
+                                                   const int32_t* __restrict__ nu_eff, const double* __restrict__ eps,
+                                                   const double* __restrict__ zc, int max_row,
+                                                   const int32_t* __restrict__ Hrp, const int32_t* __restrict__ Hcol,
+                                                   const double* __restrict__ lv, double sigma,
+                                                   double* __restrict__ cmax, int32_t* __restrict__ amax) {
+    __shared__ int tjs;
+    const int b = blockIdx.x;
+    if (b >= nseeds) return;
+    const int m = nu_eff[b];
+    if (m <= 0) {
+        if (threadIdx.x == 0) {
+            cmax[b] = -1.0;
+            amax[b] = 0;
+        }
+        return;
+    }
+    const int j = seeds[b];
+    const int rlo = Hrp[j], nP = Hrp[j + 1] - rlo;
+    if ((int)threadIdx.x < nP && Hcol[rlo + threadIdx.x] == j) tjs = threadIdx.x;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const double* zb = zc + (int64_t)b * nu * max_row;
+    double best = -1.0;
+    int ba = 0;
+    for (int a = 0; a < m; ++a) {
+        const double c = fabs(zb[a * max_row + tjs] * level_window(eps[(int64_t)b * nu + a], lv[1], lv[2], sigma));
+        if (c > best) {
+            best = c;
+            ba = a;
+        }
+    }
+    cmax[b] = best;
+    amax[b] = ba;
+}
+
+__global__ __launch_bounds__(64) void k_es_argmax(int nseeds, const int32_t* __restrict__ seeds,
+                                                  const double* __restrict__ cmax, const int32_t* __restrict__ amax,
+                                                  int32_t* __restrict__ ref, int32_t* __restrict__ refseed) {
+    if (threadIdx.x != 0) return;
+    double best = -1.0;
+    int bb = 0;
+    for (int b = 0; b < nseeds; ++b)
+        if (cmax[b] > best) {
+            best = cmax[b];
+            bb = b;
+        }
+    ref[0] = bb;
+    ref[1] = nseeds > 0 ? amax[bb] : 0;
+    ref[2] = nseeds > 0 ? seeds[bb] : 0;
+    refseed[0] = ref[2];
+}
+
+LaunchInfo launch_es_reference(int nseeds, const int32_t* seeds, int nu, const int32_t* nu_eff, const double* eps,
+                               const double* zc, int max_row, const int32_t* Hrp, const int32_t* Hcol,
+                               const double* lv, double sigma, double* cmax, int32_t* amax, int32_t* ref,
+                               int32_t* refseed, hipStream_t s) {
+    if (nseeds > 0)
+        hipLaunchKernelGGL(k_es_contrib, dim3(nseeds), dim3(WG), 0, s, nseeds, seeds, nu, nu_eff, eps, zc, max_row, Hrp,
+                           Hcol, lv, sigma, cmax, amax);
+    hipLaunchKernelGGL(k_es_argmax, dim3(1), dim3(64), 0, s, nseeds, seeds, cmax, amax, ref, refseed);
+    LaunchInfo li;
+    li.wgs = nseeds;
+    li.bytes = (double)nseeds * nu * 16.0;
+    return li;
+}
+
+// Reference seed (solved alone, B = 1): pick among its subspace eigenvectors
+// the one with the largest |(e_j . v_alpha) window_alpha| (v_alpha = K y_alpha),
+// and form v_ref = K y_ref over all rows.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_es_pick(const T* __restrict__ K, int64_t stride, const int32_t* __restrict__ seed,
+                                                int nu, const int32_t* __restrict__ nu_eff,
+                                                const double* __restrict__ Y, const double* __restrict__ eps,
+                                                const double* __restrict__ lv, double sigma,
+                                                double* __restrict__ yref) {
+    __shared__ double cs[WG];
+    __shared__ int as[WG];
+    const int m = nu_eff[0];
+    const int j = seed[0];
+    double best = -1.0;
+    int ba = 0;
+    for (int a = threadIdx.x; a < m; a += WG) {
+        double z = 0.0;
+        for (int k = 0; k < m; ++k) z += (double)K[(int64_t)k * stride + j] * Y[(int64_t)a * nu + k];
+        const double c = fabs(z * level_window(eps[a], lv[1], lv[2], sigma));
+        if (c > best) {
+            best = c;
+            ba = a;
+        }
+    }
+    cs[threadIdx.x] = best;
+    as[threadIdx.x] = ba;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int t = 1; t < WG; ++t)
+        if (cs[t] > best || (cs[t] == best && as[t] < ba)) {
+            best = cs[t];
+            ba = as[t];
+        }
+    for (int k = 0; k < nu; ++k) yref[k] = k < m ? Y[(int64_t)ba * nu + k] : 0.0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(WG) void k_es_vref(const T* __restrict__ K, int64_t stride, int64_t M, int nu,
+                                                const int32_t* __restrict__ nu_eff, const double* __restrict__ yref,
+                                                double* __restrict__ vref) {
+    const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (i >= M) return;
+    const int m = nu_eff[0];
+    double v = 0.0;
+    for (int k = 0; k < m; ++k) v += (double)K[(int64_t)k * stride + i] * yref[k];
+    vref[i] = v;
+}
+
+template <typename T>
+LaunchInfo launch_es_refvec(const T* K, int64_t stride, int64_t M, const int32_t* seed, int nu,
+                            const int32_t* nu_eff, const double* Y, const double* eps, const double* lv, double sigma,
+                            double* yref, double* vref, hipStream_t s) {
+    hipLaunchKernelGGL((k_es_pick<T>), dim3(1), dim3(WG), 0, s, K, stride, seed, nu, nu_eff, Y, eps, lv, sigma, yref);
+    const int64_t wgs = (M + WG - 1) / WG;
+    hipLaunchKernelGGL((k_es_vref<T>), dim3((unsigned)wgs), dim3(WG), 0, s, K, stride, M, nu, nu_eff, yref, vref);
+    LaunchInfo li;
+    li.wgs = wgs;
+    li.bytes = (double)nu * M * (sizeof(T) + 8.0 / nu);
+    return li;
+}
+template LaunchInfo launch_es_refvec<float>(const float*, int64_t, int64_t, const int32_t*, int, const int32_t*,
+                                            const double*, const double*, const double*, double, double*, double*,
+                                            hipStream_t);
+template LaunchInfo launch_es_refvec<double>(const double*, int64_t, int64_t, const int32_t*, int, const int32_t*,
+                                             const double*, const double*, const double*, double, double*, double*,
+                                             hipStream_t);
 
 template <typename T>
 static LaunchInfo launch_gather_t(int B, int nseeds, const int32_t* seeds, int nu, const int32_t* nu_eff_blk,

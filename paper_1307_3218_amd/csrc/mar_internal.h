@@ -105,11 +105,22 @@ template <typename T>
 LaunchInfo launch_gather(int B, int nseeds, const int32_t* seeds, int nu, const int32_t* nu_eff_blk, const T* K,
                          int64_t stride, const int32_t* Hrp, const int32_t* Hcol, int max_row, double* Kp,
                          int32_t* nu_copy, hipStream_t s);
+// Eigen-state modes of the subspace eigensolver (Sec. 3, Eq. 3; Appendix).
+struct EigExtra {
+    int mode = 0;                 // 0: assembly (or kept rows); 1: full eigenvectors; 2: signed Eq. 3 component
+    double* Rg = nullptr;         // mode 1: R in global memory, [seed][nu][nu + 1]
+    double* Y = nullptr;          // mode 1: y_alpha of each seed, [seed][alpha][nu]
+    const double* pref = nullptr; // mode 2: K^T v_ref, [k][pB]
+    int pB = 1;
+    const double* win = nullptr;  // mode 2: {eps_k, eta(k-1), eta(k)} on the device
+    double sigma = 0.0;           // mode 2: width of the smoothed delta
+    double* phi = nullptr;        // mode 2: e_j^T phi_k of each seed
+};
 LaunchInfo launch_eig(int nseeds, const int32_t* seeds, int nu, double* h, const int32_t* nu_eff_blk,
                       const double* Kp, const int32_t* Hrp, const int32_t* Hcol, const double* Hval,
                       const double* SvalH, const double* diagS, int max_row, double mu, double kT, double* rho,
                       double* e_seed, double* n_seed, int32_t* nu_eff_out, double* eps_out, double* w_out,
-                      double* zc, hipStream_t s);
+                      double* zc, const EigExtra& ex, hipStream_t s);
 // zc != nullptr: k_eig keeps zc[(b*nu + alpha)*max_row + t] = e_i.v_alpha (i = P(j)[t]) and writes levels
 // and weights (eps_out, w_out required) instead of assembling; k_assemble finishes at mu = *mu.
 constexpr int MAX_NU_ASSEMBLE = 4096;
@@ -117,6 +128,24 @@ LaunchInfo launch_assemble(int nseeds, const int32_t* seeds, int nu, const int32
                            const double* zc, int max_row, const int32_t* Hrp, const int32_t* Hcol,
                            const double* Hval, const double* SvalH, const double* mu, double kT, double* rho,
                            double* e_seed, double* n_seed, hipStream_t s);
+// Eigen states: bisection of the smoothed integrated density of states for the counts k - 1, k - 1/2, k
+// (lv = {eta(k - 1/2), eta(k - 1), eta(k)}); part >= 3 * 512 doubles, st >= 6 doubles.
+LaunchInfo launch_dos_search(int64_t nseeds, int nu, const int32_t* nu_eff, const double* eps, const double* w,
+                             double sigma, int k, int iters, double* part, double* st, double* lv, hipStream_t s);
+// The seed and subspace eigenvector with the largest |(e_j.v_alpha) window| (ref = {position, alpha, seed}).
+LaunchInfo launch_es_reference(int nseeds, const int32_t* seeds, int nu, const int32_t* nu_eff, const double* eps,
+                               const double* zc, int max_row, const int32_t* Hrp, const int32_t* Hcol,
+                               const double* lv, double sigma, double* cmax, int32_t* amax, int32_t* ref,
+                               int32_t* refseed, hipStream_t s);
+// Reference seed solved alone (B = 1): y_ref among its eigenvectors Y, then v_ref = K y_ref (M doubles).
+template <typename T>
+LaunchInfo launch_es_refvec(const T* K, int64_t stride, int64_t M, const int32_t* seed, int nu,
+                            const int32_t* nu_eff, const double* Y, const double* eps, const double* lv, double sigma,
+                            double* yref, double* vref, hipStream_t s);
+// part[(g * nu + k) * B + b] = sum over row chunk g of K[k][i][b] vref[i]; chunks of rows, G groups.
+template <typename T>
+LaunchInfo launch_es_pdot(int B, const T* K, int64_t stride, int64_t M, int64_t Mp, int nu, const double* vref,
+                          double* part, int groups, hipStream_t s);
 // Bisection for the Fermi level over the levels of nseeds seeds; part >= 2 * 512 doubles, st = {lo, hi, mu};
 // the final mu is also written to *mu_out when mu_out != nullptr.
 LaunchInfo launch_fermi_search(int64_t nseeds, int nu, const int32_t* nu_eff, const double* eps, const double* w,

@@ -615,6 +615,37 @@ __global__ __launch_bounds__(WG) void k_projr(const T* __restrict__ basis, int64
     });
 }
 
+// Projection of every basis vector of a block onto one fixed vector v (rows,
+// FP64): part[(g * nk + k) * B + b] = sum over the rows of chunk g of
+// K[k][i][b] v[i]. Grid (groups, nk).
+template <typename T, int B>
+__global__ __launch_bounds__(WG) void k_es_pdot(const T* __restrict__ basis, int64_t slab, int64_t M,
+                                                const double* __restrict__ v, int64_t nvec, int64_t chunk,
+                                                double* __restrict__ part) {
+    using SM = SeedMap<T, B>;
+    constexpr int VEC = SM::VEC, SW = SM::SW, P = SM::P;
+    using VT = typename Vec16<T>::type;
+    const int g = blockIdx.x, k = blockIdx.y, nk = gridDim.y;
+    const VT* bv = reinterpret_cast<const VT*>(basis) + (int64_t)k * (slab / VEC);
+    double acc[1][SW];
+#pragma unroll
+    for (int i = 0; i < SW; ++i) acc[0][i] = 0.0;
+    const int64_t v0 = (int64_t)g * chunk, v1 = v0 + chunk < nvec ? v0 + chunk : nvec;
+    for (int64_t vi = v0 + threadIdx.x; vi < v1; vi += WG) {
+        T a[VEC];
+        unpack(bv[vi], a);
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) {
+            const int64_t e = vi * VEC + i;   // element (row e / B, seed e % B)
+            const int64_t row = e / B;
+            const double x = row < M ? v[row] : 0.0;
+            acc[0][i % SW] += (double)a[i] * x;
+        }
+    }
+    __shared__ double lds[SeedReduce<P, SW, 1>::LDS];
+    wg_seed_reduce<P, SW, 1>(acc, lds, [&](int, int b, double sum) { part[((int64_t)g * nk + k) * B + b] = sum; });
+}
+
 // Dual update of the delayed schedule, one pass over slabs 0..n-1:
 //   u_n = (u~ - sum_k K_k cA_k) / gamma       (second Gram-Schmidt pass of u~)
 //   w'  = (y  - sum_k K_k cB_k - u_n F_n) / gamma   (first pass of y = H u~)
@@ -901,6 +932,20 @@ int projr_blocks_per_cu<MAR_T>(int B, int variant) {
     else { MAR_OCC(PROJR_Q, 4, false); }
 #undef MAR_OCC
     return nb > 0 ? nb : 1;
+}
+
+template <>
+LaunchInfo launch_es_pdot<MAR_T>(int B, const MAR_T* K, int64_t stride, int64_t M, int64_t Mp, int nu,
+                                 const double* vref, double* part, int groups, hipStream_t s) {
+    constexpr int VEC = Vec16<MAR_T>::n;
+    const int64_t nvec = Mp * B / VEC;
+    const int64_t chunk = ((nvec + groups - 1) / groups + WG - 1) / WG * WG;
+    MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_es_pdot<MAR_T, BB>), dim3(groups, nu), dim3(WG), 0, s, K, stride, M, vref, nvec, chunk, part))
+    LaunchInfo li;
+    li.wgs = (int64_t)groups * nu;
+    li.bytes = (double)nu * Mp * B * sizeof(MAR_T) + (double)M * 8.0;
+    li.flops = 2.0 * nu * (double)Mp * B;
+    return li;
 }
 
 template <>

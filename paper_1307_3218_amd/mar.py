@@ -84,6 +84,10 @@ def lib() -> C.CDLL:
     L.mar_solve_fermi_async.argtypes = [_P, _P, i64, i32, f64, f64, C.c_int, C.c_int, _P, _P, _P, _P, _P, _P, _P,
                                         _P, _P]
     L.mar_solve_fermi_async.restype = C.c_int
+    L.mar_eigen_state.argtypes = [_P, _P, i64, i32, i32, f64, C.c_int, C.c_int, _P, _P, _P]
+    L.mar_eigen_state.restype = C.c_int
+    L.mar_eigen_state_async.argtypes = [_P, _P, i64, i32, i32, f64, C.c_int, C.c_int, _P, _P, _P, _P]
+    L.mar_eigen_state_async.restype = C.c_int
     L.mar_solve_many.argtypes = [i32, C.POINTER(_P), C.POINTER(mar_request), _P]
     L.mar_solve_many.restype = C.c_int
     L.mar_autotune.argtypes = [_P, i32, C.c_int, _P, i64, f64, f64, _P, C.POINTER(i32), C.POINTER(i32),
@@ -179,6 +183,18 @@ def mar_solve_fermi_async(ctx, d_seeds, n_seeds, nu, n_target, kT, prec, form, d
                                        int(prec), int(form), _tptr(d_rho), _tptr(d_e_band), _tptr(d_e_seed),
                                        _tptr(d_n_seed), _tptr(d_nu_eff), _tptr(d_eps), _tptr(d_weight), _tptr(d_mu),
                                        stream)
+
+
+def mar_eigen_state(ctx, seeds, nu, k, sigma, prec, form, phi, levels, ref=None) -> int:
+    """Blocking k-th eigen state over the listed seeds (phi [n], levels [3], ref [3] int32 or None)."""
+    return lib().mar_eigen_state(ctx, _ptr(seeds), len(seeds), int(nu), int(k), float(sigma), int(prec), int(form),
+                                 _ptr(phi), _ptr(levels), _ptr(ref))
+
+
+def mar_eigen_state_async(ctx, d_seeds, n_seeds, nu, k, sigma, prec, form, d_phi, d_levels, d_ref=None,
+                          stream=None) -> int:
+    return lib().mar_eigen_state_async(ctx, _tptr(d_seeds), int(n_seeds), int(nu), int(k), float(sigma), int(prec),
+                                       int(form), _tptr(d_phi), _tptr(d_levels), _tptr(d_ref), stream)
 
 
 def mar_request_of(d_seeds, nu, mu, kT, prec, form, d_rho, d_e_band, d_e_seed=None, d_n_seed=None,
@@ -307,6 +323,17 @@ class Context:
                                    FORM[form], d_rho, d_e_band, d_e_seed, d_n_seed, d_nu_eff, d_eps, d_weight, d_mu,
                                    stream)
         _check(self.handle, st)
+
+    def eigen_state(self, seeds, nu, k, sigma, precision="fp64", form="batched") -> dict:
+        """The k-th eigen level and eigenvector components over the listed seeds (Sec. 3, Eq. 3)."""
+        seeds = np.ascontiguousarray(seeds, dtype=np.int32)
+        phi = np.zeros(len(seeds))
+        levels = np.zeros(3)
+        ref = np.zeros(3, dtype=np.int32)
+        st = mar_eigen_state(self.handle, seeds, nu, k, sigma, PRECISION[precision], FORM[form], phi, levels, ref)
+        _check(self.handle, st)
+        return dict(phi=phi, eps_k=float(levels[0]), eta_lo=float(levels[1]), eta_hi=float(levels[2]),
+                    ref=(int(ref[0]), int(ref[1]), int(ref[2])))
 
     def solve_async(self, d_seeds, nu, mu, kT, precision="fp64", form="batched", *, d_rho, d_e_band,
                     d_e_seed=None, d_n_seed=None, d_nu_eff=None, d_eps=None, d_weight=None, stream=None):

@@ -1,0 +1,73 @@
+"""Eigen states on the GPU (mar_eigen_state): the k-th level eps_k = eta(k - 1/2)
+and the components e_j^T phi_k of Eq. 3 with the inner-product sign method.
+
+At nu = M (every subspace is the whole space) the result must be the exact
+generalized eigenpair (LAPACK) up to one global sign; at nu < M it must match the
+eigen-state oracle (oracle/mar_eigenstate.py) on the same seeds.
+"""
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import mar_eigenstate as ES
+from paper_1307_3218_amd import lattice, mar
+
+pytestmark = pytest.mark.gpu
+
+
+def _sign_free(a, b):
+    return min(np.linalg.norm(a - b), np.linalg.norm(a + b)) / np.linalg.norm(b)
+
+
+@pytest.fixture(scope="module")
+def small():
+    s = lattice.generate(2, 1, 1)
+    ev, V = scipy.linalg.eigh(s.H.toarray(), s.S.toarray())
+    ctx = mar.Context(s.H, s.S)
+    yield s, ev, V, ctx
+    ctx.close()
+
+
+@pytest.mark.parametrize("form", ["batched", "plain"])
+@pytest.mark.parametrize("k", [1, 32, 33, 64])
+def test_exact_state_at_nu_M(small, form, k):
+    s, ev, V, ctx = small
+    seeds = np.arange(s.M, dtype=np.int32)
+    out = ctx.eigen_state(seeds, s.M, k, 1e-6, "fp64", form)
+    print(f"[es exact {form} k={k}] eps_k {out['eps_k']:.12f} exact {ev[k - 1]:.12f} ref {out['ref']}", flush=True)
+    assert abs(out["eps_k"] - ev[k - 1]) <= 1e-9
+    assert out["eta_lo"] < out["eps_k"] < out["eta_hi"]
+    assert _sign_free(out["phi"], V[:, k - 1]) <= 1e-8
+
+
+@pytest.fixture(scope="module")
+def c1_states(c1):
+    return ES.subspace_states(c1.H, c1.S, np.arange(c1.M), 30)
+
+
+@pytest.mark.parametrize("k", [128, 129])
+def test_c1_state_against_oracle(c1, c1_states, k):
+    sigma = 0.02
+    ref = ES.eigen_state(c1_states, k, sigma)
+    ctx = mar.Context(c1.H, c1.S)
+    try:
+        for prec, bar in (("fp64", 1e-8), ("fp32", 1e-3)):
+            out = ctx.eigen_state(np.arange(c1.M, dtype=np.int32), 30, k, sigma, prec, "batched")
+            err = _sign_free(out["phi"], ref.phi)
+            print(f"[es c1 k={k} {prec}] eps_k {out['eps_k']:.10f} oracle {ref.eps_k:.10f} phi err {err:.2e} "
+                  f"ref {out['ref'][:2]} oracle ref {ref.ref}", flush=True)
+            assert abs(out["eps_k"] - ref.eps_k) <= (1e-9 if prec == "fp64" else 1e-4)
+            assert abs(out["eta_lo"] - ref.eta_lo) <= (1e-9 if prec == "fp64" else 1e-3)
+            assert abs(out["eta_hi"] - ref.eta_hi) <= (1e-9 if prec == "fp64" else 1e-3)
+            assert err <= bar
+    finally:
+        ctx.close()
+
+
+def test_eigen_state_argument_errors(small):
+    s, ev, V, ctx = small
+    seeds = np.arange(8, dtype=np.int32)
+    for k, sigma in ((0, 0.1), (9, 0.1), (1, -1.0)):
+        with pytest.raises(mar.MarError) as e:
+            ctx.eigen_state(seeds, 8, k, sigma)
+        assert e.value.status == mar.MAR_ERR_ARG
