@@ -224,6 +224,9 @@ def main() -> int:
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--seed-block", type=int, default=0)
+    ap.add_argument("--seed-order", choices=["natural", "random"], default="natural",
+                    help="natural: consecutive seeds (neighbouring atoms) share a block; random: a permutation")
+    ap.add_argument("--no-support", action="store_true", help="stream every row of every slab")
     ap.add_argument("--uneven-calls", type=int, default=8,
                     help="uneven8: mar_solve_many calls per pass over all seeds (each takes M/calls seeds per system)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
@@ -259,12 +262,15 @@ def main() -> int:
         log(f"copy calibration: {args.copy_calibration} MiB read + {args.copy_calibration} MiB written")
         del a, c
     ctx = mar.Context(system.H, system.S)
-    if args.seed_block:
-        ctx.set_tuning(args.seed_block)
+    if args.seed_block or args.no_support:
+        ctx.set_tuning(args.seed_block, support=not args.no_support)
     B = ctx.seed_block(nu, "fp32")
     S_step = args.seeds_per_step
     stream = torch.cuda.current_stream().cuda_stream
-    order = np.random.default_rng(0).permutation(M).astype(np.int32)
+    if args.seed_order == "natural":
+        order = np.arange(M, dtype=np.int32)
+    else:
+        order = np.random.default_rng(0).permutation(M).astype(np.int32)
     n_steps = args.warmup + args.steps
     d_order = torch.from_numpy(order).to(dev)
 
@@ -409,7 +415,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"{system.name} mixed sp2/sp3 lattice, M={M}, nu={nu}, kT={KT}, FP32 batched",
                    "M": M, "nnz": int(system.H.nnz), "nu": nu, "seeds_per_step": S_step, "seed_block": B,
-                   "precision": "fp32", "form": "batched", "mu": mu},
+                   "precision": "fp32", "form": "batched", "mu": mu, "seed_order": args.seed_order,
+                   "support_tracking": not args.no_support},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fp64_plain": plain,

@@ -91,7 +91,11 @@ typedef struct {
                               tile: 0 = 4 x 4, 1 = 8 x 4, 2 = 4 x 4 with non-temporal basis loads,
                               3 = 4 x 2, 4 = 8 x 2 */
     int32_t upd_q;         /* delayed-schedule update: 16-byte vectors per thread, 2/4/8 (0 = 8) */
-    int32_t reserved[2];
+    int32_t support_off;   /* 1 = stream every row of every slab; 0 (default) = skip, in the batched
+                              delayed schedule on a 4x4-block H, the row tiles where all vectors of the
+                              seed block are exactly zero (farther from each seed than the step, in hops
+                              of H's pattern). The results differ only in the order of partial sums. */
+    int32_t reserved[1];
 } mar_tuning;
 
 /* Create a context from host CSR arrays of H and S (M x M, 0-based, columns

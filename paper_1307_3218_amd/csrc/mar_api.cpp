@@ -24,16 +24,26 @@ namespace {
 // One class per kernel variant, so that a class maps to one kernel symbol in a trace.
 enum ProfClass {
     P_INIT = 0, P_SPMM, P_SPMM_DOT, P_PROJ2, P_PROJ1, P_UPD, P_REDUCE, P_NORM, P_APPEND, P_EIG, P_SUM,
-    P_PROJR, P_UPD2, P_COEF, P_MU, P_COUNT
+    P_PROJR, P_UPD2, P_COEF, P_MU, P_SUPPORT, P_COUNT
 };
 const char* kProfNames[P_COUNT] = {"init",   "spmm",     "spmm_dot",  "cgs_proj_KSK", "cgs_proj_1",
                                    "cgs_upd", "reduce",  "norm",      "append",       "eig",
-                                   "sum",     "dcgs_proj", "dcgs_upd", "dcgs_coef", "fermi_search"};
+                                   "sum",     "dcgs_proj", "dcgs_upd", "dcgs_coef", "fermi_search",
+                                   "support"};
 
+// Launches restricted to a block's support record where the block's tile
+// counts were copied (sp_cnt, device) and the step; the collector turns the
+// full-sweep bytes and flops into the restricted ones.
+enum SpKind { SP_NONE = 0, SP_PROJR, SP_UPD2, SP_UPD2_LAST, SP_FRAC };
 struct ProfRec {
     int cls;
     hipEvent_t a, b;
     double bytes, flops;
+    int sp = SP_NONE, sp_n = 0, sp_len = 0;
+    const int32_t* sp_cnt = nullptr;
+    double sp_unit = 0.0;     // bytes of one tile of one vector
+    double sp_elem = 4.0;     // bytes of one element
+    double sp_ntiles = 1.0;
 };
 
 thread_local std::string g_create_err;
@@ -91,6 +101,7 @@ struct mar_ctx {
     bool refused = false;   // a launcher refused to run in the current solve
     std::vector<ProfRec> recs;
     std::vector<hipEvent_t> evfree;
+    std::vector<void*> plogs;     // tile-count logs of profiled support-restricted solves
     mar_prof_entry agg[MAR_PROF_CLASSES];
     std::vector<void*> allocs;
 
@@ -100,6 +111,7 @@ struct mar_ctx {
             hipEventDestroy(r.b);
         }
         for (auto e : evfree) hipEventDestroy(e);
+        for (void* p : plogs) hipFree(p);
         for (void* p : allocs) hipFree(p);
         if (ws) hipFree(ws);
         if (io) hipFree(io);
@@ -258,19 +270,59 @@ hipEvent_t get_event(mar_ctx* c) {
 
 // Runs one launcher; a launcher that refuses (partial-sum buffer too small)
 // marks the solve as failed, and no later kernel of the solve is enqueued.
+// Bytes and flops of a support-restricted launch from its block's tile counts
+// cnt[h] (tiles with distance <= h): every slab and right-hand side read once
+// on the tiles where it can be nonzero, every result written once there.
+void support_figures(ProfRec& r, const std::vector<int32_t>& cnt) {
+    const int n = r.sp_n, hmax = (int)cnt.size() - 1;
+    auto at = [&](int h) { return (double)cnt[(size_t)std::min(std::max(h, 0), hmax)]; };
+    double below = 0.0;   // sum of cnt[k] over k < n
+    for (int k = 0; k < n; ++k) below += at(k);
+    const double el = r.sp_unit / r.sp_elem;   // elements of one tile of one vector
+    switch (r.sp) {
+        case SP_PROJR:       // slabs 0..n and three right-hand sides
+            r.bytes = (below + at(n) + 3.0 * at(n)) * r.sp_unit;
+            r.flops = 6.0 * (below + at(n)) * el;
+            break;
+        case SP_UPD2:        // slabs 0..n-1, u~ and y read; u_n and w' written
+            r.bytes = (below + 2.0 * at(n) + 2.0 * at(n + 1)) * r.sp_unit;
+            r.flops = 4.0 * below * el;
+            break;
+        case SP_UPD2_LAST:   // slabs 0..n-1 and u~ read; u_n written
+            r.bytes = (below + 2.0 * at(n)) * r.sp_unit;
+            r.flops = 2.0 * below * el;
+            break;
+        case SP_FRAC: {      // rows of the tiles within distance n
+            const double f = at(n) / r.sp_ntiles;
+            r.bytes *= f;
+            r.flops *= f;
+            break;
+        }
+        default: break;
+    }
+}
+
+// Returns whether a profile record was added (the last one of c->recs).
 template <class F>
-void launch(mar_ctx* c, hipStream_t s, int cls, F&& f) {
-    if (c->refused || c->dry) return;
+bool launch(mar_ctx* c, hipStream_t s, int cls, F&& f) {
+    if (c->refused || c->dry) return false;
     if (!c->prof) {
         if (f().wgs < 0) c->refused = true;
-        return;
+        return false;
     }
     hipEvent_t a = get_event(c), b = get_event(c);
     hipEventRecord(a, s);
     LaunchInfo li = f();
     hipEventRecord(b, s);
     if (li.wgs < 0) c->refused = true;
-    c->recs.push_back({cls, a, b, li.bytes, li.flops});
+    ProfRec r;
+    r.cls = cls;
+    r.a = a;
+    r.b = b;
+    r.bytes = li.bytes;
+    r.flops = li.flops;
+    c->recs.push_back(r);
+    return true;
 }
 
 // ---------------------------------------------------------------- block size
@@ -543,11 +595,21 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     const int64_t spmm_wgs = std::max((c->S.n * P + mar::WG - 1) / mar::WG, (c->H.n * P + mar::WG - 1) / mar::WG);
     const size_t slab = (size_t)M * B * sizeof(T);
     const int64_t stride = slab_stride(c, M, B, sizeof(T));
+    // H u and S u of the same vector in one pass when H is BSR (S on H's pattern)
+    const bool dual = c->H.bsr && c->SH.nnz == c->H.nnz && B >= VEC;
+    // Support tracking: the kernels of a step skip the row tiles on which the block's vectors are exactly
+    // zero (farther from every seed of the block than the step in hops of H's pattern).
+    const bool sparse = dual && c->tune.support_off == 0;
+    const int kg = variant == 1 || variant == 4 ? 8 : 4;
+    const int64_t nbrow = c->H.n, bpt = mar::WG / std::max(P, 1);
+    const int64_t ntiles = (nbrow + bpt - 1) / bpt;
+    const int64_t grid_max = mar::projr_sp_grid(target, nu, kg);
     size_t part_doubles = (size_t)spmm_wgs * 2 * B;
     for (int nk = 1; nk <= nu; ++nk) {
         const mar::ProjrGeom gm = mar::projr_geometry(nvec, nk, variant, target);
         part_doubles = std::max<size_t>(part_doubles, (size_t)gm.groups * 3 * nk * B);
     }
+    if (sparse) part_doubles = std::max<size_t>(part_doubles, (size_t)grid_max * 3 * kg * B);
     const int64_t part_cap = (int64_t)part_doubles;
 
     size_t off = 0;
@@ -570,9 +632,39 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     const bool own_e = d_e_seed == nullptr, own_n = d_n_seed == nullptr, own_nu = d_nu_eff == nullptr;
     const size_t oE = take(own_e ? (size_t)n_seeds * 8 : 0), oN = take(own_n ? (size_t)n_seeds * 8 : 0);
     const size_t oNuOut = take(own_nu ? (size_t)n_seeds * 4 : 0);
+    const size_t oDist = take(sparse ? (size_t)nbrow * 4 : 0), oTD = take(sparse ? (size_t)ntiles * 4 : 0);
+    const size_t oCnt = take(sparse ? (size_t)(nu + 1) * 4 : 0), oList = take(sparse ? (size_t)ntiles * 4 : 0);
+    const size_t oDl = take(sparse ? (size_t)ntiles * 4 : 0), oPlan = take(sparse ? (size_t)(8 + 4 * grid_max) * 4 : 0);
     mar_status st = ensure_ws(c, off);
     if (st != MAR_OK) return st;
     char* w = c->ws;
+    int32_t* sdist = (int32_t*)(w + oDist);
+    int32_t* TD = sparse ? (int32_t*)(w + oTD) : nullptr;
+    int32_t* scnt = (int32_t*)(w + oCnt);
+    int32_t* slist = (int32_t*)(w + oList);
+    int32_t* sDl = (int32_t*)(w + oDl);
+    int32_t* splan = (int32_t*)(w + oPlan);
+    // profiled solve: each block's tile counts are kept for the restricted byte counts
+    int32_t* plog = nullptr;
+    if (sparse && c->prof && !c->dry) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
+            const int64_t nb = (n_seeds + B - 1) / B;
+            if (nb > 0 && hipMalloc((void**)&plog, (size_t)nb * (nu + 1) * 4) == hipSuccess) c->plogs.push_back(plog);
+            else plog = nullptr;
+        }
+    }
+    auto tag = [&](bool rec, int kind, int n, int64_t blk, double dense_tiles) {
+        if (!rec || !plog) return;
+        ProfRec& r = c->recs.back();
+        r.sp = kind;
+        r.sp_n = n;
+        r.sp_cnt = plog + blk * (nu + 1);
+        r.sp_len = nu + 1;
+        r.sp_unit = 4.0 * mar::WG * 16.0;
+        r.sp_elem = (double)sizeof(T);
+        r.sp_ntiles = dense_tiles;
+    };
     T* K = (T*)(w + oK);
     T* Y = (T*)(w + oY);
     T* SY = (T*)(w + oSY);
@@ -607,6 +699,7 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     for (int64_t blk0 = 0; blk0 < n_seeds; blk0 += B) {
         const int ns = (int)std::min<int64_t>(B, n_seeds - blk0);
         const int32_t* seeds = d_seeds + blk0;
+        const int64_t bi = blk0 / B;
         if (M != c->M && blk0 == 0) {
             // padded rows of Y, S y and S u~ must read as zero (spmm writes rows < M only)
             launch(c, s, P_INIT, [&] { return mar::launch_zero(Y, (int64_t)slab, s); });
@@ -616,9 +709,21 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
         launch(c, s, P_INIT, [&] {
             return mar::launch_init<T>(B, M, c->M, seeds, ns, c->diagS, nu, K, active, nu_blk, UU, s);
         });
-        // H u and S u of the same vector in one pass when H is BSR (S on H's pattern); at steps n >= 1 that
-        // pass also gives the norms of slab n (the unnormalized residual of step n - 1)
-        const bool dual = c->H.bsr && c->SH.nnz == c->H.nnz && B >= VEC;
+        if (sparse) {
+            // Slabs 1.. and y = H u~ start at zero: a tile is written only once the support reaches it, and
+            // y is read on the neighbour rows of the tiles where S y is formed.
+            launch(c, s, P_INIT, [&] {
+                return mar::launch_zero(K + slab_el, (int64_t)((size_t)(nu - 1) * stride * sizeof(T)), s);
+            });
+            launch(c, s, P_INIT, [&] { return mar::launch_zero(Y, (int64_t)slab, s); });
+            launch(c, s, P_SUPPORT, [&] {
+                return mar::launch_support(c->M, nbrow, c->H.ptr, c->H.idx, c->H.nnz, seeds, ns, (int)bpt, nu, sdist,
+                                           TD, scnt, slist, sDl, s);
+            });
+            if (plog && !c->refused)
+                hipMemcpyAsync(plog + bi * (nu + 1), scnt, (size_t)(nu + 1) * 4, hipMemcpyDeviceToDevice, s);
+        }
+        // at steps n >= 1 the dual pass also gives the norms of slab n (the unnormalized residual of step n - 1)
         if (!dual) launch(c, s, P_SPMM, [&] { return mar::launch_spmm<T>(B, c->S, K, ZT, nullptr, 0, 0, s); });
         for (int n = 0; n < nu; ++n) {
             T* Kn = K + (size_t)n * slab_el;
@@ -626,12 +731,13 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
             const bool last = n + 1 == nu;
             int64_t swgs = 0;
             if (dual) {
-                launch(c, s, n == 0 ? P_SPMM : P_SPMM_DOT, [&] {
+                const bool rec = launch(c, s, n == 0 ? P_SPMM : P_SPMM_DOT, [&] {
                     LaunchInfo li = mar::launch_spmm2<T>(B, c->H, c->SH, Kn, Y, ZT, n == 0 ? nullptr : part,
-                                                         n == 0 ? 0 : 2, part_cap, s);
+                                                         n == 0 ? 0 : 2, part_cap, s, TD, n + 1);
                     swgs = li.wgs;
                     return li;
                 });
+                tag(rec, SP_FRAC, n + 1, bi, (double)ntiles);
             } else if (n >= 1) {
                 launch(c, s, P_SPMM_DOT, [&] {
                     LaunchInfo li = mar::launch_spmm<T>(B, c->S, Kn, ZT, part, 2, part_cap, s);
@@ -646,23 +752,40 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
                 });
             }
             if (!dual) launch(c, s, P_SPMM, [&] { return mar::launch_spmm<T>(B, c->H, Kn, Y, nullptr, 0, 0, s); });
-            launch(c, s, P_SPMM, [&] { return mar::launch_spmm<T>(B, c->S, Y, SY, nullptr, 0, 0, s); });
-            int64_t ngroups = 0;
-            launch(c, s, P_PROJR, [&] {
-                return mar::launch_projr<T>(B, K, M, stride, nk, ZT, SY, Y, part, part_cap, &ngroups, target,
-                                            variant, s);
-            });
-            const int64_t L = (int64_t)3 * nk * B;
-            launch(c, s, P_REDUCE, [&] { return mar::launch_reduce(part, ngroups, L, red, nullptr, B, nu, n, s); });
+            if (sparse) {
+                const bool rec = launch(c, s, P_SPMM, [&] {
+                    return mar::launch_spmm<T>(B, c->SH, Y, SY, nullptr, 0, 0, s, TD, n);
+                });
+                tag(rec, SP_FRAC, n, bi, (double)ntiles);
+                const int64_t grid = mar::projr_sp_grid(target, nk, kg);
+                launch(c, s, P_SUPPORT, [&] { return mar::launch_projr_plan(scnt, sDl, n, kg, target, grid, splan, s); });
+                const bool rp = launch(c, s, P_PROJR, [&] {
+                    return mar::launch_projr_sp<T>(B, K, M, stride, n, ZT, SY, Y, slist, scnt, splan, grid, part,
+                                                   part_cap, variant, s);
+                });
+                tag(rp, SP_PROJR, n, bi, (double)ntiles);
+                launch(c, s, P_REDUCE, [&] { return mar::launch_reduce_sp(part, splan, grid, kg, nk, B, red, s); });
+            } else {
+                launch(c, s, P_SPMM, [&] { return mar::launch_spmm<T>(B, c->S, Y, SY, nullptr, 0, 0, s); });
+                int64_t ngroups = 0;
+                launch(c, s, P_PROJR, [&] {
+                    return mar::launch_projr<T>(B, K, M, stride, nk, ZT, SY, Y, part, part_cap, &ngroups, target,
+                                                variant, s);
+                });
+                const int64_t L = (int64_t)3 * nk * B;
+                launch(c, s, P_REDUCE, [&] { return mar::launch_reduce(part, ngroups, L, red, nullptr, B, nu, n, s); });
+            }
             launch(c, s, P_COEF, [&] {
                 return mar::launch_coef(B, nu, n, red, h, G, R, C1, BT, UU, cA, cB, cAf, cBf, gam, Fn, active,
                                         nu_blk, tau, s);
             });
-            launch(c, s, P_UPD2, [&] {
+            const bool ru = launch(c, s, P_UPD2, [&] {
                 // w' goes straight into slab n + 1, unnormalized (its scale is handled by k_coef)
                 return mar::launch_upd2<T>(B, K, M, stride, n, cAT, cBT, gam, Fn, Y,
-                                           last ? nullptr : K + (size_t)(n + 1) * slab_el, !last, c->tune.upd_q, s);
+                                           last ? nullptr : K + (size_t)(n + 1) * slab_el, !last, c->tune.upd_q, s,
+                                           TD);
             });
+            tag(ru, last ? SP_UPD2_LAST : SP_UPD2, n, bi, (double)ntiles);
             if (last) break;
         }
         // rows K[P(j), :] leave the basis, then the subspace eigensolve and assembly
@@ -1409,6 +1532,7 @@ mar_status mar_set_tuning(mar_ctx* c, const mar_tuning* t) {
     if (t->proj_variant < 0 || t->proj_variant > 4) return set_err(c, MAR_ERR_ARG, "proj_variant outside [0, 4]");
     if (t->upd_q != 0 && t->upd_q != 2 && t->upd_q != 4 && t->upd_q != 8)
         return set_err(c, MAR_ERR_ARG, "upd_q must be 0, 2, 4 or 8");
+    if (t->support_off != 0 && t->support_off != 1) return set_err(c, MAR_ERR_ARG, "support_off must be 0 or 1");
     c->tune = *t;
     return MAR_OK;
 }
@@ -1441,6 +1565,8 @@ mar_status mar_profile_reset(mar_ctx* c) {
         c->evfree.push_back(r.b);
     }
     c->recs.clear();
+    for (void* p : c->plogs) hipFree(p);
+    c->plogs.clear();
     for (int k = 0; k < MAR_PROF_CLASSES; ++k) {
         c->agg[k].launches = 0;
         c->agg[k].ms = c->agg[k].bytes = c->agg[k].flops = 0.0;
@@ -1450,10 +1576,20 @@ mar_status mar_profile_reset(mar_ctx* c) {
 
 mar_status mar_profile_collect(mar_ctx* c, mar_prof_entry* out, int32_t* n_out) {
     if (!c) return MAR_ERR_STATE;
+    std::map<const int32_t*, std::vector<int32_t>> counts;   // tile counts of each logged block
     for (auto& r : c->recs) {
         HIP_OR(c, hipEventSynchronize(r.b));
         float ms = 0.f;
         HIP_OR(c, hipEventElapsedTime(&ms, r.a, r.b));
+        if (r.sp != SP_NONE) {
+            auto it = counts.find(r.sp_cnt);
+            if (it == counts.end()) {
+                std::vector<int32_t> h((size_t)r.sp_len);
+                HIP_OR(c, hipMemcpy(h.data(), r.sp_cnt, h.size() * 4, hipMemcpyDeviceToHost));
+                it = counts.emplace(r.sp_cnt, std::move(h)).first;
+            }
+            support_figures(r, it->second);
+        }
         mar_prof_entry& e = c->agg[r.cls];
         e.launches += 1;
         e.ms += ms;
@@ -1463,6 +1599,8 @@ mar_status mar_profile_collect(mar_ctx* c, mar_prof_entry* out, int32_t* n_out) 
         c->evfree.push_back(r.b);
     }
     c->recs.clear();
+    for (void* p : c->plogs) hipFree(p);
+    c->plogs.clear();
     if (out) std::memcpy(out, c->agg, sizeof(mar_prof_entry) * MAR_PROF_CLASSES);
     if (n_out) *n_out = P_COUNT;
     return MAR_OK;

@@ -87,9 +87,11 @@ LaunchInfo launch_init(int B, int64_t Mp, int64_t M, const int32_t* seeds, int n
                        int nu, T* K0, int32_t* active, int32_t* nu_eff, double* uu, hipStream_t s);
 // ndot = 0: Y = A X; 1: also partial sums of X.Y per seed; 2: X.Y and X.X (part[wg][d][b]).
 // part_cap: doubles available at part (checked before launch).
+// tdist (optional, BSR and B >= vector width only): tile distances; tiles with tdist > lim are skipped (their
+// outputs are not written, their partials are zero).
 template <typename T>
 LaunchInfo launch_spmm(int B, const DevMat& A, const T* X, T* Y, double* part, int ndot, int64_t part_cap,
-                       hipStream_t s);
+                       hipStream_t s, const int32_t* tdist = nullptr, int lim = 0);
 template <typename T>
 // stride: elements between consecutive basis slabs (>= M * B).
 LaunchInfo launch_proj(int B, int ns, const T* b0, const T* b1, int64_t M, int64_t stride, int nk, const T* x,
@@ -156,7 +158,7 @@ LaunchInfo launch_fermi_search(int64_t nseeds, int nu, const int32_t* nu_eff, co
 // and B >= the vector width. ndot as in launch_spmm, against Z.
 template <typename T>
 LaunchInfo launch_spmm2(int B, const DevMat& H, const DevMat& SH, const T* X, T* Y, T* Z, double* part, int ndot,
-                        int64_t part_cap, hipStream_t s);
+                        int64_t part_cap, hipStream_t s, const int32_t* tdist = nullptr, int lim = 0);
 // Delayed-reorthogonalization schedule.
 // Projection sweep (variants as in projr_geometry); target_wgs > 0.
 template <typename T>
@@ -169,9 +171,11 @@ int projr_blocks_per_cu(int B, int variant);
 // cA/cB: [n][B] coefficients in the basis precision T.
 template <typename T>
 // upd_q: 16-byte vectors per thread (2, 4 or 8; 0 = 8), reduced for small grids.
+// tdist (optional): tile distances; tiles with tdist > n + 1 are skipped and the slab loop of a tile starts
+// at its distance (slabs below it are zero there).
 LaunchInfo launch_upd2(int B, T* basis, int64_t M, int64_t stride, int n, const T* cA, const T* cB,
                        const double* gam, const double* Fn, const T* y, T* wout, bool want_w, int upd_q,
-                       hipStream_t s);
+                       hipStream_t s, const int32_t* tdist = nullptr);
 // cAf/cBf (optional): the update coefficients rounded to FP32 for an FP32 basis.
 LaunchInfo launch_coef(int B, int nu, int n, const double* red, double* A, double* G, double* R, double* C1,
                        const double* BT, const double* UU, double* cA, double* cB, float* cAf, float* cBf,
@@ -181,6 +185,27 @@ LaunchInfo launch_norm2(int B, int nu, int n, const double* redb, const double* 
 
 LaunchInfo launch_reduce(const double* part, int64_t nchunks, int64_t L, double* out, double* h, int B, int nu,
                          int n, hipStream_t s);
+
+// ---- support tracking of a seed block (exact zeros of the Krylov vectors) ----
+constexpr int32_t SUP_FAR = 0x3fffffff;   // tile distance: farther than the largest hop count kept
+// BFS over H's block pattern from the block rows of the seeds (hmax levels), tile distances D (bpt block rows
+// per tile, ceil(nbrow / bpt) tiles), cnt[h] = tiles with D <= h (h = 0..hmax), and the tiles with D <= hmax
+// sorted by (D, index) into list (Dl: their D).
+LaunchInfo launch_support(int64_t M, int64_t nbrow, const int32_t* brp, const int32_t* bcol, int64_t nnzb,
+                          const int32_t* seeds, int ns, int bpt, int hmax, int32_t* dist, int32_t* D,
+                          int32_t* cnt, int32_t* list, int32_t* Dl, hipStream_t s);
+// Work plan of the support-restricted projection of step n: 8 + 4 * grid ints at plan, grid = G + chunks.
+inline int64_t projr_sp_grid(int64_t G, int nk, int kg) { return G + (nk + kg - 1) / kg; }
+LaunchInfo launch_projr_plan(const int32_t* cnt, const int32_t* Dl, int n, int kg, int64_t G, int64_t grid,
+                             int32_t* plan, hipStream_t s);
+// Fixed-order sum of the per-workgroup partials of that projection into red[3][nk][B].
+LaunchInfo launch_reduce_sp(const double* part, const int32_t* plan, int64_t grid, int kg, int nk, int B,
+                            double* out, hipStream_t s);
+// The projection sweep over the planned tiles (variants as in projr_geometry); partials part[wg][3][kg][B].
+template <typename T>
+LaunchInfo launch_projr_sp(int B, const T* basis, int64_t M, int64_t stride, int n, const T* r0, const T* r1,
+                           const T* r2, const int32_t* list, const int32_t* cnt, const int32_t* plan, int64_t grid,
+                           double* part, int64_t part_cap, int variant, hipStream_t s);
 LaunchInfo launch_norm(int B, int nk, const double* beta2, const double* c1, const double* c2, double tau,
                        int32_t* active, int32_t* nu_eff, double* beta, int n, hipStream_t s);
 LaunchInfo launch_sum(const double* x, int64_t n, double* out, hipStream_t s);

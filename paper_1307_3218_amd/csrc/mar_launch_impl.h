@@ -63,11 +63,17 @@ template <typename T, int B, int NDOT>
 __global__ __launch_bounds__(WG) void k_spmm_bsr4(int64_t nbrow, const int32_t* __restrict__ brp,
                                                   const int32_t* __restrict__ bcol, const T* __restrict__ bval,
                                                   const T* __restrict__ X, T* __restrict__ Y,
-                                                  double* __restrict__ part) {
+                                                  double* __restrict__ part, const int32_t* __restrict__ tdist,
+                                                  int lim) {
     using SM = SeedMap<T, B>;
     constexpr int VEC = SM::VEC, SW = SM::SW, P = SM::P;
     using VT = typename Vec16<T>::type;
     const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
+    if (tdist != nullptr && tdist[bid] > lim) {   // a tile outside the support (B >= VEC: one tile per workgroup)
+        if constexpr (NDOT > 0)
+            for (int i = threadIdx.x; i < NDOT * B; i += WG) part[bid * NDOT * B + i] = 0.0;
+        return;
+    }
     const int64_t g = bid * WG + threadIdx.x;
     const int64_t I = g / P;
     const int grp = threadIdx.x % P;
@@ -215,13 +221,19 @@ template <typename T, int B, int NDOT>
 __global__ __launch_bounds__(WG) void k_spmm2_bsr4(int64_t nbrow, const int32_t* __restrict__ brp,
                                                    const int32_t* __restrict__ bcol, const T* __restrict__ hval,
                                                    const T* __restrict__ sval, const T* __restrict__ X,
-                                                   T* __restrict__ Y, T* __restrict__ Z, double* __restrict__ part) {
+                                                   T* __restrict__ Y, T* __restrict__ Z, double* __restrict__ part,
+                                                   const int32_t* __restrict__ tdist, int lim) {
     using SM = SeedMap<T, B>;
     constexpr int VEC = SM::VEC, SW = SM::SW, P = SM::P;
     static_assert(B >= VEC, "dual product needs one seed group per lane");
     using VT = typename Vec16<T>::type;
     constexpr int CH = 2;   // blocks in flight per row (two value sets per block)
     const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
+    if (tdist != nullptr && tdist[bid] > lim) {   // a tile outside the support
+        if constexpr (NDOT > 0)
+            for (int i = threadIdx.x; i < NDOT * B; i += WG) part[bid * NDOT * B + i] = 0.0;
+        return;
+    }
     const int64_t g = bid * WG + threadIdx.x;
     const int64_t I = g / P;
     const int s0 = (threadIdx.x % P) * VEC;
@@ -615,6 +627,108 @@ __global__ __launch_bounds__(WG) void k_projr(const T* __restrict__ basis, int64
     });
 }
 
+// The projection sweep restricted to the support of the block: the same
+// products as k_projr, taken only over the tiles on which a slab of the
+// workgroup's chunk can be nonzero. Workgroup w takes (group g, chunk ks) from
+// the plan, the list entries [g Tg, min((g + 1) Tg, cnt[min(k0 + KG - 1, n)]))
+// and slabs k0 .. k0 + KG - 1, and writes one partial per (r, slab, seed) to
+// part[((w * NR + r) * KG + kk) * B + b]. A tile is 4 * WG vectors: 4 / Q
+// passes of Q vectors per thread.
+template <typename T, int B, int NR, int Q, int KG, bool NT>
+__global__ __launch_bounds__(WG) void k_projr_sp(const T* __restrict__ basis, int64_t slab, int n,
+                                                 const T* __restrict__ r0, const T* __restrict__ r1,
+                                                 const T* __restrict__ r2, int64_t nvec,
+                                                 const int32_t* __restrict__ list, const int32_t* __restrict__ cnt,
+                                                 const int32_t* __restrict__ plan, int64_t grid,
+                                                 double* __restrict__ part) {
+    using SM = SeedMap<T, B>;
+    constexpr int VEC = SM::VEC, SW = SM::SW, P = SM::P;
+    constexpr int SUB = 4 / Q;
+    static_assert(SUB * Q == 4, "a tile is 4 * WG vectors");
+    using VT = typename Vec16<T>::type;
+    const int tid = threadIdx.x;
+    // The plan uses nact <= gridDim.x workgroups; they are spread evenly over the
+    // XCDs, consecutive numbers (the chunks of one group) on the same XCD.
+    const int64_t nact = plan[2];
+    if ((int64_t)blockIdx.x >= nact) return;
+    const int64_t w = xcd_remap(blockIdx.x, nact);
+    const int32_t* tg = plan + 8 + 2 * grid;
+    const int g = tg[w];
+    if (g < 0) return;
+    const int ks = tg[grid + w];
+    const int Tg = plan[1];
+    const int nk = n + 1;
+    const int k0 = ks * KG;
+    const int nkl = min(KG, nk - k0);
+    const int64_t e0 = (int64_t)g * Tg;
+    const int64_t ce = cnt[min(k0 + KG - 1, n)];
+    const int64_t e1 = e0 + Tg < ce ? e0 + Tg : ce;
+    const int64_t slabv = slab / VEC;
+    const VT* bv = reinterpret_cast<const VT*>(basis) + (int64_t)k0 * slabv;
+    const VT* rv[3] = {reinterpret_cast<const VT*>(r0), reinterpret_cast<const VT*>(r1),
+                       reinterpret_cast<const VT*>(r2)};
+    T raw[NR][KG][VEC];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int kk = 0; kk < KG; ++kk)
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) raw[r][kk][i] = (T)0;
+    int koff[KG];
+#pragma unroll
+    for (int kk = 0; kk < KG; ++kk) koff[kk] = kk < nkl ? kk : nkl - 1;
+    // the next tile's index is fetched one tile ahead, so its loads need not wait for it
+    int64_t t = e0 < e1 ? list[e0] : 0;
+    for (int64_t e = e0; e < e1; ++e) {
+        const int64_t tn = e + 1 < e1 ? list[e + 1] : 0;
+#pragma unroll
+        for (int sub = 0; sub < SUB; ++sub) {
+            const int64_t tbase = t * (int64_t)(4 * WG) + (int64_t)sub * (WG * Q);
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int64_t vi = tbase + (int64_t)q * WG + tid;
+                const bool ok = vi < nvec;
+                const int64_t vs = ok ? vi : 0;
+                T x[NR][VEC];
+#pragma unroll
+                for (int r = 0; r < NR; ++r) {
+                    unpack(rv[r][vs], x[r]);
+#pragma unroll
+                    for (int i = 0; i < VEC; ++i) x[r][i] = ok ? x[r][i] : (T)0;
+                }
+                T a[KG][VEC];
+#pragma unroll
+                for (int kk = 0; kk < KG; ++kk) {
+                    if constexpr (NT) unpack_nt(bv + (int64_t)koff[kk] * slabv + vs, a[kk]);
+                    else unpack(bv[(int64_t)koff[kk] * slabv + vs], a[kk]);
+                }
+#pragma unroll
+                for (int kk = 0; kk < KG; ++kk)
+#pragma unroll
+                    for (int r = 0; r < NR; ++r)
+#pragma unroll
+                        for (int i = 0; i < VEC; ++i) raw[r][kk][i] = fma(a[kk][i], x[r][i], raw[r][kk][i]);
+            }
+        }
+        t = tn;
+    }
+    T acc[NR * KG][SW];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int kk = 0; kk < KG; ++kk) {
+#pragma unroll
+            for (int i = 0; i < SW; ++i) acc[r * KG + kk][i] = (T)0;
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) acc[r * KG + kk][i % SW] += raw[r][kk][i];
+        }
+    __shared__ T red_lds[SeedReduce<P, SW, NR * KG>::LDS];
+    wg_seed_reduce<P, SW, NR * KG>(acc, red_lds, [&](int v, int b, T sum) {
+        const int r = v / KG, kk = v % KG;
+        if (kk < nkl) part[((w * NR + r) * KG + kk) * B + b] = (double)sum;
+    });
+}
+
 // Projection of every basis vector of a block onto one fixed vector v (rows,
 // FP64): part[(g * nk + k) * B + b] = sum over the rows of chunk g of
 // K[k][i][b] v[i]. Grid (groups, nk).
@@ -658,11 +772,25 @@ template <typename T, int B, int Q, bool WANT_W>
 __global__ __launch_bounds__(WG) void k_upd2(T* __restrict__ basis, int64_t slab, int n, const T* __restrict__ cA,
                                              const T* __restrict__ cB, const double* __restrict__ gam,
                                              const double* __restrict__ Fn, const T* __restrict__ y,
-                                             T* __restrict__ wout, int64_t nvec) {
+                                             T* __restrict__ wout, int64_t nvec, const int32_t* __restrict__ tdist,
+                                             int64_t ntiles) {
     using SM = SeedMap<T, B>;
     constexpr int VEC = SM::VEC, P = SM::P;
     using VT = typename Vec16<T>::type;
     const int tid = threadIdx.x;
+    // Support: the workgroup's vectors lie in at most two tiles of 4 * WG
+    // vectors (Q <= 8). Nothing to do beyond distance n + 1; slabs below the
+    // smaller distance are zero on these rows.
+    int kst = 0;
+    if (tdist != nullptr) {
+        const int64_t v0 = (int64_t)blockIdx.x * (WG * Q);
+        const int64_t t0 = v0 / (4 * WG);
+        int64_t t1 = (v0 + WG * Q - 1) / (4 * WG);
+        t1 = t1 < ntiles ? t1 : ntiles - 1;
+        const int dm = min(tdist[t0], tdist[t1]);
+        if (dm > n + 1) return;
+        kst = min(dm, n);
+    }
     const int64_t slabv = slab / VEC;
     const int sb = (B < VEC) ? 0 : (tid % P) * VEC;
     VT* bv = reinterpret_cast<VT*>(basis);
@@ -685,7 +813,7 @@ __global__ __launch_bounds__(WG) void k_upd2(T* __restrict__ basis, int64_t slab
         unpack(bv[(int64_t)n * slabv + vsq[q]], au[q]);
         if constexpr (WANT_W) unpack(yv[vsq[q]], aw[q]);
     }
-    for (int k = 0; k < n; ++k) {
+    for (int k = kst; k < n; ++k) {
         T ca[VEC], cb[VEC];
         if constexpr (B >= VEC) {
             unpack(reinterpret_cast<const VT*>(cA + (int64_t)k * B + sb)[0], ca);
@@ -754,11 +882,11 @@ LaunchInfo launch_init<MAR_T>(int B, int64_t Mp, int64_t M, const int32_t* seeds
 
 template <>
 LaunchInfo launch_spmm<MAR_T>(int B, const DevMat& A, const MAR_T* X, MAR_T* Y, double* part, int ndot,
-                              int64_t part_cap, hipStream_t s) {
+                              int64_t part_cap, hipStream_t s, const int32_t* tdist, int lim) {
     constexpr int VEC = Vec16<MAR_T>::n;
     const int P = B < VEC ? 1 : B / VEC;
     const int64_t wgs = (A.n * P + WG - 1) / WG;
-    if (ndot > 0 && wgs * ndot * B > part_cap) {
+    if ((ndot > 0 && wgs * ndot * B > part_cap) || (tdist != nullptr && (!A.bsr || B < VEC))) {
         LaunchInfo bad;
         bad.wgs = -1;
         return bad;
@@ -766,10 +894,13 @@ LaunchInfo launch_spmm<MAR_T>(int B, const DevMat& A, const MAR_T* X, MAR_T* Y, 
     const MAR_T* val = std::is_same<MAR_T, float>::value ? (const MAR_T*)A.v32 : (const MAR_T*)A.v64;
 #define MAR_SPMM_LAUNCH(KERNEL, ND) \
     MAR_DISPATCH_B(B, hipLaunchKernelGGL((KERNEL<MAR_T, BB, ND>), dim3(wgs), dim3(WG), 0, s, A.n, A.ptr, A.idx, val, X, Y, part))
+#define MAR_SPMM_BSR(ND) \
+    MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_spmm_bsr4<MAR_T, BB, ND>), dim3(wgs), dim3(WG), 0, s, A.n, A.ptr, A.idx, val, X, Y, part, tdist, lim))
     if (A.bsr) {
-        if (ndot == 2) { MAR_SPMM_LAUNCH(k_spmm_bsr4, 2); }
-        else if (ndot == 1) { MAR_SPMM_LAUNCH(k_spmm_bsr4, 1); }
-        else { MAR_SPMM_LAUNCH(k_spmm_bsr4, 0); }
+        if (ndot == 2) { MAR_SPMM_BSR(2); }
+        else if (ndot == 1) { MAR_SPMM_BSR(1); }
+        else { MAR_SPMM_BSR(0); }
+#undef MAR_SPMM_BSR
     } else {
         if (ndot == 2) { MAR_SPMM_LAUNCH(k_spmm_csr, 2); }
         else if (ndot == 1) { MAR_SPMM_LAUNCH(k_spmm_csr, 1); }
@@ -786,7 +917,8 @@ LaunchInfo launch_spmm<MAR_T>(int B, const DevMat& A, const MAR_T* X, MAR_T* Y, 
 
 template <>
 LaunchInfo launch_spmm2<MAR_T>(int B, const DevMat& H, const DevMat& SH, const MAR_T* X, MAR_T* Y, MAR_T* Z,
-                               double* part, int ndot, int64_t part_cap, hipStream_t s) {
+                               double* part, int ndot, int64_t part_cap, hipStream_t s, const int32_t* tdist,
+                               int lim) {
     constexpr int VEC = Vec16<MAR_T>::n;
     LaunchInfo li;
     if (!H.bsr || B < VEC || SH.nnz != H.nnz) {
@@ -803,7 +935,7 @@ LaunchInfo launch_spmm2<MAR_T>(int B, const DevMat& H, const DevMat& SH, const M
     const MAR_T* hv = f32 ? (const MAR_T*)H.v32 : (const MAR_T*)H.v64;
     const MAR_T* sv = f32 ? (const MAR_T*)SH.v32 : (const MAR_T*)SH.v64;
 #define MAR_SPMM2(ND) \
-    MAR_DISPATCH_B(B, if constexpr (BB >= VEC) hipLaunchKernelGGL((k_spmm2_bsr4<MAR_T, BB, ND>), dim3(wgs), dim3(WG), 0, s, H.n, H.ptr, H.idx, hv, sv, X, Y, Z, part))
+    MAR_DISPATCH_B(B, if constexpr (BB >= VEC) hipLaunchKernelGGL((k_spmm2_bsr4<MAR_T, BB, ND>), dim3(wgs), dim3(WG), 0, s, H.n, H.ptr, H.idx, hv, sv, X, Y, Z, part, tdist, lim))
     if (ndot == 2) { MAR_SPMM2(2); }
     else if (ndot == 1) { MAR_SPMM2(1); }
     else { MAR_SPMM2(0); }
@@ -935,6 +1067,39 @@ int projr_blocks_per_cu<MAR_T>(int B, int variant) {
 }
 
 template <>
+LaunchInfo launch_projr_sp<MAR_T>(int B, const MAR_T* basis, int64_t M, int64_t stride, int n, const MAR_T* r0,
+                                  const MAR_T* r1, const MAR_T* r2, const int32_t* list, const int32_t* cnt,
+                                  const int32_t* plan, int64_t grid, double* part, int64_t part_cap, int variant,
+                                  hipStream_t s) {
+    constexpr int VEC = Vec16<MAR_T>::n;
+    constexpr int NR = 3;
+    const int64_t nvec = M * B / VEC;
+    const int kg = variant == 1 || variant == 4 ? 8 : 4;
+    const int64_t nks = (n + 1 + kg - 1) / kg;
+    // one round of the device: the plan uses at most max(G, chunks) workgroups (grid = G + chunks)
+    const int64_t wgs = std::max(grid - nks, nks);
+    if (B < VEC || grid * NR * kg * B > part_cap) {
+        LaunchInfo bad;
+        bad.wgs = -1;
+        return bad;
+    }
+#define MAR_PROJR_SP(QV, KGV, NTV) \
+    MAR_DISPATCH_B(B, if constexpr (BB >= VEC) hipLaunchKernelGGL((k_projr_sp<MAR_T, BB, NR, QV, KGV, NTV>), dim3((unsigned)wgs), dim3(WG), 0, s, basis, stride, n, r0, r1, r2, nvec, list, cnt, plan, grid, part))
+    if (variant == 1) { MAR_PROJR_SP(PROJR_Q, 8, false); }
+    else if (variant == 2) { MAR_PROJR_SP(PROJR_Q, 4, true); }
+    else if (variant == 3) { MAR_PROJR_SP(2, 4, false); }
+    else if (variant == 4) { MAR_PROJR_SP(2, 8, false); }
+    else { MAR_PROJR_SP(PROJR_Q, 4, false); }
+#undef MAR_PROJR_SP
+    LaunchInfo li;
+    li.wgs = wgs;
+    // full-sweep figures; the profiler replaces them by the support-restricted ones
+    li.bytes = ((double)(n + 1) + NR) * (double)(M * B) * sizeof(MAR_T);
+    li.flops = 2.0 * NR * (n + 1) * (double)(M * B);
+    return li;
+}
+
+template <>
 LaunchInfo launch_es_pdot<MAR_T>(int B, const MAR_T* K, int64_t stride, int64_t M, int64_t Mp, int nu,
                                  const double* vref, double* part, int groups, hipStream_t s) {
     constexpr int VEC = Vec16<MAR_T>::n;
@@ -951,15 +1116,16 @@ LaunchInfo launch_es_pdot<MAR_T>(int B, const MAR_T* K, int64_t stride, int64_t 
 template <>
 LaunchInfo launch_upd2<MAR_T>(int B, MAR_T* basis, int64_t M, int64_t stride, int n, const MAR_T* cA,
                               const MAR_T* cB, const double* gam, const double* Fn, const MAR_T* y, MAR_T* wout,
-                              bool want_w, int upd_q, hipStream_t s) {
+                              bool want_w, int upd_q, hipStream_t s, const int32_t* tdist) {
     constexpr int VEC = Vec16<MAR_T>::n;
     const int64_t nvec = M * B / VEC;
+    const int64_t ntiles = (nvec + 4 * WG - 1) / (4 * WG);
     // vectors per thread: the requested depth when the grid still has >= 1024 workgroups
     int Q = upd_q == 2 || upd_q == 4 || upd_q == 8 ? upd_q : 8;
     while (Q > 1 && nvec < (int64_t)WG * Q * 1024) Q /= 2;
     const int64_t wgs = (nvec + WG * Q - 1) / (WG * Q);
 #define MAR_UPD2(QQ, WW) \
-    MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_upd2<MAR_T, BB, QQ, WW>), dim3(wgs), dim3(WG), 0, s, basis, stride, n, cA, cB, gam, Fn, y, wout, nvec))
+    MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_upd2<MAR_T, BB, QQ, WW>), dim3(wgs), dim3(WG), 0, s, basis, stride, n, cA, cB, gam, Fn, y, wout, nvec, tdist, ntiles))
 #define MAR_UPD2W(QQ) \
     if (want_w) { MAR_UPD2(QQ, true); } else { MAR_UPD2(QQ, false); }
     if (Q == 8) { MAR_UPD2W(8) }
