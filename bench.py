@@ -6,6 +6,9 @@ atom, seeded synthetic H and S), nu = 100, kT = 0.1 eV, mu at half filling.
 A step is one pass of the whole hot path (Krylov subspace + CGS2 + subspace
 eigensolve + Fermi-weighted assembly + band-energy sum) over one batch of
 seeds, in the batched FP32 form, with seeds, outputs and H/S resident in HBM.
+Seeds go in their natural order (a block holds orbitals of neighbouring atoms,
+whose early Krylov vectors are zero on most rows); --seed-order random or
+sampled changes that, --no-support streams every row of every slab.
 Reported: seed-subspaces/s of that form; beside it the plain FP64 form on the
 same GPU (one seed at a time), the per-kernel roofline from HIP events on the
 solve stream, and the FP64 CPU oracle on a bounded seed sample.
@@ -18,7 +21,8 @@ Other workloads (not the headline line):
                          FP32 batched through mar_solve_many (one graph launch
                          per call, autotuned block sizes), beside the same work
                          issued eagerly system after system.
-    --workload mixed_32x32x32 --nu 300   the M = 1048576 lattice (seed blocks of 64).
+    --workload mixed_32x32x32 --nu 300 --seed-order sampled   the M = 1048576
+                         lattice (seed blocks of 64) over its 16384 sampled seeds.
     --workload eigenstate  the k-th eigen state (Sec. 3, Eq. 3) of the 4096-atom
                          diamond cell (M = 16384, nu = 30, every seed, FP32
                          batched): two passes over all seeds plus the reference.
@@ -55,7 +59,7 @@ def measured_traffic(kernel: str, workload: str):
     import glob
     import hashlib
     src = b"".join(open(os.path.join(ROOT, "paper_1307_3218_amd", "csrc", f), "rb").read()
-                   for f in ("mar_launch_impl.h", "mar_device.h"))
+                   for f in ("mar_launch_impl.h", "mar_device.h", "mar_support.hip"))
     sha = hashlib.sha256(src).hexdigest()[:16]
     for path in glob.glob(os.path.join(ROOT, "profiles", "hbm_traffic_*.md")):
         text = open(path).read()
@@ -101,7 +105,8 @@ def run_uneven(args) -> int:
     log(f"8 systems built ({time.perf_counter() - t:.1f} s): M = {[s.M for s, _ in systems]}")
     tuned = []
     for (s, nu), c in zip(systems, ctxs):
-        order = torch.from_numpy(np.random.default_rng(0).permutation(s.M).astype(np.int32)).to(dev)
+        perm = np.arange(s.M) if args.seed_order != "random" else np.random.default_rng(0).permutation(s.M)
+        order = torch.from_numpy(perm.astype(np.int32)).to(dev)
         seeds_all.append(order)
         tuned.append(c.autotune(order[: min(256, s.M)], nu, mu, KT, "fp32"))
         n = s.M // calls
@@ -224,8 +229,9 @@ def main() -> int:
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--seed-block", type=int, default=0)
-    ap.add_argument("--seed-order", choices=["natural", "random"], default="natural",
-                    help="natural: consecutive seeds (neighbouring atoms) share a block; random: a permutation")
+    ap.add_argument("--seed-order", choices=["natural", "random", "sampled"], default="natural",
+                    help="natural: consecutive seeds (neighbouring atoms) share a block; random: a permutation of "
+                         "all seeds; sampled: a sorted uniform sample of min(M, 16384) seeds")
     ap.add_argument("--no-support", action="store_true", help="stream every row of every slab")
     ap.add_argument("--uneven-calls", type=int, default=8,
                     help="uneven8: mar_solve_many calls per pass over all seeds (each takes M/calls seeds per system)")
@@ -269,13 +275,15 @@ def main() -> int:
     stream = torch.cuda.current_stream().cuda_stream
     if args.seed_order == "natural":
         order = np.arange(M, dtype=np.int32)
+    elif args.seed_order == "sampled":
+        order = lattice.sample_seeds(M, min(M, 16384), seed=0).astype(np.int32)
     else:
         order = np.random.default_rng(0).permutation(M).astype(np.int32)
     n_steps = args.warmup + args.steps
     d_order = torch.from_numpy(order).to(dev)
 
     def seeds_for(k):
-        lo = (k * S_step) % M
+        lo = (k * S_step) % len(order)
         return d_order[lo: lo + S_step]
 
     d_rho = torch.zeros(system.H.nnz, dtype=torch.float64, device=dev)
@@ -349,7 +357,7 @@ def main() -> int:
         e = prof[dom]
         ach = e["bytes"] / (e["ms"] * 1e-3) / 1e9
         kind, cells = system.name.split("_", 1)          # e.g. mixed, 16x16x16
-        wl = f"{kind}{cells.split('x')[0]}_nu{nu}_fp32_b{B}"
+        wl = f"{kind}{cells.split('x')[0]}_nu{nu}_fp32_b{B}_{args.seed_order}" + ("_full" if args.no_support else "")
         traffic = measured_traffic(dom, wl) if S_step % B == 0 else None
         roofline = dict(kernel=dom, bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
                         frac=round(ach / HBM_PEAK_GBPS, 4), traffic=traffic,

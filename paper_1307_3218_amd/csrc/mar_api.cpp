@@ -610,6 +610,8 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
         part_doubles = std::max<size_t>(part_doubles, (size_t)gm.groups * 3 * nk * B);
     }
     if (sparse) part_doubles = std::max<size_t>(part_doubles, (size_t)grid_max * 3 * kg * B);
+    // update depth: one tile of 4 * WG vectors per workgroup when tiles are skipped, else 8 vectors per thread
+    const int upd_q = c->tune.upd_q > 0 ? c->tune.upd_q : (sparse ? 4 : 8);
     const int64_t part_cap = (int64_t)part_doubles;
 
     size_t off = 0;
@@ -782,7 +784,7 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
             const bool ru = launch(c, s, P_UPD2, [&] {
                 // w' goes straight into slab n + 1, unnormalized (its scale is handled by k_coef)
                 return mar::launch_upd2<T>(B, K, M, stride, n, cAT, cBT, gam, Fn, Y,
-                                           last ? nullptr : K + (size_t)(n + 1) * slab_el, !last, c->tune.upd_q, s,
+                                           last ? nullptr : K + (size_t)(n + 1) * slab_el, !last, upd_q, s,
                                            TD);
             });
             tag(ru, last ? SP_UPD2_LAST : SP_UPD2, n, bi, (double)ntiles);

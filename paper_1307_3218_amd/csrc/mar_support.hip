@@ -153,26 +153,39 @@ __global__ __launch_bounds__(WG) void k_projr_plan(const int32_t* __restrict__ c
     __shared__ int sTg, sNg;
     __shared__ int64_t carry;
     __shared__ int scan[WG];
-    if (tid == 0) {
-        // workgroups used for Tg tiles per group: sum over chunks of ceil(cnt_ks / Tg); the smallest Tg
-        // (binary search; the count does not grow with Tg) that keeps them within G, so the sweep runs
-        // in one round of the device
+    constexpr int MAXK = 1024;
+    __shared__ int ck[MAXK];   // tiles read by each chunk
+    for (int ks = tid; ks < nks && ks < MAXK; ks += WG) ck[ks] = cnt[min(ks * kg + kg - 1, n)];
+    __syncthreads();
+    if (tid < 64) {
+        // One wavefront: workgroups used for Tg tiles per group are the sum over chunks of
+        // ceil(cnt_ks / Tg); take the smallest Tg (binary search; the count does not grow with Tg) that
+        // keeps them within G, so that the sweep runs in one round of the device.
+        auto chunk = [&](int ks) -> int64_t { return ks < MAXK ? ck[ks] : cnt[min(ks * kg + kg - 1, n)]; };
+        auto wsum = [&](int64_t v) {
+            for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+            return v;
+        };
         auto used = [&](int64_t t) {
             int64_t u = 0;
-            for (int ks = 0; ks < nks; ++ks) u += (cnt[min(ks * kg + kg - 1, n)] + t - 1) / t;
-            return u;
+            for (int ks = tid; ks < nks; ks += 64) u += (chunk(ks) + t - 1) / t;
+            return wsum(u);
         };
         int64_t W = 0;
-        for (int ks = 0; ks < nks; ++ks) W += cnt[min(ks * kg + kg - 1, n)];
-        int64_t lo = W > G ? (W + G - 1) / G : 1, hi = cnt[n] > lo ? cnt[n] : lo;
+        for (int ks = tid; ks < nks; ks += 64) W += chunk(ks);
+        W = wsum(W);
+        const int64_t cn = cnt[n];
+        int64_t lo = W > G ? (W + G - 1) / G : 1, hi = cn > lo ? cn : lo;
         while (lo < hi) {
             const int64_t mid = lo + (hi - lo) / 2;
             if (used(mid) <= G) hi = mid;
             else lo = mid + 1;
         }
-        sTg = (int)lo;
-        sNg = (int)((cnt[n] + lo - 1) / lo);
-        carry = 0;
+        if (tid == 0) {
+            sTg = (int)lo;
+            sNg = (int)((cn + lo - 1) / lo);
+            carry = 0;
+        }
     }
     for (int64_t w = tid; w < grid; w += WG) tg[w] = -1;
     __syncthreads();
