@@ -246,6 +246,23 @@ mar_status mar_autotune(mar_ctx* ctx, int32_t nu, mar_precision prec, const int3
                         double mu, double kT, void* hip_stream, int32_t* best_block, int32_t* best_variant,
                         double* best_rate);
 
+/* Local regions: the order-N form of the method (Sec. 1 gives its cost as
+ * proportional to the number of atoms, so the work of one seed may not grow
+ * with the system; how the subspace is kept local is left to the cited mArnoldi
+ * paper). hops >= 0: later solves of ctx generate the Krylov subspace of seed j
+ * inside its local region R_j, the rows whose 4-row block lies within `hops`
+ * hops of j's block in the graph of H's 4x4 block pattern (0 = j's block
+ * alone): the method runs on the principal submatrices H[R_j, R_j] and
+ * S[R_j, R_j], and rho_ij for i in P(j) outside R_j is 0. The regions are per
+ * seed, so results do not depend on the seed order or the block size (up to
+ * the order of partial sums). hops < 0 (the default) restores the full system.
+ * Needs H with 4x4 block structure (MAR_ERR_ARG here otherwise); solves then
+ * need the batched delayed form with blocks of at least 4 (FP32) / 2 (FP64)
+ * seeds, and the eigen-state entry points refuse a local region (MAR_ERR_ARG). */
+mar_status mar_set_local_region(mar_ctx* ctx, int32_t hops);
+/* Current local-region hops of ctx (-1: the full system, or ctx NULL). */
+int32_t mar_local_region(const mar_ctx* ctx);
+
 /* Set the tuning used by later solves (NULL restores the defaults). */
 mar_status mar_set_tuning(mar_ctx* ctx, const mar_tuning* t);
 mar_status mar_get_tuning(const mar_ctx* ctx, mar_tuning* t);

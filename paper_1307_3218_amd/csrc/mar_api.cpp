@@ -91,6 +91,7 @@ struct mar_ctx {
     size_t fws_bytes = 0;
 
     mar_tuning tune{};
+    int32_t loc = -1;             // local-region hops of later solves (< 0: the full system)
     char* ws = nullptr;
     size_t ws_bytes = 0;
     char* io = nullptr;
@@ -602,6 +603,10 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     const bool sparse = dual && c->tune.support_off == 0;
     const int kg = variant == 1 || variant == 4 ? 8 : 4;
     const int64_t nbrow = c->H.n, bpt = mar::WG / std::max(P, 1);
+    // local regions (order-N form): per block row and seed, inside the seed's region or not
+    const bool local = c->loc >= 0 && dual;
+    const int mW = (B + 31) / 32;
+    const int hreach = local ? std::min(nu, (int)c->loc) : nu;   // farthest hop a vector can reach
     const int64_t ntiles = (nbrow + bpt - 1) / bpt;
     const int64_t grid_max = mar::projr_sp_grid(target, nu, kg);
     size_t part_doubles = (size_t)spmm_wgs * 2 * B;
@@ -637,6 +642,7 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     const size_t oDist = take(sparse ? (size_t)nbrow * 4 : 0), oTD = take(sparse ? (size_t)ntiles * 4 : 0);
     const size_t oCnt = take(sparse ? (size_t)(nu + 1) * 4 : 0), oList = take(sparse ? (size_t)ntiles * 4 : 0);
     const size_t oDl = take(sparse ? (size_t)ntiles * 4 : 0), oPlan = take(sparse ? (size_t)(8 + 4 * grid_max) * 4 : 0);
+    const size_t oM0 = take(local ? (size_t)nbrow * mW * 4 : 0), oM1 = take(local ? (size_t)nbrow * mW * 4 : 0);
     mar_status st = ensure_ws(c, off);
     if (st != MAR_OK) return st;
     char* w = c->ws;
@@ -646,6 +652,9 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     int32_t* slist = (int32_t*)(w + oList);
     int32_t* sDl = (int32_t*)(w + oDl);
     int32_t* splan = (int32_t*)(w + oPlan);
+    uint32_t* lm0 = (uint32_t*)(w + oM0);
+    uint32_t* lm1 = (uint32_t*)(w + oM1);
+    const uint32_t* lmask = nullptr;
     // profiled solve: each block's tile counts are kept for the restricted byte counts
     int32_t* plog = nullptr;
     if (sparse && c->prof && !c->dry) {
@@ -711,6 +720,16 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
         launch(c, s, P_INIT, [&] {
             return mar::launch_init<T>(B, M, c->M, seeds, ns, c->diagS, nu, K, active, nu_blk, UU, s);
         });
+        if (local) {
+            lmask = c->loc % 2 == 0 ? lm0 : lm1;   // where the last of loc hops leaves the masks
+            launch(c, s, P_SUPPORT, [&] {
+                mar::launch_local_masks(c->M, nbrow, c->H.ptr, c->H.idx, seeds, ns, mW, c->loc, lm0, lm1, s);
+                LaunchInfo li;
+                li.wgs = 1;
+                li.bytes = (double)(c->loc + 1) * (double)(nbrow + c->H.nnz) * mW * 4.0;
+                return li;
+            });
+        }
         if (sparse) {
             // Slabs 1.. and y = H u~ start at zero: a tile is written only once the support reaches it, and
             // y is read on the neighbour rows of the tiles where S y is formed.
@@ -719,8 +738,8 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
             });
             launch(c, s, P_INIT, [&] { return mar::launch_zero(Y, (int64_t)slab, s); });
             launch(c, s, P_SUPPORT, [&] {
-                return mar::launch_support(c->M, nbrow, c->H.ptr, c->H.idx, c->H.nnz, seeds, ns, (int)bpt, nu, sdist,
-                                           TD, scnt, slist, sDl, s);
+                return mar::launch_support(c->M, nbrow, c->H.ptr, c->H.idx, c->H.nnz, seeds, ns, (int)bpt, hreach, nu,
+                                           sdist, TD, scnt, slist, sDl, s);
             });
             if (plog && !c->refused)
                 hipMemcpyAsync(plog + bi * (nu + 1), scnt, (size_t)(nu + 1) * 4, hipMemcpyDeviceToDevice, s);
@@ -735,7 +754,7 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
             if (dual) {
                 const bool rec = launch(c, s, n == 0 ? P_SPMM : P_SPMM_DOT, [&] {
                     LaunchInfo li = mar::launch_spmm2<T>(B, c->H, c->SH, Kn, Y, ZT, n == 0 ? nullptr : part,
-                                                         n == 0 ? 0 : 2, part_cap, s, TD, n + 1);
+                                                         n == 0 ? 0 : 2, part_cap, s, TD, n + 1, lmask, mW);
                     swgs = li.wgs;
                     return li;
                 });
@@ -756,7 +775,7 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
             if (!dual) launch(c, s, P_SPMM, [&] { return mar::launch_spmm<T>(B, c->H, Kn, Y, nullptr, 0, 0, s); });
             if (sparse) {
                 const bool rec = launch(c, s, P_SPMM, [&] {
-                    return mar::launch_spmm<T>(B, c->SH, Y, SY, nullptr, 0, 0, s, TD, n);
+                    return mar::launch_spmm<T>(B, c->SH, Y, SY, nullptr, 0, 0, s, TD, n, lmask, mW);
                 });
                 tag(rec, SP_FRAC, n, bi, (double)ntiles);
                 const int64_t grid = mar::projr_sp_grid(target, nk, kg);
@@ -768,7 +787,10 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
                 tag(rp, SP_PROJR, n, bi, (double)ntiles);
                 launch(c, s, P_REDUCE, [&] { return mar::launch_reduce_sp(part, splan, grid, kg, nk, B, red, s); });
             } else {
-                launch(c, s, P_SPMM, [&] { return mar::launch_spmm<T>(B, c->S, Y, SY, nullptr, 0, 0, s); });
+                launch(c, s, P_SPMM, [&] {
+                    return local ? mar::launch_spmm<T>(B, c->SH, Y, SY, nullptr, 0, 0, s, nullptr, 0, lmask, mW)
+                                 : mar::launch_spmm<T>(B, c->S, Y, SY, nullptr, 0, 0, s);
+                });
                 int64_t ngroups = 0;
                 launch(c, s, P_PROJR, [&] {
                     return mar::launch_projr<T>(B, K, M, stride, nk, ZT, SY, Y, part, part_cap, &ngroups, target,
@@ -833,6 +855,13 @@ mar_status check_request(mar_ctx* c, const mar_request& r) {
 // Enqueue one solve (validated) on stream s with a resolved plan.
 mar_status dispatch_solve(mar_ctx* c, const mar_request& r, const Plan& pl, hipStream_t s) {
     c->refused = false;
+    if (c->loc >= 0) {
+        const int vec = r.prec == MAR_FP32 ? 4 : 2;
+        if (!c->H.bsr || c->SH.nnz != c->H.nnz || !pl.delayed || pl.B < vec)
+            return set_err(c, MAR_ERR_ARG,
+                           fmt("a local region needs a 4x4-block H and the batched delayed form with blocks of at "
+                               "least %d seeds (block %d)", vec, pl.B));
+    }
     mar_status st;
     if (r.prec == MAR_FP32)
         st = pl.delayed ? run_solve_delayed<float>(c, r.d_seeds, r.n_seeds, r.nu, r.mu, r.kT, pl.B, pl.variant,
@@ -914,6 +943,7 @@ void put_request(std::vector<char>& k, mar_ctx* c, const mar_request& r, const P
     put(k, (int32_t)pl.delayed);
     put(k, pl.variant);
     put(k, c->tune);
+    put(k, c->loc);
     put(k, c->ws);
 }
 
@@ -1131,7 +1161,12 @@ mar_status mar_autotune(mar_ctx* c, int32_t nu, mar_precision prec, const int32_
     }
     int bestB = 0, bestV = 0;
     double bestR = -1.0;
-    for (int B = std::min(cap, 16); B <= cap && st == MAR_OK; B *= 2) {
+    int B0 = std::min(cap, 16), cap_t = cap;
+    if (c->loc >= 0) {   // local regions need blocks of at least one 16-byte vector of seeds
+        B0 = std::max(B0, prec == MAR_FP32 ? 4 : 2);
+        cap_t = std::max(cap_t, B0);
+    }
+    for (int B = B0; B <= cap_t && st == MAR_OK; B *= 2) {
         for (int v : {0, 3}) {
             if (!delayed && v != 0) continue;
             Plan pl{B, delayed, v};
@@ -1258,6 +1293,7 @@ mar_status mar_eigen_state_async(mar_ctx* c, const int32_t* d_seeds, int64_t n_s
     if (!(sigma >= 0.0) || !std::isfinite(sigma)) return set_err(c, MAR_ERR_ARG, "sigma must be finite and >= 0");
     if (!d_phi || !d_levels) return set_err(c, MAR_ERR_ARG, "phi or levels output is NULL");
     if ((size_t)nu > (size_t)mar::MAX_NU_ASSEMBLE) return set_err(c, MAR_ERR_ARG, "nu too large for the eigen states");
+    if (c->loc >= 0) return set_err(c, MAR_ERR_ARG, "eigen states are not available with a local region");
     HIP_OR(c, hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)hip_stream;
     const Plan pl = plan_solve(c, nu, prec, form, n_seeds);
@@ -1518,6 +1554,16 @@ mar_status mar_solve(mar_ctx* c, const int32_t* seeds, int64_t n_seeds, int32_t 
             return set_err(c, MAR_ERR_NOT_SPD, fmt("w^T S w < 0 for seed %d: S is not positive definite", seeds[i]));
     return MAR_OK;
 }
+
+mar_status mar_set_local_region(mar_ctx* c, int32_t hops) {
+    if (!c) return MAR_ERR_STATE;
+    if (hops >= 0 && (!c->H.bsr || c->SH.nnz != c->H.nnz))
+        return set_err(c, MAR_ERR_ARG, "a local region needs H with 4x4 block structure");
+    c->loc = hops < 0 ? -1 : hops;
+    return MAR_OK;
+}
+
+int32_t mar_local_region(const mar_ctx* c) { return c ? c->loc : -1; }
 
 mar_status mar_set_tuning(mar_ctx* c, const mar_tuning* t) {
     if (!c) return MAR_ERR_STATE;

@@ -89,9 +89,12 @@ LaunchInfo launch_init(int B, int64_t Mp, int64_t M, const int32_t* seeds, int n
 // part_cap: doubles available at part (checked before launch).
 // tdist (optional, BSR and B >= vector width only): tile distances; tiles with tdist > lim are skipped (their
 // outputs are not written, their partials are zero).
+// mask (optional, BSR and B >= vector width only): local-region bits per block row (W words); the product
+// is kept only on the rows inside each seed's region.
 template <typename T>
 LaunchInfo launch_spmm(int B, const DevMat& A, const T* X, T* Y, double* part, int ndot, int64_t part_cap,
-                       hipStream_t s, const int32_t* tdist = nullptr, int lim = 0);
+                       hipStream_t s, const int32_t* tdist = nullptr, int lim = 0, const uint32_t* mask = nullptr,
+                       int W = 0);
 template <typename T>
 // stride: elements between consecutive basis slabs (>= M * B).
 LaunchInfo launch_proj(int B, int ns, const T* b0, const T* b1, int64_t M, int64_t stride, int nk, const T* x,
@@ -158,7 +161,8 @@ LaunchInfo launch_fermi_search(int64_t nseeds, int nu, const int32_t* nu_eff, co
 // and B >= the vector width. ndot as in launch_spmm, against Z.
 template <typename T>
 LaunchInfo launch_spmm2(int B, const DevMat& H, const DevMat& SH, const T* X, T* Y, T* Z, double* part, int ndot,
-                        int64_t part_cap, hipStream_t s, const int32_t* tdist = nullptr, int lim = 0);
+                        int64_t part_cap, hipStream_t s, const int32_t* tdist = nullptr, int lim = 0,
+                        const uint32_t* mask = nullptr, int W = 0);
 // Delayed-reorthogonalization schedule.
 // Projection sweep (variants as in projr_geometry); target_wgs > 0.
 template <typename T>
@@ -191,9 +195,15 @@ constexpr int32_t SUP_FAR = 0x3fffffff;   // tile distance: farther than the lar
 // BFS over H's block pattern from the block rows of the seeds (hmax levels), tile distances D (bpt block rows
 // per tile, ceil(nbrow / bpt) tiles), cnt[h] = tiles with D <= h (h = 0..hmax), and the tiles with D <= hmax
 // sorted by (D, index) into list (Dl: their D).
+// Distances above hmax count as SUP_FAR (never nonzero); cnt has hcnt + 1 entries (hcnt >= hmax).
 LaunchInfo launch_support(int64_t M, int64_t nbrow, const int32_t* brp, const int32_t* bcol, int64_t nnzb,
-                          const int32_t* seeds, int ns, int bpt, int hmax, int32_t* dist, int32_t* D,
+                          const int32_t* seeds, int ns, int bpt, int hmax, int hcnt, int32_t* dist, int32_t* D,
                           int32_t* cnt, int32_t* list, int32_t* Dl, hipStream_t s);
+// Local regions: per block row, W = ceil(B / 32) words whose bit b says the row is within r hops of seed b's
+// block; m0, m1 hold nbrow * W words each; returns the buffer that holds the result.
+const uint32_t* launch_local_masks(int64_t M, int64_t nbrow, const int32_t* brp, const int32_t* bcol,
+                                   const int32_t* seeds, int ns, int W, int r, uint32_t* m0, uint32_t* m1,
+                                   hipStream_t s);
 // Work plan of the support-restricted projection of step n: 8 + 4 * grid ints at plan, grid = G + chunks.
 inline int64_t projr_sp_grid(int64_t G, int nk, int kg) { return G + (nk + kg - 1) / kg; }
 LaunchInfo launch_projr_plan(const int32_t* cnt, const int32_t* Dl, int n, int kg, int64_t G, int64_t grid,

@@ -64,7 +64,7 @@ __global__ __launch_bounds__(WG) void k_spmm_bsr4(int64_t nbrow, const int32_t* 
                                                   const int32_t* __restrict__ bcol, const T* __restrict__ bval,
                                                   const T* __restrict__ X, T* __restrict__ Y,
                                                   double* __restrict__ part, const int32_t* __restrict__ tdist,
-                                                  int lim) {
+                                                  int lim, const uint32_t* __restrict__ mask, int W) {
     using SM = SeedMap<T, B>;
     constexpr int VEC = SM::VEC, SW = SM::SW, P = SM::P;
     using VT = typename Vec16<T>::type;
@@ -131,6 +131,14 @@ __global__ __launch_bounds__(WG) void k_spmm_bsr4(int64_t nbrow, const int32_t* 
                             }
                     }
                 }
+            }
+            if (mask != nullptr) {   // local regions: keep the rows inside each seed's region
+                const uint32_t bits = mask[Iu * W + s0 / 32] >> (s0 % 32);
+#pragma unroll
+                for (int i = 0; i < SW; ++i)
+                    if (!((bits >> i) & 1u))
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) acc[r][i] = (T)0;
             }
             VT* Yv = reinterpret_cast<VT*>(Y);
 #pragma unroll
@@ -222,7 +230,8 @@ __global__ __launch_bounds__(WG) void k_spmm2_bsr4(int64_t nbrow, const int32_t*
                                                    const int32_t* __restrict__ bcol, const T* __restrict__ hval,
                                                    const T* __restrict__ sval, const T* __restrict__ X,
                                                    T* __restrict__ Y, T* __restrict__ Z, double* __restrict__ part,
-                                                   const int32_t* __restrict__ tdist, int lim) {
+                                                   const int32_t* __restrict__ tdist, int lim,
+                                                   const uint32_t* __restrict__ mask, int W) {
     using SM = SeedMap<T, B>;
     constexpr int VEC = SM::VEC, SW = SM::SW, P = SM::P;
     static_assert(B >= VEC, "dual product needs one seed group per lane");
@@ -295,6 +304,14 @@ __global__ __launch_bounds__(WG) void k_spmm2_bsr4(int64_t nbrow, const int32_t*
                         }
                 }
             }
+        }
+        if (mask != nullptr) {   // local regions: keep the rows inside each seed's region
+            const uint32_t bits = mask[Iu * W + s0 / 32] >> (s0 % 32);
+#pragma unroll
+            for (int i = 0; i < SW; ++i)
+                if (!((bits >> i) & 1u))
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) ah[r][i] = as[r][i] = (T)0;
         }
         VT* Yv = reinterpret_cast<VT*>(Y);
         VT* Zv = reinterpret_cast<VT*>(Z);
@@ -882,11 +899,13 @@ LaunchInfo launch_init<MAR_T>(int B, int64_t Mp, int64_t M, const int32_t* seeds
 
 template <>
 LaunchInfo launch_spmm<MAR_T>(int B, const DevMat& A, const MAR_T* X, MAR_T* Y, double* part, int ndot,
-                              int64_t part_cap, hipStream_t s, const int32_t* tdist, int lim) {
+                              int64_t part_cap, hipStream_t s, const int32_t* tdist, int lim, const uint32_t* mask,
+                              int W) {
     constexpr int VEC = Vec16<MAR_T>::n;
     const int P = B < VEC ? 1 : B / VEC;
     const int64_t wgs = (A.n * P + WG - 1) / WG;
-    if ((ndot > 0 && wgs * ndot * B > part_cap) || (tdist != nullptr && (!A.bsr || B < VEC))) {
+    if ((ndot > 0 && wgs * ndot * B > part_cap) ||
+        ((tdist != nullptr || mask != nullptr) && (!A.bsr || B < VEC))) {
         LaunchInfo bad;
         bad.wgs = -1;
         return bad;
@@ -895,7 +914,7 @@ LaunchInfo launch_spmm<MAR_T>(int B, const DevMat& A, const MAR_T* X, MAR_T* Y, 
 #define MAR_SPMM_LAUNCH(KERNEL, ND) \
     MAR_DISPATCH_B(B, hipLaunchKernelGGL((KERNEL<MAR_T, BB, ND>), dim3(wgs), dim3(WG), 0, s, A.n, A.ptr, A.idx, val, X, Y, part))
 #define MAR_SPMM_BSR(ND) \
-    MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_spmm_bsr4<MAR_T, BB, ND>), dim3(wgs), dim3(WG), 0, s, A.n, A.ptr, A.idx, val, X, Y, part, tdist, lim))
+    MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_spmm_bsr4<MAR_T, BB, ND>), dim3(wgs), dim3(WG), 0, s, A.n, A.ptr, A.idx, val, X, Y, part, tdist, lim, mask, W))
     if (A.bsr) {
         if (ndot == 2) { MAR_SPMM_BSR(2); }
         else if (ndot == 1) { MAR_SPMM_BSR(1); }
@@ -918,7 +937,7 @@ LaunchInfo launch_spmm<MAR_T>(int B, const DevMat& A, const MAR_T* X, MAR_T* Y, 
 template <>
 LaunchInfo launch_spmm2<MAR_T>(int B, const DevMat& H, const DevMat& SH, const MAR_T* X, MAR_T* Y, MAR_T* Z,
                                double* part, int ndot, int64_t part_cap, hipStream_t s, const int32_t* tdist,
-                               int lim) {
+                               int lim, const uint32_t* mask, int W) {
     constexpr int VEC = Vec16<MAR_T>::n;
     LaunchInfo li;
     if (!H.bsr || B < VEC || SH.nnz != H.nnz) {
@@ -935,7 +954,7 @@ LaunchInfo launch_spmm2<MAR_T>(int B, const DevMat& H, const DevMat& SH, const M
     const MAR_T* hv = f32 ? (const MAR_T*)H.v32 : (const MAR_T*)H.v64;
     const MAR_T* sv = f32 ? (const MAR_T*)SH.v32 : (const MAR_T*)SH.v64;
 #define MAR_SPMM2(ND) \
-    MAR_DISPATCH_B(B, if constexpr (BB >= VEC) hipLaunchKernelGGL((k_spmm2_bsr4<MAR_T, BB, ND>), dim3(wgs), dim3(WG), 0, s, H.n, H.ptr, H.idx, hv, sv, X, Y, Z, part, tdist, lim))
+    MAR_DISPATCH_B(B, if constexpr (BB >= VEC) hipLaunchKernelGGL((k_spmm2_bsr4<MAR_T, BB, ND>), dim3(wgs), dim3(WG), 0, s, H.n, H.ptr, H.idx, hv, sv, X, Y, Z, part, tdist, lim, mask, W))
     if (ndot == 2) { MAR_SPMM2(2); }
     else if (ndot == 1) { MAR_SPMM2(1); }
     else { MAR_SPMM2(0); }

@@ -113,7 +113,7 @@ __global__ __launch_bounds__(WG) void k_sup_scatter(int64_t ntiles, const int32_
 }
 
 LaunchInfo launch_support(int64_t M, int64_t nbrow, const int32_t* brp, const int32_t* bcol, int64_t nnzb,
-                          const int32_t* seeds, int ns, int bpt, int hmax, int32_t* dist, int32_t* D,
+                          const int32_t* seeds, int ns, int bpt, int hmax, int hcnt, int32_t* dist, int32_t* D,
                           int32_t* cnt, int32_t* list, int32_t* Dl, hipStream_t s) {
     const int64_t ntiles = (nbrow + bpt - 1) / bpt;
     const unsigned rw = (unsigned)((nbrow + WG - 1) / WG), tw = (unsigned)((ntiles + WG - 1) / WG);
@@ -121,7 +121,7 @@ LaunchInfo launch_support(int64_t M, int64_t nbrow, const int32_t* brp, const in
     if (ns > 0) hipLaunchKernelGGL(k_sup_seed, dim3((ns + WG - 1) / WG), dim3(WG), 0, s, seeds, ns, M, dist);
     for (int h = 1; h <= hmax; ++h) hipLaunchKernelGGL(k_sup_hop, dim3(rw), dim3(WG), 0, s, nbrow, brp, bcol, dist, h);
     hipLaunchKernelGGL(k_sup_tiles, dim3(tw), dim3(WG), 0, s, nbrow, bpt, ntiles, dist, hmax, D);
-    hipLaunchKernelGGL(k_sup_count, dim3(hmax + 1), dim3(WG), 0, s, ntiles, D, cnt);
+    hipLaunchKernelGGL(k_sup_count, dim3(hcnt + 1), dim3(WG), 0, s, ntiles, D, cnt);
     hipLaunchKernelGGL(k_sup_scatter, dim3(hmax + 1), dim3(WG), 0, s, ntiles, D, cnt, list, Dl);
     LaunchInfo li;
     li.wgs = rw;
@@ -225,6 +225,56 @@ __global__ __launch_bounds__(WG) void k_projr_plan(const int32_t* __restrict__ c
         plan[2] = (int32_t)carry;
         plan[3] = nks;
     }
+}
+
+// Local regions (order-N form): bit b of mask[I * W + b / 32] is set when block
+// row I lies within r hops of the block of seed b. k_loc_seed marks the seeds'
+// own blocks; each k_loc_hop adds the blocks one hop further (from a separate
+// input buffer, so a launch moves exactly one hop).
+__global__ __launch_bounds__(WG) void k_loc_seed(int64_t nbrow, int W, const int32_t* __restrict__ seeds, int ns,
+                                                 int64_t M, uint32_t* __restrict__ mask) {
+    const int64_t g = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (g >= nbrow * W) return;
+    const int64_t I = g / W;
+    const int w = (int)(g % W);
+    uint32_t bits = 0;
+    for (int i = 0; i < 32; ++i) {
+        const int b = w * 32 + i;
+        if (b < ns) {
+            const int j = seeds[b];
+            if (j >= 0 && j < M && j / 4 == I) bits |= 1u << i;
+        }
+    }
+    mask[g] = bits;
+}
+
+__global__ __launch_bounds__(WG) void k_loc_hop(int64_t nbrow, int W, const int32_t* __restrict__ brp,
+                                                const int32_t* __restrict__ bcol, const uint32_t* __restrict__ in,
+                                                uint32_t* __restrict__ out) {
+    const int64_t g = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (g >= nbrow * W) return;
+    const int64_t I = g / W;
+    const int w = (int)(g % W);
+    uint32_t bits = in[g];
+    const int lo = brp[I], hi = brp[I + 1];
+    for (int p = lo; p < hi; ++p) bits |= in[(int64_t)bcol[p] * W + w];
+    out[g] = bits;
+}
+
+const uint32_t* launch_local_masks(int64_t M, int64_t nbrow, const int32_t* brp, const int32_t* bcol,
+                                   const int32_t* seeds, int ns, int W, int r, uint32_t* m0, uint32_t* m1,
+                                   hipStream_t s) {
+    const unsigned g = (unsigned)((nbrow * W + WG - 1) / WG);
+    hipLaunchKernelGGL(k_loc_seed, dim3(g), dim3(WG), 0, s, nbrow, W, seeds, ns, M, m0);
+    uint32_t* a = m0;
+    uint32_t* b = m1;
+    for (int h = 0; h < r; ++h) {
+        hipLaunchKernelGGL(k_loc_hop, dim3(g), dim3(WG), 0, s, nbrow, W, brp, bcol, a, b);
+        uint32_t* t = a;
+        a = b;
+        b = t;
+    }
+    return a;
 }
 
 LaunchInfo launch_projr_plan(const int32_t* cnt, const int32_t* Dl, int n, int kg, int64_t G, int64_t grid,

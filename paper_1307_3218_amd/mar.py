@@ -97,6 +97,10 @@ def lib() -> C.CDLL:
     L.mar_set_tuning.restype = C.c_int
     L.mar_get_tuning.argtypes = [_P, C.POINTER(mar_tuning)]
     L.mar_get_tuning.restype = C.c_int
+    L.mar_set_local_region.argtypes = [_P, i32]
+    L.mar_set_local_region.restype = C.c_int
+    L.mar_local_region.argtypes = [_P]
+    L.mar_local_region.restype = i32
     L.mar_seed_block.argtypes = [_P, i32, C.c_int]
     L.mar_seed_block.restype = i32
     L.mar_last_error.argtypes = [_P]
@@ -227,6 +231,14 @@ def mar_set_tuning(ctx, seed_block: int = 0, schedule: int = 0, proj_wgs: int = 
     return lib().mar_set_tuning(ctx, C.byref(t))
 
 
+def mar_set_local_region(ctx, hops: int) -> int:
+    return lib().mar_set_local_region(ctx, int(hops))
+
+
+def mar_local_region(ctx) -> int:
+    return lib().mar_local_region(ctx)
+
+
 def mar_seed_block(ctx, nu: int, prec: int) -> int:
     return lib().mar_seed_block(ctx, int(nu), int(prec))
 
@@ -343,6 +355,13 @@ class Context:
         st = mar_solve_async(self.handle, d_seeds, d_seeds.numel(), nu, mu, kT, PRECISION[precision], FORM[form],
                              d_rho, d_e_band, d_e_seed, d_n_seed, d_nu_eff, d_eps, d_weight, stream)
         _check(self.handle, st)
+
+    def set_local_region(self, hops: int | None):
+        """Later solves run each seed on the rows within `hops` block hops of it (None or < 0: the full system)."""
+        _check(self.handle, mar_set_local_region(self.handle, -1 if hops is None else hops))
+
+    def local_region(self) -> int:
+        return mar_local_region(self.handle)
 
     def set_tuning(self, seed_block: int = 0, schedule: str = "auto", proj_wgs: int = 0, slab_pad_kb: int = 0,
                    proj_variant: int = 0, upd_q: int = 0, support: bool = True):
