@@ -42,6 +42,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "seed-subspaces/s at ν=100, M=131072: FP32-batched vs FP64 plain; SpMM HBM %"
+METRIC_LOCAL = "seed-subspaces/s, local regions of {r} block hops (order-N form), FP32 batched"
 HBM_PEAK_GBPS = 8000.0
 KT = 0.1
 
@@ -85,6 +86,19 @@ def cpu_baseline(system, nu, mu, n_seeds, workers):
     return dict(value=n_seeds / dt, unit="seed-subspaces/s", cores=workers, kind="oracle",
                 sample=f"{n_seeds} uniformly sampled seeds of the same workload (nu={nu}), "
                        f"FP64 NumPy/SciPy, one process per core, {dt:.1f} s wall")
+
+
+def cpu_baseline_local(system, nu, mu, r, budget_s=12.0):
+    """The local-region oracle, serial, on neighbouring seeds until about budget_s of CPU work."""
+    from oracle import mar_local as OL
+    n, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < budget_s and n < system.M:
+        OL.solve_local(system.H, system.S, np.arange(n, min(n + 8, system.M)), nu, r, mu, KT)
+        n = min(n + 8, system.M)
+    dt = time.perf_counter() - t0
+    return dict(value=n / dt, unit="seed-subspaces/s", cores=1, kind="oracle",
+                sample=f"seeds 0..{n - 1} of the same workload (nu={nu}, regions of {r} hops), FP64 NumPy/SciPy, "
+                       f"one process, {dt:.1f} s wall")
 
 
 def run_uneven(args) -> int:
@@ -233,6 +247,9 @@ def main() -> int:
                     help="natural: consecutive seeds (neighbouring atoms) share a block; random: a permutation of "
                          "all seeds; sampled: a sorted uniform sample of min(M, 16384) seeds")
     ap.add_argument("--no-support", action="store_true", help="stream every row of every slab")
+    ap.add_argument("--r-cut", type=int, default=-1, metavar="HOPS",
+                    help="local regions of HOPS block hops (the order-N form; a different computation from the "
+                         "headline line, reported under its own metric); the seed block is autotuned unless given")
     ap.add_argument("--uneven-calls", type=int, default=8,
                     help="uneven8: mar_solve_many calls per pass over all seeds (each takes M/calls seeds per system)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
@@ -270,6 +287,13 @@ def main() -> int:
     ctx = mar.Context(system.H, system.S)
     if args.seed_block or args.no_support:
         ctx.set_tuning(args.seed_block, support=not args.no_support)
+    local = args.r_cut >= 0
+    if local:
+        ctx.set_local_region(args.r_cut)
+        args.no_plain = True                       # the plain form has no local regions
+        if not args.seed_block:
+            tn = ctx.autotune(torch.from_numpy(np.arange(min(M, 1024), dtype=np.int32)).to(dev), nu, 0.0, KT, "fp32")
+            log(f"local regions of {args.r_cut} hops: autotuned block {tn['seed_block']}, variant {tn['proj_variant']}")
     B = ctx.seed_block(nu, "fp32")
     S_step = args.seeds_per_step
     stream = torch.cuda.current_stream().cuda_stream
@@ -357,7 +381,8 @@ def main() -> int:
         e = prof[dom]
         ach = e["bytes"] / (e["ms"] * 1e-3) / 1e9
         kind, cells = system.name.split("_", 1)          # e.g. mixed, 16x16x16
-        wl = f"{kind}{cells.split('x')[0]}_nu{nu}_fp32_b{B}_{args.seed_order}" + ("_full" if args.no_support else "")
+        wl = f"{kind}{cells.split('x')[0]}_nu{nu}_fp32_b{B}_{args.seed_order}" + ("_full" if args.no_support else "") \
+            + (f"_r{args.r_cut}" if local else "")
         traffic = measured_traffic(dom, wl) if S_step % B == 0 else None
         roofline = dict(kernel=dom, bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
                         frac=round(ach / HBM_PEAK_GBPS, 4), traffic=traffic,
@@ -400,7 +425,10 @@ def main() -> int:
             log(f"{prec} {form}: {n_x} seeds in {dtx:.3f} s -> {n_x / dtx:.2f} seed-subspaces/s")
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and local:
+        cpu = cpu_baseline_local(system, nu, mu, args.r_cut)
+        log(f"cpu oracle (local regions): {cpu['value']:.2f} seed-subspaces/s on 1 core")
+    elif not args.no_cpu_baseline:
         from oracle import mar_oracle as O
         workers = min(16, O.default_workers())
         n_cpu = args.cpu_seeds or max(workers, int(round(20.0 / 1.3)))
@@ -409,7 +437,7 @@ def main() -> int:
         log(f"cpu oracle: {cpu['value']:.2f} seed-subspaces/s on {workers} cores")
 
     out = {
-        "metric": METRIC,
+        "metric": METRIC_LOCAL.format(r=args.r_cut) if local else METRIC,
         "value": round(value, 3),
         "unit": "seed-subspaces/s",
         "n_gpus": 1,
@@ -424,7 +452,7 @@ def main() -> int:
         "config": {"workload": f"{system.name} mixed sp2/sp3 lattice, M={M}, nu={nu}, kT={KT}, FP32 batched",
                    "M": M, "nnz": int(system.H.nnz), "nu": nu, "seeds_per_step": S_step, "seed_block": B,
                    "precision": "fp32", "form": "batched", "mu": mu, "seed_order": args.seed_order,
-                   "support_tracking": not args.no_support},
+                   "support_tracking": not args.no_support, "local_region_hops": args.r_cut if local else None},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fp64_plain": plain,
