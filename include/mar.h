@@ -246,6 +246,34 @@ mar_status mar_autotune(mar_ctx* ctx, int32_t nu, mar_precision prec, const int3
                         double mu, double kT, void* hip_stream, int32_t* best_block, int32_t* best_variant,
                         double* best_rate);
 
+/* Local flipping refinement of one eigenvector (Appendix). The signs of the
+ * components a_l of phi (level eps) are flipped one at a time when that lowers
+ *     R = |r|^2 (+ c (phi_ref^T S phi)^2),   r = (H - eps S) phi,
+ * the penalty acting as an orthogonality constraint to an earlier state
+ * phi_ref (the paper uses c = 5 atomic units, 5 x 27.211386^2 eV^2 for
+ * matrices in eV). A flip changes r only on the rows of P(l), so no matrix
+ * product is needed after the first residual. Rows are visited by colour of a
+ * greedy distance-2 colouring of H's pattern (row l takes the smallest colour
+ * unused by earlier rows within two hops; built on the first call and kept):
+ * rows of one colour decide together (their single-flip changes of |r|^2 are
+ * independent), row l flipping when
+ *     dR_l = sum_{i in P(l)} A_il (4 a_l^2 A_il - 4 a_l r_i)
+ *            + c (4 a_l^2 s_l^2 - 4 a_l s_l p) < 0,   A = H - eps S, s = S phi_ref,
+ * with p from the start of the colour; a sweep visits every colour; sweeps
+ * repeat until one flips nothing or max_sweeps have run. Sums run in fixed
+ * orders with separately rounded products, so the decisions are reproducible.
+ *   d_phi     [M] device, FP64, in/out.
+ *   d_phi_ref [M] device or NULL (no penalty when NULL or c == 0).
+ *   d_R       [max_sweeps + 1] device or NULL: R before the first sweep and after
+ *             each sweep run (later entries untouched).
+ *   d_info    [2] device or NULL: sweeps run, flips made.
+ * One workgroup on the caller's stream; asynchronous. MAR_ERR_ARG for a NULL
+ * phi, eps or c not finite, c < 0 or max_sweeps < 0. */
+mar_status mar_local_flip(mar_ctx* ctx, double* d_phi, double eps, const double* d_phi_ref, double c,
+                          int32_t max_sweeps, double* d_R, int32_t* d_info, void* hip_stream);
+/* Number of colours of that colouring (built if needed; synchronous); -1 on error. */
+int32_t mar_flip_colours(mar_ctx* ctx);
+
 /* Local regions: the order-N form of the method (Sec. 1 gives its cost as
  * proportional to the number of atoms, so the work of one seed may not grow
  * with the system; how the subspace is kept local is left to the cited mArnoldi

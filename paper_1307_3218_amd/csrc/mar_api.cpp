@@ -89,6 +89,11 @@ struct mar_ctx {
     } es;
     char* fws = nullptr;          // workspace of the device Fermi-level search
     size_t fws_bytes = 0;
+    // local flipping: distance-2 colouring of H's rows (built at the first call) and workspace
+    int32_t* fl_coff = nullptr;   // [ncol + 1]
+    int32_t* fl_crow = nullptr;   // [M] rows by colour, index order within a colour
+    int fl_ncol = 0;
+    char* flws = nullptr;         // r, s [M] doubles and flags [M]
 
     mar_tuning tune{};
     int32_t loc = -1;             // local-region hops of later solves (< 0: the full system)
@@ -117,6 +122,7 @@ struct mar_ctx {
         if (ws) hipFree(ws);
         if (io) hipFree(io);
         if (fws) hipFree(fws);
+        if (flws) hipFree(flws);
         if (stream) hipStreamDestroy(stream);
     }
 };
@@ -1553,6 +1559,76 @@ mar_status mar_solve(mar_ctx* c, const int32_t* seeds, int64_t n_seeds, int32_t 
         if (nuv[i] == -1)
             return set_err(c, MAR_ERR_NOT_SPD, fmt("w^T S w < 0 for seed %d: S is not positive definite", seeds[i]));
     return MAR_OK;
+}
+
+// Greedy distance-2 colouring of H's rows in index order: row l takes the
+// smallest colour not used by an earlier row within two hops of it.
+mar_status build_colouring(mar_ctx* c) {
+    const int64_t M = c->M;
+    std::vector<int32_t> rp(M + 1), col((size_t)c->nnzH);
+    HIP_OR(c, hipMemcpy(rp.data(), c->Hrp, rp.size() * 4, hipMemcpyDeviceToHost));
+    HIP_OR(c, hipMemcpy(col.data(), c->Hcol, col.size() * 4, hipMemcpyDeviceToHost));
+    std::vector<int32_t> colour(M, -1);
+    std::vector<int64_t> stamp;
+    int ncol = 0;
+    for (int64_t l = 0; l < M; ++l) {
+        auto mark = [&](int64_t m) {
+            if (m < l) stamp[colour[m]] = l;
+        };
+        for (int q = rp[l]; q < rp[l + 1]; ++q) {
+            const int64_t j = col[q];
+            if (stamp.size() < (size_t)ncol + 1) stamp.resize((size_t)ncol + 1, -1);
+            mark(j);
+            for (int t = rp[j]; t < rp[j + 1]; ++t) mark(col[t]);
+        }
+        if (stamp.size() < (size_t)ncol + 1) stamp.resize((size_t)ncol + 1, -1);
+        int k = 0;
+        while (k < ncol && stamp[k] == l) ++k;
+        colour[l] = k;
+        if (k == ncol) ++ncol;
+    }
+    std::vector<int32_t> off(ncol + 1, 0), rows(M);
+    for (int64_t l = 0; l < M; ++l) ++off[colour[l] + 1];
+    for (int k = 0; k < ncol; ++k) off[k + 1] += off[k];
+    std::vector<int32_t> fill(off.begin(), off.end() - 1);
+    for (int64_t l = 0; l < M; ++l) rows[fill[colour[l]]++] = (int32_t)l;
+    mar_status st;
+    if ((st = upload(c, &c->fl_coff, off.data(), off.size())) != MAR_OK) return st;
+    if ((st = upload(c, &c->fl_crow, rows.data(), rows.size())) != MAR_OK) return st;
+    c->fl_ncol = ncol;
+    return MAR_OK;
+}
+
+mar_status mar_local_flip(mar_ctx* c, double* d_phi, double eps, const double* d_phi_ref, double cpen,
+                          int32_t max_sweeps, double* d_R, int32_t* d_info, void* hip_stream) {
+    if (!c) return MAR_ERR_STATE;
+    if (!d_phi) return set_err(c, MAR_ERR_ARG, "phi is NULL");
+    if (!std::isfinite(eps)) return set_err(c, MAR_ERR_ARG, "eps is not finite");
+    if (!(cpen >= 0.0) || !std::isfinite(cpen)) return set_err(c, MAR_ERR_ARG, "c must be finite and >= 0");
+    if (max_sweeps < 0) return set_err(c, MAR_ERR_ARG, "max_sweeps < 0");
+    HIP_OR(c, hipSetDevice(c->device));
+    if (!c->fl_crow) {
+        mar_status st = build_colouring(c);
+        if (st != MAR_OK) return st;
+    }
+    if (!c->flws) {
+        void* p = nullptr;
+        HIP_OR(c, hipMalloc(&p, (size_t)c->M * 17 + 16));
+        c->flws = (char*)p;
+    }
+    double* r = (double*)c->flws;
+    double* sv = r + c->M;
+    int8_t* flag = (int8_t*)(sv + c->M);
+    mar::launch_flip(c->M, c->Hrp, c->Hcol, c->Hval, c->SvalH, eps, d_phi, d_phi_ref, cpen, c->fl_ncol, c->fl_coff,
+                     c->fl_crow, max_sweeps, r, sv, flag, d_R, d_info, (hipStream_t)hip_stream);
+    HIP_OR(c, hipGetLastError());
+    return MAR_OK;
+}
+
+int32_t mar_flip_colours(mar_ctx* c) {
+    if (!c) return -1;
+    if (!c->fl_crow && (hipSetDevice(c->device) != hipSuccess || build_colouring(c) != MAR_OK)) return -1;
+    return c->fl_ncol;
 }
 
 mar_status mar_set_local_region(mar_ctx* c, int32_t hops) {

@@ -221,6 +221,13 @@ LaunchInfo launch_norm(int B, int nk, const double* beta2, const double* c1, con
 LaunchInfo launch_sum(const double* x, int64_t n, double* out, hipStream_t s);
 LaunchInfo launch_zero(void* p, int64_t bytes, hipStream_t s);  // bytes: multiple of 16
 
+// Local flipping refinement (Appendix), one workgroup: phi [M] in/out; colours: ncol lists, rows crow[coff[k]..
+// coff[k+1]) in index order; r, s [M] and flag [M] workspace; Rout [max_sweeps + 1] and info [2] optional.
+LaunchInfo launch_flip(int64_t M, const int32_t* rp, const int32_t* col, const double* hv, const double* sv,
+                       double eps, double* phi, const double* phi_ref, double cpen, int ncol, const int32_t* coff,
+                       const int32_t* crow, int max_sweeps, double* r, double* s, int8_t* flag, double* Rout,
+                       int32_t* info, hipStream_t st);
+
 // Largest B accepted for an element type (P = B / vector width must fit one wavefront).
 template <typename T>
 constexpr int max_block() { return sizeof(T) == 4 ? 256 : 128; }

@@ -97,6 +97,10 @@ def lib() -> C.CDLL:
     L.mar_set_tuning.restype = C.c_int
     L.mar_get_tuning.argtypes = [_P, C.POINTER(mar_tuning)]
     L.mar_get_tuning.restype = C.c_int
+    L.mar_local_flip.argtypes = [_P, _P, f64, _P, f64, i32, _P, _P, _P]
+    L.mar_local_flip.restype = C.c_int
+    L.mar_flip_colours.argtypes = [_P]
+    L.mar_flip_colours.restype = i32
     L.mar_set_local_region.argtypes = [_P, i32]
     L.mar_set_local_region.restype = C.c_int
     L.mar_local_region.argtypes = [_P]
@@ -231,6 +235,15 @@ def mar_set_tuning(ctx, seed_block: int = 0, schedule: int = 0, proj_wgs: int = 
     return lib().mar_set_tuning(ctx, C.byref(t))
 
 
+def mar_local_flip(ctx, d_phi, eps, d_phi_ref, c, max_sweeps, d_R, d_info, stream) -> int:
+    return lib().mar_local_flip(ctx, _tptr(d_phi), float(eps), _tptr(d_phi_ref), float(c), int(max_sweeps),
+                                _tptr(d_R), _tptr(d_info), stream)
+
+
+def mar_flip_colours(ctx) -> int:
+    return lib().mar_flip_colours(ctx)
+
+
 def mar_set_local_region(ctx, hops: int) -> int:
     return lib().mar_set_local_region(ctx, int(hops))
 
@@ -355,6 +368,28 @@ class Context:
         st = mar_solve_async(self.handle, d_seeds, d_seeds.numel(), nu, mu, kT, PRECISION[precision], FORM[form],
                              d_rho, d_e_band, d_e_seed, d_n_seed, d_nu_eff, d_eps, d_weight, stream)
         _check(self.handle, st)
+
+    def local_flip(self, phi, eps, phi_ref=None, c=0.0, max_sweeps=100, stream=None) -> dict:
+        """Sign-flip refinement of the eigenvector phi of level eps (Appendix); phi: host array of M values.
+
+        Returns dict(phi, R, sweeps, flips): the refined vector, R before the first and after every sweep.
+        """
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device())
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        d_phi = torch.as_tensor(np.ascontiguousarray(phi, dtype=np.float64)).to(dev)
+        d_ref = None if phi_ref is None else torch.as_tensor(np.ascontiguousarray(phi_ref, dtype=np.float64)).to(dev)
+        d_R = torch.full((max_sweeps + 1,), float("nan"), dtype=torch.float64, device=dev)
+        d_info = torch.zeros(2, dtype=torch.int32, device=dev)
+        _check(self.handle, mar_local_flip(self.handle, d_phi, eps, d_ref, c, max_sweeps, d_R, d_info, stream))
+        torch.cuda.synchronize()
+        info = d_info.cpu().numpy()
+        return dict(phi=d_phi.cpu().numpy(), R=d_R.cpu().numpy()[: int(info[0]) + 1], sweeps=int(info[0]),
+                    flips=int(info[1]))
+
+    def flip_colours(self) -> int:
+        return mar_flip_colours(self.handle)
 
     def set_local_region(self, hops: int | None):
         """Later solves run each seed on the rows within `hops` block hops of it (None or < 0: the full system)."""
