@@ -609,13 +609,16 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     const bool sparse = dual && c->tune.support_off == 0;
     const int kg = variant == 1 || variant == 4 ? 8 : 4;
     const int64_t nbrow = c->H.n, bpt = mar::WG / std::max(P, 1);
-    // local regions (order-N form): per block row and seed, inside the seed's region or not
+    // local regions (order-N form): per block row and seed, inside the seed's region or not. With the support
+    // tracking on, the products and the update then run over the support list (a small grid of kListWgs
+    // workgroups in a grid-stride loop) instead of a workgroup per row tile of the whole cell.
     const bool local = c->loc >= 0 && dual;
+    constexpr int64_t kListWgs = 2048;
     const int mW = (B + 31) / 32;
     const int hreach = local ? std::min(nu, (int)c->loc) : nu;   // farthest hop a vector can reach
     const int64_t ntiles = (nbrow + bpt - 1) / bpt;
     const int64_t grid_max = mar::projr_sp_grid(target, nu, kg);
-    size_t part_doubles = (size_t)spmm_wgs * 2 * B;
+    size_t part_doubles = (size_t)std::max<int64_t>(spmm_wgs, 2048) * 2 * B;
     for (int nk = 1; nk <= nu; ++nk) {
         const mar::ProjrGeom gm = mar::projr_geometry(nvec, nk, variant, target);
         part_doubles = std::max<size_t>(part_doubles, (size_t)gm.groups * 3 * nk * B);
@@ -738,15 +741,23 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
         }
         if (sparse) {
             // Slabs 1.. and y = H u~ start at zero: a tile is written only once the support reaches it, and
-            // y is read on the neighbour rows of the tiles where S y is formed.
-            launch(c, s, P_INIT, [&] {
-                return mar::launch_zero(K + slab_el, (int64_t)((size_t)(nu - 1) * stride * sizeof(T)), s);
-            });
-            launch(c, s, P_INIT, [&] { return mar::launch_zero(Y, (int64_t)slab, s); });
+            // y is read on the neighbour rows of the tiles where S y is formed. With local regions only the
+            // tiles within one hop of the regions' union are ever read.
+            if (!local) {
+                launch(c, s, P_INIT, [&] {
+                    return mar::launch_zero(K + slab_el, (int64_t)((size_t)(nu - 1) * stride * sizeof(T)), s);
+                });
+                launch(c, s, P_INIT, [&] { return mar::launch_zero(Y, (int64_t)slab, s); });
+            }
             launch(c, s, P_SUPPORT, [&] {
                 return mar::launch_support(c->M, nbrow, c->H.ptr, c->H.idx, c->H.nnz, seeds, ns, (int)bpt, hreach, nu,
                                            sdist, TD, scnt, slist, sDl, s);
             });
+            if (local)
+                launch(c, s, P_INIT, [&] {
+                    return mar::launch_zero_ring(nbrow, c->H.ptr, c->H.idx, sdist, hreach, (int)bpt, K + slab_el,
+                                                 (int64_t)(stride * sizeof(T)), nu - 1, Y, nvec, s);
+                });
             if (plog && !c->refused)
                 hipMemcpyAsync(plog + bi * (nu + 1), scnt, (size_t)(nu + 1) * 4, hipMemcpyDeviceToDevice, s);
         }
@@ -759,8 +770,12 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
             int64_t swgs = 0;
             if (dual) {
                 const bool rec = launch(c, s, n == 0 ? P_SPMM : P_SPMM_DOT, [&] {
-                    LaunchInfo li = mar::launch_spmm2<T>(B, c->H, c->SH, Kn, Y, ZT, n == 0 ? nullptr : part,
-                                                         n == 0 ? 0 : 2, part_cap, s, TD, n + 1, lmask, mW);
+                    LaunchInfo li = local && sparse
+                        ? mar::launch_spmm2_list<T>(B, c->H, c->SH, Kn, Y, ZT, n == 0 ? nullptr : part,
+                                                    n == 0 ? 0 : 2, part_cap, slist, scnt, n + 1, lmask, mW,
+                                                    kListWgs, s)
+                        : mar::launch_spmm2<T>(B, c->H, c->SH, Kn, Y, ZT, n == 0 ? nullptr : part, n == 0 ? 0 : 2,
+                                               part_cap, s, TD, n + 1, lmask, mW);
                     swgs = li.wgs;
                     return li;
                 });
@@ -781,7 +796,8 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
             if (!dual) launch(c, s, P_SPMM, [&] { return mar::launch_spmm<T>(B, c->H, Kn, Y, nullptr, 0, 0, s); });
             if (sparse) {
                 const bool rec = launch(c, s, P_SPMM, [&] {
-                    return mar::launch_spmm<T>(B, c->SH, Y, SY, nullptr, 0, 0, s, TD, n, lmask, mW);
+                    return local ? mar::launch_spmm_list<T>(B, c->SH, Y, SY, slist, scnt, n, lmask, mW, kListWgs, s)
+                                 : mar::launch_spmm<T>(B, c->SH, Y, SY, nullptr, 0, 0, s, TD, n, lmask, mW);
                 });
                 tag(rec, SP_FRAC, n, bi, (double)ntiles);
                 const int64_t grid = mar::projr_sp_grid(target, nk, kg);
@@ -811,9 +827,11 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
             });
             const bool ru = launch(c, s, P_UPD2, [&] {
                 // w' goes straight into slab n + 1, unnormalized (its scale is handled by k_coef)
-                return mar::launch_upd2<T>(B, K, M, stride, n, cAT, cBT, gam, Fn, Y,
-                                           last ? nullptr : K + (size_t)(n + 1) * slab_el, !last, upd_q, s,
-                                           TD);
+                T* wout = last ? nullptr : K + (size_t)(n + 1) * slab_el;
+                return local && sparse
+                    ? mar::launch_upd2_list<T>(B, K, M, stride, n, cAT, cBT, gam, Fn, Y, wout, !last, slist, sDl,
+                                               scnt, n + 1, kListWgs, s)
+                    : mar::launch_upd2<T>(B, K, M, stride, n, cAT, cBT, gam, Fn, Y, wout, !last, upd_q, s, TD);
             });
             tag(ru, last ? SP_UPD2_LAST : SP_UPD2, n, bi, (double)ntiles);
             if (last) break;

@@ -163,6 +163,24 @@ template <typename T>
 LaunchInfo launch_spmm2(int B, const DevMat& H, const DevMat& SH, const T* X, T* Y, T* Z, double* part, int ndot,
                         int64_t part_cap, hipStream_t s, const int32_t* tdist = nullptr, int lim = 0,
                         const uint32_t* mask = nullptr, int W = 0);
+// Local regions: the dual product, S y and the update over the row tiles of the support list (entries
+// [0, cnt[lim])) in a grid-stride loop of `grid` workgroups; spmm2 partials are per workgroup (grid slots).
+template <typename T>
+LaunchInfo launch_spmm2_list(int B, const DevMat& H, const DevMat& SH, const T* X, T* Y, T* Z, double* part,
+                             int ndot, int64_t part_cap, const int32_t* list, const int32_t* cnt, int lim,
+                             const uint32_t* mask, int W, int64_t grid, hipStream_t s);
+template <typename T>
+LaunchInfo launch_spmm_list(int B, const DevMat& A, const T* X, T* Y, const int32_t* list, const int32_t* cnt,
+                            int lim, const uint32_t* mask, int W, int64_t grid, hipStream_t s);
+template <typename T>
+LaunchInfo launch_upd2_list(int B, T* basis, int64_t M, int64_t stride, int n, const T* cA, const T* cB,
+                            const double* gam, const double* Fn, const T* y, T* wout, bool want_w,
+                            const int32_t* list, const int32_t* Dl, const int32_t* cnt, int lim, int64_t grid,
+                            hipStream_t s);
+// Zero the row tiles within hmax + 1 hops of a block's seeds (one more BFS level on dist, which holds the levels
+// up to hmax) in nsl slabs of slab_bytes from base and in y; tiles are 4 * WG vectors of 16 bytes, nvec per slab.
+LaunchInfo launch_zero_ring(int64_t nbrow, const int32_t* brp, const int32_t* bcol, int32_t* dist, int hmax,
+                            int bpt, void* base, int64_t slab_bytes, int nsl, void* y, int64_t nvec, hipStream_t s);
 // Delayed-reorthogonalization schedule.
 // Projection sweep (variants as in projr_geometry); target_wgs > 0.
 template <typename T>

@@ -47,6 +47,74 @@ __global__ __launch_bounds__(WG) void k_init(int64_t Mp, int64_t M, const int32_
     reinterpret_cast<VT*>(K0)[vi] = pack(a);
 }
 
+// Local regions: zero the products of the seeds whose region leaves out block row I.
+template <typename T, int SW>
+__device__ __forceinline__ void region_mask(const uint32_t* __restrict__ mask, int W, int64_t I, int s0,
+                                            T (&acc)[4][SW]) {
+    const uint32_t bits = mask[I * W + s0 / 32] >> (s0 % 32);
+#pragma unroll
+    for (int i = 0; i < SW; ++i)
+        if (!((bits >> i) & 1u))
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[r][i] = (T)0;
+}
+
+// Block row Iu of Y = A X for the seeds s0 .. s0 + VEC - 1 (B >= VEC): the
+// row's blocks are taken CH at a time, all indices, X vectors and values of a
+// chunk requested before any is used; acc must start at zero.
+template <typename T, int B, int CH>
+__device__ __forceinline__ void spmm_row_vec(int64_t Iu, int s0, const int32_t* __restrict__ brp,
+                                             const int32_t* __restrict__ bcol, const T* __restrict__ bval,
+                                             const typename Vec16<T>::type* __restrict__ Xv,
+                                             T (&acc)[4][SeedMap<T, B>::SW]) {
+    using SM = SeedMap<T, B>;
+    constexpr int VEC = SM::VEC, SW = SM::SW;
+    using VT = typename Vec16<T>::type;
+    const int lo = brp[Iu], hi = brp[Iu + 1];
+    for (int b0 = lo; b0 < hi; b0 += CH) {
+        int blk[CH];
+        int64_t J[CH];
+#pragma unroll
+        for (int t = 0; t < CH; ++t) {
+            blk[t] = b0 + t < hi ? b0 + t : hi - 1;   // repeats the last block; its sum is skipped
+            J[t] = bcol[blk[t]];
+        }
+        T xv[CH][4][VEC];
+#pragma unroll
+        for (int t = 0; t < CH; ++t)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) unpack(Xv[((4 * J[t] + c) * B + s0) / VEC], xv[t][c]);
+        T a[CH][16];
+#pragma unroll
+        for (int t = 0; t < CH; ++t) {
+            const VT* av = reinterpret_cast<const VT*>(bval + (int64_t)blk[t] * 16);
+#pragma unroll
+            for (int q = 0; q < 16 / VEC; ++q) {
+                T u[VEC];
+                unpack(av[q], u);
+#pragma unroll
+                for (int i = 0; i < VEC; ++i) a[t][q * VEC + i] = u[i];
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < CH; ++t) {
+            if (b0 + t < hi) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int i = 0; i < SW; ++i) {
+                        T sacc = acc[r][i];
+                        sacc = fma(a[t][r * 4 + 0], xv[t][0][i], sacc);
+                        sacc = fma(a[t][r * 4 + 1], xv[t][1][i], sacc);
+                        sacc = fma(a[t][r * 4 + 2], xv[t][2][i], sacc);
+                        sacc = fma(a[t][r * 4 + 3], xv[t][3][i], sacc);
+                        acc[r][i] = sacc;
+                    }
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Y = A X over B seed-interleaved vectors, A in BSR 4x4. Thread = (block row,
 // seed group). The 16 block values are read once per thread and reused for
@@ -89,57 +157,8 @@ __global__ __launch_bounds__(WG) void k_spmm_bsr4(int64_t nbrow, const int32_t* 
         int64_t Iu = I;
         if constexpr (P == 64) Iu = __builtin_amdgcn_readfirstlane((int)I);   // one row per wavefront
         if (Iu < nbrow) {
-            const int lo = brp[Iu], hi = brp[Iu + 1];
-            for (int b0 = lo; b0 < hi; b0 += CH) {
-                int blk[CH];
-                int64_t J[CH];
-#pragma unroll
-                for (int t = 0; t < CH; ++t) {
-                    blk[t] = b0 + t < hi ? b0 + t : hi - 1;   // repeats the last block; its sum is skipped
-                    J[t] = bcol[blk[t]];
-                }
-                T xv[CH][4][VEC];
-#pragma unroll
-                for (int t = 0; t < CH; ++t)
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) unpack(Xv[((4 * J[t] + c) * B + s0) / VEC], xv[t][c]);
-                T a[CH][16];
-#pragma unroll
-                for (int t = 0; t < CH; ++t) {
-                    const VT* av = reinterpret_cast<const VT*>(bval + (int64_t)blk[t] * 16);
-#pragma unroll
-                    for (int q = 0; q < 16 / VEC; ++q) {
-                        T u[VEC];
-                        unpack(av[q], u);
-#pragma unroll
-                        for (int i = 0; i < VEC; ++i) a[t][q * VEC + i] = u[i];
-                    }
-                }
-#pragma unroll
-                for (int t = 0; t < CH; ++t) {
-                    if (b0 + t < hi) {
-#pragma unroll
-                        for (int r = 0; r < 4; ++r)
-#pragma unroll
-                            for (int i = 0; i < SW; ++i) {
-                                T sacc = acc[r][i];
-                                sacc = fma(a[t][r * 4 + 0], xv[t][0][i], sacc);
-                                sacc = fma(a[t][r * 4 + 1], xv[t][1][i], sacc);
-                                sacc = fma(a[t][r * 4 + 2], xv[t][2][i], sacc);
-                                sacc = fma(a[t][r * 4 + 3], xv[t][3][i], sacc);
-                                acc[r][i] = sacc;
-                            }
-                    }
-                }
-            }
-            if (mask != nullptr) {   // local regions: keep the rows inside each seed's region
-                const uint32_t bits = mask[Iu * W + s0 / 32] >> (s0 % 32);
-#pragma unroll
-                for (int i = 0; i < SW; ++i)
-                    if (!((bits >> i) & 1u))
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) acc[r][i] = (T)0;
-            }
+            spmm_row_vec<T, B, CH>(Iu, s0, brp, bcol, bval, Xv, acc);
+            if (mask != nullptr) region_mask<T, SW>(mask, W, Iu, s0, acc);   // local regions
             VT* Yv = reinterpret_cast<VT*>(Y);
 #pragma unroll
             for (int r = 0; r < 4; ++r) Yv[((4 * Iu + r) * B + s0) / VEC] = pack(acc[r]);
@@ -221,10 +240,104 @@ __global__ __launch_bounds__(WG) void k_spmm_bsr4(int64_t nbrow, const int32_t* 
     }
 }
 
-// Y = A X with A in CSR (patterns without 4x4 block structure). Thread = (row, seed group).
+// Block row Iu of Y = H X and Z = S X for the seeds s0 .. s0 + VEC - 1,
+// masked to the seeds' regions when mask != nullptr, stored; the S-norm
+// partials X.(S X) and X.X of the row are added to d (NDOT > 0).
+template <typename T, int B, int NDOT>
+__device__ __forceinline__ void spmm2_row(int64_t Iu, int s0, const int32_t* __restrict__ brp,
+                                          const int32_t* __restrict__ bcol, const T* __restrict__ hval,
+                                          const T* __restrict__ sval, const typename Vec16<T>::type* __restrict__ Xv,
+                                          T* __restrict__ Y, T* __restrict__ Z, const uint32_t* __restrict__ mask,
+                                          int W, double (&d)[NDOT > 0 ? NDOT : 1][SeedMap<T, B>::SW]) {
+    using SM = SeedMap<T, B>;
+    constexpr int VEC = SM::VEC, SW = SM::SW;
+    using VT = typename Vec16<T>::type;
+    constexpr int CH = 2;   // blocks in flight per row (two value sets per block)
+    T ah[4][SW], as[4][SW];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int i = 0; i < SW; ++i) ah[r][i] = as[r][i] = (T)0;
+    const int lo = brp[Iu], hi = brp[Iu + 1];
+    for (int b0 = lo; b0 < hi; b0 += CH) {
+        int blk[CH];
+        int64_t J[CH];
+#pragma unroll
+        for (int t = 0; t < CH; ++t) {
+            blk[t] = b0 + t < hi ? b0 + t : hi - 1;   // repeats the last block; its sum is skipped
+            J[t] = bcol[blk[t]];
+        }
+        T xv[CH][4][VEC];
+#pragma unroll
+        for (int t = 0; t < CH; ++t)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) unpack(Xv[((4 * J[t] + c) * B + s0) / VEC], xv[t][c]);
+        T hv[CH][16], sv[CH][16];
+#pragma unroll
+        for (int t = 0; t < CH; ++t) {
+            const VT* hp = reinterpret_cast<const VT*>(hval + (int64_t)blk[t] * 16);
+            const VT* sp = reinterpret_cast<const VT*>(sval + (int64_t)blk[t] * 16);
+#pragma unroll
+            for (int q = 0; q < 16 / VEC; ++q) {
+                T u[VEC], w[VEC];
+                unpack(hp[q], u);
+                unpack(sp[q], w);
+#pragma unroll
+                for (int i = 0; i < VEC; ++i) {
+                    hv[t][q * VEC + i] = u[i];
+                    sv[t][q * VEC + i] = w[i];
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < CH; ++t) {
+            if (b0 + t < hi) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int i = 0; i < SW; ++i) {
+                        T h = ah[r][i], z = as[r][i];
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            h = fma(hv[t][r * 4 + c], xv[t][c][i], h);
+                            z = fma(sv[t][r * 4 + c], xv[t][c][i], z);
+                        }
+                        ah[r][i] = h;
+                        as[r][i] = z;
+                    }
+            }
+        }
+    }
+    if (mask != nullptr) {
+        region_mask<T, SW>(mask, W, Iu, s0, ah);
+        region_mask<T, SW>(mask, W, Iu, s0, as);
+    }
+    VT* Yv = reinterpret_cast<VT*>(Y);
+    VT* Zv = reinterpret_cast<VT*>(Z);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        Yv[((4 * Iu + r) * B + s0) / VEC] = pack(ah[r]);
+        Zv[((4 * Iu + r) * B + s0) / VEC] = pack(as[r]);
+    }
+    if constexpr (NDOT > 0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            T xr[SW];
+            unpack(Xv[((4 * Iu + r) * B + s0) / VEC], xr);
+#pragma unroll
+            for (int i = 0; i < SW; ++i) {
+                const double xd = (double)xr[i];
+                d[0][i] += xd * (double)as[r][i];
+                if constexpr (NDOT > 1) d[1][i] += xd * xd;
+            }
+        }
+    }
+}
+
 // Y = H X and Z = S X in one pass over X, for S stored on H's block pattern
 // (zero blocks where S has none); B >= VEC only. NDOT as in k_spmm_bsr4, with
-// the products taken against Z: X.(S X) and X.X per seed.
+// the products taken against Z: X.(S X) and X.X per seed. One row tile of
+// WG / P block rows per workgroup; tiles with tdist > lim are skipped.
 template <typename T, int B, int NDOT>
 __global__ __launch_bounds__(WG) void k_spmm2_bsr4(int64_t nbrow, const int32_t* __restrict__ brp,
                                                    const int32_t* __restrict__ bcol, const T* __restrict__ hval,
@@ -236,115 +349,95 @@ __global__ __launch_bounds__(WG) void k_spmm2_bsr4(int64_t nbrow, const int32_t*
     constexpr int VEC = SM::VEC, SW = SM::SW, P = SM::P;
     static_assert(B >= VEC, "dual product needs one seed group per lane");
     using VT = typename Vec16<T>::type;
-    constexpr int CH = 2;   // blocks in flight per row (two value sets per block)
     const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
     if (tdist != nullptr && tdist[bid] > lim) {   // a tile outside the support
         if constexpr (NDOT > 0)
             for (int i = threadIdx.x; i < NDOT * B; i += WG) part[bid * NDOT * B + i] = 0.0;
         return;
     }
-    const int64_t g = bid * WG + threadIdx.x;
-    const int64_t I = g / P;
     const int s0 = (threadIdx.x % P) * VEC;
     const VT* Xv = reinterpret_cast<const VT*>(X);
-    T ah[4][SW], as[4][SW];
+    double d[NDOT > 0 ? NDOT : 1][SW];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int v = 0; v < (NDOT > 0 ? NDOT : 1); ++v)
 #pragma unroll
-        for (int i = 0; i < SW; ++i) ah[r][i] = as[r][i] = (T)0;
-    int64_t Iu = I;
-    if constexpr (P == 64) Iu = __builtin_amdgcn_readfirstlane((int)I);   // one row per wavefront
-    if (Iu < nbrow) {
-        const int lo = brp[Iu], hi = brp[Iu + 1];
-        for (int b0 = lo; b0 < hi; b0 += CH) {
-            int blk[CH];
-            int64_t J[CH];
-#pragma unroll
-            for (int t = 0; t < CH; ++t) {
-                blk[t] = b0 + t < hi ? b0 + t : hi - 1;   // repeats the last block; its sum is skipped
-                J[t] = bcol[blk[t]];
-            }
-            T xv[CH][4][VEC];
-#pragma unroll
-            for (int t = 0; t < CH; ++t)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) unpack(Xv[((4 * J[t] + c) * B + s0) / VEC], xv[t][c]);
-            T hv[CH][16], sv[CH][16];
-#pragma unroll
-            for (int t = 0; t < CH; ++t) {
-                const VT* hp = reinterpret_cast<const VT*>(hval + (int64_t)blk[t] * 16);
-                const VT* sp = reinterpret_cast<const VT*>(sval + (int64_t)blk[t] * 16);
-#pragma unroll
-                for (int q = 0; q < 16 / VEC; ++q) {
-                    T u[VEC], w[VEC];
-                    unpack(hp[q], u);
-                    unpack(sp[q], w);
-#pragma unroll
-                    for (int i = 0; i < VEC; ++i) {
-                        hv[t][q * VEC + i] = u[i];
-                        sv[t][q * VEC + i] = w[i];
-                    }
-                }
-            }
-#pragma unroll
-            for (int t = 0; t < CH; ++t) {
-                if (b0 + t < hi) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-#pragma unroll
-                        for (int i = 0; i < SW; ++i) {
-                            T h = ah[r][i], z = as[r][i];
-#pragma unroll
-                            for (int c = 0; c < 4; ++c) {
-                                h = fma(hv[t][r * 4 + c], xv[t][c][i], h);
-                                z = fma(sv[t][r * 4 + c], xv[t][c][i], z);
-                            }
-                            ah[r][i] = h;
-                            as[r][i] = z;
-                        }
-                }
-            }
-        }
-        if (mask != nullptr) {   // local regions: keep the rows inside each seed's region
-            const uint32_t bits = mask[Iu * W + s0 / 32] >> (s0 % 32);
-#pragma unroll
-            for (int i = 0; i < SW; ++i)
-                if (!((bits >> i) & 1u))
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) ah[r][i] = as[r][i] = (T)0;
-        }
-        VT* Yv = reinterpret_cast<VT*>(Y);
-        VT* Zv = reinterpret_cast<VT*>(Z);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            Yv[((4 * Iu + r) * B + s0) / VEC] = pack(ah[r]);
-            Zv[((4 * Iu + r) * B + s0) / VEC] = pack(as[r]);
-        }
-    }
+        for (int i = 0; i < SW; ++i) d[v][i] = 0.0;
+    int64_t Iu = (bid * WG + threadIdx.x) / P;
+    if constexpr (P == 64) Iu = __builtin_amdgcn_readfirstlane((int)Iu);   // one row per wavefront
+    if (Iu < nbrow) spmm2_row<T, B, NDOT>(Iu, s0, brp, bcol, hval, sval, Xv, Y, Z, mask, W, d);
     if constexpr (NDOT > 0) {
-        double d[NDOT][SW];
-#pragma unroll
-        for (int v = 0; v < NDOT; ++v)
-#pragma unroll
-            for (int i = 0; i < SW; ++i) d[v][i] = 0.0;
-        if (I < nbrow) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                T xr[SW];
-                unpack(Xv[((4 * I + r) * B + s0) / VEC], xr);
-#pragma unroll
-                for (int i = 0; i < SW; ++i) {
-                    const double xd = (double)xr[i];
-                    d[0][i] += xd * (double)as[r][i];
-                    if constexpr (NDOT > 1) d[1][i] += xd * xd;
-                }
-            }
-        }
         __shared__ double lds[SeedReduce<P, SW, NDOT>::LDS];
         wg_seed_reduce<P, SW, NDOT>(d, lds, [&](int v, int b, double sdot) { part[(bid * NDOT + v) * B + b] = sdot; });
     }
 }
 
+// The same product over the row tiles of a list (local regions): entries
+// [0, cnt[lim]) in a grid-stride loop; partials per workgroup, part[wg][d][b].
+template <typename T, int B, int NDOT>
+__global__ __launch_bounds__(WG) void k_spmm2_list(int64_t nbrow, const int32_t* __restrict__ brp,
+                                                   const int32_t* __restrict__ bcol, const T* __restrict__ hval,
+                                                   const T* __restrict__ sval, const T* __restrict__ X,
+                                                   T* __restrict__ Y, T* __restrict__ Z, double* __restrict__ part,
+                                                   const int32_t* __restrict__ list, const int32_t* __restrict__ cnt,
+                                                   int lim, const uint32_t* __restrict__ mask, int W) {
+    using SM = SeedMap<T, B>;
+    constexpr int VEC = SM::VEC, SW = SM::SW, P = SM::P;
+    static_assert(B >= VEC, "dual product needs one seed group per lane");
+    using VT = typename Vec16<T>::type;
+    const int s0 = (threadIdx.x % P) * VEC;
+    const VT* Xv = reinterpret_cast<const VT*>(X);
+    double d[NDOT > 0 ? NDOT : 1][SW];
+#pragma unroll
+    for (int v = 0; v < (NDOT > 0 ? NDOT : 1); ++v)
+#pragma unroll
+        for (int i = 0; i < SW; ++i) d[v][i] = 0.0;
+    const int64_t ce = cnt[lim];
+    for (int64_t e = blockIdx.x; e < ce; e += gridDim.x) {
+        int64_t Iu = ((int64_t)list[e] * WG + threadIdx.x) / P;
+        if constexpr (P == 64) Iu = __builtin_amdgcn_readfirstlane((int)Iu);
+        if (Iu < nbrow) spmm2_row<T, B, NDOT>(Iu, s0, brp, bcol, hval, sval, Xv, Y, Z, mask, W, d);
+    }
+    if constexpr (NDOT > 0) {
+        __shared__ double lds[SeedReduce<P, SW, NDOT>::LDS];
+        wg_seed_reduce<P, SW, NDOT>(d, lds, [&](int v, int b, double sdot) {
+            part[((int64_t)blockIdx.x * NDOT + v) * B + b] = sdot;
+        });
+    }
+}
+
+// Y = A X on the row tiles of a list (local regions), no partials.
+template <typename T, int B>
+__global__ __launch_bounds__(WG) void k_spmm_list(int64_t nbrow, const int32_t* __restrict__ brp,
+                                                  const int32_t* __restrict__ bcol, const T* __restrict__ bval,
+                                                  const T* __restrict__ X, T* __restrict__ Y,
+                                                  const int32_t* __restrict__ list, const int32_t* __restrict__ cnt,
+                                                  int lim, const uint32_t* __restrict__ mask, int W) {
+    using SM = SeedMap<T, B>;
+    constexpr int VEC = SM::VEC, SW = SM::SW, P = SM::P;
+    static_assert(B >= VEC, "one seed group per lane");
+    using VT = typename Vec16<T>::type;
+    constexpr int CH = P == 64 ? 4 : 2;
+    const int s0 = (threadIdx.x % P) * VEC;
+    const VT* Xv = reinterpret_cast<const VT*>(X);
+    VT* Yv = reinterpret_cast<VT*>(Y);
+    const int64_t ce = cnt[lim];
+    for (int64_t e = blockIdx.x; e < ce; e += gridDim.x) {
+        int64_t Iu = ((int64_t)list[e] * WG + threadIdx.x) / P;
+        if constexpr (P == 64) Iu = __builtin_amdgcn_readfirstlane((int)Iu);
+        if (Iu >= nbrow) continue;
+        T acc[4][SW];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int i = 0; i < SW; ++i) acc[r][i] = (T)0;
+        spmm_row_vec<T, B, CH>(Iu, s0, brp, bcol, bval, Xv, acc);
+        if (mask != nullptr) region_mask<T, SW>(mask, W, Iu, s0, acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Yv[((4 * Iu + r) * B + s0) / VEC] = pack(acc[r]);
+    }
+}
+
+// Y = A X with A in CSR (patterns without 4x4 block structure). Thread = (row, seed group).
 template <typename T, int B, int NDOT>
 __global__ __launch_bounds__(WG) void k_spmm_csr(int64_t nrow, const int32_t* __restrict__ rp,
                                                  const int32_t* __restrict__ col, const T* __restrict__ val,
@@ -777,37 +870,17 @@ __global__ __launch_bounds__(WG) void k_es_pdot(const T* __restrict__ basis, int
     wg_seed_reduce<P, SW, 1>(acc, lds, [&](int, int b, double sum) { part[((int64_t)g * nk + k) * B + b] = sum; });
 }
 
-// Dual update of the delayed schedule, one pass over slabs 0..n-1:
-//   u_n = (u~ - sum_k K_k cA_k) / gamma       (second Gram-Schmidt pass of u~)
-//   w'  = (y  - sum_k K_k cB_k - u_n F_n) / gamma   (first pass of y = H u~)
-// u~ is slab n and is overwritten by u_n; w' goes to wout (WANT_W), the next
-// slab, unnormalized. The slab may hold u~ times a per-seed scale s and y
-// times the same s: the caller passes s cA, s cB, s F_n and s gamma.
-// The coefficients are [k][B] in the basis precision: one 16-byte load per
-// lane and slab for each of cA, cB when B >= VEC.
+// One chunk of WG * Q vectors starting at v0, slabs from kst on (the slabs
+// below kst are zero on these rows).
 template <typename T, int B, int Q, bool WANT_W>
-__global__ __launch_bounds__(WG) void k_upd2(T* __restrict__ basis, int64_t slab, int n, const T* __restrict__ cA,
-                                             const T* __restrict__ cB, const double* __restrict__ gam,
-                                             const double* __restrict__ Fn, const T* __restrict__ y,
-                                             T* __restrict__ wout, int64_t nvec, const int32_t* __restrict__ tdist,
-                                             int64_t ntiles) {
+__device__ __forceinline__ void upd2_chunk(int64_t v0, int kst, T* __restrict__ basis, int64_t slab, int n,
+                                           const T* __restrict__ cA, const T* __restrict__ cB,
+                                           const double* __restrict__ gam, const double* __restrict__ Fn,
+                                           const T* __restrict__ y, T* __restrict__ wout, int64_t nvec) {
     using SM = SeedMap<T, B>;
     constexpr int VEC = SM::VEC, P = SM::P;
     using VT = typename Vec16<T>::type;
     const int tid = threadIdx.x;
-    // Support: the workgroup's vectors lie in at most two tiles of 4 * WG
-    // vectors (Q <= 8). Nothing to do beyond distance n + 1; slabs below the
-    // smaller distance are zero on these rows.
-    int kst = 0;
-    if (tdist != nullptr) {
-        const int64_t v0 = (int64_t)blockIdx.x * (WG * Q);
-        const int64_t t0 = v0 / (4 * WG);
-        int64_t t1 = (v0 + WG * Q - 1) / (4 * WG);
-        t1 = t1 < ntiles ? t1 : ntiles - 1;
-        const int dm = min(tdist[t0], tdist[t1]);
-        if (dm > n + 1) return;
-        kst = min(dm, n);
-    }
     const int64_t slabv = slab / VEC;
     const int sb = (B < VEC) ? 0 : (tid % P) * VEC;
     VT* bv = reinterpret_cast<VT*>(basis);
@@ -820,7 +893,7 @@ __global__ __launch_bounds__(WG) void k_upd2(T* __restrict__ basis, int64_t slab
         g[i] = (T)gam[b];
         fn[i] = (T)Fn[b];
     }
-    const int64_t vbase = (int64_t)blockIdx.x * (WG * Q) + tid;
+    const int64_t vbase = v0 + tid;
     T au[Q][VEC], aw[Q][VEC];
     int64_t vsq[Q];  // always-valid load indices (lanes past nvec read vector 0 and store nothing)
 #pragma unroll
@@ -865,6 +938,54 @@ __global__ __launch_bounds__(WG) void k_upd2(T* __restrict__ basis, int64_t slab
             bv[(int64_t)n * slabv + vi] = pack(au[q]);
             if constexpr (WANT_W) wv[vi] = pack(aw[q]);
         }
+    }
+}
+
+// Dual update of the delayed schedule, one pass over slabs 0..n-1:
+//   u_n = (u~ - sum_k K_k cA_k) / gamma       (second Gram-Schmidt pass of u~)
+//   w'  = (y  - sum_k K_k cB_k - u_n F_n) / gamma   (first pass of y = H u~)
+// u~ is slab n and is overwritten by u_n; w' goes to wout (WANT_W), the next
+// slab, unnormalized. The slab may hold u~ times a per-seed scale s and y
+// times the same s: the caller passes s cA, s cB, s F_n and s gamma.
+// The coefficients are [k][B] in the basis precision: one 16-byte load per
+// lane and slab for each of cA, cB when B >= VEC. One chunk of WG * Q
+// vectors per workgroup.
+template <typename T, int B, int Q, bool WANT_W>
+__global__ __launch_bounds__(WG) void k_upd2(T* __restrict__ basis, int64_t slab, int n, const T* __restrict__ cA,
+                                             const T* __restrict__ cB, const double* __restrict__ gam,
+                                             const double* __restrict__ Fn, const T* __restrict__ y,
+                                             T* __restrict__ wout, int64_t nvec, const int32_t* __restrict__ tdist,
+                                             int64_t ntiles) {
+    // Support: the workgroup's vectors lie in at most two tiles of 4 * WG
+    // vectors (Q <= 8). Nothing to do beyond distance n + 1; slabs below the
+    // smaller distance are zero on these rows.
+    const int64_t v0 = (int64_t)blockIdx.x * (WG * Q);
+    int kst = 0;
+    if (tdist != nullptr) {
+        const int64_t t0 = v0 / (4 * WG);
+        int64_t t1 = (v0 + WG * Q - 1) / (4 * WG);
+        t1 = t1 < ntiles ? t1 : ntiles - 1;
+        const int dm = min(tdist[t0], tdist[t1]);
+        if (dm > n + 1) return;
+        kst = min(dm, n);
+    }
+    upd2_chunk<T, B, Q, WANT_W>(v0, kst, basis, slab, n, cA, cB, gam, Fn, y, wout, nvec);
+}
+
+// The same update over the row tiles of a list (local regions): entries
+// [0, cnt[min(n + 1, hcnt)]) in a grid-stride loop, one tile of 4 * WG vectors
+// per step, its slab loop starting at the tile's distance Dl.
+template <typename T, int B, bool WANT_W>
+__global__ __launch_bounds__(WG) void k_upd2_list(T* __restrict__ basis, int64_t slab, int n,
+                                                  const T* __restrict__ cA, const T* __restrict__ cB,
+                                                  const double* __restrict__ gam, const double* __restrict__ Fn,
+                                                  const T* __restrict__ y, T* __restrict__ wout, int64_t nvec,
+                                                  const int32_t* __restrict__ list, const int32_t* __restrict__ Dl,
+                                                  const int32_t* __restrict__ cnt, int lim) {
+    const int64_t ce = cnt[lim];
+    for (int64_t e = blockIdx.x; e < ce; e += gridDim.x) {
+        const int64_t t = list[e];
+        upd2_chunk<T, B, 4, WANT_W>(t * (4 * WG), min(Dl[e], n), basis, slab, n, cA, cB, gam, Fn, y, wout, nvec);
     }
 }
 
@@ -963,6 +1084,50 @@ LaunchInfo launch_spmm2<MAR_T>(int B, const DevMat& H, const DevMat& SH, const M
     li.bytes = (double)H.nnz * (2.0 * 16.0 * sizeof(MAR_T) + 4.0) + (double)(H.n + 1) * 4.0 +
                3.0 * (double)(4 * H.n) * B * sizeof(MAR_T);
     li.flops = 4.0 * (double)H.nnz * 16.0 * B;
+    return li;
+}
+
+template <>
+LaunchInfo launch_spmm2_list<MAR_T>(int B, const DevMat& H, const DevMat& SH, const MAR_T* X, MAR_T* Y, MAR_T* Z,
+                                    double* part, int ndot, int64_t part_cap, const int32_t* list, const int32_t* cnt,
+                                    int lim, const uint32_t* mask, int W, int64_t grid, hipStream_t s) {
+    constexpr int VEC = Vec16<MAR_T>::n;
+    LaunchInfo li;
+    if (!H.bsr || B < VEC || SH.nnz != H.nnz || (ndot > 0 && grid * ndot * B > part_cap)) {
+        li.wgs = -1;
+        return li;
+    }
+    const bool f32 = std::is_same<MAR_T, float>::value;
+    const MAR_T* hv = f32 ? (const MAR_T*)H.v32 : (const MAR_T*)H.v64;
+    const MAR_T* sv = f32 ? (const MAR_T*)SH.v32 : (const MAR_T*)SH.v64;
+#define MAR_SPMM2L(ND) \
+    MAR_DISPATCH_B(B, if constexpr (BB >= VEC) hipLaunchKernelGGL((k_spmm2_list<MAR_T, BB, ND>), dim3((unsigned)grid), dim3(WG), 0, s, H.n, H.ptr, H.idx, hv, sv, X, Y, Z, part, list, cnt, lim, mask, W))
+    if (ndot == 2) { MAR_SPMM2L(2); }
+    else if (ndot == 1) { MAR_SPMM2L(1); }
+    else { MAR_SPMM2L(0); }
+#undef MAR_SPMM2L
+    li.wgs = grid;
+    li.bytes = (double)H.nnz * (2.0 * 16.0 * sizeof(MAR_T) + 4.0) + (double)(H.n + 1) * 4.0 +
+               3.0 * (double)(4 * H.n) * B * sizeof(MAR_T);
+    li.flops = 4.0 * (double)H.nnz * 16.0 * B;
+    return li;
+}
+
+template <>
+LaunchInfo launch_spmm_list<MAR_T>(int B, const DevMat& A, const MAR_T* X, MAR_T* Y, const int32_t* list,
+                                   const int32_t* cnt, int lim, const uint32_t* mask, int W, int64_t grid,
+                                   hipStream_t s) {
+    constexpr int VEC = Vec16<MAR_T>::n;
+    LaunchInfo li;
+    if (!A.bsr || B < VEC) {
+        li.wgs = -1;
+        return li;
+    }
+    const MAR_T* val = std::is_same<MAR_T, float>::value ? (const MAR_T*)A.v32 : (const MAR_T*)A.v64;
+    MAR_DISPATCH_B(B, if constexpr (BB >= VEC) hipLaunchKernelGGL((k_spmm_list<MAR_T, BB>), dim3((unsigned)grid), dim3(WG), 0, s, A.n, A.ptr, A.idx, val, X, Y, list, cnt, lim, mask, W))
+    li.wgs = grid;
+    li.bytes = A.bytes_per_pass(sizeof(MAR_T)) + 2.0 * (double)(4 * A.n) * B * sizeof(MAR_T);
+    li.flops = 2.0 * (double)A.nnz * 16.0 * B;
     return li;
 }
 
@@ -1129,6 +1294,29 @@ LaunchInfo launch_es_pdot<MAR_T>(int B, const MAR_T* K, int64_t stride, int64_t 
     li.wgs = (int64_t)groups * nu;
     li.bytes = (double)nu * Mp * B * sizeof(MAR_T) + (double)M * 8.0;
     li.flops = 2.0 * nu * (double)Mp * B;
+    return li;
+}
+
+template <>
+LaunchInfo launch_upd2_list<MAR_T>(int B, MAR_T* basis, int64_t M, int64_t stride, int n, const MAR_T* cA,
+                                   const MAR_T* cB, const double* gam, const double* Fn, const MAR_T* y, MAR_T* wout,
+                                   bool want_w, const int32_t* list, const int32_t* Dl, const int32_t* cnt, int lim,
+                                   int64_t grid, hipStream_t s) {
+    constexpr int VEC = Vec16<MAR_T>::n;
+    const int64_t nvec = M * B / VEC;
+    LaunchInfo li;
+    if (B < VEC) {
+        li.wgs = -1;
+        return li;
+    }
+#define MAR_UPD2L(WW) \
+    MAR_DISPATCH_B(B, if constexpr (BB >= VEC) hipLaunchKernelGGL((k_upd2_list<MAR_T, BB, WW>), dim3((unsigned)grid), dim3(WG), 0, s, basis, stride, n, cA, cB, gam, Fn, y, wout, nvec, list, Dl, cnt, lim))
+    if (want_w) { MAR_UPD2L(true); } else { MAR_UPD2L(false); }
+#undef MAR_UPD2L
+    li.wgs = grid;
+    const double slabs_read = (double)n + (want_w ? 2.0 : 1.0), slabs_written = want_w ? 2.0 : 1.0;
+    li.bytes = (slabs_read + slabs_written) * (double)(M * B) * sizeof(MAR_T);
+    li.flops = (want_w ? 4.0 : 2.0) * n * (double)(M * B);
     return li;
 }
 

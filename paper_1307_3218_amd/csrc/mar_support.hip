@@ -227,6 +227,38 @@ __global__ __launch_bounds__(WG) void k_projr_plan(const int32_t* __restrict__ c
     }
 }
 
+// Zero every row tile (4 * WG vectors of 16 bytes) whose nearest block row is
+// within lim hops, in nsl slabs and in y; one workgroup per tile.
+__global__ __launch_bounds__(WG) void k_zero_tiles(int64_t nbrow, int bpt, const int32_t* __restrict__ dist, int lim,
+                                                   double2* __restrict__ base, int64_t slab_v, int nsl,
+                                                   double2* __restrict__ y, int64_t nvec) {
+    const int64_t t = blockIdx.x;
+    const int64_t I0 = t * bpt, I1 = I0 + bpt < nbrow ? I0 + bpt : nbrow;
+    int m = SUP_FAR;
+    for (int64_t I = I0; I < I1; ++I) m = min(m, dist[I]);
+    if (m > lim) return;
+    const double2 z = make_double2(0.0, 0.0);
+    for (int q = 0; q < 4; ++q) {
+        const int64_t vi = t * (4 * WG) + q * WG + threadIdx.x;
+        if (vi >= nvec) continue;
+        for (int sl = 0; sl < nsl; ++sl) base[sl * slab_v + vi] = z;
+        y[vi] = z;
+    }
+}
+
+LaunchInfo launch_zero_ring(int64_t nbrow, const int32_t* brp, const int32_t* bcol, int32_t* dist, int hmax,
+                            int bpt, void* base, int64_t slab_bytes, int nsl, void* y, int64_t nvec, hipStream_t s) {
+    const unsigned rw = (unsigned)((nbrow + WG - 1) / WG);
+    const int64_t ntiles = (nbrow + bpt - 1) / bpt;
+    hipLaunchKernelGGL(k_sup_hop, dim3(rw), dim3(WG), 0, s, nbrow, brp, bcol, dist, hmax + 1);
+    hipLaunchKernelGGL(k_zero_tiles, dim3((unsigned)ntiles), dim3(WG), 0, s, nbrow, bpt, dist, hmax + 1,
+                       (double2*)base, slab_bytes / 16, nsl, (double2*)y, nvec);
+    LaunchInfo li;
+    li.wgs = ntiles;
+    li.bytes = (double)nbrow * 8.0;
+    return li;
+}
+
 // Local regions (order-N form): bit b of mask[I * W + b / 32] is set when block
 // row I lies within r hops of the block of seed b. k_loc_seed marks the seeds'
 // own blocks; each k_loc_hop adds the blocks one hop further (from a separate
