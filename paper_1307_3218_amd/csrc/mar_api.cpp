@@ -73,6 +73,7 @@ struct mar_ctx {
     int max_row = 0;
     int n_cu = 1;             // compute units of the device
     bool dry = false;         // size and allocate the workspace only; launch nothing
+    bool in_graph = false;    // sizing or capturing a mar_solve_many graph (one stream per system there)
     // projection workgroups per compute unit, by (element bytes, B, variant)
     std::map<std::tuple<int, int, int>, int> occ;
     // autotuned (B, projection variant) by (nu, precision)
@@ -102,6 +103,8 @@ struct mar_ctx {
     char* io = nullptr;
     size_t io_bytes = 0;
     hipStream_t stream = nullptr;
+    hipStream_t stream2 = nullptr;   // second seed-block stream of the batched form (non-blocking)
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::string err;
     bool prof = false;
     bool refused = false;   // a launcher refused to run in the current solve
@@ -124,6 +127,9 @@ struct mar_ctx {
         if (fws) hipFree(fws);
         if (flws) hipFree(flws);
         if (stream) hipStreamDestroy(stream);
+        if (stream2) hipStreamDestroy(stream2);
+        if (ev_fork) hipEventDestroy(ev_fork);
+        if (ev_join) hipEventDestroy(ev_join);
     }
 };
 
@@ -614,6 +620,7 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     // workgroups in a grid-stride loop) instead of a workgroup per row tile of the whole cell.
     const bool local = c->loc >= 0 && dual;
     constexpr int64_t kListWgs = 2048;
+    constexpr double kTwoSetBytes = 160e9;   // two seed-block workspaces only when both fit in this
     const int mW = (B + 31) / 32;
     const int hreach = local ? std::min(nu, (int)c->loc) : nu;   // farthest hop a vector can reach
     const int64_t ntiles = (nbrow + bpt - 1) / bpt;
@@ -634,6 +641,9 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
         off += align_up(bytes);
         return o;
     };
+    // Per-set arrays (everything a seed block works on); with two sets, consecutive blocks alternate between
+    // them and between the caller's stream and the context's second stream, so that one block's short FP64
+    // kernels (reductions, coefficients, norms, eigensolver) overlap the other block's streaming sweeps.
     const size_t oK = take((size_t)nu * stride * sizeof(T)), oY = take(slab), oSY = take(slab), oZT = take(slab);
     const size_t oPart = take(part_doubles * 8);
     const size_t oRed = take((size_t)3 * nu * B * 8), oRedb = take((size_t)2 * B * 8);
@@ -645,32 +655,31 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     const size_t oCA = take((size_t)nu * B * 8), oCB = take((size_t)nu * B * 8);
     const size_t oCAf = take((size_t)nu * B * 4), oCBf = take((size_t)nu * B * 4);
     const size_t oAct = take((size_t)B * 4), oNu = take((size_t)B * 4);
-    const bool own_e = d_e_seed == nullptr, own_n = d_n_seed == nullptr, own_nu = d_nu_eff == nullptr;
-    const size_t oE = take(own_e ? (size_t)n_seeds * 8 : 0), oN = take(own_n ? (size_t)n_seeds * 8 : 0);
-    const size_t oNuOut = take(own_nu ? (size_t)n_seeds * 4 : 0);
     const size_t oDist = take(sparse ? (size_t)nbrow * 4 : 0), oTD = take(sparse ? (size_t)ntiles * 4 : 0);
     const size_t oCnt = take(sparse ? (size_t)(nu + 1) * 4 : 0), oList = take(sparse ? (size_t)ntiles * 4 : 0);
     const size_t oDl = take(sparse ? (size_t)ntiles * 4 : 0), oPlan = take(sparse ? (size_t)(8 + 4 * grid_max) * 4 : 0);
     const size_t oM0 = take(local ? (size_t)nbrow * mW * 4 : 0), oM1 = take(local ? (size_t)nbrow * mW * 4 : 0);
+    const size_t set_bytes = off;
+    const int64_t n_blocks = (n_seeds + B - 1) / B;
+    const int nset = n_blocks >= 2 && !c->prof && !c->in_graph && c->es.mode == 0 && c->tune.single_stream == 0 &&
+                             c->stream2 &&
+                             2.0 * (double)set_bytes <= kTwoSetBytes
+                         ? 2
+                         : 1;
+    off = (size_t)nset * set_bytes;
+    const bool own_e = d_e_seed == nullptr, own_n = d_n_seed == nullptr, own_nu = d_nu_eff == nullptr;
+    const size_t oE = take(own_e ? (size_t)n_seeds * 8 : 0), oN = take(own_n ? (size_t)n_seeds * 8 : 0);
+    const size_t oNuOut = take(own_nu ? (size_t)n_seeds * 4 : 0);
     mar_status st = ensure_ws(c, off);
     if (st != MAR_OK) return st;
     char* w = c->ws;
-    int32_t* sdist = (int32_t*)(w + oDist);
-    int32_t* TD = sparse ? (int32_t*)(w + oTD) : nullptr;
-    int32_t* scnt = (int32_t*)(w + oCnt);
-    int32_t* slist = (int32_t*)(w + oList);
-    int32_t* sDl = (int32_t*)(w + oDl);
-    int32_t* splan = (int32_t*)(w + oPlan);
-    uint32_t* lm0 = (uint32_t*)(w + oM0);
-    uint32_t* lm1 = (uint32_t*)(w + oM1);
-    const uint32_t* lmask = nullptr;
     // profiled solve: each block's tile counts are kept for the restricted byte counts
     int32_t* plog = nullptr;
     if (sparse && c->prof && !c->dry) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
-            const int64_t nb = (n_seeds + B - 1) / B;
-            if (nb > 0 && hipMalloc((void**)&plog, (size_t)nb * (nu + 1) * 4) == hipSuccess) c->plogs.push_back(plog);
+            if (n_blocks > 0 && hipMalloc((void**)&plog, (size_t)n_blocks * (nu + 1) * 4) == hipSuccess)
+                c->plogs.push_back(plog);
             else plog = nullptr;
         }
     }
@@ -685,42 +694,59 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
         r.sp_elem = (double)sizeof(T);
         r.sp_ntiles = dense_tiles;
     };
-    T* K = (T*)(w + oK);
-    T* Y = (T*)(w + oY);
-    T* SY = (T*)(w + oSY);
-    T* ZT = (T*)(w + oZT);
-    double* part = (double*)(w + oPart);
-    double* red = (double*)(w + oRed);
-    double* redb = (double*)(w + oRedb);
-    double* h = (double*)(w + oH);
-    double* Kp = (double*)(w + oKp);
-    int32_t* nucp = (int32_t*)(w + oNc);
-    double* G = (double*)(w + oG);
-    double* R = (double*)(w + oR);
-    double* C1 = (double*)(w + oC1);
-    double* BT = (double*)(w + oBT);
-    double* UU = (double*)(w + oUU);
-    double* gam = (double*)(w + oGam);
-    double* Fn = (double*)(w + oFn);
-    double* cA = (double*)(w + oCA);
-    double* cB = (double*)(w + oCB);
-    float* cAf = sizeof(T) == 4 ? (float*)(w + oCAf) : nullptr;
-    float* cBf = sizeof(T) == 4 ? (float*)(w + oCBf) : nullptr;
-    const T* cAT = sizeof(T) == 4 ? (const T*)cAf : (const T*)cA;
-    const T* cBT = sizeof(T) == 4 ? (const T*)cBf : (const T*)cB;
-    int32_t* active = (int32_t*)(w + oAct);
-    int32_t* nu_blk = (int32_t*)(w + oNu);
     double* e_seed = own_e ? (double*)(w + oE) : d_e_seed;
     double* n_seed = own_n ? (double*)(w + oN) : d_n_seed;
     int32_t* nu_out = own_nu ? (int32_t*)(w + oNuOut) : d_nu_eff;
     const double tau = sizeof(T) == 4 ? 1e-5 : 1e-12;
     const int64_t slab_el = stride;
 
+    hipStream_t s_caller = s;
+    if (nset == 2 && !c->dry) {   // the second stream starts after the caller's earlier work
+        hipEventRecord(c->ev_fork, s_caller);
+        hipStreamWaitEvent(c->stream2, c->ev_fork, 0);
+    }
     for (int64_t blk0 = 0; blk0 < n_seeds; blk0 += B) {
         const int ns = (int)std::min<int64_t>(B, n_seeds - blk0);
         const int32_t* seeds = d_seeds + blk0;
         const int64_t bi = blk0 / B;
-        if (M != c->M && blk0 == 0) {
+        const int set = (int)(bi % nset);
+        hipStream_t s = set ? c->stream2 : s_caller;
+        char* ws = w + (size_t)set * set_bytes;
+        T* K = (T*)(ws + oK);
+        T* Y = (T*)(ws + oY);
+        T* SY = (T*)(ws + oSY);
+        T* ZT = (T*)(ws + oZT);
+        double* part = (double*)(ws + oPart);
+        double* red = (double*)(ws + oRed);
+        double* redb = (double*)(ws + oRedb);
+        double* h = (double*)(ws + oH);
+        double* Kp = (double*)(ws + oKp);
+        int32_t* nucp = (int32_t*)(ws + oNc);
+        double* G = (double*)(ws + oG);
+        double* R = (double*)(ws + oR);
+        double* C1 = (double*)(ws + oC1);
+        double* BT = (double*)(ws + oBT);
+        double* UU = (double*)(ws + oUU);
+        double* gam = (double*)(ws + oGam);
+        double* Fn = (double*)(ws + oFn);
+        double* cA = (double*)(ws + oCA);
+        double* cB = (double*)(ws + oCB);
+        float* cAf = sizeof(T) == 4 ? (float*)(ws + oCAf) : nullptr;
+        float* cBf = sizeof(T) == 4 ? (float*)(ws + oCBf) : nullptr;
+        const T* cAT = sizeof(T) == 4 ? (const T*)cAf : (const T*)cA;
+        const T* cBT = sizeof(T) == 4 ? (const T*)cBf : (const T*)cB;
+        int32_t* active = (int32_t*)(ws + oAct);
+        int32_t* nu_blk = (int32_t*)(ws + oNu);
+        int32_t* sdist = (int32_t*)(ws + oDist);
+        int32_t* TD = sparse ? (int32_t*)(ws + oTD) : nullptr;
+        int32_t* scnt = (int32_t*)(ws + oCnt);
+        int32_t* slist = (int32_t*)(ws + oList);
+        int32_t* sDl = (int32_t*)(ws + oDl);
+        int32_t* splan = (int32_t*)(ws + oPlan);
+        uint32_t* lm0 = (uint32_t*)(ws + oM0);
+        uint32_t* lm1 = (uint32_t*)(ws + oM1);
+        const uint32_t* lmask = nullptr;
+        if (M != c->M && bi < nset) {
             // padded rows of Y, S y and S u~ must read as zero (spmm writes rows < M only)
             launch(c, s, P_INIT, [&] { return mar::launch_zero(Y, (int64_t)slab, s); });
             launch(c, s, P_INIT, [&] { return mar::launch_zero(SY, (int64_t)slab, s); });
@@ -843,6 +869,10 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
         });
         eig_stage<T>(c, s, B, ns, seeds, nu, h, nucp, Kp, K, stride, M, mu, kT, d_rho, e_seed + blk0, n_seed + blk0,
                      nu_out + blk0, d_eps ? d_eps + blk0 * nu : nullptr, d_w ? d_w + blk0 * nu : nullptr, blk0);
+    }
+    if (nset == 2 && !c->dry) {   // the caller's stream waits for the second stream's blocks
+        hipEventRecord(c->ev_join, c->stream2);
+        hipStreamWaitEvent(s, c->ev_join, 0);
     }
     if (!c->zc_defer && !c->es.mode) launch(c, s, P_SUM, [&] { return mar::launch_sum(e_seed, n_seeds, d_e_band, s); });
     if (c->refused) {
@@ -1039,6 +1069,9 @@ mar_status mar_create(int64_t M, const int64_t* H_rowptr, const int32_t* H_col, 
     if ((st = upload(c, &c->SvalH, svalH.data(), svalH.size())) != MAR_OK) return fail(st);
     if ((st = upload(c, &c->diagS, diag.data(), diag.size())) != MAR_OK) return fail(st);
     he = hipStreamCreate(&c->stream);
+    if (he == hipSuccess) he = hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking);
+    if (he == hipSuccess) he = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+    if (he == hipSuccess) he = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
     if (he != hipSuccess) {
         c->err = fmt("stream creation failed: %s", hipGetErrorString(he));
         return fail(MAR_ERR_HIP);
@@ -1091,8 +1124,10 @@ mar_status mar_solve_many(int32_t n_sys, mar_ctx* const* ctx, const mar_request*
         // size and allocate every workspace first: nothing may allocate under capture
         for (int i = 0; i < n_sys; ++i) {
             ctx[i]->dry = true;
+            ctx[i]->in_graph = true;
             mar_status st = dispatch_solve(ctx[i], req[i], plans[i], ctx[i]->stream);
             ctx[i]->dry = false;
+            ctx[i]->in_graph = false;
             if (st != MAR_OK) return st;
         }
         HIP_OR(c0, hipDeviceSynchronize());
@@ -1125,7 +1160,9 @@ mar_status mar_solve_many(int32_t n_sys, mar_ctx* const* ctx, const mar_request*
             hipEventRecord(g->events[n_sys], g->cap);
             for (int i = 0; i < n_sys && st == MAR_OK; ++i) {
                 hipStreamWaitEvent(ctx[i]->stream, g->events[n_sys], 0);
+                ctx[i]->in_graph = true;
                 st = dispatch_solve(ctx[i], req[i], plans[i], ctx[i]->stream);
+                ctx[i]->in_graph = false;
                 if (st != MAR_OK) bad = i;
                 hipEventRecord(g->events[i], ctx[i]->stream);
                 hipStreamWaitEvent(g->cap, g->events[i], 0);
@@ -1675,6 +1712,7 @@ mar_status mar_set_tuning(mar_ctx* c, const mar_tuning* t) {
     if (t->upd_q != 0 && t->upd_q != 2 && t->upd_q != 4 && t->upd_q != 8)
         return set_err(c, MAR_ERR_ARG, "upd_q must be 0, 2, 4 or 8");
     if (t->support_off != 0 && t->support_off != 1) return set_err(c, MAR_ERR_ARG, "support_off must be 0 or 1");
+    if (t->single_stream != 0 && t->single_stream != 1) return set_err(c, MAR_ERR_ARG, "single_stream must be 0 or 1");
     c->tune = *t;
     return MAR_OK;
 }

@@ -135,3 +135,19 @@ def test_support_profile_bytes(sysm, ctx):
     # one support build per block of 64 and one projection plan per step
     assert out[True]["support"]["launches"] == 4 * (1 + 40)
     assert out[False]["support"]["launches"] == 0
+
+
+@pytest.mark.parametrize("prec,B", [("fp32", 64), ("fp64", 32)])
+def test_two_streams_bit_equal(sysm, ctx, prec, B):
+    """Alternating seed blocks between two workspaces and streams changes nothing in the results."""
+    seeds = np.arange(100, 100 + 5 * B + 11, dtype=np.int32)
+    out = []
+    for two in (True, False):
+        ctx.set_tuning(seed_block=B, schedule="delayed", two_streams=two)
+        try:
+            out.append(ctx.solve(seeds, 30, -0.3, KT, precision=prec, form="batched", levels=True))
+        finally:
+            ctx.set_tuning()
+    a, b = out
+    assert np.array_equal(a.rho, b.rho) and a.e_band == b.e_band
+    assert np.array_equal(a.nu_eff, b.nu_eff) and np.array_equal(a.eps, b.eps)
