@@ -14,7 +14,7 @@ def pytest_configure(config):
 
 
 @pytest.fixture(scope="session")
-def c1():
+def cell256():
     """64-atom periodic diamond cell (2x2x2 conventional cells), M = 256, rng seed 0."""
     from paper_1307_3218_amd import lattice
     return lattice.workload("diamond_2x2x2")

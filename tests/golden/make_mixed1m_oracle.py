@@ -1,5 +1,5 @@
 #!/usr/bin/env python3
-"""Write c5_oracle_nu300.json: the FP64 oracle on 8 seeds of the 262144-atom
+"""Write mixed1m_oracle_nu300.json: the FP64 oracle on 8 seeds of the 262144-atom
 mixed sp2/sp3 lattice (M = 1048576) at nu = 300, kT = 0.1 eV, mu = -0.45 eV.
 
 The seeds are every 2048th entry of the sorted 16384-seed sample of that
@@ -8,7 +8,7 @@ half filling (the method takes mu as given; both sides receive the same double).
 Calls only the oracle and the seeded input generator. A run takes several
 minutes and about 5 GB of host memory per worker.
 
-    python tests/golden/make_c5_oracle.py [--workers 4]
+    python tests/golden/make_mixed1m_oracle.py [--workers 4]
 """
 from __future__ import annotations
 
@@ -27,7 +27,7 @@ from oracle import mar_oracle as O  # noqa: E402
 from paper_1307_3218_amd import lattice  # noqa: E402
 
 WORKLOAD, NU, MU, KT = "mixed_32x32x32", 300, -0.45, 0.1
-OUT = os.path.join(HERE, "c5_oracle_nu300.json")
+OUT = os.path.join(HERE, "mixed1m_oracle_nu300.json")
 
 
 def main() -> int:

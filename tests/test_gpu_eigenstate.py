@@ -41,20 +41,20 @@ def test_exact_state_at_nu_M(small, form, k):
 
 
 @pytest.fixture(scope="module")
-def c1_states(c1):
-    return ES.subspace_states(c1.H, c1.S, np.arange(c1.M), 30)
+def cell256_states(cell256):
+    return ES.subspace_states(cell256.H, cell256.S, np.arange(cell256.M), 30)
 
 
 @pytest.mark.parametrize("k", [128, 129])
-def test_c1_state_against_oracle(c1, c1_states, k):
+def test_cell256_state_against_oracle(cell256, cell256_states, k):
     sigma = 0.02
-    ref = ES.eigen_state(c1_states, k, sigma)
-    ctx = mar.Context(c1.H, c1.S)
+    ref = ES.eigen_state(cell256_states, k, sigma)
+    ctx = mar.Context(cell256.H, cell256.S)
     try:
         for prec, bar in (("fp64", 1e-8), ("fp32", 1e-3)):
-            out = ctx.eigen_state(np.arange(c1.M, dtype=np.int32), 30, k, sigma, prec, "batched")
+            out = ctx.eigen_state(np.arange(cell256.M, dtype=np.int32), 30, k, sigma, prec, "batched")
             err = _sign_free(out["phi"], ref.phi)
-            print(f"[es c1 k={k} {prec}] eps_k {out['eps_k']:.10f} oracle {ref.eps_k:.10f} phi err {err:.2e} "
+            print(f"[es cell256 k={k} {prec}] eps_k {out['eps_k']:.10f} oracle {ref.eps_k:.10f} phi err {err:.2e} "
                   f"ref {out['ref'][:2]} oracle ref {ref.ref}", flush=True)
             assert abs(out["eps_k"] - ref.eps_k) <= (1e-9 if prec == "fp64" else 1e-4)
             assert abs(out["eta_lo"] - ref.eta_lo) <= (1e-9 if prec == "fp64" else 1e-3)

@@ -20,8 +20,8 @@ TOL = {"fp64": 1e-10, "fp32": 1e-5}
 
 
 @pytest.fixture(scope="module")
-def ctx1(c1):
-    ctx = mar.Context(c1.H, c1.S)
+def ctx1(cell256):
+    ctx = mar.Context(cell256.H, cell256.S)
     yield ctx
     ctx.close()
 
@@ -36,41 +36,41 @@ def _rows(H, seeds):
 
 
 @pytest.mark.parametrize("prec,form", [("fp64", "batched"), ("fp64", "plain"), ("fp32", "batched")])
-def test_c1_fermi_all_seeds(c1, ctx1, prec, form):
-    seeds = np.arange(c1.M, dtype=np.int32)
+def test_cell256_fermi_all_seeds(cell256, ctx1, prec, form):
+    seeds = np.arange(cell256.M, dtype=np.int32)
     nu = 30
-    out, mu = ctx1.solve_fermi(seeds, nu, float(c1.M), KT, prec, form, levels=True)
-    mu_ref = _oracle_mu(c1.H, c1.S, seeds, nu, float(c1.M), KT)
-    print(f"[fermi c1 {prec} {form}] mu {mu:.15f} oracle {mu_ref:.15f}", flush=True)
+    out, mu = ctx1.solve_fermi(seeds, nu, float(cell256.M), KT, prec, form, levels=True)
+    mu_ref = _oracle_mu(cell256.H, cell256.S, seeds, nu, float(cell256.M), KT)
+    print(f"[fermi cell256 {prec} {form}] mu {mu:.15f} oracle {mu_ref:.15f}", flush=True)
     tol = TOL[prec]
     assert abs(mu - mu_ref) <= (1e-10 if prec == "fp64" else 1e-4) * max(1.0, abs(mu_ref))
     # sum rule at the returned level
-    assert abs(out.n_seed.sum() - c1.M) <= 100 * tol * c1.M
+    assert abs(out.n_seed.sum() - cell256.M) <= 100 * tol * cell256.M
     # the ordinary solve at the same mu gives the same bits
     plain = ctx1.solve(seeds, nu, mu, KT, prec, form)
     assert np.array_equal(plain.rho, out.rho) and plain.e_band == out.e_band
     # against the oracle solved at the oracle's level
-    ref = O.solve(c1.H, c1.S, seeds, nu, mu_ref, KT, workers=4)
-    idx = _rows(c1.H, seeds)
+    ref = O.solve(cell256.H, cell256.S, seeds, nu, mu_ref, KT, workers=4)
+    idx = _rows(cell256.H, seeds)
     rho_rel = np.linalg.norm(out.rho[idx] - ref.rho[idx]) / np.linalg.norm(ref.rho[idx])
     e_rel = abs(out.e_band - ref.e_band) / abs(ref.e_band)
-    print(f"[fermi c1 {prec} {form}] rho {rho_rel:.2e} E {e_rel:.2e}", flush=True)
+    print(f"[fermi cell256 {prec} {form}] rho {rho_rel:.2e} E {e_rel:.2e}", flush=True)
     bar = tol if prec == "fp64" else 10 * tol   # mu itself carries the FP32 level error into rho
     assert rho_rel <= bar and e_rel <= bar
 
 
-def test_c1_fermi_zero_temperature(c1, ctx1):
-    seeds = np.arange(0, c1.M, 3, dtype=np.int32)
+def test_cell256_fermi_zero_temperature(cell256, ctx1):
+    seeds = np.arange(0, cell256.M, 3, dtype=np.int32)
     nu = 30
     out, mu = ctx1.solve_fermi(seeds, nu, float(len(seeds)), 0.0, "fp64", "batched")
-    mu_ref = _oracle_mu(c1.H, c1.S, seeds, nu, float(len(seeds)), 0.0)
+    mu_ref = _oracle_mu(cell256.H, cell256.S, seeds, nu, float(len(seeds)), 0.0)
     print(f"[fermi kT=0] mu {mu:.15f} oracle {mu_ref:.15f}", flush=True)
     assert abs(mu - mu_ref) <= 1e-9 * max(1.0, abs(mu_ref))
     plain = ctx1.solve(seeds, nu, mu, 0.0, "fp64", "batched")
     assert np.array_equal(plain.rho, out.rho)
 
 
-def test_c2_fermi_sample_fp32():
+def test_cell16k_fermi_sample_fp32():
     s = lattice.workload("diamond_8x8x8")
     seeds = lattice.sample_seeds(s.M, 512, seed=7)
     nu = 30
@@ -79,7 +79,7 @@ def test_c2_fermi_sample_fp32():
         out, mu = ctx.solve_fermi(seeds, nu, float(len(seeds)), KT, "fp32", "batched")
         ref = O.solve(s.H, s.S, seeds, nu, 0.0, KT, workers=8)
         mu_ref = O.fermi_level(ref.eps, ref.weight, float(len(seeds)), KT)
-        print(f"[fermi c2 fp32] mu {mu:.10f} oracle {mu_ref:.10f}", flush=True)
+        print(f"[fermi cell16k fp32] mu {mu:.10f} oracle {mu_ref:.10f}", flush=True)
         assert abs(mu - mu_ref) <= 1e-4 * max(1.0, abs(mu_ref))
         assert abs(out.n_seed.sum() - len(seeds)) <= 1e-3
         out64, mu64 = ctx.solve_fermi(seeds, nu, float(len(seeds)), KT, "fp64", "batched")
@@ -88,14 +88,14 @@ def test_c2_fermi_sample_fp32():
         ctx.close()
 
 
-def test_fermi_async_matches_host(c1, ctx1):
+def test_fermi_async_matches_host(cell256, ctx1):
     import torch
     dev = torch.device("cuda:0")
-    seeds = np.arange(0, c1.M, 2, dtype=np.int32)
+    seeds = np.arange(0, cell256.M, 2, dtype=np.int32)
     nu = 30
     host, mu = ctx1.solve_fermi(seeds, nu, float(len(seeds)), KT, "fp64", "batched")
     d_seeds = torch.from_numpy(seeds).to(dev)
-    d_rho = torch.zeros(c1.H.nnz, dtype=torch.float64, device=dev)
+    d_rho = torch.zeros(cell256.H.nnz, dtype=torch.float64, device=dev)
     d_eb = torch.zeros(1, dtype=torch.float64, device=dev)
     d_mu = torch.zeros(1, dtype=torch.float64, device=dev)
     ctx1.solve_fermi_async(d_seeds, nu, float(len(seeds)), KT, "fp64", "batched", d_rho=d_rho, d_e_band=d_eb,

@@ -146,10 +146,10 @@ def test_local_refusals(sysm, ctx):
         ctx.set_local_region(None)
     assert ctx.local_region() == -1
     # a pattern without 4x4 blocks cannot take a local region
-    c1 = lattice.workload("diamond_2x2x2")
+    cell256 = lattice.workload("diamond_2x2x2")
     import scipy.sparse as sp
-    H = sp.csr_matrix(c1.H)[:255, :255]
-    S = sp.csr_matrix(c1.S)[:255, :255]
+    H = sp.csr_matrix(cell256.H)[:255, :255]
+    S = sp.csr_matrix(cell256.S)[:255, :255]
     c = mar.Context(H, S)
     try:
         with pytest.raises(mar.MarError):

@@ -1,6 +1,6 @@
 """The largest single-GPU instance: the 262144-atom mixed sp2/sp3 lattice
 (M = 1048576) at nu = 300, seed blocks of 64, against the FP64 oracle on 8
-sampled seeds (stored by tests/golden/make_c5_oracle.py, which calls only the
+sampled seeds (stored by tests/golden/make_mixed1m_oracle.py, which calls only the
 oracle; mu = -0.45 eV, kT = 0.1 eV).
 
 Bars: FP64 form 1e-10 (relative, on the listed rows of rho and on the summed
@@ -20,7 +20,7 @@ from paper_1307_3218_amd import lattice, mar
 
 pytestmark = pytest.mark.gpu
 
-GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c5_oracle_nu300.json")
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "mixed1m_oracle_nu300.json")
 TOL = {"fp64": 1e-10, "fp32": 1e-5}
 RHO32 = 3e-5
 
@@ -32,15 +32,15 @@ def golden():
 
 
 @pytest.fixture(scope="module")
-def c5(golden):
+def mixed1m(golden):
     s = lattice.workload(golden["workload"])
     assert s.M == golden["M"] and s.H.nnz == golden["nnz"]
     return s
 
 
 @pytest.fixture(scope="module")
-def c5_ctx(c5):
-    ctx = mar.Context(c5.H, c5.S)
+def mixed1m_ctx(mixed1m):
+    ctx = mar.Context(mixed1m.H, mixed1m.S)
     yield ctx
     ctx.close()
 
@@ -61,7 +61,7 @@ def _check(g, out, prec, label):
     rho_rel = (num / den) ** 0.5
     e_ref = float(np.sum(g["e_seed"]))
     e_rel = abs(float(np.sum(out.e_seed)) - e_ref) / abs(e_ref)
-    print(f"[c5 {label} {prec}] rho {rho_rel:.2e} E {e_rel:.2e} worst column {worst:.2e}", flush=True)
+    print(f"[mixed1m {label} {prec}] rho {rho_rel:.2e} E {e_rel:.2e} worst column {worst:.2e}", flush=True)
     rho_tol = RHO32 if prec == "fp32" else tol
     assert rho_rel <= rho_tol and e_rel <= tol and worst <= 100 * rho_tol
     assert np.abs(np.array(out.n_seed) - np.array(g["n_seed"])).max() <= 100 * tol
@@ -86,27 +86,27 @@ class _Rows:
         self.e_seed, self.n_seed, self.nu_eff, self.eps, self.weight = o.e_seed, o.n_seed, o.nu_eff, o.eps, o.weight
 
 
-def _solve(ctx, c5, g, prec, form, block=0):
+def _solve(ctx, mixed1m, g, prec, form, block=0):
     ctx.set_tuning(seed_block=block)
     try:
         o = ctx.solve(np.array(g["seeds"], dtype=np.int32), g["nu"], g["mu"], g["kT"], prec, form, levels=True)
     finally:
         ctx.set_tuning()
-    return _Rows(c5.H, g["seeds"], o)
+    return _Rows(mixed1m.H, g["seeds"], o)
 
 
-def test_c5_block_size(c5_ctx, golden):
+def test_mixed1m_block_size(mixed1m_ctx, golden):
     """The widest block that keeps the FP32 basis within 128 GB is the configured 64."""
-    assert c5_ctx.seed_block(golden["nu"], "fp32") == 64
+    assert mixed1m_ctx.seed_block(golden["nu"], "fp32") == 64
 
 
-def test_c5_fp32_batched(c5_ctx, c5, golden):
-    _check(golden, _solve(c5_ctx, c5, golden, "fp32", "batched", block=64), "fp32", "batched B=64")
+def test_mixed1m_fp32_batched(mixed1m_ctx, mixed1m, golden):
+    _check(golden, _solve(mixed1m_ctx, mixed1m, golden, "fp32", "batched", block=64), "fp32", "batched B=64")
 
 
-def test_c5_fp64_plain(c5_ctx, c5, golden):
-    _check(golden, _solve(c5_ctx, c5, golden, "fp64", "plain"), "fp64", "plain")
+def test_mixed1m_fp64_plain(mixed1m_ctx, mixed1m, golden):
+    _check(golden, _solve(mixed1m_ctx, mixed1m, golden, "fp64", "plain"), "fp64", "plain")
 
 
-def test_c5_fp64_batched(c5_ctx, c5, golden):
-    _check(golden, _solve(c5_ctx, c5, golden, "fp64", "batched", block=8), "fp64", "batched B=8")
+def test_mixed1m_fp64_batched(mixed1m_ctx, mixed1m, golden):
+    _check(golden, _solve(mixed1m_ctx, mixed1m, golden, "fp64", "batched", block=8), "fp64", "batched B=8")

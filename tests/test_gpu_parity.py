@@ -70,8 +70,8 @@ def check_identities(gpu, mu, kT, prec):
 
 # ------------------------------------------------------------------ fixtures
 @pytest.fixture(scope="module")
-def c1_ctx(c1):
-    ctx = mar.Context(c1.H, c1.S)
+def cell256_ctx(cell256):
+    ctx = mar.Context(cell256.H, cell256.S)
     info = ctx.info()
     assert info["H_bsr"] and info["S_bsr"]
     yield ctx
@@ -79,168 +79,168 @@ def c1_ctx(c1):
 
 
 @pytest.fixture(scope="module")
-def c1_mu(c1):
-    r = O.solve(c1.H, c1.S, np.arange(c1.M), 30, 0.0, KT)
-    return O.fermi_level(r.eps, r.weight, c1.M, KT)
+def cell256_mu(cell256):
+    r = O.solve(cell256.H, cell256.S, np.arange(cell256.M), 30, 0.0, KT)
+    return O.fermi_level(r.eps, r.weight, cell256.M, KT)
 
 
 @pytest.fixture(scope="module")
-def c1_ref30(c1, c1_mu):
-    return O.solve(c1.H, c1.S, np.arange(c1.M), 30, c1_mu, KT, workers=_workers(8))
+def cell256_ref30(cell256, cell256_mu):
+    return O.solve(cell256.H, cell256.S, np.arange(cell256.M), 30, cell256_mu, KT, workers=_workers(8))
 
 
 # ------------------------------------------------------------------ M = 256
 @pytest.mark.parametrize("prec,form", [("fp64", "batched"), ("fp64", "plain"), ("fp32", "batched"),
                                        ("fp32", "plain")])
-def test_c1_all_seeds_nu30(c1, c1_ctx, c1_mu, c1_ref30, prec, form):
-    seeds = np.arange(c1.M, dtype=np.int32)
-    g = c1_ctx.solve(seeds, 30, c1_mu, KT, precision=prec, form=form, levels=True)
-    compare(c1.H, seeds, g, c1_ref30, prec, label=f"M=256 nu=30 {form}")
-    check_identities(g, c1_mu, KT, prec)
+def test_cell256_all_seeds_nu30(cell256, cell256_ctx, cell256_mu, cell256_ref30, prec, form):
+    seeds = np.arange(cell256.M, dtype=np.int32)
+    g = cell256_ctx.solve(seeds, 30, cell256_mu, KT, precision=prec, form=form, levels=True)
+    compare(cell256.H, seeds, g, cell256_ref30, prec, label=f"M=256 nu=30 {form}")
+    check_identities(g, cell256_mu, KT, prec)
     # electron-count sum rule at the bisected level
-    assert abs(g.n_seed.sum() - c1.M) <= 1e3 * TOL[prec] * c1.M
+    assert abs(g.n_seed.sum() - cell256.M) <= 1e3 * TOL[prec] * cell256.M
 
 
 @pytest.mark.parametrize("sched", ["delayed", "textbook"])
 @pytest.mark.parametrize("prec,B", [("fp64", b) for b in (1, 2, 4, 8, 16, 32, 64, 128)] +
                          [("fp32", b) for b in (1, 2, 4, 8, 16, 32, 64, 128, 256)])
-def test_c1_every_block_size_ragged(c1, c1_ctx, c1_mu, prec, B, sched):
-    seeds = lattice.sample_seeds(c1.M, 37, seed=B).astype(np.int32)    # 37: ragged last block
-    ref = O.solve(c1.H, c1.S, seeds, 24, c1_mu, KT)
-    c1_ctx.set_tuning(seed_block=B, schedule=sched)
+def test_cell256_every_block_size_ragged(cell256, cell256_ctx, cell256_mu, prec, B, sched):
+    seeds = lattice.sample_seeds(cell256.M, 37, seed=B).astype(np.int32)    # 37: ragged last block
+    ref = O.solve(cell256.H, cell256.S, seeds, 24, cell256_mu, KT)
+    cell256_ctx.set_tuning(seed_block=B, schedule=sched)
     try:
-        g = c1_ctx.solve(seeds, 24, c1_mu, KT, precision=prec, form="batched", levels=True)
+        g = cell256_ctx.solve(seeds, 24, cell256_mu, KT, precision=prec, form="batched", levels=True)
     finally:
-        c1_ctx.set_tuning(0)
-    compare(c1.H, seeds, g, ref, prec, label=f"M=256 B={B} {sched}")
+        cell256_ctx.set_tuning(0)
+    compare(cell256.H, seeds, g, ref, prec, label=f"M=256 B={B} {sched}")
 
 
 @pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_c1_projection_variants(c1, c1_ctx, c1_mu, c1_ref30, prec, variant):
+def test_cell256_projection_variants(cell256, cell256_ctx, cell256_mu, cell256_ref30, prec, variant):
     """Every projection variant (4 or 8 slabs, 2 or 4 vectors per thread, non-temporal loads) at the widest block."""
-    seeds = np.arange(c1.M, dtype=np.int32)
-    c1_ctx.set_tuning(seed_block=0, schedule="delayed", proj_variant=variant)
+    seeds = np.arange(cell256.M, dtype=np.int32)
+    cell256_ctx.set_tuning(seed_block=0, schedule="delayed", proj_variant=variant)
     try:
-        g = c1_ctx.solve(seeds, 30, c1_mu, KT, precision=prec, levels=True)
+        g = cell256_ctx.solve(seeds, 30, cell256_mu, KT, precision=prec, levels=True)
     finally:
-        c1_ctx.set_tuning(0)
-    compare(c1.H, seeds, g, c1_ref30, prec, label=f"projection variant {variant}")
+        cell256_ctx.set_tuning(0)
+    compare(cell256.H, seeds, g, cell256_ref30, prec, label=f"projection variant {variant}")
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_c1_delayed_plain_and_projection_grids(c1, c1_ctx, c1_mu, c1_ref30, prec):
+def test_cell256_delayed_plain_and_projection_grids(cell256, cell256_ctx, cell256_mu, cell256_ref30, prec):
     """The delayed schedule at B = 1 and with tiny / huge projection grids (many tiles per workgroup)."""
-    seeds = np.arange(0, c1.M, 5, dtype=np.int32)
+    seeds = np.arange(0, cell256.M, 5, dtype=np.int32)
     for wgs in (1, 7, 100000):
-        c1_ctx.set_tuning(seed_block=0, schedule="delayed", proj_wgs=wgs)
+        cell256_ctx.set_tuning(seed_block=0, schedule="delayed", proj_wgs=wgs)
         try:
-            g = c1_ctx.solve(seeds, 30, c1_mu, KT, precision=prec, form="plain", levels=True)
+            g = cell256_ctx.solve(seeds, 30, cell256_mu, KT, precision=prec, form="plain", levels=True)
         finally:
-            c1_ctx.set_tuning(0)
-        ref = O.solve(c1.H, c1.S, seeds, 30, c1_mu, KT)
-        compare(c1.H, seeds, g, ref, prec, label=f"delayed plain proj_wgs={wgs}")
+            cell256_ctx.set_tuning(0)
+        ref = O.solve(cell256.H, cell256.S, seeds, 30, cell256_mu, KT)
+        compare(cell256.H, seeds, g, ref, prec, label=f"delayed plain proj_wgs={wgs}")
 
 
-def test_c1_nu_equals_M_exact(c1, c1_ctx):
+def test_cell256_nu_equals_M_exact(cell256, cell256_ctx):
     """nu = M: the subspace result equals the dense generalized eigensolve (global-memory eigensolver path)."""
     mu = -0.448
-    seeds = np.arange(c1.M, dtype=np.int32)
-    ref = O.solve(c1.H, c1.S, seeds, c1.M, mu, KT, workers=_workers(8))
-    rho_d, E_d, _ = O.dense(c1.H, c1.S, mu, KT)
-    rows = np.repeat(np.arange(c1.M), np.diff(c1.H.indptr))
-    exact = rho_d[c1.H.indices, rows]
+    seeds = np.arange(cell256.M, dtype=np.int32)
+    ref = O.solve(cell256.H, cell256.S, seeds, cell256.M, mu, KT, workers=_workers(8))
+    rho_d, E_d, _ = O.dense(cell256.H, cell256.S, mu, KT)
+    rows = np.repeat(np.arange(cell256.M), np.diff(cell256.H.indptr))
+    exact = rho_d[cell256.H.indices, rows]
     for form in ("batched", "plain"):
-        g = c1_ctx.solve(seeds, c1.M, mu, KT, precision="fp64", form=form, levels=True)
-        compare(c1.H, seeds, g, ref, "fp64", label=f"M=256 nu=M {form}")
+        g = cell256_ctx.solve(seeds, cell256.M, mu, KT, precision="fp64", form=form, levels=True)
+        compare(cell256.H, seeds, g, ref, "fp64", label=f"M=256 nu=M {form}")
         assert np.linalg.norm(g.rho - exact) / np.linalg.norm(exact) < 1e-10
         assert abs(g.e_band - E_d) / abs(E_d) < 1e-10
-    g = c1_ctx.solve(seeds, c1.M, mu, KT, precision="fp32", levels=True)
-    compare(c1.H, seeds, g, ref, "fp32", label="M=256 nu=M fp32")
+    g = cell256_ctx.solve(seeds, cell256.M, mu, KT, precision="fp32", levels=True)
+    compare(cell256.H, seeds, g, ref, "fp32", label="M=256 nu=M fp32")
 
 
-def test_c1_determinism(c1, c1_ctx, c1_mu):
-    seeds = np.arange(0, c1.M, 3, dtype=np.int32)
-    a = c1_ctx.solve(seeds, 30, c1_mu, KT, precision="fp64")
-    b = c1_ctx.solve(seeds, 30, c1_mu, KT, precision="fp64")
+def test_cell256_determinism(cell256, cell256_ctx, cell256_mu):
+    seeds = np.arange(0, cell256.M, 3, dtype=np.int32)
+    a = cell256_ctx.solve(seeds, 30, cell256_mu, KT, precision="fp64")
+    b = cell256_ctx.solve(seeds, 30, cell256_mu, KT, precision="fp64")
     assert np.array_equal(a.rho, b.rho) and a.e_band == b.e_band
 
 
-def test_small_nu_closed_forms(c1, c1_ctx):
+def test_small_nu_closed_forms(cell256, cell256_ctx):
     seeds = np.array([0, 5, 130, 255], dtype=np.int32)
     for nu in (1, 2, 3):
-        ref = O.solve(c1.H, c1.S, seeds, nu, -0.3, KT)
-        g = c1_ctx.solve(seeds, nu, -0.3, KT, precision="fp64", levels=True)
-        compare(c1.H, seeds, g, ref, "fp64", label=f"nu={nu}")
-    g = c1_ctx.solve(seeds, 1, -0.3, KT, precision="fp64")
-    Hd, Sd = c1.H.toarray(), c1.S.toarray()
+        ref = O.solve(cell256.H, cell256.S, seeds, nu, -0.3, KT)
+        g = cell256_ctx.solve(seeds, nu, -0.3, KT, precision="fp64", levels=True)
+        compare(cell256.H, seeds, g, ref, "fp64", label=f"nu={nu}")
+    g = cell256_ctx.solve(seeds, 1, -0.3, KT, precision="fp64")
+    Hd, Sd = cell256.H.toarray(), cell256.S.toarray()
     for j in seeds:
         f = 1.0 / (1.0 + math.exp((Hd[j, j] / Sd[j, j] + 0.3) / KT))
-        lo = c1.H.indptr[j]
-        t = list(c1.H.indices[lo:c1.H.indptr[j + 1]]).index(j)
+        lo = cell256.H.indptr[j]
+        t = list(cell256.H.indices[lo:cell256.H.indptr[j + 1]]).index(j)
         assert math.isclose(g.rho[lo + t], 2 * f / Sd[j, j], rel_tol=1e-13)
 
 
-def test_full_occupation_and_zero_temperature(c1, c1_ctx):
-    seeds = np.arange(0, c1.M, 7, dtype=np.int32)
+def test_full_occupation_and_zero_temperature(cell256, cell256_ctx):
+    seeds = np.arange(0, cell256.M, 7, dtype=np.int32)
     for prec in ("fp64", "fp32"):
-        g = c1_ctx.solve(seeds, 20, 1e3, 0.0, precision=prec)
+        g = cell256_ctx.solve(seeds, 20, 1e3, 0.0, precision=prec)
         assert np.allclose(g.n_seed, 2.0, atol=100 * TOL[prec])
-        g = c1_ctx.solve(seeds, 20, -1e3, 0.0, precision=prec)
+        g = cell256_ctx.solve(seeds, 20, -1e3, 0.0, precision=prec)
         assert np.all(g.rho == 0.0) and g.e_band == 0.0
 
 
-def test_rows_of_unlisted_seeds_untouched(c1, c1_ctx):
+def test_rows_of_unlisted_seeds_untouched(cell256, cell256_ctx):
     seeds = np.array([3, 9], dtype=np.int32)
-    rho0 = np.full(c1.H.nnz, 7.25)
-    g = c1_ctx.solve(seeds, 10, 0.0, KT, precision="fp64", rho=rho0)
-    mask = np.ones(c1.H.nnz, bool)
-    mask[_slots(c1.H, seeds)] = False
+    rho0 = np.full(cell256.H.nnz, 7.25)
+    g = cell256_ctx.solve(seeds, 10, 0.0, KT, precision="fp64", rho=rho0)
+    mask = np.ones(cell256.H.nnz, bool)
+    mask[_slots(cell256.H, seeds)] = False
     assert np.all(g.rho[mask] == 7.25)
     assert np.all(g.rho[~mask] != 7.25)
 
 
-def test_empty_seed_list(c1, c1_ctx):
-    g = c1_ctx.solve(np.zeros(0, np.int32), 10, 0.0, KT, precision="fp32", rho=np.full(c1.H.nnz, 1.5))
+def test_empty_seed_list(cell256, cell256_ctx):
+    g = cell256_ctx.solve(np.zeros(0, np.int32), 10, 0.0, KT, precision="fp32", rho=np.full(cell256.H.nnz, 1.5))
     assert g.e_band == 0.0 and np.all(g.rho == 1.5)
 
 
-def test_argument_errors(c1, c1_ctx):
+def test_argument_errors(cell256, cell256_ctx):
     with pytest.raises(mar.MarError) as e:
-        c1_ctx.solve(np.array([1, 1], np.int32), 5, 0.0, KT)
+        cell256_ctx.solve(np.array([1, 1], np.int32), 5, 0.0, KT)
     assert e.value.status == mar.MAR_ERR_ARG
     with pytest.raises(mar.MarError):
-        c1_ctx.solve(np.array([c1.M], np.int32), 5, 0.0, KT)
+        cell256_ctx.solve(np.array([cell256.M], np.int32), 5, 0.0, KT)
     with pytest.raises(mar.MarError):
-        c1_ctx.solve(np.array([0], np.int32), c1.M + 1, 0.0, KT)
+        cell256_ctx.solve(np.array([0], np.int32), cell256.M + 1, 0.0, KT)
     with pytest.raises(mar.MarError):
-        c1_ctx.solve(np.array([0], np.int32), 5, 0.0, -1.0)
+        cell256_ctx.solve(np.array([0], np.int32), 5, 0.0, -1.0)
     with pytest.raises(mar.MarError):
-        c1_ctx.solve(np.array([0], np.int32), 5, float("nan"), KT)
+        cell256_ctx.solve(np.array([0], np.int32), 5, float("nan"), KT)
 
 
-def test_async_device_buffers_and_invalid_seed(c1, c1_ctx, c1_mu, c1_ref30):
+def test_async_device_buffers_and_invalid_seed(cell256, cell256_ctx, cell256_mu, cell256_ref30):
     import torch
     dev = torch.device("cuda:0")
-    seeds = np.array([0, 17, c1.M + 5, 200], dtype=np.int32)          # one seed out of range
+    seeds = np.array([0, 17, cell256.M + 5, 200], dtype=np.int32)          # one seed out of range
     d_seeds = torch.from_numpy(seeds).to(dev)
-    d_rho = torch.zeros(c1.H.nnz, dtype=torch.float64, device=dev)
+    d_rho = torch.zeros(cell256.H.nnz, dtype=torch.float64, device=dev)
     d_eb = torch.zeros(1, dtype=torch.float64, device=dev)
     d_nu = torch.zeros(4, dtype=torch.int32, device=dev)
     d_e = torch.zeros(4, dtype=torch.float64, device=dev)
-    c1_ctx.solve_async(d_seeds, 30, c1_mu, KT, "fp64", d_rho=d_rho, d_e_band=d_eb, d_nu_eff=d_nu, d_e_seed=d_e)
+    cell256_ctx.solve_async(d_seeds, 30, cell256_mu, KT, "fp64", d_rho=d_rho, d_e_band=d_eb, d_nu_eff=d_nu, d_e_seed=d_e)
     torch.cuda.synchronize()
     nu = d_nu.cpu().numpy()
     assert list(nu) == [30, 30, -2, 30]
     e = d_e.cpu().numpy()
-    ref = {j: c1_ref30.e_seed[j] for j in (0, 17, 200)}
+    ref = {j: cell256_ref30.e_seed[j] for j in (0, 17, 200)}
     for s, j in ((0, 0), (1, 17), (3, 200)):
         assert abs(e[s] - ref[j]) <= 1e-10 * abs(ref[j])
     assert e[2] == 0.0
 
 
 # ------------------------------------------------------------------ other patterns
-def test_breakdown_truncates(c1):
+def test_breakdown_truncates(cell256):
     blocks = [np.array([[1.0, 0.3, 0.0, 0.2], [0.3, -1.0, 0.5, 0.0],
                         [0.0, 0.5, 0.5, 0.1], [0.2, 0.0, 0.1, 2.0]]) * (k + 1) for k in range(3)]
     H = sp.block_diag(blocks, format="csr")
@@ -304,55 +304,55 @@ def test_mixed_lattice_small():
 
 # ------------------------------------------------------------------ M = 16384
 @pytest.fixture(scope="module")
-def c2():
+def cell16k():
     return lattice.workload("diamond_8x8x8")
 
 
 @pytest.fixture(scope="module")
-def c2_ctx(c2):
-    ctx = mar.Context(c2.H, c2.S)
+def cell16k_ctx(cell16k):
+    ctx = mar.Context(cell16k.H, cell16k.S)
     yield ctx
     ctx.close()
 
 
 @pytest.mark.parametrize("prec,sched", [("fp64", "delayed"), ("fp32", "delayed"), ("fp32", "textbook")])
-def test_c2_all_seeds_sampled_oracle(c2, c2_ctx, prec, sched):
+def test_cell16k_all_seeds_sampled_oracle(cell16k, cell16k_ctx, prec, sched):
     """All 16384 seeds on the GPU at nu = 30; the oracle checks a 300-seed sample element by element."""
-    seeds = np.arange(c2.M, dtype=np.int32)
+    seeds = np.arange(cell16k.M, dtype=np.int32)
     mu = 0.0
-    c2_ctx.set_tuning(0, schedule=sched)
+    cell16k_ctx.set_tuning(0, schedule=sched)
     try:
-        g = c2_ctx.solve(seeds, 30, mu, KT, precision=prec, levels=True)
+        g = cell16k_ctx.solve(seeds, 30, mu, KT, precision=prec, levels=True)
     finally:
-        c2_ctx.set_tuning(0)
+        cell16k_ctx.set_tuning(0)
     assert np.all(g.nu_eff == 30)
     check_identities(g, mu, KT, prec)
-    sample = lattice.sample_seeds(c2.M, 300, seed=7)
-    ref = O.solve(c2.H, c2.S, sample, 30, mu, KT, workers=_workers(16))
+    sample = lattice.sample_seeds(cell16k.M, 300, seed=7)
+    ref = O.solve(cell16k.H, cell16k.S, sample, 30, mu, KT, workers=_workers(16))
     sub = mar.SolveOutput(rho=g.rho, e_band=float(np.sum(g.e_seed[sample])), e_seed=g.e_seed[sample],
                           n_seed=g.n_seed[sample], nu_eff=g.nu_eff[sample], eps=g.eps[sample], weight=None)
-    compare(c2.H, sample, sub, ref, prec, label=f"M=16384 nu=30 {sched}")
+    compare(cell16k.H, sample, sub, ref, prec, label=f"M=16384 nu=30 {sched}")
 
 
 # ------------------------------------------------------------------ M = 131072 (bench shape)
 @pytest.fixture(scope="module")
-def c4():
+def mixed131k():
     return lattice.workload("mixed_16x16x16")
 
 
-def test_c4_bench_block_sampled_oracle(c4):
+def test_mixed131k_bench_block_sampled_oracle(mixed131k):
     """The bench's launch configuration (FP32 batched, nu = 100) on one seed block; oracle on 4 of its seeds."""
-    ctx = mar.Context(c4.H, c4.S)
+    ctx = mar.Context(mixed131k.H, mixed131k.S)
     B = ctx.seed_block(100, "fp32")
-    seeds = lattice.sample_seeds(c4.M, B, seed=11)
+    seeds = lattice.sample_seeds(mixed131k.M, B, seed=11)
     mu = 0.0
     g32 = ctx.solve(seeds, 100, mu, KT, precision="fp32", levels=True)
     check_identities(g32, mu, KT, "fp32")
     pick = np.array([0, B // 3, (2 * B) // 3, B - 1])
-    ref = O.solve(c4.H, c4.S, seeds[pick], 100, mu, KT, workers=_workers(4))
+    ref = O.solve(mixed131k.H, mixed131k.S, seeds[pick], 100, mu, KT, workers=_workers(4))
     sub = mar.SolveOutput(rho=g32.rho, e_band=float(np.sum(g32.e_seed[pick])), e_seed=g32.e_seed[pick],
                           n_seed=g32.n_seed[pick], nu_eff=g32.nu_eff[pick], eps=g32.eps[pick], weight=None)
-    compare(c4.H, seeds[pick], sub, ref, "fp32", label="M=131072 nu=100 fp32")
+    compare(mixed131k.H, seeds[pick], sub, ref, "fp32", label="M=131072 nu=100 fp32")
     g64 = ctx.solve(seeds[pick], 100, mu, KT, precision="fp64", form="plain", levels=True)
-    compare(c4.H, seeds[pick], g64, ref, "fp64", label="M=131072 nu=100 fp64 plain")
+    compare(mixed131k.H, seeds[pick], g64, ref, "fp64", label="M=131072 nu=100 fp64 plain")
     ctx.close()

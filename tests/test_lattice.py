@@ -18,8 +18,8 @@ def _block_pattern_ok(A, n_atoms):
     return True
 
 
-def test_diamond_small(c1):
-    s = c1
+def test_diamond_small(cell256):
+    s = cell256
     assert s.M == 256 and s.n_atoms == 64
     assert s.H.nnz == 16 * 64 * 5 == s.S.nnz
     assert np.all(s.degree == 4)

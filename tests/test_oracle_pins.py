@@ -22,16 +22,16 @@ def _pattern_rows(H):
 
 
 @pytest.fixture(scope="module")
-def mu30(c1):
+def mu30(cell256):
     """Half-filling Fermi level bisected on the nu = 30 subspace electron count."""
-    r = O.solve(c1.H, c1.S, np.arange(c1.M), 30, 0.0, KT)
-    return O.fermi_level(r.eps, r.weight, c1.M, KT)
+    r = O.solve(cell256.H, cell256.S, np.arange(cell256.M), 30, 0.0, KT)
+    return O.fermi_level(r.eps, r.weight, cell256.M, KT)
 
 
 # P1 / P12 -------------------------------------------------------------------
-def test_nu_equals_M_matches_dense_generalized_eigensolve(c1):
+def test_nu_equals_M_matches_dense_generalized_eigensolve(cell256):
     """At nu = M the subspace is the whole space: rho and E must be exact (Eq. 1, 2)."""
-    H, S, M = c1.H, c1.S, c1.M
+    H, S, M = cell256.H, cell256.S, cell256.M
     mu = -0.448
     r = O.solve(H, S, np.arange(M), M, mu, KT, workers=min(8, O.default_workers()))
     rho_d, E_d, _ = O.dense(H, S, mu, KT)
@@ -47,9 +47,9 @@ def test_nu_equals_M_matches_dense_generalized_eigensolve(c1):
     assert abs(r.n_seed.sum() - n_exact) < 1e-9
 
 
-def test_nu_lt_M_differs_from_exact(c1, mu30):
+def test_nu_lt_M_differs_from_exact(cell256, mu30):
     """Sanity: nu = 30 is an approximation (not exact), with a nonsymmetric rho."""
-    H, S, M = c1.H, c1.S, c1.M
+    H, S, M = cell256.H, cell256.S, cell256.M
     r = O.solve(H, S, np.arange(M), 30, mu30, KT)
     _, E_d, _ = O.dense(H, S, mu30, KT)
     assert abs(r.e_band - E_d) / abs(E_d) > 1e-4
@@ -58,16 +58,16 @@ def test_nu_lt_M_differs_from_exact(c1, mu30):
 
 
 # P2 -------------------------------------------------------------------------
-def test_identity_overlap_is_lanczos(c1):
+def test_identity_overlap_is_lanczos(cell256):
     """S = I: A is tridiagonal and reproduces e_j^T H^k e_j for k <= 2 nu - 1."""
-    H = c1.H
-    S = sp.identity(c1.M, format="csr")
+    H = cell256.H
+    S = sp.identity(cell256.M, format="csr")
     nu, j = 12, 37
     r = O.solve_seed(H, S, j, nu, 0.0, KT, keep=True)
     A = r.A
     off = np.abs(np.triu(A, 2)).max() / np.abs(A).max()
     assert off < 1e-13
-    x = np.zeros(c1.M)
+    x = np.zeros(cell256.M)
     x[j] = 1.0
     e1 = np.zeros(nu)
     e1[0] = 1.0
@@ -87,8 +87,8 @@ def test_identity_overlap_is_lanczos(c1):
 
 # P3 -------------------------------------------------------------------------
 @pytest.mark.parametrize("j", [0, 5, 130, 255])
-def test_nu1_closed_form(c1, j):
-    H, S = c1.H, c1.S
+def test_nu1_closed_form(cell256, j):
+    H, S = cell256.H, cell256.S
     Sd = S.toarray()
     Hd = H.toarray()
     mu = -0.3
@@ -103,11 +103,11 @@ def test_nu1_closed_form(c1, j):
 
 # P4 -------------------------------------------------------------------------
 @pytest.mark.parametrize("j", [3, 77, 200])
-def test_nu2_closed_form(c1, j):
+def test_nu2_closed_form(cell256, j):
     """span{e_j, H e_j}: 2x2 generalized eigenproblem solved by the quadratic formula."""
-    H, S = c1.H.toarray(), c1.S.toarray()
+    H, S = cell256.H.toarray(), cell256.S.toarray()
     mu = 0.4
-    ej = np.zeros(c1.M)
+    ej = np.zeros(cell256.M)
     ej[j] = 1.0
     g = H @ ej
     a11, a12, a22 = ej @ H @ ej, ej @ H @ g, g @ H @ g
@@ -117,14 +117,14 @@ def test_nu2_closed_form(c1, j):
     qc = a11 * a22 - a12 ** 2
     disc = math.sqrt(qb * qb - 4 * qa * qc)
     lams = [(-qb - disc) / (2 * qa), (-qb + disc) / (2 * qa)]
-    rho = np.zeros(c1.M)
+    rho = np.zeros(cell256.M)
     for lam in lams:
         y = np.array([a12 - lam * b12, -(a11 - lam * b11)])
         y /= math.sqrt(y @ np.array([[b11, b12], [b12, b22]]) @ y)
         v = y[0] * ej + y[1] * g
         f = 1.0 / (1.0 + math.exp((lam - mu) / KT))
         rho += 2.0 * f * v * v[j]
-    r = O.solve_seed(c1.H, c1.S, j, 2, mu, KT)
+    r = O.solve_seed(cell256.H, cell256.S, j, 2, mu, KT)
     assert np.allclose(np.sort(r.eps), lams, rtol=1e-12)
     assert np.allclose(r.rho_row, rho[r.cols], rtol=1e-10, atol=1e-13 * np.abs(rho).max())
     assert math.isclose(r.E, rho[r.cols] @ H[j, r.cols], rel_tol=1e-10)
@@ -132,19 +132,19 @@ def test_nu2_closed_form(c1, j):
 
 # P5 -------------------------------------------------------------------------
 @pytest.mark.parametrize("nu", [1, 3, 30])
-def test_full_and_empty_occupation(c1, nu):
-    seeds = np.arange(0, c1.M, 17)
-    full = O.solve(c1.H, c1.S, seeds, nu, 1e6, KT)
+def test_full_and_empty_occupation(cell256, nu):
+    seeds = np.arange(0, cell256.M, 17)
+    full = O.solve(cell256.H, cell256.S, seeds, nu, 1e6, KT)
     assert np.allclose(full.n_seed, 2.0, rtol=0, atol=1e-12)
-    empty = O.solve(c1.H, c1.S, seeds, nu, -1e6, KT)
+    empty = O.solve(cell256.H, cell256.S, seeds, nu, -1e6, KT)
     assert np.all(empty.rho == 0.0) and empty.e_band == 0.0
 
 
 # P6 -------------------------------------------------------------------------
 @pytest.mark.parametrize("nu", [5, 30])
-def test_energy_count_weight_identities(c1, mu30, nu):
+def test_energy_count_weight_identities(cell256, mu30, nu):
     for j in [0, 9, 101, 254]:
-        r = O.solve_seed(c1.H, c1.S, j, nu, mu30, KT)
+        r = O.solve_seed(cell256.H, cell256.S, j, nu, mu30, KT)
         f = O.fermi(r.eps, mu30, KT)
         assert math.isclose(r.weight.sum(), 1.0, rel_tol=1e-12)
         assert math.isclose(r.E, 2.0 * np.sum(f * r.eps * r.weight), rel_tol=1e-11, abs_tol=1e-12)
@@ -153,20 +153,20 @@ def test_energy_count_weight_identities(c1, mu30, nu):
 
 # P7 -------------------------------------------------------------------------
 @pytest.mark.parametrize("nu", [30, 256])
-def test_basis_is_S_orthonormal(c1, nu):
+def test_basis_is_S_orthonormal(cell256, nu):
     for j in [0, 128]:
-        r = O.solve_seed(c1.H, c1.S, j, nu, 0.0, KT, keep=True)
-        G = r.K @ (c1.S @ r.K.T)
+        r = O.solve_seed(cell256.H, cell256.S, j, nu, 0.0, KT, keep=True)
+        G = r.K @ (cell256.S @ r.K.T)
         assert np.abs(G - np.eye(r.nu_eff)).max() < 1e-13
 
 
 # P8 -------------------------------------------------------------------------
 @pytest.mark.parametrize("nu", [2, 3, 5, 8])
-def test_cgs2_matches_explicit_krylov_cholesky(c1, nu):
+def test_cgs2_matches_explicit_krylov_cholesky(cell256, nu):
     mu = 0.02
     for j in [1, 64, 250]:
-        r = O.solve_seed(c1.H, c1.S, j, nu, mu, KT)
-        eps_b, rho_b, E_b, N_b = O.brute_seed(c1.H, c1.S, j, nu, mu, KT)
+        r = O.solve_seed(cell256.H, cell256.S, j, nu, mu, KT)
+        eps_b, rho_b, E_b, N_b = O.brute_seed(cell256.H, cell256.S, j, nu, mu, KT)
         # the explicit Krylov matrix loses ~10x accuracy per extra column; 1e-9 covers nu = 8
         assert np.allclose(r.eps, eps_b, rtol=0, atol=1e-9)
         assert np.abs(r.rho_row - rho_b).max() <= 1e-10 * np.abs(rho_b).max()
@@ -174,18 +174,18 @@ def test_cgs2_matches_explicit_krylov_cholesky(c1, nu):
 
 
 # P9 -------------------------------------------------------------------------
-def test_energy_scale_covariance(c1):
+def test_energy_scale_covariance(cell256):
     a = 2.5
     seeds = [0, 33, 199]
-    r1 = O.solve(c1.H, c1.S, seeds, 20, 0.1, KT)
-    r2 = O.solve(a * c1.H, c1.S, seeds, 20, a * 0.1, a * KT)
+    r1 = O.solve(cell256.H, cell256.S, seeds, 20, 0.1, KT)
+    r2 = O.solve(a * cell256.H, cell256.S, seeds, 20, a * 0.1, a * KT)
     assert np.allclose(r2.rho, r1.rho, rtol=1e-10, atol=1e-12)
     assert math.isclose(r2.e_band, a * r1.e_band, rel_tol=1e-11)
 
 
-def test_permutation_covariance(c1):
+def test_permutation_covariance(cell256):
     rng = np.random.default_rng(5)
-    perm_at = rng.permutation(c1.n_atoms)
+    perm_at = rng.permutation(cell256.n_atoms)
     perm = (4 * perm_at[:, None] + np.arange(4)).ravel()     # new index -> old index
     inv = np.argsort(perm)                                   # old index -> new index
 
@@ -196,10 +196,10 @@ def test_permutation_covariance(c1):
         B.sort_indices()
         return B
 
-    H2, S2 = relabel(c1.H), relabel(c1.S)
-    assert H2.nnz == c1.H.nnz
+    H2, S2 = relabel(cell256.H), relabel(cell256.S)
+    assert H2.nnz == cell256.H.nnz
     for j in [0, 42, 255]:
-        r1 = O.solve_seed(c1.H, c1.S, j, 25, 0.1, KT)
+        r1 = O.solve_seed(cell256.H, cell256.S, j, 25, 0.1, KT)
         r2 = O.solve_seed(H2, S2, int(inv[j]), 25, 0.1, KT)
         d1 = dict(zip(r1.cols, r1.rho_row))
         d2 = dict(zip(perm[r2.cols], r2.rho_row))
@@ -210,10 +210,10 @@ def test_permutation_covariance(c1):
 
 
 # P11 ------------------------------------------------------------------------
-def test_electron_count_at_bisected_mu(c1, mu30):
-    r = O.solve(c1.H, c1.S, np.arange(c1.M), 30, mu30, KT)
-    assert abs(r.n_seed.sum() - c1.M) < 1e-8
-    assert abs(O.electron_count(r.eps, r.weight, mu30, KT) - c1.M) < 1e-8
+def test_electron_count_at_bisected_mu(cell256, mu30):
+    r = O.solve(cell256.H, cell256.S, np.arange(cell256.M), 30, mu30, KT)
+    assert abs(r.n_seed.sum() - cell256.M) < 1e-8
+    assert abs(O.electron_count(r.eps, r.weight, mu30, KT) - cell256.M) < 1e-8
 
 
 # Breakdown and errors --------------------------------------------------------
