@@ -267,6 +267,8 @@ def main() -> int:
                     help="natural: consecutive seeds (neighbouring atoms) share a block; random: a permutation of "
                          "all seeds; sampled: a sorted uniform sample of min(M, 16384) seeds")
     ap.add_argument("--no-support", action="store_true", help="stream every row of every slab")
+    ap.add_argument("--one-stream", action="store_true",
+                    help="one seed block at a time (default: two blocks in flight on two streams)")
     ap.add_argument("--no-flip", action="store_true", help="eigenstate: skip the local flipping refinement")
     ap.add_argument("--r-cut", type=int, default=-1, metavar="HOPS",
                     help="local regions of HOPS block hops (the order-N form; a different computation from the "
@@ -306,8 +308,7 @@ def main() -> int:
         log(f"copy calibration: {args.copy_calibration} MiB read + {args.copy_calibration} MiB written")
         del a, c
     ctx = mar.Context(system.H, system.S)
-    if args.seed_block or args.no_support:
-        ctx.set_tuning(args.seed_block, support=not args.no_support)
+    ctx.set_tuning(args.seed_block, support=not args.no_support, two_streams=not args.one_stream)
     local = args.r_cut >= 0
     if local:
         ctx.set_local_region(args.r_cut)
@@ -483,7 +484,8 @@ def main() -> int:
         "config": {"workload": f"{system.name} mixed sp2/sp3 lattice, M={M}, nu={nu}, kT={KT}, FP32 batched",
                    "M": M, "nnz": int(system.H.nnz), "nu": nu, "seeds_per_step": S_step, "seed_block": B,
                    "precision": "fp32", "form": "batched", "mu": mu, "seed_order": args.seed_order,
-                   "support_tracking": not args.no_support, "local_region_hops": args.r_cut if local else None},
+                   "support_tracking": not args.no_support, "local_region_hops": args.r_cut if local else None,
+                   "two_streams": not args.one_stream},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fp64_plain": plain,

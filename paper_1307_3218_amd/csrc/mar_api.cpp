@@ -661,7 +661,7 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     const size_t oM0 = take(local ? (size_t)nbrow * mW * 4 : 0), oM1 = take(local ? (size_t)nbrow * mW * 4 : 0);
     const size_t set_bytes = off;
     const int64_t n_blocks = (n_seeds + B - 1) / B;
-    const int nset = n_blocks >= 2 && !c->prof && !c->in_graph && c->es.mode == 0 && c->tune.single_stream == 0 &&
+    const int nset = n_blocks >= 2 && !c->prof && !c->in_graph && c->es.mode == 0 && c->tune.two_streams == 1 &&
                              c->stream2 &&
                              2.0 * (double)set_bytes <= kTwoSetBytes
                          ? 2
@@ -1712,7 +1712,7 @@ mar_status mar_set_tuning(mar_ctx* c, const mar_tuning* t) {
     if (t->upd_q != 0 && t->upd_q != 2 && t->upd_q != 4 && t->upd_q != 8)
         return set_err(c, MAR_ERR_ARG, "upd_q must be 0, 2, 4 or 8");
     if (t->support_off != 0 && t->support_off != 1) return set_err(c, MAR_ERR_ARG, "support_off must be 0 or 1");
-    if (t->single_stream != 0 && t->single_stream != 1) return set_err(c, MAR_ERR_ARG, "single_stream must be 0 or 1");
+    if (t->two_streams != 0 && t->two_streams != 1) return set_err(c, MAR_ERR_ARG, "two_streams must be 0 or 1");
     c->tune = *t;
     return MAR_OK;
 }

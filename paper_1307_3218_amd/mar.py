@@ -37,7 +37,7 @@ class MarError(RuntimeError):
 class mar_tuning(C.Structure):
     _fields_ = [("seed_block", C.c_int32), ("schedule", C.c_int32), ("proj_wgs", C.c_int32),
                 ("slab_pad_kb", C.c_int32), ("proj_variant", C.c_int32), ("upd_q", C.c_int32),
-                ("support_off", C.c_int32), ("single_stream", C.c_int32)]
+                ("support_off", C.c_int32), ("two_streams", C.c_int32)]
 
 
 class mar_request(C.Structure):
@@ -230,8 +230,8 @@ def mar_autotune(ctx, nu, prec, d_seeds, mu, kT, stream=None) -> tuple:
 
 
 def mar_set_tuning(ctx, seed_block: int = 0, schedule: int = 0, proj_wgs: int = 0, slab_pad_kb: int = 0,
-                   proj_variant: int = 0, upd_q: int = 0, support_off: int = 0, single_stream: int = 0) -> int:
-    t = mar_tuning(seed_block, schedule, proj_wgs, slab_pad_kb, proj_variant, upd_q, support_off, single_stream)
+                   proj_variant: int = 0, upd_q: int = 0, support_off: int = 0, two_streams: int = 0) -> int:
+    t = mar_tuning(seed_block, schedule, proj_wgs, slab_pad_kb, proj_variant, upd_q, support_off, two_streams)
     return lib().mar_set_tuning(ctx, C.byref(t))
 
 
@@ -399,9 +399,9 @@ class Context:
         return mar_local_region(self.handle)
 
     def set_tuning(self, seed_block: int = 0, schedule: str = "auto", proj_wgs: int = 0, slab_pad_kb: int = 0,
-                   proj_variant: int = 0, upd_q: int = 0, support: bool = True, two_streams: bool = True):
+                   proj_variant: int = 0, upd_q: int = 0, support: bool = True, two_streams: bool = False):
         _check(self.handle, mar_set_tuning(self.handle, seed_block, SCHEDULE[schedule], proj_wgs, slab_pad_kb,
-                                           proj_variant, upd_q, 0 if support else 1, 0 if two_streams else 1))
+                                           proj_variant, upd_q, 0 if support else 1, 1 if two_streams else 0))
 
     def autotune(self, d_seeds, nu, mu, kT, precision="fp32", stream=None) -> dict:
         """Pick the seed block and projection tiles for (nu, precision) by timing probe solves."""
