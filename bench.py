@@ -81,11 +81,42 @@ def cpu_baseline(system, nu, mu, n_seeds, workers):
     from paper_1307_3218_amd import lattice
     seeds = lattice.sample_seeds(system.M, n_seeds, seed=99)
     t0 = time.perf_counter()
-    O.solve(system.H, system.S, seeds, nu, mu, KT, workers=workers)
+    ref = O.solve(system.H, system.S, seeds, nu, mu, KT, workers=workers)
     dt = time.perf_counter() - t0
     return dict(value=n_seeds / dt, unit="seed-subspaces/s", cores=workers, kind="oracle",
                 sample=f"{n_seeds} uniformly sampled seeds of the same workload (nu={nu}), "
-                       f"FP64 NumPy/SciPy, one process per core, {dt:.1f} s wall")
+                       f"FP64 NumPy/SciPy, one process per core, {dt:.1f} s wall"), seeds, ref
+
+
+def copy_rate(torch, dev, mib=1024, reps=3):
+    """Bytes read + written per second by a 1 GiB device-to-device copy (best of reps)."""
+    a = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device=dev)
+    c = torch.empty_like(a)
+    best = float("inf")
+    for _ in range(reps + 1):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        c.copy_(a)
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t)
+    del a, c
+    return 2.0 * mib * (1 << 20) / best / 1e9
+
+
+def errors_vs_oracle(ctx, system, seeds, ref, nu, mu):
+    """Per-result error of the device forms against the oracle on the oracle's seeds."""
+    H = system.H
+    idx = np.concatenate([np.arange(H.indptr[j], H.indptr[j + 1]) for j in seeds])
+    out = {}
+    for prec, form in (("fp32", "batched"), ("fp64", "batched"), ("fp64", "plain")):
+        g = ctx.solve(np.asarray(seeds, dtype=np.int32), nu, mu, KT, precision=prec, form=form)
+        out[f"{prec}_{form}"] = dict(
+            e_band_rel=float(abs(g.e_band - ref.e_band) / abs(ref.e_band)),
+            rho_rel=float(np.linalg.norm(g.rho[idx] - ref.rho[idx]) / np.linalg.norm(ref.rho[idx])),
+            e_seed_max_abs=float(np.abs(g.e_seed - ref.e_seed).max()),
+            n_seed_max_abs=float(np.abs(g.n_seed - ref.n_seed).max()),
+            nu_eff_equal=bool(np.array_equal(g.nu_eff, ref.nu_eff)))
+    return out
 
 
 def cpu_baseline_local(system, nu, mu, r, budget_s=12.0):
@@ -232,6 +263,18 @@ def run_eigenstate(args) -> int:
         flip = dict(seconds=round(tf, 4), sweeps=int(info[0]), flips=int(info[1]), colours=ctx.flip_colours(),
                     R_before=float(R[0]), R_after=float(R[-1]))
         log(f"local flipping: {info[0]} sweeps, {info[1]} flips, R {R[0]:.4e} -> {R[-1]:.4e} in {tf * 1e3:.1f} ms")
+        if not args.no_cpu_baseline:
+            # the flip oracle on the same vector, on one host core: its time, and the same refined vector
+            from oracle import mar_flip as OF
+            col = OF.distance2_colouring(s.H)
+            t0 = time.perf_counter()
+            ref = OF.local_flip(s.H, s.S, phi, float(lv[0]), max_sweeps=100, colour=col)
+            tc = time.perf_counter() - t0
+            same = bool(np.array_equal(ref.phi, d_x.cpu().numpy())) and ref.flips == flip["flips"]
+            flip["cpu_baseline"] = dict(value=round(tc, 3), unit="s", cores=1, kind="oracle",
+                                        sample="the same eigen-state vector (all 16384 components), 100 sweeps max")
+            flip["equal_to_oracle"] = same
+            log(f"flip oracle: {tc:.2f} s on one core; refined vector equal to the device's: {same}")
     out = {
         "metric": "eigen state (Sec. 3, Eq. 3): time for one level and vector over every seed",
         "value": round(dt, 4), "unit": "s", "n_gpus": 1, "steps": len(times), "warmup": 1,
@@ -422,8 +465,10 @@ def main() -> int:
         s = prof.get("spmm")
         if s and s["ms"] > 0:
             sa = s["bytes"] / (s["ms"] * 1e-3) / 1e9
+            cp = copy_rate(torch, dev)
             spmm = dict(achieved=round(sa, 1), peak=HBM_PEAK_GBPS, unit="GB/s", frac=round(sa / HBM_PEAK_GBPS, 4),
-                        avg_launch_us=1e3 * s["ms"] / s["launches"])
+                        avg_launch_us=1e3 * s["ms"] / s["launches"], device_copy_GBps=round(cp, 1),
+                        frac_of_copy=round(sa / cp, 4))
 
     # the plain FP64 form on the same GPU (one seed per block, one launch per phase)
     plain = None
@@ -457,6 +502,7 @@ def main() -> int:
             log(f"{prec} {form}: {n_x} seeds in {dtx:.3f} s -> {n_x / dtx:.2f} seed-subspaces/s")
 
     cpu = None
+    errors = None
     if not args.no_cpu_baseline and local:
         cpu = cpu_baseline_local(system, nu, mu, args.r_cut)
         log(f"cpu oracle (local regions): {cpu['value']:.2f} seed-subspaces/s on 1 core")
@@ -465,8 +511,12 @@ def main() -> int:
         workers = min(16, O.default_workers())
         n_cpu = args.cpu_seeds or max(workers, int(round(20.0 / 1.3)))
         n_cpu = max(n_cpu, workers)
-        cpu = cpu_baseline(system, nu, mu, n_cpu, workers)
+        cpu, cpu_seeds, cpu_ref = cpu_baseline(system, nu, mu, n_cpu, workers)
         log(f"cpu oracle: {cpu['value']:.2f} seed-subspaces/s on {workers} cores")
+        errors = errors_vs_oracle(ctx, system, cpu_seeds, cpu_ref, nu, mu)
+        for k, e in errors.items():
+            log(f"error vs oracle, {k}: E_band {e['e_band_rel']:.2e}, rho {e['rho_rel']:.2e}, "
+                f"nu_eff equal {e['nu_eff_equal']}")
 
     out = {
         "metric": METRIC_LOCAL.format(r=args.r_cut) if local else METRIC,
@@ -488,6 +538,7 @@ def main() -> int:
                    "two_streams": not args.one_stream},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "error_vs_oracle": errors,
         "fp64_plain": plain,
         "ratio_fp32_batched_over_fp64_plain": round(value / plain["value"], 3) if plain else None,
         "precision_batching_split": split or None,
