@@ -135,18 +135,23 @@ LaunchInfo launch_sum(const double* x, int64_t n, double* out, hipStream_t s) {
     return li;
 }
 
-// Zero n16 16-byte words (used for the padded rows of the work vectors; a
-// kernel rather than a memset so the sequence stays capturable).
+// Zero n16 16-byte words (the padded rows of the work vectors, and the basis
+// of a seed block under support tracking; a kernel rather than a memset so the
+// sequence stays capturable). A grid-stride loop over a bounded grid: a launch
+// must stay below 2^32 work-items, and the basis of the largest instance is
+// 80 GB (5e9 words).
+constexpr int64_t ZERO_MAX_WGS = 16384;
 __global__ __launch_bounds__(WG) void k_zero(double2* __restrict__ p, int64_t n16) {
-    const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
-    if (i < n16) p[i] = make_double2(0.0, 0.0);
+    const int64_t step = (int64_t)gridDim.x * WG;
+    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n16; i += step) p[i] = make_double2(0.0, 0.0);
 }
 
 LaunchInfo launch_zero(void* p, int64_t bytes, hipStream_t s) {
     const int64_t n16 = bytes / 16;
-    const int64_t wgs = (n16 + WG - 1) / WG;
+    const int64_t need = (n16 + WG - 1) / WG;
+    const int64_t wgs = need < ZERO_MAX_WGS ? need : ZERO_MAX_WGS;
     LaunchInfo li;
-    if (wgs > 0) hipLaunchKernelGGL(k_zero, dim3(wgs), dim3(WG), 0, s, (double2*)p, n16);
+    if (wgs > 0) hipLaunchKernelGGL(k_zero, dim3((unsigned)wgs), dim3(WG), 0, s, (double2*)p, n16);
     li.wgs = wgs;
     li.bytes = (double)bytes;
     return li;

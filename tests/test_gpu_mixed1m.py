@@ -110,3 +110,22 @@ def test_mixed1m_fp64_plain(mixed1m_ctx, mixed1m, golden):
 
 def test_mixed1m_fp64_batched(mixed1m_ctx, mixed1m, golden):
     _check(golden, _solve(mixed1m_ctx, mixed1m, golden, "fp64", "batched", block=8), "fp64", "batched B=8")
+
+
+def test_mixed1m_blocks_in_sequence(mixed1m_ctx, golden):
+    """A block of neighbouring seeds solved after another block equals that block solved alone.
+
+    Between blocks the whole 80 GB basis is zeroed (support tracking reads tiles the block has not
+    written yet as zeros); a fill of more than 2^32 work-items in one launch covers only part of it and
+    leaves later slabs holding the previous block's vectors.
+    """
+    fill = np.arange(0, 64, dtype=np.int32)
+    x = np.arange(500000, 500064, dtype=np.int32)
+    mixed1m_ctx.set_tuning(seed_block=64)
+    try:
+        both = mixed1m_ctx.solve(np.concatenate([fill, x]), golden["nu"], golden["mu"], golden["kT"], "fp32")
+        alone = mixed1m_ctx.solve(x, golden["nu"], golden["mu"], golden["kT"], "fp32")
+    finally:
+        mixed1m_ctx.set_tuning()
+    assert np.array_equal(both.nu_eff[64:], alone.nu_eff)
+    assert np.array_equal(both.e_seed[64:], alone.e_seed)
