@@ -310,8 +310,8 @@ def main() -> int:
                     help="natural: consecutive seeds (neighbouring atoms) share a block; random: a permutation of "
                          "all seeds; sampled: a sorted uniform sample of min(M, 16384) seeds")
     ap.add_argument("--no-support", action="store_true", help="stream every row of every slab")
-    ap.add_argument("--one-stream", action="store_true",
-                    help="one seed block at a time (default: two blocks in flight on two streams)")
+    ap.add_argument("--two-streams", action="store_true",
+                    help="two seed blocks in flight on two streams (default: one block at a time)")
     ap.add_argument("--no-flip", action="store_true", help="eigenstate: skip the local flipping refinement")
     ap.add_argument("--r-cut", type=int, default=-1, metavar="HOPS",
                     help="local regions of HOPS block hops (the order-N form; a different computation from the "
@@ -351,7 +351,7 @@ def main() -> int:
         log(f"copy calibration: {args.copy_calibration} MiB read + {args.copy_calibration} MiB written")
         del a, c
     ctx = mar.Context(system.H, system.S)
-    ctx.set_tuning(args.seed_block, support=not args.no_support, two_streams=not args.one_stream)
+    ctx.set_tuning(args.seed_block, support=not args.no_support, two_streams=args.two_streams)
     local = args.r_cut >= 0
     if local:
         ctx.set_local_region(args.r_cut)
@@ -412,8 +412,8 @@ def main() -> int:
             torch.cuda.synchronize()
         log(f"warmup step {k}: {time.perf_counter() - t:.2f} s")
 
-    # timed region: the batched FP32 form (no per-kernel events: with two seed blocks in flight the library
-    # alternates them between two streams, which its profiling mode does not)
+    # timed region: the batched FP32 form (no per-kernel events: with --two-streams the library alternates
+    # seed blocks between two streams, which its profiling mode does not)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.warmup, n_steps):
@@ -535,7 +535,7 @@ def main() -> int:
                    "M": M, "nnz": int(system.H.nnz), "nu": nu, "seeds_per_step": S_step, "seed_block": B,
                    "precision": "fp32", "form": "batched", "mu": mu, "seed_order": args.seed_order,
                    "support_tracking": not args.no_support, "local_region_hops": args.r_cut if local else None,
-                   "two_streams": not args.one_stream},
+                   "two_streams": args.two_streams},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "error_vs_oracle": errors,

@@ -625,7 +625,11 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     const int hreach = local ? std::min(nu, (int)c->loc) : nu;   // farthest hop a vector can reach
     const int64_t ntiles = (nbrow + bpt - 1) / bpt;
     const int64_t grid_max = mar::projr_sp_grid(target, nu, kg);
-    size_t part_doubles = (size_t)std::max<int64_t>(spmm_wgs, 2048) * 2 * B;
+    size_t part_doubles = 0;
+    // S-norm partials of the fused product, one slot per workgroup (read by the coefficient kernel after the
+    // projection has reused part)
+    const size_t np_doubles = (size_t)std::max<int64_t>(spmm_wgs, kListWgs) * 2 * B;
+    const int64_t np_cap = (int64_t)np_doubles;
     for (int nk = 1; nk <= nu; ++nk) {
         const mar::ProjrGeom gm = mar::projr_geometry(nvec, nk, variant, target);
         part_doubles = std::max<size_t>(part_doubles, (size_t)gm.groups * 3 * nk * B);
@@ -645,7 +649,7 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     // them and between the caller's stream and the context's second stream, so that one block's short FP64
     // kernels (reductions, coefficients, norms, eigensolver) overlap the other block's streaming sweeps.
     const size_t oK = take((size_t)nu * stride * sizeof(T)), oY = take(slab), oSY = take(slab), oZT = take(slab);
-    const size_t oPart = take(part_doubles * 8);
+    const size_t oPart = take(part_doubles * 8), oNP = take(np_doubles * 8);
     const size_t oRed = take((size_t)3 * nu * B * 8), oRedb = take((size_t)2 * B * 8);
     const size_t oH = take((size_t)B * nu * nu * 8), oG = take((size_t)B * nu * nu * 8);
     const size_t oKp = take((size_t)B * nu * std::max(1, c->max_row) * 8), oNc = take((size_t)B * 4);
@@ -717,6 +721,7 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
         T* SY = (T*)(ws + oSY);
         T* ZT = (T*)(ws + oZT);
         double* part = (double*)(ws + oPart);
+        double* npart = (double*)(ws + oNP);
         double* red = (double*)(ws + oRed);
         double* redb = (double*)(ws + oRedb);
         double* h = (double*)(ws + oH);
@@ -797,28 +802,26 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
             if (dual) {
                 const bool rec = launch(c, s, n == 0 ? P_SPMM : P_SPMM_DOT, [&] {
                     LaunchInfo li = local && sparse
-                        ? mar::launch_spmm2_list<T>(B, c->H, c->SH, Kn, Y, ZT, n == 0 ? nullptr : part,
-                                                    n == 0 ? 0 : 2, part_cap, slist, scnt, n + 1, lmask, mW,
+                        ? mar::launch_spmm2_list<T>(B, c->H, c->SH, Kn, Y, ZT, n == 0 ? nullptr : npart,
+                                                    n == 0 ? 0 : 2, np_cap, slist, scnt, n + 1, lmask, mW,
                                                     kListWgs, s)
-                        : mar::launch_spmm2<T>(B, c->H, c->SH, Kn, Y, ZT, n == 0 ? nullptr : part, n == 0 ? 0 : 2,
-                                               part_cap, s, TD, n + 1, lmask, mW);
+                        : mar::launch_spmm2<T>(B, c->H, c->SH, Kn, Y, ZT, n == 0 ? nullptr : npart, n == 0 ? 0 : 2,
+                                               np_cap, s, TD, n + 1, lmask, mW);
                     swgs = li.wgs;
                     return li;
                 });
                 tag(rec, SP_FRAC, n + 1, bi, (double)ntiles);
             } else if (n >= 1) {
                 launch(c, s, P_SPMM_DOT, [&] {
-                    LaunchInfo li = mar::launch_spmm<T>(B, c->S, Kn, ZT, part, 2, part_cap, s);
+                    LaunchInfo li = mar::launch_spmm<T>(B, c->S, Kn, ZT, npart, 2, np_cap, s);
                     swgs = li.wgs;
                     return li;
                 });
             }
-            if (n >= 1) {
-                launch(c, s, P_REDUCE, [&] { return mar::launch_reduce(part, swgs, 2 * B, redb, nullptr, B, nu, n, s); });
-                launch(c, s, P_NORM, [&] {
-                    return mar::launch_norm2(B, nu, n - 1, redb, C1, tau, active, nu_blk, BT, UU, s);
-                });
-            }
+            // the S-norm partials of slab n, summed across workgroups (a coalesced transposing reduction);
+            // the breakdown test itself runs at the start of this step's coefficient kernel
+            if (n >= 1)
+                launch(c, s, P_REDUCE, [&] { return mar::launch_reduce(npart, swgs, 2 * B, redb, nullptr, B, nu, n, s); });
             if (!dual) launch(c, s, P_SPMM, [&] { return mar::launch_spmm<T>(B, c->H, Kn, Y, nullptr, 0, 0, s); });
             if (sparse) {
                 const bool rec = launch(c, s, P_SPMM, [&] {
@@ -849,7 +852,7 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
             }
             launch(c, s, P_COEF, [&] {
                 return mar::launch_coef(B, nu, n, red, h, G, R, C1, BT, UU, cA, cB, cAf, cBf, gam, Fn, active,
-                                        nu_blk, tau, s);
+                                        nu_blk, tau, n >= 1 ? redb : nullptr, s);
             });
             const bool ru = launch(c, s, P_UPD2, [&] {
                 // w' goes straight into slab n + 1, unnormalized (its scale is handled by k_coef)

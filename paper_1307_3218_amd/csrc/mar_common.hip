@@ -186,11 +186,12 @@ LaunchInfo launch_zero(void* p, int64_t bytes, hipStream_t s) {
 __global__ __launch_bounds__(WG) void k_coef(int B, int nu, int n, const double* __restrict__ red,
                                              double* __restrict__ Ah, double* __restrict__ Gm,
                                              double* __restrict__ Rm, double* __restrict__ C1,
-                                             const double* __restrict__ BT, const double* __restrict__ UU,
+                                             double* __restrict__ BT, double* __restrict__ UU,
                                              double* __restrict__ cA, double* __restrict__ cB,
                                              float* __restrict__ cAf, float* __restrict__ cBf,
                                              double* __restrict__ gam, double* __restrict__ Fn,
-                                             int32_t* __restrict__ active, int32_t* __restrict__ nu_eff, double tau) {
+                                             int32_t* __restrict__ active, int32_t* __restrict__ nu_eff, double tau,
+                                             const double* __restrict__ redb) {
     extern __shared__ double sm[];
     const int b = blockIdx.x, tid = threadIdx.x;
     const int nk = n + 1;
@@ -228,6 +229,40 @@ __global__ __launch_bounds__(WG) void k_coef(int B, int nu, int n, const double*
             }
         }
     };
+    // Step n >= 1 (redb != nullptr): first the breakdown test of slab n, the unnormalized residual of step
+    // n - 1, from redb = {u~.S u~ [B], u~.u~ [B]}: beta~ = sqrt(u~.S u~) <= tau sqrt(|c1_prev|^2 + beta~^2)
+    // stops the seed at nu_eff = n; a negative or non-finite u~.S u~ flags S as not positive definite
+    // (nu_eff = -1). Otherwise beta~ and u~.u~ / beta~^2 become BT and UU.
+    double btp = BT[b], uu = UU[b];
+    if (redb != nullptr) {
+        double s2 = 0.0;
+        for (int k = tid; k < n; k += WG) {
+            const double a = C1[(int64_t)b * nu + k];
+            s2 += a * a;
+        }
+        const double bb = redb[b], ww = redb[B + b], cc = bsum(s2);
+        if (active[b]) {
+            int nu_new = 0;
+            const bool bad = !(bb >= 0.0) || !(bb < INFINITY);
+            if (bad) nu_new = -1;
+            else if (sqrt(bb) <= tau * sqrt(cc + bb)) nu_new = n;
+            if (bad || nu_new == n) {
+                if (tid == 0) {
+                    nu_eff[b] = nu_new;
+                    active[b] = 0;
+                    BT[b] = 0.0;
+                }
+                stop(-1);
+                return;
+            }
+            btp = sqrt(bb);
+            uu = ww / bb;
+            if (tid == 0) {
+                BT[b] = btp;
+                UU[b] = uu;
+            }
+        }
+    }
     if (!active[b]) {
         stop(-1);
         return;
@@ -235,7 +270,7 @@ __global__ __launch_bounds__(WG) void k_coef(int B, int nu, int n, const double*
     double* A = Ah + (int64_t)b * nu * nu;
     double* G = Gm + (int64_t)b * nu * nu;
     double* Rc = Rm + (int64_t)b * nu * (nu + 1);
-    const double sc = n >= 1 ? BT[b] : 1.0;   // scale of slab n
+    const double sc = n >= 1 ? btp : 1.0;   // scale of slab n
     for (int k = tid; k < n; k += WG) {
         c2[k] = red[((int64_t)0 * nk + k) * B + b] / sc;
         g[k] = red[((int64_t)1 * nk + k) * B + b] / sc;
@@ -259,7 +294,6 @@ __global__ __launch_bounds__(WG) void k_coef(int B, int nu, int n, const double*
         return;
     }
     const double gm = sqrt(gam2);
-    const double btp = BT[b], uu = UU[b];
     if (n >= 1) {
         const double bf = btp * gm;
         const double eta = sqrt(s_c1p + btp * btp * (s_cc + gam2));
@@ -323,68 +357,17 @@ __global__ __launch_bounds__(WG) void k_coef(int B, int nu, int n, const double*
 }
 
 LaunchInfo launch_coef(int B, int nu, int n, const double* red, double* A, double* G, double* R, double* C1,
-                       const double* BT, const double* UU, double* cA, double* cB, float* cAf, float* cBf,
-                       double* gam, double* Fn, int32_t* active, int32_t* nu_eff, double tau, hipStream_t s) {
+                       double* BT, double* UU, double* cA, double* cB, float* cAf, float* cBf,
+                       double* gam, double* Fn, int32_t* active, int32_t* nu_eff, double tau, const double* redb,
+                       hipStream_t s) {
     const size_t lds = (size_t)(7 * (nu + 1) + 8) * sizeof(double);
     hipLaunchKernelGGL(k_coef, dim3(B), dim3(WG), lds, s, B, nu, n, red, A, G, R, C1, BT, UU, cA, cB, cAf, cBf, gam,
-                       Fn, active, nu_eff, tau);
+                       Fn, active, nu_eff, tau, redb);
     LaunchInfo li;
     li.wgs = B;
     const double nn = (double)n + 1.0;
     li.bytes = (double)B * (3.0 * nn * nn + 8.0 * nn) * 8.0;
     li.flops = (double)B * 8.0 * nn * nn;
-    return li;
-}
-
-// First-pass norm of the new residual w' (FP64): beta~ = sqrt(w'.S w'); the
-// vector is dropped when beta~ <= tau * sqrt(|c1|^2 + beta~^2); a negative or
-// non-finite w'.S w' flags S as not positive definite (nu_eff = -1).
-__global__ __launch_bounds__(WG) void k_norm2(int B, int nk, int nu, const double* __restrict__ redb,
-                                              const double* __restrict__ C1, double tau,
-                                              int32_t* __restrict__ active, int32_t* __restrict__ nu_eff,
-                                              double* __restrict__ BT, double* __restrict__ UU, int n) {
-    __shared__ double lds[WG];
-    const int np = WG / B;
-    const int b = threadIdx.x % B, part = threadIdx.x / B;
-    double s = 0.0;
-    if (part < np)
-        for (int k = part; k < nk; k += np) {
-            const double a = C1[(int64_t)b * nu + k];
-            s += a * a;
-        }
-    lds[threadIdx.x] = s;
-    __syncthreads();
-    if ((int)threadIdx.x >= B) return;
-    double cc = 0.0;
-    for (int p = 0; p < np; ++p) cc += lds[p * B + b];
-    if (!active[b]) {
-        BT[b] = 0.0;
-        return;
-    }
-    const double bb = redb[b], ww = redb[B + b];
-    if (!(bb >= 0.0) || !(bb < INFINITY)) {
-        nu_eff[b] = -1;
-        active[b] = 0;
-        BT[b] = 0.0;
-        return;
-    }
-    const double bt = sqrt(bb);
-    if (bt <= tau * sqrt(cc + bb)) {
-        nu_eff[b] = n + 1;
-        active[b] = 0;
-        BT[b] = 0.0;
-        return;
-    }
-    BT[b] = bt;
-    UU[b] = ww / bb;
-}
-
-LaunchInfo launch_norm2(int B, int nu, int n, const double* redb, const double* C1, double tau, int32_t* active,
-                        int32_t* nu_eff, double* BT, double* UU, hipStream_t s) {
-    hipLaunchKernelGGL(k_norm2, dim3(1), dim3(WG), 0, s, B, n + 1, nu, redb, C1, tau, active, nu_eff, BT, UU, n);
-    LaunchInfo li;
-    li.wgs = 1;
-    li.bytes = (double)B * (n + 4) * 8.0;
     return li;
 }
 

@@ -199,11 +199,12 @@ LaunchInfo launch_upd2(int B, T* basis, int64_t M, int64_t stride, int n, const 
                        const double* gam, const double* Fn, const T* y, T* wout, bool want_w, int upd_q,
                        hipStream_t s, const int32_t* tdist = nullptr);
 // cAf/cBf (optional): the update coefficients rounded to FP32 for an FP32 basis.
+// redb (n >= 1): {u~.S u~ [B], u~.u~ [B]} of slab n; the kernel first takes the breakdown test of slab n and
+// sets BT, UU.
 LaunchInfo launch_coef(int B, int nu, int n, const double* red, double* A, double* G, double* R, double* C1,
-                       const double* BT, const double* UU, double* cA, double* cB, float* cAf, float* cBf,
-                       double* gam, double* Fn, int32_t* active, int32_t* nu_eff, double tau, hipStream_t s);
-LaunchInfo launch_norm2(int B, int nu, int n, const double* redb, const double* C1, double tau, int32_t* active,
-                        int32_t* nu_eff, double* BT, double* UU, hipStream_t s);
+                       double* BT, double* UU, double* cA, double* cB, float* cAf, float* cBf,
+                       double* gam, double* Fn, int32_t* active, int32_t* nu_eff, double tau, const double* redb,
+                       hipStream_t s);
 
 LaunchInfo launch_reduce(const double* part, int64_t nchunks, int64_t L, double* out, double* h, int B, int nu,
                          int n, hipStream_t s);
