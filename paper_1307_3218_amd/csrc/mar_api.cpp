@@ -821,7 +821,10 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
             // the S-norm partials of slab n, summed across workgroups (a coalesced transposing reduction);
             // the breakdown test itself runs at the start of this step's coefficient kernel
             if (n >= 1)
-                launch(c, s, P_REDUCE, [&] { return mar::launch_reduce(npart, swgs, 2 * B, redb, nullptr, B, nu, n, s); });
+                // (the projection partials of this step are not written yet: their buffer is the scratch)
+                launch(c, s, P_REDUCE, [&] {
+                    return mar::launch_reduce(npart, swgs, 2 * B, redb, nullptr, B, nu, n, s, part, part_cap);
+                });
             if (!dual) launch(c, s, P_SPMM, [&] { return mar::launch_spmm<T>(B, c->H, Kn, Y, nullptr, 0, 0, s); });
             if (sparse) {
                 const bool rec = launch(c, s, P_SPMM, [&] {

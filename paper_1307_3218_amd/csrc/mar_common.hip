@@ -41,10 +41,53 @@ __global__ __launch_bounds__(WG) void k_reduce(const double* __restrict__ part, 
     }
 }
 
+// First stage of a two-stage reduction of many chunks onto few outputs:
+// tmp[y * L + o] = sum of part[c * L + o] over the chunks c of range y
+// (chunks [y * cps, (y + 1) * cps)), four chunk lanes of 64 outputs per
+// workgroup, each lane's chunks in order with four running sums, then the
+// lanes in order. Rows of 64 consecutive outputs are read whole.
+__global__ __launch_bounds__(WG) void k_reduce_split(const double* __restrict__ part, int64_t nchunks, int64_t L,
+                                                     int64_t cps, double* __restrict__ tmp) {
+    const int oi = threadIdx.x % 64, cl = threadIdx.x / 64;
+    const int64_t o = (int64_t)blockIdx.x * 64 + oi;
+    const int64_t c0 = (int64_t)blockIdx.y * cps;
+    const int64_t c1 = c0 + cps < nchunks ? c0 + cps : nchunks;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    if (o < L) {
+        int64_t c = c0 + cl;
+        for (; c + 12 < c1; c += 16) {
+            s0 += part[c * L + o];
+            s1 += part[(c + 4) * L + o];
+            s2 += part[(c + 8) * L + o];
+            s3 += part[(c + 12) * L + o];
+        }
+        for (; c < c1; c += 4) s0 += part[c * L + o];
+    }
+    __shared__ double lds[WG];
+    lds[threadIdx.x] = (s0 + s1) + (s2 + s3);
+    __syncthreads();
+    if (cl == 0 && o < L)
+        tmp[(int64_t)blockIdx.y * L + o] = ((lds[oi] + lds[64 + oi]) + lds[128 + oi]) + lds[192 + oi];
+}
+
 LaunchInfo launch_reduce(const double* part, int64_t nchunks, int64_t L, double* out, double* h, int B, int nu,
-                         int n, hipStream_t s) {
+                         int n, hipStream_t s, double* tmp, int64_t tmp_cap) {
     const int64_t hL = h ? (int64_t)(n + 1) * B : 0;
     LaunchInfo li;
+    // Many chunks onto few outputs (the per-workgroup partials of a product kernel): split the chunks into
+    // ranges of RED_CPS, reduce each range over whole rows, then the range sums in order.
+    constexpr int64_t RED_CPS = 128;
+    const int64_t nsplit = (nchunks + RED_CPS - 1) / RED_CPS;
+    if (tmp != nullptr && nchunks >= 8 * RED_CPS && L <= 4096 && nsplit * L <= tmp_cap) {
+        const dim3 grid((unsigned)((L + 63) / 64), (unsigned)nsplit);
+        hipLaunchKernelGGL(k_reduce_split, grid, dim3(WG), 0, s, part, nchunks, L, RED_CPS, tmp);
+        const int64_t wgs = (L + 3) / 4;
+        hipLaunchKernelGGL((k_reduce<4>), dim3(wgs), dim3(WG), 0, s, tmp, nsplit, L, out, h, B, nu, n, hL);
+        li.wgs = (int64_t)grid.x * grid.y + wgs;
+        li.bytes = (double)(nchunks + 2 * nsplit + 1) * L * 8.0;
+        li.flops = (double)nchunks * L;
+        return li;
+    }
     if (L <= 2048) {
         const int64_t wgs = (L + 3) / 4;
         hipLaunchKernelGGL((k_reduce<4>), dim3(wgs), dim3(WG), 0, s, part, nchunks, L, out, h, B, nu, n, hL);
@@ -304,14 +347,24 @@ __global__ __launch_bounds__(WG) void k_coef(int B, int nu, int n, const double*
         for (int p = tid; p < n; p += WG) Rc[(int64_t)(n - 1) * (nu + 1) + p] = c1p[p] + btp * c2[p];
         if (tid == 0) Rc[(int64_t)(n - 1) * (nu + 1) + n] = btp * gm;
         for (int p = tid; p < n; p += WG) {
-            double sg = 0.0, sc = 0.0;
-            for (int k = 0; k < n; ++k) {
-                const double gkp = G[(int64_t)k * nu + p];
-                sg += gkp * c1p[k];
-                sc += gkp * c2[k];
+            // four running sums each, so that four loads of G are in flight
+            double sg[4] = {0.0, 0.0, 0.0, 0.0}, sv[4] = {0.0, 0.0, 0.0, 0.0};
+            int k = 0;
+            for (; k + 3 < n; k += 4) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const double gkp = G[(int64_t)(k + i) * nu + p];
+                    sg[i] += gkp * c1p[k + i];
+                    sv[i] += gkp * c2[k + i];
+                }
             }
-            t[p] = (A[(int64_t)p * nu + (n - 1)] - sg) / btp;
-            gc2[p] = sc;
+            for (; k < n; ++k) {
+                const double gkp = G[(int64_t)k * nu + p];
+                sg[0] += gkp * c1p[k];
+                sv[0] += gkp * c2[k];
+            }
+            t[p] = (A[(int64_t)p * nu + (n - 1)] - ((sg[0] + sg[1]) + (sg[2] + sg[3]))) / btp;
+            gc2[p] = (sv[0] + sv[1]) + (sv[2] + sv[3]);
         }
     }
     __syncthreads();
@@ -327,16 +380,27 @@ __global__ __launch_bounds__(WG) void k_coef(int B, int nu, int n, const double*
     if (tid == 0) G[(int64_t)n * nu + n] = (uu - 2.0 * s_ct + s_cgc) / gam2;
     // q = R[:n+1, :n] c2 (R_{p,k} vanishes for p > k + 1)
     for (int p = tid; p <= n; p += WG) {
-        double sq = 0.0;
-        for (int k = (p > 0 ? p - 1 : 0); k < n; ++k) sq += Rc[(int64_t)k * (nu + 1) + p] * c2[k];
-        q[p] = sq;
+        double sq[4] = {0.0, 0.0, 0.0, 0.0};
+        int k = p > 0 ? p - 1 : 0;
+        for (; k + 3 < n; k += 4) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) sq[i] += Rc[(int64_t)(k + i) * (nu + 1) + p] * c2[k + i];
+        }
+        for (; k < n; ++k) sq[0] += Rc[(int64_t)k * (nu + 1) + p] * c2[k];
+        q[p] = (sq[0] + sq[1]) + (sq[2] + sq[3]);
     }
     __syncthreads();
     const double En = (uty - s_ce) / gm;
     const double Fnn = (utsy - s_cg) / gm;
     for (int p = tid; p <= n; p += WG) {
-        double sgq = 0.0;
-        for (int k = 0; k <= n; ++k) sgq += G[(int64_t)k * nu + p] * q[k];
+        double sq[4] = {0.0, 0.0, 0.0, 0.0};
+        int k = 0;
+        for (; k + 3 <= n; k += 4) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) sq[i] += G[(int64_t)(k + i) * nu + p] * q[k + i];
+        }
+        for (; k <= n; ++k) sq[0] += G[(int64_t)k * nu + p] * q[k];
+        const double sgq = (sq[0] + sq[1]) + (sq[2] + sq[3]);
         const double Ep = p < n ? e[p] : En;
         A[(int64_t)p * nu + n] = (Ep - sgq) / gm;
         const double Fp = p < n ? g[p] : Fnn;

@@ -206,8 +206,10 @@ LaunchInfo launch_coef(int B, int nu, int n, const double* red, double* A, doubl
                        double* gam, double* Fn, int32_t* active, int32_t* nu_eff, double tau, const double* redb,
                        hipStream_t s);
 
+// Fixed-order sums out[o] = sum_c part[c * L + o]. With tmp (tmp_cap doubles, not read by anything in flight)
+// and many chunks onto few outputs, the sum runs in two stages through tmp.
 LaunchInfo launch_reduce(const double* part, int64_t nchunks, int64_t L, double* out, double* h, int B, int nu,
-                         int n, hipStream_t s);
+                         int n, hipStream_t s, double* tmp = nullptr, int64_t tmp_cap = 0);
 
 // ---- support tracking of a seed block (exact zeros of the Krylov vectors) ----
 constexpr int32_t SUP_FAR = 0x3fffffff;   // tile distance: farther than the largest hop count kept
