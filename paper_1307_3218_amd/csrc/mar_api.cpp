@@ -636,7 +636,7 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     }
     if (sparse) part_doubles = std::max<size_t>(part_doubles, (size_t)grid_max * 3 * kg * B);
     // update depth: one tile of 4 * WG vectors per workgroup when tiles are skipped, else 8 vectors per thread
-    const int upd_q = c->tune.upd_q > 0 ? c->tune.upd_q : (sparse ? 4 : 8);
+    const int upd_q = c->tune.upd_q > 0 ? c->tune.upd_q : 4;
     const int64_t part_cap = (int64_t)part_doubles;
 
     size_t off = 0;

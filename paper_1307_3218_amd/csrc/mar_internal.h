@@ -190,11 +190,14 @@ LaunchInfo launch_projr(int B, const T* basis, int64_t M, int64_t stride, int nk
 // Workgroups of that projection kernel one compute unit holds at once (>= 1).
 template <typename T>
 int projr_blocks_per_cu(int B, int variant);
+// Slab bytes per update sweep above which the slab loads are non-temporal: twice the 256 MB last-level
+// (Infinity) cache, so that a basis that fits in it keeps being served from it.
+constexpr double kNtSweepBytes = 512.0 * 1024 * 1024;
 // cA/cB: [n][B] coefficients in the basis precision T.
-template <typename T>
-// upd_q: 16-byte vectors per thread (2, 4 or 8; 0 = 8), reduced for small grids.
+// upd_q: 16-byte vectors per thread (2, 4 or 8; 0 = 4), reduced for small grids.
 // tdist (optional): tile distances; tiles with tdist > n + 1 are skipped and the slab loop of a tile starts
 // at its distance (slabs below it are zero there).
+template <typename T>
 LaunchInfo launch_upd2(int B, T* basis, int64_t M, int64_t stride, int n, const T* cA, const T* cB,
                        const double* gam, const double* Fn, const T* y, T* wout, bool want_w, int upd_q,
                        hipStream_t s, const int32_t* tdist = nullptr);

@@ -872,7 +872,7 @@ __global__ __launch_bounds__(WG) void k_es_pdot(const T* __restrict__ basis, int
 
 // One chunk of WG * Q vectors starting at v0, slabs from kst on (the slabs
 // below kst are zero on these rows).
-template <typename T, int B, int Q, bool WANT_W>
+template <typename T, int B, int Q, bool WANT_W, bool NT>
 __device__ __forceinline__ void upd2_chunk(int64_t v0, int kst, T* __restrict__ basis, int64_t slab, int n,
                                            const T* __restrict__ cA, const T* __restrict__ cB,
                                            const double* __restrict__ gam, const double* __restrict__ Fn,
@@ -915,9 +915,14 @@ __device__ __forceinline__ void upd2_chunk(int64_t v0, int kst, T* __restrict__ 
                 if constexpr (WANT_W) cb[i] = cB[(int64_t)k * B + i % B];
             }
         }
+        // NT: the slabs swept exceed the last-level cache and are read once per sweep, so non-temporal loads
+        // keep them from displacing reused lines; a smaller basis stays cached from one sweep to the next
         T a[Q][VEC];
 #pragma unroll
-        for (int q = 0; q < Q; ++q) unpack(bv[(int64_t)k * slabv + vsq[q]], a[q]);
+        for (int q = 0; q < Q; ++q) {
+            if constexpr (NT) unpack_nt(bv + (int64_t)k * slabv + vsq[q], a[q]);
+            else unpack(bv[(int64_t)k * slabv + vsq[q]], a[q]);
+        }
 #pragma unroll
         for (int q = 0; q < Q; ++q)
 #pragma unroll
@@ -949,8 +954,8 @@ __device__ __forceinline__ void upd2_chunk(int64_t v0, int kst, T* __restrict__ 
 // times the same s: the caller passes s cA, s cB, s F_n and s gamma.
 // The coefficients are [k][B] in the basis precision: one 16-byte load per
 // lane and slab for each of cA, cB when B >= VEC. One chunk of WG * Q
-// vectors per workgroup.
-template <typename T, int B, int Q, bool WANT_W>
+// vectors per workgroup; NT: non-temporal slab loads.
+template <typename T, int B, int Q, bool WANT_W, bool NT>
 __global__ __launch_bounds__(WG) void k_upd2(T* __restrict__ basis, int64_t slab, int n, const T* __restrict__ cA,
                                              const T* __restrict__ cB, const double* __restrict__ gam,
                                              const double* __restrict__ Fn, const T* __restrict__ y,
@@ -969,7 +974,7 @@ __global__ __launch_bounds__(WG) void k_upd2(T* __restrict__ basis, int64_t slab
         if (dm > n + 1) return;
         kst = min(dm, n);
     }
-    upd2_chunk<T, B, Q, WANT_W>(v0, kst, basis, slab, n, cA, cB, gam, Fn, y, wout, nvec);
+    upd2_chunk<T, B, Q, WANT_W, NT>(v0, kst, basis, slab, n, cA, cB, gam, Fn, y, wout, nvec);
 }
 
 // The same update over the row tiles of a list (local regions): entries
@@ -985,7 +990,9 @@ __global__ __launch_bounds__(WG) void k_upd2_list(T* __restrict__ basis, int64_t
     const int64_t ce = cnt[lim];
     for (int64_t e = blockIdx.x; e < ce; e += gridDim.x) {
         const int64_t t = list[e];
-        upd2_chunk<T, B, 4, WANT_W>(t * (4 * WG), min(Dl[e], n), basis, slab, n, cA, cB, gam, Fn, y, wout, nvec);
+        // a local region's tiles are few and stay cached between sweeps: cached loads
+        upd2_chunk<T, B, 4, WANT_W, false>(t * (4 * WG), min(Dl[e], n), basis, slab, n, cA, cB, gam, Fn, y, wout,
+                                           nvec);
     }
 }
 
@@ -1328,17 +1335,20 @@ LaunchInfo launch_upd2<MAR_T>(int B, MAR_T* basis, int64_t M, int64_t stride, in
     const int64_t nvec = M * B / VEC;
     const int64_t ntiles = (nvec + 4 * WG - 1) / (4 * WG);
     // vectors per thread: the requested depth when the grid still has >= 1024 workgroups
-    int Q = upd_q == 2 || upd_q == 4 || upd_q == 8 ? upd_q : 8;
+    int Q = upd_q == 2 || upd_q == 4 || upd_q == 8 ? upd_q : 4;
     while (Q > 1 && nvec < (int64_t)WG * Q * 1024) Q /= 2;
     const int64_t wgs = (nvec + WG * Q - 1) / (WG * Q);
-#define MAR_UPD2(QQ, WW) \
-    MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_upd2<MAR_T, BB, QQ, WW>), dim3(wgs), dim3(WG), 0, s, basis, stride, n, cA, cB, gam, Fn, y, wout, nvec, tdist, ntiles))
-#define MAR_UPD2W(QQ) \
-    if (want_w) { MAR_UPD2(QQ, true); } else { MAR_UPD2(QQ, false); }
-    if (Q == 8) { MAR_UPD2W(8) }
-    else if (Q == 4) { MAR_UPD2W(4) }
-    else if (Q == 2) { MAR_UPD2W(2) }
-    else { MAR_UPD2W(1) }
+    // non-temporal slab loads once the slabs swept are well beyond the 256 MB last-level cache (a smaller basis
+    // is served from it sweep after sweep); the small-grid depths (Q < 4) always load through the caches
+    const bool nt = (double)(n + 2) * (double)(M * B) * sizeof(MAR_T) > kNtSweepBytes;
+#define MAR_UPD2(QQ, WW, NTT) \
+    MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_upd2<MAR_T, BB, QQ, WW, NTT>), dim3(wgs), dim3(WG), 0, s, basis, stride, n, cA, cB, gam, Fn, y, wout, nvec, tdist, ntiles))
+#define MAR_UPD2W(QQ, NTT) \
+    if (want_w) { MAR_UPD2(QQ, true, NTT); } else { MAR_UPD2(QQ, false, NTT); }
+    if (Q == 8) { if (nt) { MAR_UPD2W(8, true) } else { MAR_UPD2W(8, false) } }
+    else if (Q == 4) { if (nt) { MAR_UPD2W(4, true) } else { MAR_UPD2W(4, false) } }
+    else if (Q == 2) { MAR_UPD2W(2, false) }
+    else { MAR_UPD2W(1, false) }
 #undef MAR_UPD2W
 #undef MAR_UPD2
     LaunchInfo li;
