@@ -86,7 +86,7 @@ typedef struct {
     int32_t schedule;      /* mar_schedule */
     int32_t proj_wgs;      /* workgroup cap of a delayed-schedule projection sweep (0 = as many as
                               the device holds at once) */
-    int32_t slab_pad_kb;   /* extra KiB between consecutive basis slabs (0 = none) */
+    int32_t slab_pad_kb;   /* extra KiB between consecutive basis slabs (0 = 1 KiB) */
     int32_t proj_variant;  /* delayed-schedule projection, slabs x 16-byte vectors per thread and row
                               tile: 0 = 4 x 4, 1 = 8 x 4, 2 = 4 x 4 with non-temporal basis loads,
                               3 = 4 x 2, 4 = 8 x 2 */

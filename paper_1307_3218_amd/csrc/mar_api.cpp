@@ -409,10 +409,11 @@ int projr_occupancy(mar_ctx* c, int B, int variant) {
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Elements between consecutive basis slabs: M*B plus a pad, so that the
-// same row of different slabs need not sit at a power-of-two distance.
+// Elements between consecutive basis slabs: M*B plus a pad (1 KiB unless tuned), so that the same row of
+// different slabs does not sit at a power-of-two distance (at M*B*4 = 2^27 bytes the projection, which reads
+// four slabs at one row offset, ran 3 % slower without it).
 int64_t slab_stride(const mar_ctx* c, int64_t Mp, int B, size_t elem) {
-    const int64_t pad_bytes = (int64_t)(c->tune.slab_pad_kb > 0 ? c->tune.slab_pad_kb : 0) * 1024;
+    const int64_t pad_bytes = (int64_t)(c->tune.slab_pad_kb > 0 ? c->tune.slab_pad_kb : 1) * 1024;
     return Mp * B + pad_bytes / (int64_t)elem;
 }
 
@@ -860,10 +861,14 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
             const bool ru = launch(c, s, P_UPD2, [&] {
                 // w' goes straight into slab n + 1, unnormalized (its scale is handled by k_coef)
                 T* wout = last ? nullptr : K + (size_t)(n + 1) * slab_el;
-                return local && sparse
-                    ? mar::launch_upd2_list<T>(B, K, M, stride, n, cAT, cBT, gam, Fn, Y, wout, !last, slist, sDl,
-                                               scnt, n + 1, kListWgs, s)
-                    : mar::launch_upd2<T>(B, K, M, stride, n, cAT, cBT, gam, Fn, Y, wout, !last, upd_q, s, TD);
+                // with support tracking the tiles are taken in distance order, one workgroup per tile (local
+                // regions: a grid-stride loop over the few tiles of the regions, which stay cached)
+                if (sparse) {
+                    const bool nt = !local && (double)(n + 2) * (double)slab > mar::kNtSweepBytes;
+                    return mar::launch_upd2_list<T>(B, K, M, stride, n, cAT, cBT, gam, Fn, Y, wout, !last, slist,
+                                                    sDl, scnt, n + 1, local ? kListWgs : ntiles, nt, s);
+                }
+                return mar::launch_upd2<T>(B, K, M, stride, n, cAT, cBT, gam, Fn, Y, wout, !last, upd_q, s);
             });
             tag(ru, last ? SP_UPD2_LAST : SP_UPD2, n, bi, (double)ntiles);
             if (last) break;

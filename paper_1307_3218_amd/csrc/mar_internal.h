@@ -172,11 +172,13 @@ LaunchInfo launch_spmm2_list(int B, const DevMat& H, const DevMat& SH, const T* 
 template <typename T>
 LaunchInfo launch_spmm_list(int B, const DevMat& A, const T* X, T* Y, const int32_t* list, const int32_t* cnt,
                             int lim, const uint32_t* mask, int W, int64_t grid, hipStream_t s);
+// The dual update over the support list in distance order (entries [0, cnt[lim]), grid workgroups in a
+// grid-stride loop; nt: non-temporal slab loads).
 template <typename T>
 LaunchInfo launch_upd2_list(int B, T* basis, int64_t M, int64_t stride, int n, const T* cA, const T* cB,
                             const double* gam, const double* Fn, const T* y, T* wout, bool want_w,
                             const int32_t* list, const int32_t* Dl, const int32_t* cnt, int lim, int64_t grid,
-                            hipStream_t s);
+                            bool nt, hipStream_t s);
 // Zero the row tiles within hmax + 1 hops of a block's seeds (one more BFS level on dist, which holds the levels
 // up to hmax) in nsl slabs of slab_bytes from base and in y; tiles are 4 * WG vectors of 16 bytes, nvec per slab.
 LaunchInfo launch_zero_ring(int64_t nbrow, const int32_t* brp, const int32_t* bcol, int32_t* dist, int hmax,
