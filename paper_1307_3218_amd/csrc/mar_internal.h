@@ -196,13 +196,12 @@ int projr_blocks_per_cu(int B, int variant);
 // (Infinity) cache, so that a basis that fits in it keeps being served from it.
 constexpr double kNtSweepBytes = 512.0 * 1024 * 1024;
 // cA/cB: [n][B] coefficients in the basis precision T.
-// upd_q: 16-byte vectors per thread (2, 4 or 8; 0 = 4), reduced for small grids.
-// tdist (optional): tile distances; tiles with tdist > n + 1 are skipped and the slab loop of a tile starts
-// at its distance (slabs below it are zero there).
+// upd_q: 16-byte vectors per thread (2, 4 or 8; 0 = 4), reduced for small grids. Every row of every slab
+// (with support tracking the update runs over the tile list instead: launch_upd2_list).
 template <typename T>
 LaunchInfo launch_upd2(int B, T* basis, int64_t M, int64_t stride, int n, const T* cA, const T* cB,
                        const double* gam, const double* Fn, const T* y, T* wout, bool want_w, int upd_q,
-                       hipStream_t s, const int32_t* tdist = nullptr);
+                       hipStream_t s);
 // cAf/cBf (optional): the update coefficients rounded to FP32 for an FP32 basis.
 // redb (n >= 1): {u~.S u~ [B], u~.u~ [B]} of slab n; the kernel first takes the breakdown test of slab n and
 // sets BT, UU.

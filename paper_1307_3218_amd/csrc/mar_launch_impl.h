@@ -959,21 +959,9 @@ template <typename T, int B, int Q, bool WANT_W, bool NT>
 __global__ __launch_bounds__(WG) void k_upd2(T* __restrict__ basis, int64_t slab, int n, const T* __restrict__ cA,
                                              const T* __restrict__ cB, const double* __restrict__ gam,
                                              const double* __restrict__ Fn, const T* __restrict__ y,
-                                             T* __restrict__ wout, int64_t nvec, const int32_t* __restrict__ tdist,
-                                             int64_t ntiles) {
-    // Support: the workgroup's vectors lie in at most two tiles of 4 * WG
-    // vectors (Q <= 8). Nothing to do beyond distance n + 1; slabs below the
-    // smaller distance are zero on these rows.
+                                             T* __restrict__ wout, int64_t nvec) {
     const int64_t v0 = (int64_t)blockIdx.x * (WG * Q);
-    int kst = 0;
-    if (tdist != nullptr) {
-        const int64_t t0 = v0 / (4 * WG);
-        int64_t t1 = (v0 + WG * Q - 1) / (4 * WG);
-        t1 = t1 < ntiles ? t1 : ntiles - 1;
-        const int dm = min(tdist[t0], tdist[t1]);
-        if (dm > n + 1) return;
-        kst = min(dm, n);
-    }
+    const int kst = 0;
     upd2_chunk<T, B, Q, WANT_W, NT>(v0, kst, basis, slab, n, cA, cB, gam, Fn, y, wout, nvec);
 }
 
@@ -1336,10 +1324,9 @@ LaunchInfo launch_upd2_list<MAR_T>(int B, MAR_T* basis, int64_t M, int64_t strid
 template <>
 LaunchInfo launch_upd2<MAR_T>(int B, MAR_T* basis, int64_t M, int64_t stride, int n, const MAR_T* cA,
                               const MAR_T* cB, const double* gam, const double* Fn, const MAR_T* y, MAR_T* wout,
-                              bool want_w, int upd_q, hipStream_t s, const int32_t* tdist) {
+                              bool want_w, int upd_q, hipStream_t s) {
     constexpr int VEC = Vec16<MAR_T>::n;
     const int64_t nvec = M * B / VEC;
-    const int64_t ntiles = (nvec + 4 * WG - 1) / (4 * WG);
     // vectors per thread: the requested depth when the grid still has >= 1024 workgroups
     int Q = upd_q == 2 || upd_q == 4 || upd_q == 8 ? upd_q : 4;
     while (Q > 1 && nvec < (int64_t)WG * Q * 1024) Q /= 2;
@@ -1348,7 +1335,7 @@ LaunchInfo launch_upd2<MAR_T>(int B, MAR_T* basis, int64_t M, int64_t stride, in
     // is served from it sweep after sweep); the small-grid depths (Q < 4) always load through the caches
     const bool nt = (double)(n + 2) * (double)(M * B) * sizeof(MAR_T) > kNtSweepBytes;
 #define MAR_UPD2(QQ, WW, NTT) \
-    MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_upd2<MAR_T, BB, QQ, WW, NTT>), dim3(wgs), dim3(WG), 0, s, basis, stride, n, cA, cB, gam, Fn, y, wout, nvec, tdist, ntiles))
+    MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_upd2<MAR_T, BB, QQ, WW, NTT>), dim3(wgs), dim3(WG), 0, s, basis, stride, n, cA, cB, gam, Fn, y, wout, nvec))
 #define MAR_UPD2W(QQ, NTT) \
     if (want_w) { MAR_UPD2(QQ, true, NTT); } else { MAR_UPD2(QQ, false, NTT); }
     if (Q == 8) { if (nt) { MAR_UPD2W(8, true) } else { MAR_UPD2W(8, false) } }
