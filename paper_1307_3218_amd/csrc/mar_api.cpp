@@ -614,7 +614,7 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     // Support tracking: the kernels of a step skip the row tiles on which the block's vectors are exactly
     // zero (farther from every seed of the block than the step in hops of H's pattern).
     const bool sparse = dual && c->tune.support_off == 0;
-    const int kg = variant == 1 || variant == 4 ? 8 : 4;
+    const int kg = mar::projr_kg(variant);
     const int64_t nbrow = c->H.n, bpt = mar::WG / std::max(P, 1);
     // local regions (order-N form): per block row and seed, inside the seed's region or not. With the support
     // tracking on, the products and the update then run over the support list (a small grid of kListWgs
@@ -1719,7 +1719,7 @@ mar_status mar_set_tuning(mar_ctx* c, const mar_tuning* t) {
         return set_err(c, MAR_ERR_ARG, "unknown schedule");
     if (t->proj_wgs < 0) return set_err(c, MAR_ERR_ARG, "proj_wgs < 0");
     if (t->slab_pad_kb < 0 || t->slab_pad_kb > 65536) return set_err(c, MAR_ERR_ARG, "slab_pad_kb outside [0, 65536]");
-    if (t->proj_variant < 0 || t->proj_variant > 4) return set_err(c, MAR_ERR_ARG, "proj_variant outside [0, 4]");
+    if (t->proj_variant < 0 || t->proj_variant > 6) return set_err(c, MAR_ERR_ARG, "proj_variant outside [0, 6]");
     if (t->upd_q != 0 && t->upd_q != 2 && t->upd_q != 4 && t->upd_q != 8)
         return set_err(c, MAR_ERR_ARG, "upd_q must be 0, 2, 4 or 8");
     if (t->support_off != 0 && t->support_off != 1) return set_err(c, MAR_ERR_ARG, "support_off must be 0 or 1");

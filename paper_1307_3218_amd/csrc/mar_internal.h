@@ -25,14 +25,17 @@ struct ProjrGeom {
     int kg, q, nks;
     int64_t ntiles, tiles, groups;
 };
-// variant: 0 = 4 slabs x 4 vectors, 1 = 8 x 4, 2 = 4 x 4 non-temporal, 3 = 4 x 2, 4 = 8 x 2.
+// variant: 0 = 4 slabs x 4 vectors, 1 = 8 x 4, 2 = 4 x 4 non-temporal, 3 = 4 x 2, 4 = 8 x 2, 5 = 6 x 4,
+// 6 = 6 x 2 (slabs per workgroup x 16-byte vectors per thread and row tile).
+inline int projr_kg(int variant) { return variant == 1 || variant == 4 ? 8 : (variant >= 5 ? 6 : 4); }
+inline int projr_q(int variant) { return variant == 3 || variant == 4 || variant == 6 ? 2 : PROJR_Q; }
 // target_wgs (> 0) caps the grid: the row tiles are cut into target_wgs / nks
 // groups, so that a grid of the device's resident capacity runs in one round
 // and the partial sums stay few (groups * 3 * nk * B values).
 inline ProjrGeom projr_geometry(int64_t nvec, int nk, int variant, int64_t target_wgs) {
     ProjrGeom g;
-    g.kg = variant == 1 || variant == 4 ? 8 : 4;
-    g.q = variant >= 3 ? 2 : PROJR_Q;
+    g.kg = projr_kg(variant);
+    g.q = projr_q(variant);
     g.nks = (nk + g.kg - 1) / g.kg;
     g.ntiles = (nvec + WG * g.q - 1) / (WG * g.q);
     int64_t groups = (target_wgs > 0 ? target_wgs : 1) / g.nks;

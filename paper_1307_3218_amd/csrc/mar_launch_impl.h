@@ -1223,6 +1223,8 @@ LaunchInfo launch_projr<MAR_T>(int B, const MAR_T* basis, int64_t M, int64_t str
     else if (variant == 2) { MAR_PROJR(PROJR_Q, 4, true); }
     else if (variant == 3) { MAR_PROJR(2, 4, false); }
     else if (variant == 4) { MAR_PROJR(2, 8, false); }
+    else if (variant == 5) { MAR_PROJR(PROJR_Q, 6, false); }
+    else if (variant == 6) { MAR_PROJR(2, 6, false); }
     else { MAR_PROJR(PROJR_Q, 4, false); }
 #undef MAR_PROJR
     *ngroups = groups;
@@ -1242,6 +1244,8 @@ int projr_blocks_per_cu<MAR_T>(int B, int variant) {
     else if (variant == 2) { MAR_OCC(PROJR_Q, 4, true); }
     else if (variant == 3) { MAR_OCC(2, 4, false); }
     else if (variant == 4) { MAR_OCC(2, 8, false); }
+    else if (variant == 5) { MAR_OCC(PROJR_Q, 6, false); }
+    else if (variant == 6) { MAR_OCC(2, 6, false); }
     else { MAR_OCC(PROJR_Q, 4, false); }
 #undef MAR_OCC
     return nb > 0 ? nb : 1;
@@ -1255,7 +1259,7 @@ LaunchInfo launch_projr_sp<MAR_T>(int B, const MAR_T* basis, int64_t M, int64_t 
     constexpr int VEC = Vec16<MAR_T>::n;
     constexpr int NR = 3;
     const int64_t nvec = M * B / VEC;
-    const int kg = variant == 1 || variant == 4 ? 8 : 4;
+    const int kg = projr_kg(variant);
     const int64_t nks = (n + 1 + kg - 1) / kg;
     // one round of the device: the plan uses at most max(G, chunks) workgroups (grid = G + chunks)
     const int64_t wgs = std::max(grid - nks, nks);
@@ -1270,6 +1274,8 @@ LaunchInfo launch_projr_sp<MAR_T>(int B, const MAR_T* basis, int64_t M, int64_t 
     else if (variant == 2) { MAR_PROJR_SP(PROJR_Q, 4, true); }
     else if (variant == 3) { MAR_PROJR_SP(2, 4, false); }
     else if (variant == 4) { MAR_PROJR_SP(2, 8, false); }
+    else if (variant == 5) { MAR_PROJR_SP(PROJR_Q, 6, false); }
+    else if (variant == 6) { MAR_PROJR_SP(2, 6, false); }
     else { MAR_PROJR_SP(PROJR_Q, 4, false); }
 #undef MAR_PROJR_SP
     LaunchInfo li;
