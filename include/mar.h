@@ -95,12 +95,16 @@ typedef struct {
                               delayed schedule on a 4x4-block H, the row tiles where all vectors of the
                               seed block are exactly zero (farther from each seed than the step, in hops
                               of H's pattern). The results differ only in the order of partial sums. */
-    int32_t two_streams;   /* 1 = with two or more blocks, alternate blocks between two workspaces and
-                              streams (the second one the context's own), so that one block's short
-                              FP64 kernels overlap the other's sweeps; 0 (default) = one seed block at
-                              a time on the caller's stream. Two workspaces are used only when both fit
-                              in 160 GB, never while profiling, for the eigen-state passes or inside
-                              mar_solve_many's graphs. The results do not depend on it. */
+    int32_t two_streams;   /* with two or more seed blocks: 0 (default) = one block at a time on the
+                              caller's stream, each block's subspace eigensolve on the context's second
+                              stream, overlapping the next block's sweeps (two copies of the subspace
+                              matrices); 1 = alternate whole blocks between two workspaces and the two
+                              streams, so that one block's short FP64 kernels overlap the other's
+                              sweeps (only when both workspaces fit in 160 GB); 2 = everything on the
+                              caller's stream. Neither overlap is used while profiling, for the
+                              eigen-state passes or inside mar_solve_many's graphs; the caller's stream
+                              waits for the second one before the solve's last kernel. The results do
+                              not depend on it. */
 } mar_tuning;
 
 /* Create a context from host CSR arrays of H and S (M x M, 0-based, columns

@@ -103,8 +103,10 @@ struct mar_ctx {
     char* io = nullptr;
     size_t io_bytes = 0;
     hipStream_t stream = nullptr;
-    hipStream_t stream2 = nullptr;   // second seed-block stream of the batched form (non-blocking)
+    hipStream_t stream2 = nullptr;   // second stream of the batched form (non-blocking): the eigensolves, or
+                                     // every other seed block
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_ready[2] = {nullptr, nullptr}, ev_eig[2] = {nullptr, nullptr};   // per eigensolve buffer
     std::string err;
     bool prof = false;
     bool refused = false;   // a launcher refused to run in the current solve
@@ -130,6 +132,10 @@ struct mar_ctx {
         if (stream2) hipStreamDestroy(stream2);
         if (ev_fork) hipEventDestroy(ev_fork);
         if (ev_join) hipEventDestroy(ev_join);
+        for (int i = 0; i < 2; ++i) {
+            if (ev_ready[i]) hipEventDestroy(ev_ready[i]);
+            if (ev_eig[i]) hipEventDestroy(ev_eig[i]);
+        }
     }
 };
 
@@ -666,12 +672,24 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     const size_t oM0 = take(local ? (size_t)nbrow * mW * 4 : 0), oM1 = take(local ? (size_t)nbrow * mW * 4 : 0);
     const size_t set_bytes = off;
     const int64_t n_blocks = (n_seeds + B - 1) / B;
-    const int nset = n_blocks >= 2 && !c->prof && !c->in_graph && c->es.mode == 0 && c->tune.two_streams == 1 &&
+    // a caller that captures its stream into a graph of its own gets every kernel on that stream
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    const bool capturing = !c->dry && hipStreamIsCapturing(s, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone;
+    const int nset = n_blocks >= 2 && !c->prof && !c->in_graph && !capturing && c->es.mode == 0 &&
+                             c->tune.two_streams == 1 &&
                              c->stream2 &&
                              2.0 * (double)set_bytes <= kTwoSetBytes
                          ? 2
                          : 1;
     off = (size_t)nset * set_bytes;
+    // One block at a time (the default): each block's eigensolve runs on the second stream while the next
+    // block's sweeps run on the caller's; the subspace matrix and the gathered rows alternate between two
+    // copies. Not while profiling, inside graphs, for the eigen-state passes, or with tuning two_streams = 2.
+    const bool eig_ovl = nset == 1 && n_blocks >= 2 && !c->prof && !c->in_graph && !capturing && c->es.mode == 0 &&
+                         c->tune.two_streams == 0 && c->stream2;
+    const size_t oH2 = take(eig_ovl ? (size_t)B * nu * nu * 8 : 0);
+    const size_t oKp2 = take(eig_ovl ? (size_t)B * nu * std::max(1, c->max_row) * 8 : 0);
+    const size_t oNc2 = take(eig_ovl ? (size_t)B * 4 : 0);
     const bool own_e = d_e_seed == nullptr, own_n = d_n_seed == nullptr, own_nu = d_nu_eff == nullptr;
     const size_t oE = take(own_e ? (size_t)n_seeds * 8 : 0), oN = take(own_n ? (size_t)n_seeds * 8 : 0);
     const size_t oNuOut = take(own_nu ? (size_t)n_seeds * 4 : 0);
@@ -728,6 +746,15 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
         double* h = (double*)(ws + oH);
         double* Kp = (double*)(ws + oKp);
         int32_t* nucp = (int32_t*)(ws + oNc);
+        // overlapped eigensolves: odd blocks use the second copy of h and the gathered rows, and a block waits
+        // until the eigensolve of the block before last has released its copy
+        const int ep = (int)(bi % 2);
+        if (eig_ovl && ep == 1) {
+            h = (double*)(w + oH2);
+            Kp = (double*)(w + oKp2);
+            nucp = (int32_t*)(w + oNc2);
+        }
+        if (eig_ovl && bi >= 2 && !c->dry) hipStreamWaitEvent(s, c->ev_eig[ep], 0);
         double* G = (double*)(ws + oG);
         double* R = (double*)(ws + oR);
         double* C1 = (double*)(ws + oC1);
@@ -878,10 +905,17 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
             return mar::launch_gather<T>(B, ns, seeds, nu, nu_blk, K, stride, c->Hrp, c->Hcol, c->max_row, Kp, nucp,
                                          s);
         });
-        eig_stage<T>(c, s, B, ns, seeds, nu, h, nucp, Kp, K, stride, M, mu, kT, d_rho, e_seed + blk0, n_seed + blk0,
+        hipStream_t se = s;
+        if (eig_ovl && !c->dry) {   // the eigensolve reads only h, the gathered rows and H: off the caller's stream
+            hipEventRecord(c->ev_ready[ep], s);
+            hipStreamWaitEvent(c->stream2, c->ev_ready[ep], 0);
+            se = c->stream2;
+        }
+        eig_stage<T>(c, se, B, ns, seeds, nu, h, nucp, Kp, K, stride, M, mu, kT, d_rho, e_seed + blk0, n_seed + blk0,
                      nu_out + blk0, d_eps ? d_eps + blk0 * nu : nullptr, d_w ? d_w + blk0 * nu : nullptr, blk0);
+        if (eig_ovl && !c->dry) hipEventRecord(c->ev_eig[ep], c->stream2);
     }
-    if (nset == 2 && !c->dry) {   // the caller's stream waits for the second stream's blocks
+    if ((nset == 2 || eig_ovl) && !c->dry) {   // the caller's stream waits for the second stream's work
         hipEventRecord(c->ev_join, c->stream2);
         hipStreamWaitEvent(s, c->ev_join, 0);
     }
@@ -1083,6 +1117,10 @@ mar_status mar_create(int64_t M, const int64_t* H_rowptr, const int32_t* H_col, 
     if (he == hipSuccess) he = hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking);
     if (he == hipSuccess) he = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
     if (he == hipSuccess) he = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+    for (int i = 0; i < 2; ++i) {
+        if (he == hipSuccess) he = hipEventCreateWithFlags(&c->ev_ready[i], hipEventDisableTiming);
+        if (he == hipSuccess) he = hipEventCreateWithFlags(&c->ev_eig[i], hipEventDisableTiming);
+    }
     if (he != hipSuccess) {
         c->err = fmt("stream creation failed: %s", hipGetErrorString(he));
         return fail(MAR_ERR_HIP);
@@ -1723,7 +1761,7 @@ mar_status mar_set_tuning(mar_ctx* c, const mar_tuning* t) {
     if (t->upd_q != 0 && t->upd_q != 2 && t->upd_q != 4 && t->upd_q != 8)
         return set_err(c, MAR_ERR_ARG, "upd_q must be 0, 2, 4 or 8");
     if (t->support_off != 0 && t->support_off != 1) return set_err(c, MAR_ERR_ARG, "support_off must be 0 or 1");
-    if (t->two_streams != 0 && t->two_streams != 1) return set_err(c, MAR_ERR_ARG, "two_streams must be 0 or 1");
+    if (t->two_streams < 0 || t->two_streams > 2) return set_err(c, MAR_ERR_ARG, "two_streams must be 0, 1 or 2");
     c->tune = *t;
     return MAR_OK;
 }

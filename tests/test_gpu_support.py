@@ -139,15 +139,18 @@ def test_support_profile_bytes(sysm, ctx):
 
 @pytest.mark.parametrize("prec,B", [("fp32", 64), ("fp64", 32)])
 def test_two_streams_bit_equal(sysm, ctx, prec, B):
-    """Alternating seed blocks between two workspaces and streams changes nothing in the results."""
+    """Alternating seed blocks between two workspaces and streams, or running each block's eigensolve on
+    the second stream (the default), changes nothing in the results."""
     seeds = np.arange(100, 100 + 5 * B + 11, dtype=np.int32)
     out = []
-    for two in (True, False):
-        ctx.set_tuning(seed_block=B, schedule="delayed", two_streams=two)
+    for two, ovl in ((True, True), (False, True), (False, False)):
+        ctx.set_tuning(seed_block=B, schedule="delayed", two_streams=two, overlap_eig=ovl)
         try:
             out.append(ctx.solve(seeds, 30, -0.3, KT, precision=prec, form="batched", levels=True))
         finally:
             ctx.set_tuning()
-    a, b = out
-    assert np.array_equal(a.rho, b.rho) and a.e_band == b.e_band
-    assert np.array_equal(a.nu_eff, b.nu_eff) and np.array_equal(a.eps, b.eps)
+    ref = out[2]
+    for o in out[:2]:
+        assert np.array_equal(o.rho, ref.rho) and o.e_band == ref.e_band
+        assert np.array_equal(o.nu_eff, ref.nu_eff) and np.array_equal(o.eps, ref.eps)
+        assert np.array_equal(o.weight, ref.weight) and np.array_equal(o.e_seed, ref.e_seed)
