@@ -245,7 +245,8 @@ __global__ __launch_bounds__(WG) void k_coef(int B, int nu, int n, const double*
     double* t = c1p + (nu + 1);
     double* gc2 = t + (nu + 1);
     double* q = gc2 + (nu + 1);
-    double* red8 = q + (nu + 1);
+    double* gq = q + (nu + 1);
+    double* red8 = gq + (nu + 1);
     auto bsum = [&](double v) {
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -346,38 +347,8 @@ __global__ __launch_bounds__(WG) void k_coef(int B, int nu, int n, const double*
         }
         for (int p = tid; p < n; p += WG) Rc[(int64_t)(n - 1) * (nu + 1) + p] = c1p[p] + btp * c2[p];
         if (tid == 0) Rc[(int64_t)(n - 1) * (nu + 1) + n] = btp * gm;
-        for (int p = tid; p < n; p += WG) {
-            // four running sums each, so that four loads of G are in flight
-            double sg[4] = {0.0, 0.0, 0.0, 0.0}, sv[4] = {0.0, 0.0, 0.0, 0.0};
-            int k = 0;
-            for (; k + 3 < n; k += 4) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const double gkp = G[(int64_t)(k + i) * nu + p];
-                    sg[i] += gkp * c1p[k + i];
-                    sv[i] += gkp * c2[k + i];
-                }
-            }
-            for (; k < n; ++k) {
-                const double gkp = G[(int64_t)k * nu + p];
-                sg[0] += gkp * c1p[k];
-                sv[0] += gkp * c2[k];
-            }
-            t[p] = (A[(int64_t)p * nu + (n - 1)] - ((sg[0] + sg[1]) + (sg[2] + sg[3]))) / btp;
-            gc2[p] = (sv[0] + sv[1]) + (sv[2] + sv[3]);
-        }
     }
     __syncthreads();
-    double p4 = 0.0, p5 = 0.0;
-    for (int p = tid; p < n; p += WG) {
-        const double v = (t[p] - gc2[p]) / gm;
-        G[(int64_t)p * nu + n] = v;
-        G[(int64_t)n * nu + p] = v;
-        p4 += c2[p] * t[p];
-        p5 += c2[p] * gc2[p];
-    }
-    const double s_ct = bsum(p4), s_cgc = bsum(p5);
-    if (tid == 0) G[(int64_t)n * nu + n] = (uu - 2.0 * s_ct + s_cgc) / gam2;
     // q = R[:n+1, :n] c2 (R_{p,k} vanishes for p > k + 1)
     for (int p = tid; p <= n; p += WG) {
         double sq[4] = {0.0, 0.0, 0.0, 0.0};
@@ -390,17 +361,48 @@ __global__ __launch_bounds__(WG) void k_coef(int B, int nu, int n, const double*
         q[p] = (sq[0] + sq[1]) + (sq[2] + sq[3]);
     }
     __syncthreads();
+    // one pass over the first n columns of G: G c1_prev, G c2 and G q (four running sums each, so that four
+    // loads of G are in flight); the new column n enters G q afterwards
+    for (int p = tid; p < n; p += WG) {
+        double sg[4] = {0.0, 0.0, 0.0, 0.0}, sv[4] = {0.0, 0.0, 0.0, 0.0}, sw[4] = {0.0, 0.0, 0.0, 0.0};
+        int k = 0;
+        for (; k + 3 < n; k += 4) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const double gkp = G[(int64_t)(k + i) * nu + p];
+                sg[i] += gkp * c1p[k + i];
+                sv[i] += gkp * c2[k + i];
+                sw[i] += gkp * q[k + i];
+            }
+        }
+        for (; k < n; ++k) {
+            const double gkp = G[(int64_t)k * nu + p];
+            sg[0] += gkp * c1p[k];
+            sv[0] += gkp * c2[k];
+            sw[0] += gkp * q[k];
+        }
+        t[p] = (A[(int64_t)p * nu + (n - 1)] - ((sg[0] + sg[1]) + (sg[2] + sg[3]))) / btp;
+        gc2[p] = (sv[0] + sv[1]) + (sv[2] + sv[3]);
+        gq[p] = (sw[0] + sw[1]) + (sw[2] + sw[3]);
+    }
+    __syncthreads();
+    double p4 = 0.0, p5 = 0.0, p6 = 0.0;
+    for (int p = tid; p < n; p += WG) {
+        const double v = (t[p] - gc2[p]) / gm;
+        G[(int64_t)p * nu + n] = v;
+        G[(int64_t)n * nu + p] = v;
+        p4 += c2[p] * t[p];
+        p5 += c2[p] * gc2[p];
+        p6 += v * q[p];
+    }
+    const double s_ct = bsum(p4), s_cgc = bsum(p5), s_vq = bsum(p6);
+    const double gnn = (uu - 2.0 * s_ct + s_cgc) / gam2;
+    if (tid == 0) G[(int64_t)n * nu + n] = gnn;
     const double En = (uty - s_ce) / gm;
     const double Fnn = (utsy - s_cg) / gm;
     for (int p = tid; p <= n; p += WG) {
-        double sq[4] = {0.0, 0.0, 0.0, 0.0};
-        int k = 0;
-        for (; k + 3 <= n; k += 4) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) sq[i] += G[(int64_t)(k + i) * nu + p] * q[k + i];
-        }
-        for (; k <= n; ++k) sq[0] += G[(int64_t)k * nu + p] * q[k];
-        const double sgq = (sq[0] + sq[1]) + (sq[2] + sq[3]);
+        // (G q)_p over k <= n: the old columns, then column n (G[p][n] = G[n][p], just formed)
+        const double sgq = p < n ? gq[p] + G[(int64_t)p * nu + n] * q[n] : s_vq + gnn * q[n];
         const double Ep = p < n ? e[p] : En;
         A[(int64_t)p * nu + n] = (Ep - sgq) / gm;
         const double Fp = p < n ? g[p] : Fnn;
@@ -424,7 +426,7 @@ LaunchInfo launch_coef(int B, int nu, int n, const double* red, double* A, doubl
                        double* BT, double* UU, double* cA, double* cB, float* cAf, float* cBf,
                        double* gam, double* Fn, int32_t* active, int32_t* nu_eff, double tau, const double* redb,
                        hipStream_t s) {
-    const size_t lds = (size_t)(7 * (nu + 1) + 8) * sizeof(double);
+    const size_t lds = (size_t)(8 * (nu + 1) + 8) * sizeof(double);
     hipLaunchKernelGGL(k_coef, dim3(B), dim3(WG), lds, s, B, nu, n, red, A, G, R, C1, BT, UU, cA, cB, cAf, cBf, gam,
                        Fn, active, nu_eff, tau, redb);
     LaunchInfo li;
