@@ -107,15 +107,23 @@ def errors_vs_oracle(ctx, system, seeds, ref, nu, mu):
     """Per-result error of the device forms against the oracle on the oracle's seeds."""
     H = system.H
     idx = np.concatenate([np.arange(H.indptr[j], H.indptr[j + 1]) for j in seeds])
+    from paper_1307_3218_amd import fermi
     out = {}
     for prec, form in (("fp32", "batched"), ("fp64", "batched"), ("fp64", "plain")):
-        g = ctx.solve(np.asarray(seeds, dtype=np.int32), nu, mu, KT, precision=prec, form=form)
+        g = ctx.solve(np.asarray(seeds, dtype=np.int32), nu, mu, KT, precision=prec, form=form, levels=True)
+        # invariants of the device outputs alone: sum_a w_a = 1, N_j = 2 sum f w, E_j = 2 sum f eps w
+        mask = np.arange(nu)[None, :] < g.nu_eff[:, None]
+        w = np.where(mask, g.weight, 0.0)
+        fw = np.where(mask, fermi.occupation(g.eps, mu, KT), 0.0) * w
         out[f"{prec}_{form}"] = dict(
             e_band_rel=float(abs(g.e_band - ref.e_band) / abs(ref.e_band)),
             rho_rel=float(np.linalg.norm(g.rho[idx] - ref.rho[idx]) / np.linalg.norm(ref.rho[idx])),
             e_seed_max_abs=float(np.abs(g.e_seed - ref.e_seed).max()),
             n_seed_max_abs=float(np.abs(g.n_seed - ref.n_seed).max()),
-            nu_eff_equal=bool(np.array_equal(g.nu_eff, ref.nu_eff)))
+            nu_eff_equal=bool(np.array_equal(g.nu_eff, ref.nu_eff)),
+            weight_sum_minus_1_max=float(np.abs(w.sum(axis=1) - 1.0).max()),
+            n_seed_vs_levels_max=float(np.abs(g.n_seed - 2.0 * fw.sum(axis=1)).max()),
+            e_seed_vs_levels_max=float(np.abs(g.e_seed - 2.0 * (fw * np.where(mask, g.eps, 0.0)).sum(axis=1)).max()))
     return out
 
 
@@ -402,8 +410,11 @@ def main() -> int:
             mu = float(d_mu.cpu()[0])
             nue = d_nu.cpu().numpy()
             mu_host = fermi.fermi_level(d_eps.cpu().numpy(), d_w.cpu().numpy(), nue, float(S_step), KT)
+            # sum rule: the seeds' electron count at the device's mu equals the target (half filling)
+            n_at_mu = fermi.electron_count(d_eps.cpu().numpy(), d_w.cpu().numpy(), nue, mu, KT)
             fermi_info = dict(mu=mu, seeds=S_step, search_ms=round(fs["ms"], 3) if fs else None,
-                              host_bisection_mu=mu_host)
+                              host_bisection_mu=mu_host, electron_count_at_mu=n_at_mu,
+                              electron_count_rel_error=abs(n_at_mu - float(S_step)) / float(S_step))
             log(f"half-filling Fermi level from {S_step} seeds on the device: mu = {mu:.6f} eV "
                 f"(host bisection {mu_host:.6f}); search {fermi_info['search_ms']} ms; nu_eff min {nue.min()}")
         else:
