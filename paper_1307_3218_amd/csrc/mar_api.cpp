@@ -630,6 +630,12 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     constexpr double kTwoSetBytes = 160e9;   // two seed-block workspaces only when both fit in this
     const int mW = (B + 31) / 32;
     const int hreach = local ? std::min(nu, (int)c->loc) : nu;   // farthest hop a vector can reach
+    // Hops the support search covers. The whole-cell form does not clear the basis per block: the update
+    // writes zeros into slab n + 1 on the tiles 1..kg hops past its support, the farthest a later sweep reads
+    // it (a projection chunk of kg slabs, the fused product's neighbour rows), so the search runs kg + 1 hops
+    // past the last vector. The eigen-state passes project whole slabs and clear the basis instead.
+    const bool ring = sparse && !local && c->es.mode == 0;
+    const int hsup = ring ? nu + kg + 1 : hreach;
     const int64_t ntiles = (nbrow + bpt - 1) / bpt;
     const int64_t grid_max = mar::projr_sp_grid(target, nu, kg);
     size_t part_doubles = 0;
@@ -667,7 +673,8 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     const size_t oCAf = take((size_t)nu * B * 4), oCBf = take((size_t)nu * B * 4);
     const size_t oAct = take((size_t)B * 4), oNu = take((size_t)B * 4);
     const size_t oDist = take(sparse ? (size_t)nbrow * 4 : 0), oTD = take(sparse ? (size_t)ntiles * 4 : 0);
-    const size_t oCnt = take(sparse ? (size_t)(nu + 1) * 4 : 0), oList = take(sparse ? (size_t)ntiles * 4 : 0);
+    const size_t oCnt = take(sparse ? (size_t)(std::max(hsup, nu) + 1) * 4 : 0);
+    const size_t oList = take(sparse ? (size_t)ntiles * 4 : 0);
     const size_t oDl = take(sparse ? (size_t)ntiles * 4 : 0), oPlan = take(sparse ? (size_t)(8 + 4 * grid_max) * 4 : 0);
     const size_t oM0 = take(local ? (size_t)nbrow * mW * 4 : 0), oM1 = take(local ? (size_t)nbrow * mW * 4 : 0);
     const size_t set_bytes = off;
@@ -803,14 +810,15 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
             // y is read on the neighbour rows of the tiles where S y is formed. With local regions only the
             // tiles within one hop of the regions' union are ever read.
             if (!local) {
-                launch(c, s, P_INIT, [&] {
-                    return mar::launch_zero(K + slab_el, (int64_t)((size_t)(nu - 1) * stride * sizeof(T)), s);
-                });
+                if (!ring)
+                    launch(c, s, P_INIT, [&] {
+                        return mar::launch_zero(K + slab_el, (int64_t)((size_t)(nu - 1) * stride * sizeof(T)), s);
+                    });
                 launch(c, s, P_INIT, [&] { return mar::launch_zero(Y, (int64_t)slab, s); });
             }
             launch(c, s, P_SUPPORT, [&] {
-                return mar::launch_support(c->M, nbrow, c->H.ptr, c->H.idx, c->H.nnz, seeds, ns, (int)bpt, hreach, nu,
-                                           sdist, TD, scnt, slist, sDl, s);
+                return mar::launch_support(c->M, nbrow, c->H.ptr, c->H.idx, c->H.nnz, seeds, ns, (int)bpt, hsup,
+                                           std::max(hsup, nu), sdist, TD, scnt, slist, sDl, s);
             });
             if (local)
                 launch(c, s, P_INIT, [&] {
@@ -834,7 +842,7 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
                                                     n == 0 ? 0 : 2, np_cap, slist, scnt, n + 1, lmask, mW,
                                                     kListWgs, s)
                         : mar::launch_spmm2<T>(B, c->H, c->SH, Kn, Y, ZT, n == 0 ? nullptr : npart, n == 0 ? 0 : 2,
-                                               np_cap, s, TD, n + 1, lmask, mW);
+                                               np_cap, s, TD, n + 1, lmask, mW, sparse ? sdist : nullptr);
                     swgs = li.wgs;
                     return li;
                 });
@@ -857,7 +865,7 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
             if (sparse) {
                 const bool rec = launch(c, s, P_SPMM, [&] {
                     return local ? mar::launch_spmm_list<T>(B, c->SH, Y, SY, slist, scnt, n, lmask, mW, kListWgs, s)
-                                 : mar::launch_spmm<T>(B, c->SH, Y, SY, nullptr, 0, 0, s, TD, n, lmask, mW);
+                                 : mar::launch_spmm<T>(B, c->SH, Y, SY, nullptr, 0, 0, s, TD, n, lmask, mW, sdist);
                 });
                 tag(rec, SP_FRAC, n, bi, (double)ntiles);
                 const int64_t grid = mar::projr_sp_grid(target, nk, kg);
@@ -893,7 +901,8 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
                 if (sparse) {
                     const bool nt = !local && (double)(n + 2) * (double)slab > mar::kNtSweepBytes;
                     return mar::launch_upd2_list<T>(B, K, M, stride, n, cAT, cBT, gam, Fn, Y, wout, !last, slist,
-                                                    sDl, scnt, n + 1, local ? kListWgs : ntiles, nt, s);
+                                                    sDl, scnt, n + 1, ring ? n + 1 + kg : n + 1,
+                                                    local ? kListWgs : ntiles, nt, s);
                 }
                 return mar::launch_upd2<T>(B, K, M, stride, n, cAT, cBT, gam, Fn, Y, wout, !last, upd_q, s);
             });

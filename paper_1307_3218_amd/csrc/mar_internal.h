@@ -94,10 +94,12 @@ LaunchInfo launch_init(int B, int64_t Mp, int64_t M, const int32_t* seeds, int n
 // outputs are not written, their partials are zero).
 // mask (optional, BSR and B >= vector width only): local-region bits per block row (W words); the product
 // is kept only on the rows inside each seed's region.
+// rdist (optional, BSR and B >= vector width only): block-row distances; rows with rdist > lim are written as
+// zero without reading X (the same for launch_spmm2).
 template <typename T>
 LaunchInfo launch_spmm(int B, const DevMat& A, const T* X, T* Y, double* part, int ndot, int64_t part_cap,
                        hipStream_t s, const int32_t* tdist = nullptr, int lim = 0, const uint32_t* mask = nullptr,
-                       int W = 0);
+                       int W = 0, const int32_t* rdist = nullptr);
 template <typename T>
 // stride: elements between consecutive basis slabs (>= M * B).
 LaunchInfo launch_proj(int B, int ns, const T* b0, const T* b1, int64_t M, int64_t stride, int nk, const T* x,
@@ -165,7 +167,7 @@ LaunchInfo launch_fermi_search(int64_t nseeds, int nu, const int32_t* nu_eff, co
 template <typename T>
 LaunchInfo launch_spmm2(int B, const DevMat& H, const DevMat& SH, const T* X, T* Y, T* Z, double* part, int ndot,
                         int64_t part_cap, hipStream_t s, const int32_t* tdist = nullptr, int lim = 0,
-                        const uint32_t* mask = nullptr, int W = 0);
+                        const uint32_t* mask = nullptr, int W = 0, const int32_t* rdist = nullptr);
 // Local regions: the dual product, S y and the update over the row tiles of the support list (entries
 // [0, cnt[lim])) in a grid-stride loop of `grid` workgroups; spmm2 partials are per workgroup (grid slots).
 template <typename T>
@@ -176,12 +178,13 @@ template <typename T>
 LaunchInfo launch_spmm_list(int B, const DevMat& A, const T* X, T* Y, const int32_t* list, const int32_t* cnt,
                             int lim, const uint32_t* mask, int W, int64_t grid, hipStream_t s);
 // The dual update over the support list in distance order (entries [0, cnt[lim]), grid workgroups in a
-// grid-stride loop; nt: non-temporal slab loads).
+// grid-stride loop; nt: non-temporal slab loads). With want_w, the entries [cnt[lim], cnt[limz]) (limz > lim)
+// get zeros in wout.
 template <typename T>
 LaunchInfo launch_upd2_list(int B, T* basis, int64_t M, int64_t stride, int n, const T* cA, const T* cB,
                             const double* gam, const double* Fn, const T* y, T* wout, bool want_w,
-                            const int32_t* list, const int32_t* Dl, const int32_t* cnt, int lim, int64_t grid,
-                            bool nt, hipStream_t s);
+                            const int32_t* list, const int32_t* Dl, const int32_t* cnt, int lim, int limz,
+                            int64_t grid, bool nt, hipStream_t s);
 // Zero the row tiles within hmax + 1 hops of a block's seeds (one more BFS level on dist, which holds the levels
 // up to hmax) in nsl slabs of slab_bytes from base and in y; tiles are 4 * WG vectors of 16 bytes, nvec per slab.
 LaunchInfo launch_zero_ring(int64_t nbrow, const int32_t* brp, const int32_t* bcol, int32_t* dist, int hmax,

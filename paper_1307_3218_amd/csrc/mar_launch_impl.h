@@ -66,11 +66,11 @@ template <typename T, int B, int CH>
 __device__ __forceinline__ void spmm_row_vec(int64_t Iu, int s0, const int32_t* __restrict__ brp,
                                              const int32_t* __restrict__ bcol, const T* __restrict__ bval,
                                              const typename Vec16<T>::type* __restrict__ Xv,
-                                             T (&acc)[4][SeedMap<T, B>::SW]) {
+                                             T (&acc)[4][SeedMap<T, B>::SW], bool far = false) {
     using SM = SeedMap<T, B>;
     constexpr int VEC = SM::VEC, SW = SM::SW;
     using VT = typename Vec16<T>::type;
-    const int lo = brp[Iu], hi = brp[Iu + 1];
+    const int lo = brp[Iu], hi = far ? lo : brp[Iu + 1];   // far: a row where the product is exactly zero
     for (int b0 = lo; b0 < hi; b0 += CH) {
         int blk[CH];
         int64_t J[CH];
@@ -132,7 +132,8 @@ __global__ __launch_bounds__(WG) void k_spmm_bsr4(int64_t nbrow, const int32_t* 
                                                   const int32_t* __restrict__ bcol, const T* __restrict__ bval,
                                                   const T* __restrict__ X, T* __restrict__ Y,
                                                   double* __restrict__ part, const int32_t* __restrict__ tdist,
-                                                  int lim, const uint32_t* __restrict__ mask, int W) {
+                                                  int lim, const uint32_t* __restrict__ mask, int W,
+                                                  const int32_t* __restrict__ rdist) {
     using SM = SeedMap<T, B>;
     constexpr int VEC = SM::VEC, SW = SM::SW, P = SM::P;
     using VT = typename Vec16<T>::type;
@@ -157,7 +158,9 @@ __global__ __launch_bounds__(WG) void k_spmm_bsr4(int64_t nbrow, const int32_t* 
         int64_t Iu = I;
         if constexpr (P == 64) Iu = __builtin_amdgcn_readfirstlane((int)I);   // one row per wavefront
         if (Iu < nbrow) {
-            spmm_row_vec<T, B, CH>(Iu, s0, brp, bcol, bval, Xv, acc);
+            // rdist: block rows farther than lim hops get the zero they hold without a gather (their
+            // neighbours may lie in tiles no sweep of this seed block has written)
+            spmm_row_vec<T, B, CH>(Iu, s0, brp, bcol, bval, Xv, acc, rdist != nullptr && rdist[Iu] > lim);
             if (mask != nullptr) region_mask<T, SW>(mask, W, Iu, s0, acc);   // local regions
             VT* Yv = reinterpret_cast<VT*>(Y);
 #pragma unroll
@@ -248,7 +251,8 @@ __device__ __forceinline__ void spmm2_row(int64_t Iu, int s0, const int32_t* __r
                                           const int32_t* __restrict__ bcol, const T* __restrict__ hval,
                                           const T* __restrict__ sval, const typename Vec16<T>::type* __restrict__ Xv,
                                           T* __restrict__ Y, T* __restrict__ Z, const uint32_t* __restrict__ mask,
-                                          int W, double (&d)[NDOT > 0 ? NDOT : 1][SeedMap<T, B>::SW]) {
+                                          int W, double (&d)[NDOT > 0 ? NDOT : 1][SeedMap<T, B>::SW],
+                                          bool far = false) {
     using SM = SeedMap<T, B>;
     constexpr int VEC = SM::VEC, SW = SM::SW;
     using VT = typename Vec16<T>::type;
@@ -258,7 +262,7 @@ __device__ __forceinline__ void spmm2_row(int64_t Iu, int s0, const int32_t* __r
     for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int i = 0; i < SW; ++i) ah[r][i] = as[r][i] = (T)0;
-    const int lo = brp[Iu], hi = brp[Iu + 1];
+    const int lo = brp[Iu], hi = far ? lo : brp[Iu + 1];   // far: both products are exactly zero on the row
     for (int b0 = lo; b0 < hi; b0 += CH) {
         int blk[CH];
         int64_t J[CH];
@@ -344,7 +348,8 @@ __global__ __launch_bounds__(WG) void k_spmm2_bsr4(int64_t nbrow, const int32_t*
                                                    const T* __restrict__ sval, const T* __restrict__ X,
                                                    T* __restrict__ Y, T* __restrict__ Z, double* __restrict__ part,
                                                    const int32_t* __restrict__ tdist, int lim,
-                                                   const uint32_t* __restrict__ mask, int W) {
+                                                   const uint32_t* __restrict__ mask, int W,
+                                                   const int32_t* __restrict__ rdist) {
     using SM = SeedMap<T, B>;
     constexpr int VEC = SM::VEC, SW = SM::SW, P = SM::P;
     static_assert(B >= VEC, "dual product needs one seed group per lane");
@@ -364,7 +369,9 @@ __global__ __launch_bounds__(WG) void k_spmm2_bsr4(int64_t nbrow, const int32_t*
         for (int i = 0; i < SW; ++i) d[v][i] = 0.0;
     int64_t Iu = (bid * WG + threadIdx.x) / P;
     if constexpr (P == 64) Iu = __builtin_amdgcn_readfirstlane((int)Iu);   // one row per wavefront
-    if (Iu < nbrow) spmm2_row<T, B, NDOT>(Iu, s0, brp, bcol, hval, sval, Xv, Y, Z, mask, W, d);
+    if (Iu < nbrow)
+        spmm2_row<T, B, NDOT>(Iu, s0, brp, bcol, hval, sval, Xv, Y, Z, mask, W, d,
+                              rdist != nullptr && rdist[Iu] > lim);
     if constexpr (NDOT > 0) {
         __shared__ double lds[SeedReduce<P, SW, NDOT>::LDS];
         wg_seed_reduce<P, SW, NDOT>(d, lds, [&](int v, int b, double sdot) { part[(bid * NDOT + v) * B + b] = sdot; });
@@ -972,17 +979,34 @@ __global__ __launch_bounds__(WG) void k_upd2(T* __restrict__ basis, int64_t slab
 // start at the same slab and stream the same slabs at the same time (tiles
 // taken in row order start at scattered slabs, and the sweep then runs ~20 %
 // slower). NT: non-temporal slab loads.
+// Entries [cnt[lim], cnt[limz]) (WANT_W): the tiles just beyond w''s support
+// get zeros in wout, so that the sweeps that read slab n + 1 a few hops past
+// its support find the zeros it has there (slabs are not cleared per block).
 template <typename T, int B, bool WANT_W, bool NT>
 __global__ __launch_bounds__(WG) void k_upd2_list(T* __restrict__ basis, int64_t slab, int n,
                                                   const T* __restrict__ cA, const T* __restrict__ cB,
                                                   const double* __restrict__ gam, const double* __restrict__ Fn,
                                                   const T* __restrict__ y, T* __restrict__ wout, int64_t nvec,
                                                   const int32_t* __restrict__ list, const int32_t* __restrict__ Dl,
-                                                  const int32_t* __restrict__ cnt, int lim) {
+                                                  const int32_t* __restrict__ cnt, int lim, int limz) {
+    using VT = typename Vec16<T>::type;
     const int64_t ce = cnt[lim];
-    for (int64_t e = blockIdx.x; e < ce; e += gridDim.x) {
+    const int64_t cz = WANT_W && limz > lim ? cnt[limz] : ce;
+    for (int64_t e = blockIdx.x; e < cz; e += gridDim.x) {
         const int64_t t = list[e];
-        upd2_chunk<T, B, 4, WANT_W, NT>(t * (4 * WG), min(Dl[e], n), basis, slab, n, cA, cB, gam, Fn, y, wout, nvec);
+        if (e < ce) {
+            upd2_chunk<T, B, 4, WANT_W, NT>(t * (4 * WG), min(Dl[e], n), basis, slab, n, cA, cB, gam, Fn, y, wout,
+                                            nvec);
+        } else if constexpr (WANT_W) {
+            T z[Vec16<T>::n];
+#pragma unroll
+            for (int i = 0; i < Vec16<T>::n; ++i) z[i] = (T)0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t vi = t * (4 * WG) + (int64_t)q * WG + threadIdx.x;
+                if (vi < nvec) reinterpret_cast<VT*>(wout)[vi] = pack(z);
+            }
+        }
     }
 }
 
@@ -1018,12 +1042,12 @@ LaunchInfo launch_init<MAR_T>(int B, int64_t Mp, int64_t M, const int32_t* seeds
 template <>
 LaunchInfo launch_spmm<MAR_T>(int B, const DevMat& A, const MAR_T* X, MAR_T* Y, double* part, int ndot,
                               int64_t part_cap, hipStream_t s, const int32_t* tdist, int lim, const uint32_t* mask,
-                              int W) {
+                              int W, const int32_t* rdist) {
     constexpr int VEC = Vec16<MAR_T>::n;
     const int P = B < VEC ? 1 : B / VEC;
     const int64_t wgs = (A.n * P + WG - 1) / WG;
     if ((ndot > 0 && wgs * ndot * B > part_cap) ||
-        ((tdist != nullptr || mask != nullptr) && (!A.bsr || B < VEC))) {
+        ((tdist != nullptr || mask != nullptr || rdist != nullptr) && (!A.bsr || B < VEC))) {
         LaunchInfo bad;
         bad.wgs = -1;
         return bad;
@@ -1032,7 +1056,7 @@ LaunchInfo launch_spmm<MAR_T>(int B, const DevMat& A, const MAR_T* X, MAR_T* Y, 
 #define MAR_SPMM_LAUNCH(KERNEL, ND) \
     MAR_DISPATCH_B(B, hipLaunchKernelGGL((KERNEL<MAR_T, BB, ND>), dim3(wgs), dim3(WG), 0, s, A.n, A.ptr, A.idx, val, X, Y, part))
 #define MAR_SPMM_BSR(ND) \
-    MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_spmm_bsr4<MAR_T, BB, ND>), dim3(wgs), dim3(WG), 0, s, A.n, A.ptr, A.idx, val, X, Y, part, tdist, lim, mask, W))
+    MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_spmm_bsr4<MAR_T, BB, ND>), dim3(wgs), dim3(WG), 0, s, A.n, A.ptr, A.idx, val, X, Y, part, tdist, lim, mask, W, rdist))
     if (A.bsr) {
         if (ndot == 2) { MAR_SPMM_BSR(2); }
         else if (ndot == 1) { MAR_SPMM_BSR(1); }
@@ -1055,7 +1079,7 @@ LaunchInfo launch_spmm<MAR_T>(int B, const DevMat& A, const MAR_T* X, MAR_T* Y, 
 template <>
 LaunchInfo launch_spmm2<MAR_T>(int B, const DevMat& H, const DevMat& SH, const MAR_T* X, MAR_T* Y, MAR_T* Z,
                                double* part, int ndot, int64_t part_cap, hipStream_t s, const int32_t* tdist,
-                               int lim, const uint32_t* mask, int W) {
+                               int lim, const uint32_t* mask, int W, const int32_t* rdist) {
     constexpr int VEC = Vec16<MAR_T>::n;
     LaunchInfo li;
     if (!H.bsr || B < VEC || SH.nnz != H.nnz) {
@@ -1072,7 +1096,7 @@ LaunchInfo launch_spmm2<MAR_T>(int B, const DevMat& H, const DevMat& SH, const M
     const MAR_T* hv = f32 ? (const MAR_T*)H.v32 : (const MAR_T*)H.v64;
     const MAR_T* sv = f32 ? (const MAR_T*)SH.v32 : (const MAR_T*)SH.v64;
 #define MAR_SPMM2(ND) \
-    MAR_DISPATCH_B(B, if constexpr (BB >= VEC) hipLaunchKernelGGL((k_spmm2_bsr4<MAR_T, BB, ND>), dim3(wgs), dim3(WG), 0, s, H.n, H.ptr, H.idx, hv, sv, X, Y, Z, part, tdist, lim, mask, W))
+    MAR_DISPATCH_B(B, if constexpr (BB >= VEC) hipLaunchKernelGGL((k_spmm2_bsr4<MAR_T, BB, ND>), dim3(wgs), dim3(WG), 0, s, H.n, H.ptr, H.idx, hv, sv, X, Y, Z, part, tdist, lim, mask, W, rdist))
     if (ndot == 2) { MAR_SPMM2(2); }
     else if (ndot == 1) { MAR_SPMM2(1); }
     else { MAR_SPMM2(0); }
@@ -1304,7 +1328,7 @@ template <>
 LaunchInfo launch_upd2_list<MAR_T>(int B, MAR_T* basis, int64_t M, int64_t stride, int n, const MAR_T* cA,
                                    const MAR_T* cB, const double* gam, const double* Fn, const MAR_T* y, MAR_T* wout,
                                    bool want_w, const int32_t* list, const int32_t* Dl, const int32_t* cnt, int lim,
-                                   int64_t grid, bool nt, hipStream_t s) {
+                                   int limz, int64_t grid, bool nt, hipStream_t s) {
     constexpr int VEC = Vec16<MAR_T>::n;
     const int64_t nvec = M * B / VEC;
     LaunchInfo li;
@@ -1313,7 +1337,7 @@ LaunchInfo launch_upd2_list<MAR_T>(int B, MAR_T* basis, int64_t M, int64_t strid
         return li;
     }
 #define MAR_UPD2L(WW, NTT) \
-    MAR_DISPATCH_B(B, if constexpr (BB >= VEC) hipLaunchKernelGGL((k_upd2_list<MAR_T, BB, WW, NTT>), dim3((unsigned)grid), dim3(WG), 0, s, basis, stride, n, cA, cB, gam, Fn, y, wout, nvec, list, Dl, cnt, lim))
+    MAR_DISPATCH_B(B, if constexpr (BB >= VEC) hipLaunchKernelGGL((k_upd2_list<MAR_T, BB, WW, NTT>), dim3((unsigned)grid), dim3(WG), 0, s, basis, stride, n, cA, cB, gam, Fn, y, wout, nvec, list, Dl, cnt, lim, limz))
     if (nt) {
         if (want_w) { MAR_UPD2L(true, true); } else { MAR_UPD2L(false, true); }
     } else {
