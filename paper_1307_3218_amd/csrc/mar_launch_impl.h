@@ -877,38 +877,26 @@ __global__ __launch_bounds__(WG) void k_es_pdot(const T* __restrict__ basis, int
     wg_seed_reduce<P, SW, 1>(acc, lds, [&](int, int b, double sum) { part[((int64_t)g * nk + k) * B + b] = sum; });
 }
 
-// One chunk of WG * Q vectors starting at v0, slabs from kst on (the slabs
-// below kst are zero on these rows).
+// Q vectors per thread at vbase, vbase + WG, ... (all < nvec), slabs from kst on (the slabs below kst are
+// zero on these rows). The loads of one slab share one base address, so they go out at constant offsets.
 template <typename T, int B, int Q, bool WANT_W, bool NT>
-__device__ __forceinline__ void upd2_chunk(int64_t v0, int kst, T* __restrict__ basis, int64_t slab, int n,
-                                           const T* __restrict__ cA, const T* __restrict__ cB,
-                                           const double* __restrict__ gam, const double* __restrict__ Fn,
-                                           const T* __restrict__ y, T* __restrict__ wout, int64_t nvec) {
+__device__ __forceinline__ void upd2_body(int64_t vbase, int kst, T* __restrict__ basis, int64_t slab, int n,
+                                          const T* __restrict__ cA, const T* __restrict__ cB,
+                                          const double* __restrict__ gam, const double* __restrict__ Fn,
+                                          const T* __restrict__ y, T* __restrict__ wout) {
     using SM = SeedMap<T, B>;
     constexpr int VEC = SM::VEC, P = SM::P;
     using VT = typename Vec16<T>::type;
     const int tid = threadIdx.x;
     const int64_t slabv = slab / VEC;
     const int sb = (B < VEC) ? 0 : (tid % P) * VEC;
-    VT* bv = reinterpret_cast<VT*>(basis);
-    const VT* yv = reinterpret_cast<const VT*>(y);
-    VT* wv = reinterpret_cast<VT*>(wout);
-    T g[VEC], fn[VEC];
-#pragma unroll
-    for (int i = 0; i < VEC; ++i) {
-        const int b = (B < VEC) ? (i % B) : (sb + i);
-        g[i] = (T)gam[b];
-        fn[i] = (T)Fn[b];
-    }
-    const int64_t vbase = v0 + tid;
+    VT* bv = reinterpret_cast<VT*>(basis) + vbase;
+    const VT* yv = reinterpret_cast<const VT*>(y) + vbase;
     T au[Q][VEC], aw[Q][VEC];
-    int64_t vsq[Q];  // always-valid load indices (lanes past nvec read vector 0 and store nothing)
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        const int64_t vi = vbase + (int64_t)q * WG;
-        vsq[q] = vi < nvec ? vi : 0;
-        unpack(bv[(int64_t)n * slabv + vsq[q]], au[q]);
-        if constexpr (WANT_W) unpack(yv[vsq[q]], aw[q]);
+        unpack(bv[(int64_t)n * slabv + q * WG], au[q]);
+        if constexpr (WANT_W) unpack(yv[q * WG], aw[q]);
     }
     for (int k = kst; k < n; ++k) {
         T ca[VEC], cb[VEC];
@@ -924,32 +912,60 @@ __device__ __forceinline__ void upd2_chunk(int64_t v0, int kst, T* __restrict__ 
         }
         // NT: the slabs swept exceed the last-level cache and are read once per sweep, so non-temporal loads
         // keep them from displacing reused lines; a smaller basis stays cached from one sweep to the next
-        T a[Q][VEC];
+        // One vector at a time: each load is used before the next is issued (the scheduling barrier keeps
+        // the compiler from hoisting them). Four loads in flight per wave made the sweep 20 % slower
+        // (5.4 against 6.5 TB/s on the 131072-row workload); the waves of the compute unit keep enough
+        // requests in flight.
+        const VT* bk = bv + (int64_t)k * slabv;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            if constexpr (NT) unpack_nt(bv + (int64_t)k * slabv + vsq[q], a[q]);
-            else unpack(bv[(int64_t)k * slabv + vsq[q]], a[q]);
-        }
-#pragma unroll
-        for (int q = 0; q < Q; ++q)
+            T a[VEC];
+            if constexpr (NT) unpack_nt(bk + q * WG, a);
+            else unpack(bk[q * WG], a);
 #pragma unroll
             for (int i = 0; i < VEC; ++i) {
-                au[q][i] = fma(-a[q][i], ca[i], au[q][i]);
-                if constexpr (WANT_W) aw[q][i] = fma(-a[q][i], cb[i], aw[q][i]);
+                au[q][i] = fma(-a[i], ca[i], au[q][i]);
+                if constexpr (WANT_W) aw[q][i] = fma(-a[i], cb[i], aw[q][i]);
             }
+            __builtin_amdgcn_sched_barrier(0);
+        }
     }
+    // 1 / gamma in FP64, rounded once: a multiply per element instead of a division, whose expansion held
+    // registers enough to lower the sweep's occupancy
+    T rg[VEC], fn[VEC];
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) {
+        const int b = (B < VEC) ? (i % B) : (sb + i);
+        rg[i] = (T)(1.0 / gam[b]);
+        fn[i] = (T)Fn[b];
+    }
+    VT* wv = reinterpret_cast<VT*>(wout) + vbase;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        const int64_t vi = vbase + (int64_t)q * WG;
-        if (vi < nvec) {
 #pragma unroll
-            for (int i = 0; i < VEC; ++i) {
-                au[q][i] = au[q][i] / g[i];
-                if constexpr (WANT_W) aw[q][i] = (aw[q][i] - au[q][i] * fn[i]) / g[i];
-            }
-            bv[(int64_t)n * slabv + vi] = pack(au[q]);
-            if constexpr (WANT_W) wv[vi] = pack(aw[q]);
+        for (int i = 0; i < VEC; ++i) {
+            au[q][i] = au[q][i] * rg[i];
+            if constexpr (WANT_W) aw[q][i] = (aw[q][i] - au[q][i] * fn[i]) * rg[i];
         }
+        bv[(int64_t)n * slabv + q * WG] = pack(au[q]);
+        if constexpr (WANT_W) wv[q * WG] = pack(aw[q]);
+    }
+}
+
+// One chunk of WG * Q vectors starting at v0, slabs from kst on. A whole chunk runs the branch-free body;
+// the one chunk that reaches past nvec runs it vector by vector, for the lanes still inside.
+template <typename T, int B, int Q, bool WANT_W, bool NT>
+__device__ __forceinline__ void upd2_chunk(int64_t v0, int kst, T* __restrict__ basis, int64_t slab, int n,
+                                           const T* __restrict__ cA, const T* __restrict__ cB,
+                                           const double* __restrict__ gam, const double* __restrict__ Fn,
+                                           const T* __restrict__ y, T* __restrict__ wout, int64_t nvec) {
+    const int64_t vbase = v0 + threadIdx.x;
+    if (v0 + (int64_t)Q * WG <= nvec) {
+        upd2_body<T, B, Q, WANT_W, NT>(vbase, kst, basis, slab, n, cA, cB, gam, Fn, y, wout);
+    } else {
+        for (int q = 0; q < Q; ++q)
+            if (vbase + (int64_t)q * WG < nvec)
+                upd2_body<T, B, 1, WANT_W, NT>(vbase + (int64_t)q * WG, kst, basis, slab, n, cA, cB, gam, Fn, y, wout);
     }
 }
 
@@ -982,7 +998,9 @@ __global__ __launch_bounds__(WG) void k_upd2(T* __restrict__ basis, int64_t slab
 // Entries [cnt[lim], cnt[limz]) (WANT_W): the tiles just beyond w''s support
 // get zeros in wout, so that the sweeps that read slab n + 1 a few hops past
 // its support find the zeros it has there (slabs are not cleared per block).
-template <typename T, int B, bool WANT_W, bool NT>
+// STRIDE = false: one entry per workgroup (the grid covers every tile); a grid-stride loop held registers
+// enough to lower the sweep's occupancy.
+template <typename T, int B, bool WANT_W, bool NT, bool STRIDE>
 __global__ __launch_bounds__(WG) void k_upd2_list(T* __restrict__ basis, int64_t slab, int n,
                                                   const T* __restrict__ cA, const T* __restrict__ cB,
                                                   const double* __restrict__ gam, const double* __restrict__ Fn,
@@ -992,7 +1010,7 @@ __global__ __launch_bounds__(WG) void k_upd2_list(T* __restrict__ basis, int64_t
     using VT = typename Vec16<T>::type;
     const int64_t ce = cnt[lim];
     const int64_t cz = WANT_W && limz > lim ? cnt[limz] : ce;
-    for (int64_t e = blockIdx.x; e < cz; e += gridDim.x) {
+    for (int64_t e = blockIdx.x; e < cz; e += STRIDE ? (int64_t)gridDim.x : cz) {
         const int64_t t = list[e];
         if (e < ce) {
             upd2_chunk<T, B, 4, WANT_W, NT>(t * (4 * WG), min(Dl[e], n), basis, slab, n, cA, cB, gam, Fn, y, wout,
@@ -1336,12 +1354,16 @@ LaunchInfo launch_upd2_list<MAR_T>(int B, MAR_T* basis, int64_t M, int64_t strid
         li.wgs = -1;
         return li;
     }
-#define MAR_UPD2L(WW, NTT) \
-    MAR_DISPATCH_B(B, if constexpr (BB >= VEC) hipLaunchKernelGGL((k_upd2_list<MAR_T, BB, WW, NTT>), dim3((unsigned)grid), dim3(WG), 0, s, basis, stride, n, cA, cB, gam, Fn, y, wout, nvec, list, Dl, cnt, lim, limz))
-    if (nt) {
-        if (want_w) { MAR_UPD2L(true, true); } else { MAR_UPD2L(false, true); }
+    // a grid of one workgroup per tile takes one entry each; a smaller grid loops over the entries
+    const bool stride_loop = grid < (nvec + 4 * WG - 1) / (4 * WG);
+#define MAR_UPD2L(WW, NTT, SS) \
+    MAR_DISPATCH_B(B, if constexpr (BB >= VEC) hipLaunchKernelGGL((k_upd2_list<MAR_T, BB, WW, NTT, SS>), dim3((unsigned)grid), dim3(WG), 0, s, basis, stride, n, cA, cB, gam, Fn, y, wout, nvec, list, Dl, cnt, lim, limz))
+    if (stride_loop) {   // local regions: few tiles, cached loads
+        if (want_w) { MAR_UPD2L(true, false, true); } else { MAR_UPD2L(false, false, true); }
+    } else if (nt) {
+        if (want_w) { MAR_UPD2L(true, true, false); } else { MAR_UPD2L(false, true, false); }
     } else {
-        if (want_w) { MAR_UPD2L(true, false); } else { MAR_UPD2L(false, false); }
+        if (want_w) { MAR_UPD2L(true, false, false); } else { MAR_UPD2L(false, false, false); }
     }
 #undef MAR_UPD2L
     li.wgs = grid;
