@@ -912,22 +912,34 @@ __device__ __forceinline__ void upd2_body(int64_t vbase, int kst, T* __restrict_
         }
         // NT: the slabs swept exceed the last-level cache and are read once per sweep, so non-temporal loads
         // keep them from displacing reused lines; a smaller basis stays cached from one sweep to the next
-        // One vector at a time: each load is used before the next is issued (the scheduling barrier keeps
-        // the compiler from hoisting them). Four loads in flight per wave made the sweep 20 % slower
-        // (5.4 against 6.5 TB/s on the 131072-row workload); the waves of the compute unit keep enough
-        // requests in flight.
         const VT* bk = bv + (int64_t)k * slabv;
+        if constexpr (NT) {
+            // Streaming from HBM: one vector at a time, each load used before the next is issued (the
+            // scheduling barrier keeps the compiler from hoisting them). Four loads in flight per wave
+            // made this sweep 20 % slower (5.4 against 6.5 TB/s on the 131072-row workload).
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            T a[VEC];
-            if constexpr (NT) unpack_nt(bk + q * WG, a);
-            else unpack(bk[q * WG], a);
+            for (int q = 0; q < Q; ++q) {
+                T a[VEC];
+                unpack_nt(bk + q * WG, a);
 #pragma unroll
-            for (int i = 0; i < VEC; ++i) {
-                au[q][i] = fma(-a[i], ca[i], au[q][i]);
-                if constexpr (WANT_W) aw[q][i] = fma(-a[i], cb[i], aw[q][i]);
+                for (int i = 0; i < VEC; ++i) {
+                    au[q][i] = fma(-a[i], ca[i], au[q][i]);
+                    if constexpr (WANT_W) aw[q][i] = fma(-a[i], cb[i], aw[q][i]);
+                }
+                __builtin_amdgcn_sched_barrier(0);
             }
-            __builtin_amdgcn_sched_barrier(0);
+        } else {
+            // cached slabs (a basis within the last-level cache, local regions): all loads in flight
+            T a[Q][VEC];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) unpack(bk[q * WG], a[q]);
+#pragma unroll
+            for (int q = 0; q < Q; ++q)
+#pragma unroll
+                for (int i = 0; i < VEC; ++i) {
+                    au[q][i] = fma(-a[q][i], ca[i], au[q][i]);
+                    if constexpr (WANT_W) aw[q][i] = fma(-a[q][i], cb[i], aw[q][i]);
+                }
         }
     }
     // 1 / gamma in FP64, rounded once: a multiply per element instead of a division, whose expansion held
