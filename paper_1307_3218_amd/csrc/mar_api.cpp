@@ -639,8 +639,8 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     const int64_t ntiles = (nbrow + bpt - 1) / bpt;
     const int64_t grid_max = mar::projr_sp_grid(target, nu, kg);
     size_t part_doubles = 0;
-    // S-norm partials of the fused product, one slot per workgroup (read by the coefficient kernel after the
-    // projection has reused part)
+    // S-norm partials of the fused product, one slot per workgroup (reduced into redb before the projection,
+    // with part as the reduction's scratch)
     const size_t np_doubles = (size_t)std::max<int64_t>(spmm_wgs, kListWgs) * 2 * B;
     const int64_t np_cap = (int64_t)np_doubles;
     for (int nk = 1; nk <= nu; ++nk) {
@@ -648,7 +648,7 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
         part_doubles = std::max<size_t>(part_doubles, (size_t)gm.groups * 3 * nk * B);
     }
     if (sparse) part_doubles = std::max<size_t>(part_doubles, (size_t)grid_max * 3 * kg * B);
-    // update depth: one tile of 4 * WG vectors per workgroup when tiles are skipped, else 8 vectors per thread
+    // update depth of the full sweep (support tracking runs one tile of 4 * WG vectors per workgroup)
     const int upd_q = c->tune.upd_q > 0 ? c->tune.upd_q : 4;
     const int64_t part_cap = (int64_t)part_doubles;
 
@@ -806,9 +806,10 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
             });
         }
         if (sparse) {
-            // Slabs 1.. and y = H u~ start at zero: a tile is written only once the support reaches it, and
-            // y is read on the neighbour rows of the tiles where S y is formed. With local regions only the
-            // tiles within one hop of the regions' union are ever read.
+            // What a sweep reads beyond what this block has written must be zero. The whole-cell form gets it
+            // from the update's ring of zeros and the products' row test (ring); the eigen-state passes clear
+            // slabs 1.. here, and y starts at zero in both. With local regions only the tiles within one hop of
+            // the regions' union are ever read, and those are cleared below.
             if (!local) {
                 if (!ring)
                     launch(c, s, P_INIT, [&] {
