@@ -675,7 +675,8 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     const size_t oDist = take(sparse ? (size_t)nbrow * 4 : 0), oTD = take(sparse ? (size_t)ntiles * 4 : 0);
     const size_t oCnt = take(sparse ? (size_t)(std::max(hsup, nu) + 1) * 4 : 0);
     const size_t oList = take(sparse ? (size_t)ntiles * 4 : 0);
-    const size_t oDl = take(sparse ? (size_t)ntiles * 4 : 0), oPlan = take(sparse ? (size_t)(8 + 4 * grid_max) * 4 : 0);
+    const int64_t pstride = 8 + 4 * grid_max;   // ints per projection plan; the plans of all steps are kept
+    const size_t oDl = take(sparse ? (size_t)ntiles * 4 : 0), oPlan = take(sparse ? (size_t)nu * pstride * 4 : 0);
     const size_t oM0 = take(local ? (size_t)nbrow * mW * 4 : 0), oM1 = take(local ? (size_t)nbrow * mW * 4 : 0);
     const size_t set_bytes = off;
     const int64_t n_blocks = (n_seeds + B - 1) / B;
@@ -828,6 +829,8 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
                 });
             if (plog && !c->refused)
                 hipMemcpyAsync(plog + bi * (nu + 1), scnt, (size_t)(nu + 1) * 4, hipMemcpyDeviceToDevice, s);
+            // the projection plans of every step: the counts no longer change in this block
+            launch(c, s, P_SUPPORT, [&] { return mar::launch_projr_plan(scnt, sDl, 0, nu, kg, target, pstride, splan, s); });
         }
         // at steps n >= 1 the dual pass also gives the norms of slab n (the unnormalized residual of step n - 1)
         if (!dual) launch(c, s, P_SPMM, [&] { return mar::launch_spmm<T>(B, c->S, K, ZT, nullptr, 0, 0, s); });
@@ -870,13 +873,13 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
                 });
                 tag(rec, SP_FRAC, n, bi, (double)ntiles);
                 const int64_t grid = mar::projr_sp_grid(target, nk, kg);
-                launch(c, s, P_SUPPORT, [&] { return mar::launch_projr_plan(scnt, sDl, n, kg, target, grid, splan, s); });
+                int32_t* plan_n = splan + (int64_t)n * pstride;
                 const bool rp = launch(c, s, P_PROJR, [&] {
-                    return mar::launch_projr_sp<T>(B, K, M, stride, n, ZT, SY, Y, slist, scnt, splan, grid, part,
+                    return mar::launch_projr_sp<T>(B, K, M, stride, n, ZT, SY, Y, slist, scnt, plan_n, grid, part,
                                                    part_cap, variant, s);
                 });
                 tag(rp, SP_PROJR, n, bi, (double)ntiles);
-                launch(c, s, P_REDUCE, [&] { return mar::launch_reduce_sp(part, splan, grid, kg, nk, B, red, s); });
+                launch(c, s, P_REDUCE, [&] { return mar::launch_reduce_sp(part, plan_n, grid, kg, nk, B, red, s); });
             } else {
                 launch(c, s, P_SPMM, [&] {
                     return local ? mar::launch_spmm<T>(B, c->SH, Y, SY, nullptr, 0, 0, s, nullptr, 0, lmask, mW)

@@ -235,10 +235,12 @@ LaunchInfo launch_support(int64_t M, int64_t nbrow, const int32_t* brp, const in
 const uint32_t* launch_local_masks(int64_t M, int64_t nbrow, const int32_t* brp, const int32_t* bcol,
                                    const int32_t* seeds, int ns, int W, int r, uint32_t* m0, uint32_t* m1,
                                    hipStream_t s);
-// Work plan of the support-restricted projection of step n: 8 + 4 * grid ints at plan, grid = G + chunks.
-inline int64_t projr_sp_grid(int64_t G, int nk, int kg) { return G + (nk + kg - 1) / kg; }
-LaunchInfo launch_projr_plan(const int32_t* cnt, const int32_t* Dl, int n, int kg, int64_t G, int64_t grid,
-                             int32_t* plan, hipStream_t s);
+// Work plan of the support-restricted projection of step n: 8 + 4 * grid ints, grid = G + chunks.
+__host__ __device__ inline int64_t projr_sp_grid(int64_t G, int nk, int kg) { return G + (nk + kg - 1) / kg; }
+// The plans of steps n0 .. n0 + nsteps - 1 in one launch, step n0 + i at plans + i * pstride (pstride >= the
+// largest plan; refused otherwise).
+LaunchInfo launch_projr_plan(const int32_t* cnt, const int32_t* Dl, int n0, int nsteps, int kg, int64_t G,
+                             int64_t pstride, int32_t* plans, hipStream_t s);
 // Fixed-order sum of the per-workgroup partials of that projection into red[3][nk][B].
 LaunchInfo launch_reduce_sp(const double* part, const int32_t* plan, int64_t grid, int kg, int nk, int B,
                             double* out, hipStream_t s);

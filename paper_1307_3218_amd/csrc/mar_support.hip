@@ -141,10 +141,15 @@ LaunchInfo launch_support(int64_t M, int64_t nbrow, const int32_t* brp, const in
 //   [0] groups, [1] Tg, [2] workgroups used, [3] chunks; [8, 8 + grid) off;
 //   then ksmin [grid], then the (group, chunk) of each workgroup, [grid] each
 //   (group -1: idle). The number of workgroups used never exceeds G + chunks.
+// Workgroup i writes the plan of step n0 + i at plans + i * pstride (the counts
+// are fixed once the block's search is done, so every step's plan is made at once).
 __global__ __launch_bounds__(WG) void k_projr_plan(const int32_t* __restrict__ cnt, const int32_t* __restrict__ Dl,
-                                                   int n, int kg, int64_t G, int64_t grid,
-                                                   int32_t* __restrict__ plan) {
+                                                   int n0, int kg, int64_t G, int64_t pstride,
+                                                   int32_t* __restrict__ plans) {
     const int tid = threadIdx.x;
+    const int n = n0 + (int)blockIdx.x;
+    const int64_t grid = projr_sp_grid(G, n + 1, kg);
+    int32_t* plan = plans + (int64_t)blockIdx.x * pstride;
     const int nks = (n + 1 + kg - 1) / kg;
     int32_t* off = plan + 8;
     int32_t* ksm = off + grid;
@@ -309,12 +314,16 @@ const uint32_t* launch_local_masks(int64_t M, int64_t nbrow, const int32_t* brp,
     return a;
 }
 
-LaunchInfo launch_projr_plan(const int32_t* cnt, const int32_t* Dl, int n, int kg, int64_t G, int64_t grid,
-                             int32_t* plan, hipStream_t s) {
-    hipLaunchKernelGGL(k_projr_plan, dim3(1), dim3(WG), 0, s, cnt, Dl, n, kg, G, grid, plan);
+LaunchInfo launch_projr_plan(const int32_t* cnt, const int32_t* Dl, int n0, int nsteps, int kg, int64_t G,
+                             int64_t pstride, int32_t* plans, hipStream_t s) {
     LaunchInfo li;
-    li.wgs = 1;
-    li.bytes = (double)(8 + 4 * grid) * 4.0;
+    if (nsteps <= 0 || pstride < 8 + 4 * projr_sp_grid(G, n0 + nsteps, kg)) {
+        li.wgs = nsteps <= 0 ? 0 : -1;
+        return li;
+    }
+    hipLaunchKernelGGL(k_projr_plan, dim3((unsigned)nsteps), dim3(WG), 0, s, cnt, Dl, n0, kg, G, pstride, plans);
+    li.wgs = nsteps;
+    li.bytes = (double)nsteps * (double)pstride * 4.0;
     return li;
 }
 

@@ -132,8 +132,8 @@ def test_support_profile_bytes(sysm, ctx):
     assert on["launches"] == off["launches"]
     assert 0.05 * off["bytes"] < on["bytes"] < 0.95 * off["bytes"]
     assert out[True]["dcgs_upd"]["bytes"] < out[False]["dcgs_upd"]["bytes"]
-    # one support build per block of 64 and one projection plan per step
-    assert out[True]["support"]["launches"] == 4 * (1 + 40)
+    # per block of 64: one support build and one launch that plans the projections of all steps
+    assert out[True]["support"]["launches"] == 4 * (1 + 1)
     assert out[False]["support"]["launches"] == 0
 
 
