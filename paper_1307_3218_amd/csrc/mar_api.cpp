@@ -626,7 +626,9 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     // tracking on, the products and the update then run over the support list (a small grid of kListWgs
     // workgroups in a grid-stride loop) instead of a workgroup per row tile of the whole cell.
     const bool local = c->loc >= 0 && dual;
-    constexpr int64_t kListWgs = 2048;
+    // grid of the list kernels (local regions): each workgroup also leaves a row of S-norm partials, so small
+    // regions run best on few workgroups (512: +2-7 % against 2048 at 4-10 hops, equal at 16, -2 % at 24)
+    const int64_t kListWgs = c->loc >= 0 && c->loc <= 16 ? 512 : 2048;
     constexpr double kTwoSetBytes = 160e9;   // two seed-block workspaces only when both fit in this
     const int mW = (B + 31) / 32;
     const int hreach = local ? std::min(nu, (int)c->loc) : nu;   // farthest hop a vector can reach
