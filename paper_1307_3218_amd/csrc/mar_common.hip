@@ -247,6 +247,7 @@ __global__ __launch_bounds__(WG) void k_coef(int B, int nu, int n, const double*
     double* q = gc2 + (nu + 1);
     double* gq = q + (nu + 1);
     double* red8 = gq + (nu + 1);
+    double* hsum = red8 + 8;   // [WG][3]: the two halves' sums of the Gram pass
     auto bsum = [&](double v) {
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -361,29 +362,47 @@ __global__ __launch_bounds__(WG) void k_coef(int B, int nu, int n, const double*
         q[p] = (sq[0] + sq[1]) + (sq[2] + sq[3]);
     }
     __syncthreads();
-    // one pass over the first n columns of G: G c1_prev, G c2 and G q (four running sums each, so that four
-    // loads of G are in flight); the new column n enters G q afterwards
-    for (int p = tid; p < n; p += WG) {
-        double sg[4] = {0.0, 0.0, 0.0, 0.0}, sv[4] = {0.0, 0.0, 0.0, 0.0}, sw[4] = {0.0, 0.0, 0.0, 0.0};
-        int k = 0;
-        for (; k + 3 < n; k += 4) {
+    // one pass over the first n columns of G: G c1_prev, G c2 and G q. Thread (half, pl) takes column
+    // p = p0 + pl and half of its k range (four running sums each, so that four loads of G are in flight);
+    // the halves' sums meet in LDS and add in a fixed order.
+    {
+        const int half = tid / (WG / 2), pl = tid % (WG / 2);
+        const int kmid = n / 2;
+        const int kb = half ? kmid : 0, ke = half ? n : kmid;
+        for (int p0 = 0; p0 < n; p0 += WG / 2) {
+            const int p = p0 + pl;
+            double sg[4] = {0.0, 0.0, 0.0, 0.0}, sv[4] = {0.0, 0.0, 0.0, 0.0}, sw[4] = {0.0, 0.0, 0.0, 0.0};
+            if (p < n) {
+                int k = kb;
+                for (; k + 3 < ke; k += 4) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const double gkp = G[(int64_t)(k + i) * nu + p];
-                sg[i] += gkp * c1p[k + i];
-                sv[i] += gkp * c2[k + i];
-                sw[i] += gkp * q[k + i];
+                    for (int i = 0; i < 4; ++i) {
+                        const double gkp = G[(int64_t)(k + i) * nu + p];
+                        sg[i] += gkp * c1p[k + i];
+                        sv[i] += gkp * c2[k + i];
+                        sw[i] += gkp * q[k + i];
+                    }
+                }
+                for (; k < ke; ++k) {
+                    const double gkp = G[(int64_t)k * nu + p];
+                    sg[0] += gkp * c1p[k];
+                    sv[0] += gkp * c2[k];
+                    sw[0] += gkp * q[k];
+                }
             }
+            double* hs = hsum + (int64_t)(half * (WG / 2) + pl) * 3;
+            hs[0] = (sg[0] + sg[1]) + (sg[2] + sg[3]);
+            hs[1] = (sv[0] + sv[1]) + (sv[2] + sv[3]);
+            hs[2] = (sw[0] + sw[1]) + (sw[2] + sw[3]);
+            __syncthreads();
+            if (half == 0 && p < n) {
+                const double* h1 = hsum + (int64_t)(WG / 2 + pl) * 3;
+                if (n >= 1) t[p] = (A[(int64_t)p * nu + (n - 1)] - (hs[0] + h1[0])) / btp;
+                gc2[p] = hs[1] + h1[1];
+                gq[p] = hs[2] + h1[2];
+            }
+            __syncthreads();
         }
-        for (; k < n; ++k) {
-            const double gkp = G[(int64_t)k * nu + p];
-            sg[0] += gkp * c1p[k];
-            sv[0] += gkp * c2[k];
-            sw[0] += gkp * q[k];
-        }
-        t[p] = (A[(int64_t)p * nu + (n - 1)] - ((sg[0] + sg[1]) + (sg[2] + sg[3]))) / btp;
-        gc2[p] = (sv[0] + sv[1]) + (sv[2] + sv[3]);
-        gq[p] = (sw[0] + sw[1]) + (sw[2] + sw[3]);
     }
     __syncthreads();
     double p4 = 0.0, p5 = 0.0, p6 = 0.0;
@@ -426,7 +445,7 @@ LaunchInfo launch_coef(int B, int nu, int n, const double* red, double* A, doubl
                        double* BT, double* UU, double* cA, double* cB, float* cAf, float* cBf,
                        double* gam, double* Fn, int32_t* active, int32_t* nu_eff, double tau, const double* redb,
                        hipStream_t s) {
-    const size_t lds = (size_t)(8 * (nu + 1) + 8) * sizeof(double);
+    const size_t lds = (size_t)(8 * (nu + 1) + 8 + 3 * WG) * sizeof(double);
     hipLaunchKernelGGL(k_coef, dim3(B), dim3(WG), lds, s, B, nu, n, red, A, G, R, C1, BT, UU, cA, cB, cAf, cBf, gam,
                        Fn, active, nu_eff, tau, redb);
     LaunchInfo li;
