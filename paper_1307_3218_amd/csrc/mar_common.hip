@@ -350,18 +350,30 @@ __global__ __launch_bounds__(WG) void k_coef(int B, int nu, int n, const double*
         if (tid == 0) Rc[(int64_t)(n - 1) * (nu + 1) + n] = btp * gm;
     }
     __syncthreads();
-    // q = R[:n+1, :n] c2 (R_{p,k} vanishes for p > k + 1)
-    for (int p = tid; p <= n; p += WG) {
-        double sq[4] = {0.0, 0.0, 0.0, 0.0};
-        int k = p > 0 ? p - 1 : 0;
-        for (; k + 3 < n; k += 4) {
+    // q = R[:n+1, :n] c2 (R_{p,k} vanishes for p > k + 1); each row's k range split over the two halves of
+    // the workgroup as in the Gram pass below
+    {
+        const int half = tid / (WG / 2), pl = tid % (WG / 2);
+        for (int p0 = 0; p0 <= n; p0 += WG / 2) {
+            const int p = p0 + pl;
+            double sq[4] = {0.0, 0.0, 0.0, 0.0};
+            if (p <= n) {
+                const int k0 = p > 0 ? p - 1 : 0;
+                const int kmid = k0 + (n - k0) / 2;
+                int k = half ? kmid : k0;
+                const int ke = half ? n : kmid;
+                for (; k + 3 < ke; k += 4) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) sq[i] += Rc[(int64_t)(k + i) * (nu + 1) + p] * c2[k + i];
+                    for (int i = 0; i < 4; ++i) sq[i] += Rc[(int64_t)(k + i) * (nu + 1) + p] * c2[k + i];
+                }
+                for (; k < ke; ++k) sq[0] += Rc[(int64_t)k * (nu + 1) + p] * c2[k];
+            }
+            hsum[(int64_t)(half * (WG / 2) + pl) * 3] = (sq[0] + sq[1]) + (sq[2] + sq[3]);
+            __syncthreads();
+            if (half == 0 && p <= n) q[p] = hsum[(int64_t)pl * 3] + hsum[(int64_t)(WG / 2 + pl) * 3];
+            __syncthreads();
         }
-        for (; k < n; ++k) sq[0] += Rc[(int64_t)k * (nu + 1) + p] * c2[k];
-        q[p] = (sq[0] + sq[1]) + (sq[2] + sq[3]);
     }
-    __syncthreads();
     // one pass over the first n columns of G: G c1_prev, G c2 and G q. Thread (half, pl) takes column
     // p = p0 + pl and half of its k range (four running sums each, so that four loads of G are in flight);
     // the halves' sums meet in LDS and add in a fixed order.
