@@ -55,7 +55,7 @@ def measured_traffic(kernel: str, workload: str):
     """HBM bytes per launch of ``kernel`` from the committed rocprofv3 counter summary, or None.
 
     The summary records a hash of the kernel sources it was measured on; when the
-    sources have changed since, the figure no longer describes this build (None).
+    sources have changed since, the figure no longer describes the current kernels (None).
     """
     import glob
     import hashlib
