@@ -54,20 +54,40 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
     return (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// Lane t's double, read by the whole wavefront (t uniform).
+__device__ __forceinline__ double lane_value(double x, int t) {
+    const long long b = __double_as_longlong(x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)b, t);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), t);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Implicit QL with Wilkinson shifts on the symmetric tridiagonal (d, e),
 // e[i] coupling d[i] and d[i+1], e[m-1] = 0 (Bowdler, Martin, Reinsch and
-// Wilkinson's tql2 scheme). Run by one wavefront: every lane carries the same
-// scalar recurrence, lane l applies each rotation to columns l, l + 64, ... of R.
+// Wilkinson's tql2 scheme). Run by one wavefront. The (d, e) recurrence is
+// serial: every lane carries it with the same values. A sweep reads only the
+// entries as they were when it began, so they are loaded 64 at a time into
+// lane registers and broadcast with readlane, keeping LDS latency off the
+// recurrence; the plane rotations are logged in cs/sn and then applied by the
+// lanes to their columns l, l + 64, ... of R, carrying the row each rotation
+// passes down. The split point is found by testing 64 subdiagonal entries at once.
 // Returns the number of eigenvalues left unconverged (0 on success).
-__device__ int ql_implicit(double* d, double* e, int m, double* R, int nr, int lane) {
+__device__ int ql_implicit(double* d, double* e, int m, double* R, int nr, int lane, double* cs, double* sn) {
     int fails = 0;
     for (int l = 0; l < m; ++l) {
         int iter = 0;
         for (;;) {
-            int mm = l;
-            for (; mm < m - 1; ++mm) {
-                const double dd = fabs(d[mm]) + fabs(d[mm + 1]);
-                if (fabs(e[mm]) <= DBL_EPSILON * dd) break;
+            // first mm >= l with a negligible e[mm]; e[m-1] = 0 ends the search at m-1
+            int mm = m - 1;
+            for (int base = l; base < m - 1; base += 64) {
+                const int t = base + lane;
+                bool small = false;
+                if (t < m - 1) small = fabs(e[t]) <= DBL_EPSILON * (fabs(d[t]) + fabs(d[t + 1]));
+                const unsigned long long hit = __ballot(small);
+                if (hit) {
+                    mm = base + __ffsll(hit) - 1;
+                    break;
+                }
             }
             if (mm == l) break;
             if (++iter > 80) {
@@ -79,28 +99,79 @@ __device__ int ql_implicit(double* d, double* e, int m, double* R, int nr, int l
             g = d[mm] - d[l] + e[l] / (g + copysign(r, g));
             double s = 1.0, c = 1.0, p = 0.0;
             bool split = false;
-            for (int i = mm - 1; i >= l; --i) {
-                const double f = s * e[i], bb = c * e[i];
-                r = hypot(f, g);
-                e[i + 1] = r;
-                if (r == 0.0) {
-                    d[i + 1] -= p;
-                    e[mm] = 0.0;
-                    split = true;
-                    break;
+            int nrot = 0;
+            double di1 = d[mm];   // d[i+1] as it was when the sweep began
+            for (int i0 = mm - 1; i0 >= l && !split; i0 -= 64) {
+                const int ii = i0 - lane;   // lane t holds e[i0-t], d[i0-t]
+                const double eR = ii >= l ? e[ii] : 0.0, dR = ii >= l ? d[ii] : 0.0;
+                const int nt = min(64, i0 - l + 1);
+                // wait for these two loads here, so the loop below carries no LDS wait
+                __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0), other counters unchanged
+                for (int t = 0; t < nt; ++t) {
+                    const int i = i0 - t;
+                    const double ei = lane_value(eR, t), di = lane_value(dR, t);
+                    const double f = s * ei, bb = c * ei;
+                    const double ss = fma(f, f, g * g);
+                    double rinv;
+                    if (ss > DBL_MIN && ss < DBL_MAX) {
+                        // r = sqrt(ss) and 1/r from the reciprocal square root, two Newton steps
+                        const double hs = 0.5 * ss;
+                        double y = __builtin_amdgcn_rsq(ss);
+                        y = y * fma(-hs, y * y, 1.5);
+                        y = y * fma(-hs, y * y, 1.5);
+                        r = ss * y;
+                        rinv = y;
+                    } else {
+                        r = hypot(f, g);
+                        rinv = r != 0.0 ? 1.0 / r : 0.0;
+                    }
+                    e[i + 1] = r;
+                    if (r == 0.0) {
+                        d[i + 1] = di1 - p;
+                        e[mm] = 0.0;
+                        split = true;
+                        break;
+                    }
+                    s = f * rinv;
+                    c = g * rinv;
+                    g = di1 - p;
+                    r = (di - g) * s + 2.0 * c * bb;
+                    p = s * r;
+                    d[i + 1] = g + p;
+                    g = c * r - bb;
+                    cs[nrot] = c;
+                    sn[nrot] = s;
+                    ++nrot;
+                    di1 = di;
                 }
-                s = f / r;
-                c = g / r;
-                g = d[i + 1] - p;
-                r = (d[i] - g) * s + 2.0 * c * bb;
-                p = s * r;
-                d[i + 1] = g + p;
-                g = c * r - bb;
-                for (int col = lane; col < nr; col += 64) {
-                    const double a0 = R[i * nr + col], a1 = R[(i + 1) * nr + col];
-                    R[(i + 1) * nr + col] = s * a0 + c * a1;
-                    R[i * nr + col] = c * a0 - s * a1;
+            }
+            // rotation t acts on rows (mm-1-t, mm-t); row mm-t is final after it.
+            // Four rotations at a time: their loads (rows not yet written) go out first.
+            for (int col = lane; col < nr; col += 64) {
+                double carry = R[mm * nr + col];
+                int t = 0;
+                for (; t + 4 <= nrot; t += 4) {
+                    const int i = mm - 1 - t;
+                    double a[4], cc[4], sv[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        a[u] = R[(i - u) * nr + col];
+                        cc[u] = cs[t + u];
+                        sv[u] = sn[t + u];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        R[(i - u + 1) * nr + col] = sv[u] * a[u] + cc[u] * carry;
+                        carry = cc[u] * a[u] - sv[u] * carry;
+                    }
                 }
+                for (; t < nrot; ++t) {
+                    const int i = mm - 1 - t;
+                    const double a0 = R[i * nr + col];
+                    R[(i + 1) * nr + col] = sn[t] * a0 + cs[t] * carry;
+                    carry = cs[t] * a0 - sn[t] * carry;
+                }
+                R[(mm - nrot) * nr + col] = carry;
             }
             if (split) continue;
             d[l] -= p;
@@ -295,7 +366,12 @@ __global__ __launch_bounds__(WG) void k_eig(EigExtra ex, int nseeds, const int32
         e[m - 1] = 0.0;
     }
     __syncthreads();
-    if (wave == 0) ql_implicit(d, e, m, R, NR, lane);
+    // v, q are free after the reduction; R is in LDS except in mode 1 (a separate
+    // call there, so that the LDS case compiles to LDS instructions)
+    if (wave == 0) {
+        if (ex.mode == 1) ql_implicit(d, e, m, R, NR, lane, v, q);
+        else ql_implicit(d, e, m, Rl, NR, lane, v, q);
+    }
     __syncthreads();
 
     // Fermi-weighted assembly, or (zc != nullptr) keep the rows e_i.v_alpha,
@@ -392,7 +468,7 @@ LaunchInfo launch_eig(int nseeds, const int32_t* seeds, int nu, double* h, const
     if (lds_a) {
         static bool attr = false;
         if (!attr) {
-            hipFuncSetAttribute((const void*)k_eig<true>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            (void)hipFuncSetAttribute((const void*)k_eig<true>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
             attr = true;
         }
         hipLaunchKernelGGL((k_eig<true>), dim3(nseeds), dim3(WG), lds, s, ex, nseeds, seeds, nu, h, nu_eff_blk, Kp, Hrp,
@@ -401,7 +477,7 @@ LaunchInfo launch_eig(int nseeds, const int32_t* seeds, int nu, double* h, const
     } else {
         static bool attr = false;
         if (!attr) {
-            hipFuncSetAttribute((const void*)k_eig<false>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            (void)hipFuncSetAttribute((const void*)k_eig<false>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
             attr = true;
         }
         hipLaunchKernelGGL((k_eig<false>), dim3(nseeds), dim3(WG), lds, s, ex, nseeds, seeds, nu, h, nu_eff_blk, Kp,
