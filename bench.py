@@ -319,7 +319,10 @@ def main() -> int:
                          "all seeds; sampled: a sorted uniform sample of min(M, 16384) seeds")
     ap.add_argument("--no-support", action="store_true", help="stream every row of every slab")
     ap.add_argument("--two-streams", action="store_true",
-                    help="two seed blocks in flight on two streams (default: one block at a time)")
+                    help="two seed blocks in flight on two streams (default: the library's choice, which is "
+                         "two blocks for local regions of 6 hops or more and one block at a time otherwise)")
+    ap.add_argument("--one-block", action="store_true",
+                    help="one seed block at a time, each block's eigensolve on the second stream")
     ap.add_argument("--no-flip", action="store_true", help="eigenstate: skip the local flipping refinement")
     ap.add_argument("--r-cut", type=int, default=-1, metavar="HOPS",
                     help="local regions of HOPS block hops (the order-N form; a different computation from the "
@@ -359,7 +362,8 @@ def main() -> int:
         log(f"copy calibration: {args.copy_calibration} MiB read + {args.copy_calibration} MiB written")
         del a, c
     ctx = mar.Context(system.H, system.S)
-    ctx.set_tuning(args.seed_block, support=not args.no_support, two_streams=args.two_streams)
+    ctx.set_tuning(args.seed_block, support=not args.no_support,
+                   two_streams=True if args.two_streams else (False if args.one_block else None))
     local = args.r_cut >= 0
     if local:
         ctx.set_local_region(args.r_cut)
@@ -546,7 +550,7 @@ def main() -> int:
                    "M": M, "nnz": int(system.H.nnz), "nu": nu, "seeds_per_step": S_step, "seed_block": B,
                    "precision": "fp32", "form": "batched", "mu": mu, "seed_order": args.seed_order,
                    "support_tracking": not args.no_support, "local_region_hops": args.r_cut if local else None,
-                   "two_streams": args.two_streams},
+                   "two_streams": True if args.two_streams else (False if args.one_block else "auto")},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "error_vs_oracle": errors,

@@ -95,13 +95,15 @@ typedef struct {
                               delayed schedule on a 4x4-block H, the row tiles where all vectors of the
                               seed block are exactly zero (farther from each seed than the step, in hops
                               of H's pattern). The results differ only in the order of partial sums. */
-    int32_t two_streams;   /* with two or more seed blocks: 0 (default) = one block at a time on the
-                              caller's stream, each block's subspace eigensolve on the context's second
+    int32_t two_streams;   /* with two or more seed blocks: 3 = one block at a time on the caller's
+                              stream, each block's subspace eigensolve on the context's second
                               stream, overlapping the next block's sweeps (two copies of the subspace
                               matrices); 1 = alternate whole blocks between two workspaces and the two
                               streams, so that one block's short FP64 kernels overlap the other's
                               sweeps (only when both workspaces fit in 160 GB); 2 = everything on the
-                              caller's stream. Neither overlap is used while profiling, for the
+                              caller's stream; 0 (default) = 1 for local regions of 6 hops or more
+                              (3 when the two workspaces do not fit), else 3. Neither overlap is used
+                              while profiling, for the
                               eigen-state passes or inside mar_solve_many's graphs; the caller's stream
                               waits for the second one before the solve's last kernel. The results do
                               not depend on it. */

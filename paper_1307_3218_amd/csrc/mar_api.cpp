@@ -685,18 +685,25 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     // a caller that captures its stream into a graph of its own gets every kernel on that stream
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     const bool capturing = !c->dry && hipStreamIsCapturing(s, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone;
+    // two_streams 0 picks: local regions of kTwoSetMinHops hops or more alternate two blocks (their short
+    // per-step FP64 kernels and the eigensolve leave most of the chip idle: +18 % at 6 and 8 hops, +13 % at
+    // 16, but -3 % at 5 and -13 % at 3), everything else one block at a time with the eigensolve on the
+    // second stream
+    constexpr int kTwoSetMinHops = 6;
+    const int tsm = c->tune.two_streams != 0 ? c->tune.two_streams : (local && c->loc >= kTwoSetMinHops ? 1 : 3);
     const int nset = n_blocks >= 2 && !c->prof && !c->in_graph && !capturing && c->es.mode == 0 &&
-                             c->tune.two_streams == 1 &&
+                             tsm == 1 &&
                              c->stream2 &&
                              2.0 * (double)set_bytes <= kTwoSetBytes
                          ? 2
                          : 1;
     off = (size_t)nset * set_bytes;
-    // One block at a time (the default): each block's eigensolve runs on the second stream while the next
-    // block's sweeps run on the caller's; the subspace matrix and the gathered rows alternate between two
-    // copies. Not while profiling, inside graphs, for the eigen-state passes, or with tuning two_streams = 2.
+    // One block at a time (two_streams 3, or 0 when it does not pick two blocks or they do not fit): each
+    // block's eigensolve runs on the second stream while the next block's sweeps run on the caller's; the
+    // subspace matrix and the gathered rows alternate between two copies. Not while profiling, inside graphs
+    // or for the eigen-state passes.
     const bool eig_ovl = nset == 1 && n_blocks >= 2 && !c->prof && !c->in_graph && !capturing && c->es.mode == 0 &&
-                         c->tune.two_streams == 0 && c->stream2;
+                         (c->tune.two_streams == 0 || c->tune.two_streams == 3) && c->stream2;
     const size_t oH2 = take(eig_ovl ? (size_t)B * nu * nu * 8 : 0);
     const size_t oKp2 = take(eig_ovl ? (size_t)B * nu * std::max(1, c->max_row) * 8 : 0);
     const size_t oNc2 = take(eig_ovl ? (size_t)B * 4 : 0);
@@ -1776,7 +1783,7 @@ mar_status mar_set_tuning(mar_ctx* c, const mar_tuning* t) {
     if (t->upd_q != 0 && t->upd_q != 2 && t->upd_q != 4 && t->upd_q != 8)
         return set_err(c, MAR_ERR_ARG, "upd_q must be 0, 2, 4 or 8");
     if (t->support_off != 0 && t->support_off != 1) return set_err(c, MAR_ERR_ARG, "support_off must be 0 or 1");
-    if (t->two_streams < 0 || t->two_streams > 2) return set_err(c, MAR_ERR_ARG, "two_streams must be 0, 1 or 2");
+    if (t->two_streams < 0 || t->two_streams > 3) return set_err(c, MAR_ERR_ARG, "two_streams must be 0, 1, 2 or 3");
     c->tune = *t;
     return MAR_OK;
 }

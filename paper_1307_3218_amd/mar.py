@@ -399,11 +399,15 @@ class Context:
         return mar_local_region(self.handle)
 
     def set_tuning(self, seed_block: int = 0, schedule: str = "auto", proj_wgs: int = 0, slab_pad_kb: int = 0,
-                   proj_variant: int = 0, upd_q: int = 0, support: bool = True, two_streams: bool = False,
+                   proj_variant: int = 0, upd_q: int = 0, support: bool = True, two_streams: bool | None = None,
                    overlap_eig: bool = True):
+        """two_streams: None lets the library choose (two blocks in flight for local regions of 6 hops or
+        more, else one block at a time); True alternates two blocks; False runs one block at a time, with
+        each block's eigensolve on the second stream when overlap_eig, else everything on one stream."""
         _check(self.handle, mar_set_tuning(self.handle, seed_block, SCHEDULE[schedule], proj_wgs, slab_pad_kb,
                                            proj_variant, upd_q, 0 if support else 1,
-                                           1 if two_streams else (0 if overlap_eig else 2)))
+                                           (0 if overlap_eig else 2) if two_streams is None else
+                                           1 if two_streams else (3 if overlap_eig else 2)))
 
     def autotune(self, d_seeds, nu, mu, kT, precision="fp32", stream=None) -> dict:
         """Pick the seed block and projection tiles for (nu, precision) by timing probe solves."""

@@ -128,6 +128,26 @@ def test_local_graph_launch(sysm, ctx):
         other.close()
 
 
+def test_local_stream_modes_bit_equal(sysm, ctx):
+    """Local regions of 6 hops: the library's default (two blocks in flight), one block at a time with the
+    eigensolve on the second stream, and everything on one stream give identical results."""
+    seeds = np.arange(40, 40 + 5 * 32 + 7, dtype=np.int32)
+    out = []
+    ctx.set_local_region(6)
+    try:
+        for two, ovl in ((None, True), (True, True), (False, True), (False, False)):
+            ctx.set_tuning(seed_block=32, two_streams=two, overlap_eig=ovl)
+            out.append(ctx.solve(seeds, 24, MU, KT, precision="fp32", form="batched", levels=True))
+    finally:
+        ctx.set_tuning()
+        ctx.set_local_region(None)
+    ref = out[3]
+    for o in out[:3]:
+        assert np.array_equal(o.rho, ref.rho) and o.e_band == ref.e_band
+        assert np.array_equal(o.nu_eff, ref.nu_eff) and np.array_equal(o.eps, ref.eps)
+        assert np.array_equal(o.weight, ref.weight) and np.array_equal(o.e_seed, ref.e_seed)
+
+
 def test_local_refusals(sysm, ctx):
     seeds = np.arange(10, dtype=np.int32)
     ctx.set_local_region(2)
