@@ -110,32 +110,36 @@ __device__ int ql_implicit(double* d, double* e, int m, double* R, int nr, int l
                 for (int t = 0; t < nt; ++t) {
                     const int i = i0 - t;
                     const double ei = lane_value(eR, t), di = lane_value(dR, t);
-                    const double f = s * ei, bb = c * ei;
+                    const double f = s * ei, bb = c * ei, bb2 = 2.0 * bb;
                     const double ss = fma(f, f, g * g);
-                    double rinv;
-                    if (ss > DBL_MIN && ss < DBL_MAX) {
-                        // r = sqrt(ss) and 1/r from the reciprocal square root, two Newton steps
-                        const double hs = 0.5 * ss;
-                        double y = __builtin_amdgcn_rsq(ss);
-                        y = y * fma(-hs, y * y, 1.5);
-                        y = y * fma(-hs, y * y, 1.5);
-                        r = ss * y;
-                        rinv = y;
-                    } else {
+                    // r = sqrt(ss) and 1/(2r) by two coupled Goldschmidt steps from the reciprocal
+                    // square root; tiny, huge or zero ss take the careful path below instead
+                    const double y0 = __builtin_amdgcn_rsq(ss);
+                    double gq = ss * y0, hq = 0.5 * y0;
+                    double res = fma(-gq, hq, 0.5);
+                    gq = fma(gq, res, gq);
+                    hq = fma(hq, res, hq);
+                    res = fma(-gq, hq, 0.5);
+                    gq = fma(gq, res, gq);
+                    hq = fma(hq, res, hq);
+                    r = gq;
+                    double rinv = 2.0 * hq;
+                    if (!(ss > DBL_MIN && ss < DBL_MAX)) {
                         r = hypot(f, g);
                         rinv = r != 0.0 ? 1.0 / r : 0.0;
+                        if (r == 0.0) {
+                            e[i + 1] = r;
+                            d[i + 1] = di1 - p;
+                            e[mm] = 0.0;
+                            split = true;
+                            break;
+                        }
                     }
                     e[i + 1] = r;
-                    if (r == 0.0) {
-                        d[i + 1] = di1 - p;
-                        e[mm] = 0.0;
-                        split = true;
-                        break;
-                    }
                     s = f * rinv;
                     c = g * rinv;
                     g = di1 - p;
-                    r = (di - g) * s + 2.0 * c * bb;
+                    r = (di - g) * s + c * bb2;   // c * (2 bb) equals (2 c) * bb exactly
                     p = s * r;
                     d[i + 1] = g + p;
                     g = c * r - bb;
