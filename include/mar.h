@@ -102,7 +102,8 @@ typedef struct {
                               streams, so that one block's short FP64 kernels overlap the other's
                               sweeps (only when both workspaces fit in 160 GB); 2 = everything on the
                               caller's stream; 0 (default) = 1 for local regions of 6 hops or more
-                              (3 when the two workspaces do not fit), else 3. Neither overlap is used
+                              (3 when the two workspaces do not fit in 160 GB or in the
+                              device's free memory), else 3. Neither overlap is used
                               while profiling, for the
                               eigen-state passes or inside mar_solve_many's graphs; the caller's stream
                               waits for the second one before the solve's last kernel. The results do

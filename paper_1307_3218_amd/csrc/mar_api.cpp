@@ -691,10 +691,17 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     // second stream
     constexpr int kTwoSetMinHops = 6;
     const int tsm = c->tune.two_streams != 0 ? c->tune.two_streams : (local && c->loc >= kTwoSetMinHops ? 1 : 3);
+    bool two_fit = 2.0 * (double)set_bytes <= kTwoSetBytes;
+    if (two_fit && tsm == 1 && c->tune.two_streams == 0 && !c->dry && 2 * set_bytes > c->ws_bytes) {
+        // the default takes a second workspace only when the device has room for it (the current
+        // workspace is given back first); else it runs one block at a time
+        size_t fr = 0, tot = 0;
+        two_fit = hipMemGetInfo(&fr, &tot) == hipSuccess && 2 * set_bytes + (set_bytes >> 4) <= fr + c->ws_bytes;
+    }
     const int nset = n_blocks >= 2 && !c->prof && !c->in_graph && !capturing && c->es.mode == 0 &&
                              tsm == 1 &&
                              c->stream2 &&
-                             2.0 * (double)set_bytes <= kTwoSetBytes
+                             two_fit
                          ? 2
                          : 1;
     off = (size_t)nset * set_bytes;
