@@ -14,7 +14,9 @@
 // (K^T S e_j = sqrt(S_jj) e_1 because u_1 = e_j / sqrt(S_jj) and K^T S K = I),
 //     E_j = sum_{i in P(j)} rho_ij H_ij,   N_j = sum_{i in P(j)} rho_ij S_ij.
 #include <algorithm>
+#include <atomic>
 #include <cfloat>
+#include <cstdint>
 
 #include "mar_device.h"
 #include "mar_internal.h"
@@ -461,6 +463,17 @@ __global__ __launch_bounds__(WG) void k_eig(EigExtra ex, int nseeds, const int32
     }
 }
 
+// Lets kernel f use up to 160 KB of dynamic LDS. The attribute belongs to the current device, so it is
+// set once per device (bit d of done for device d; concurrent first calls both set it, which is harmless).
+static void allow_full_lds(const void* f, std::atomic<uint64_t>& done) {
+    int dev = 0;
+    const bool known = hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64;
+    const uint64_t bit = known ? 1ull << dev : 0;
+    if (known && (done.load(std::memory_order_acquire) & bit)) return;
+    (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (known) done.fetch_or(bit, std::memory_order_acq_rel);
+}
+
 LaunchInfo launch_eig(int nseeds, const int32_t* seeds, int nu, double* h, const int32_t* nu_eff_blk,
                       const double* Kp, const int32_t* Hrp, const int32_t* Hcol, const double* Hval,
                       const double* SvalH, const double* diagS, int max_row, double mu, double kT, double* rho,
@@ -470,20 +483,14 @@ LaunchInfo launch_eig(int nseeds, const int32_t* seeds, int nu, double* h, const
     const bool lds_a = eig_a_fits_lds(nu, rcols);
     const size_t lds = eig_lds_bytes(nu, rcols, lds_a);
     if (lds_a) {
-        static bool attr = false;
-        if (!attr) {
-            (void)hipFuncSetAttribute((const void*)k_eig<true>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-            attr = true;
-        }
+        static std::atomic<uint64_t> done{0};
+        allow_full_lds((const void*)k_eig<true>, done);
         hipLaunchKernelGGL((k_eig<true>), dim3(nseeds), dim3(WG), lds, s, ex, nseeds, seeds, nu, h, nu_eff_blk, Kp, Hrp,
                            Hcol, Hval, SvalH, diagS, max_row, mu, kT, rho, e_seed, n_seed, nu_eff_out, eps_out, w_out,
                            zc);
     } else {
-        static bool attr = false;
-        if (!attr) {
-            (void)hipFuncSetAttribute((const void*)k_eig<false>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-            attr = true;
-        }
+        static std::atomic<uint64_t> done{0};
+        allow_full_lds((const void*)k_eig<false>, done);
         hipLaunchKernelGGL((k_eig<false>), dim3(nseeds), dim3(WG), lds, s, ex, nseeds, seeds, nu, h, nu_eff_blk, Kp,
                            Hrp, Hcol, Hval, SvalH, diagS, max_row, mu, kT, rho, e_seed, n_seed, nu_eff_out, eps_out,
                            w_out, zc);
