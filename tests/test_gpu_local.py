@@ -58,7 +58,9 @@ def _check(sysm, seeds, g, ref, prec, label):
     assert r_rho <= TOL[prec] and r_e <= TOL[prec]
 
 
-@pytest.mark.parametrize("prec,B,r", [("fp64", 8, 2), ("fp64", 32, 3), ("fp32", 64, 2), ("fp32", 256, 4)])
+# 6 and 7 hops run two seed blocks in flight by default (three and four blocks here)
+@pytest.mark.parametrize("prec,B,r", [("fp64", 8, 2), ("fp64", 32, 3), ("fp32", 64, 2), ("fp32", 256, 4),
+                                      ("fp32", 32, 6), ("fp64", 16, 7)])
 def test_local_against_oracle(sysm, ctx, prec, B, r):
     seeds = np.arange(2000, 2000 + 2 * B + 19)
     ref = OL.solve_local(sysm.H, sysm.S, seeds, 30, r, MU, KT)
