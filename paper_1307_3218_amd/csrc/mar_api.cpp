@@ -512,6 +512,18 @@ mar_status run_solve(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds, int nu
     const bool own_e = d_e_seed == nullptr, own_n = d_n_seed == nullptr, own_nu = d_nu_eff == nullptr;
     const size_t oE = take(own_e ? (size_t)n_seeds * 8 : 0), oN = take(own_n ? (size_t)n_seeds * 8 : 0);
     const size_t oNuOut = take(own_nu ? (size_t)n_seeds * 4 : 0);
+    // With two or more blocks each block's eigensolve runs on the second stream while the next block's
+    // steps run on the caller's (as in the delayed schedule): the subspace matrix and the gathered rows
+    // alternate between two copies. Not while profiling, inside graphs, when the caller's stream is
+    // capturing, for the eigen-state passes, or with tuning two_streams 1 or 2.
+    const int64_t n_blocks = (n_seeds + B - 1) / B;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    const bool capturing = !c->dry && hipStreamIsCapturing(s, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone;
+    const bool eig_ovl = n_blocks >= 2 && !c->prof && !c->in_graph && !capturing && c->es.mode == 0 &&
+                         (c->tune.two_streams == 0 || c->tune.two_streams == 3) && c->stream2;
+    const size_t oH2 = take(eig_ovl ? (size_t)B * nu * nu * 8 : 0);
+    const size_t oKp2 = take(eig_ovl ? (size_t)B * nu * std::max(1, c->max_row) * 8 : 0);
+    const size_t oNc2 = take(eig_ovl ? (size_t)B * 4 : 0);
     mar_status st = ensure_ws(c, off);
     if (st != MAR_OK) return st;
     char* w = c->ws;
@@ -527,6 +539,14 @@ mar_status run_solve(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds, int nu
     for (int64_t blk0 = 0; blk0 < n_seeds; blk0 += B) {
         const int ns = (int)std::min<int64_t>(B, n_seeds - blk0);
         const int32_t* seeds = d_seeds + blk0;
+        // overlapped eigensolves: odd blocks use the second copy of h and the gathered rows, and a block waits
+        // until the eigensolve of the block before last has released its copy
+        const int64_t bi = blk0 / B;
+        const int ep = (int)(bi % 2);
+        double* h = eig_ovl && ep == 1 ? (double*)(w + oH2) : ws.h;
+        double* Kp = eig_ovl && ep == 1 ? (double*)(w + oKp2) : (double*)(w + oKp);
+        int32_t* nucp = eig_ovl && ep == 1 ? (int32_t*)(w + oNc2) : (int32_t*)(w + oNuCp);
+        if (eig_ovl && bi >= 2 && !c->dry) hipStreamWaitEvent(s, c->ev_eig[ep], 0);
         if (M != c->M && blk0 == 0) {
             // padded rows of W, Z and S K_1 must read as zero (spmm writes rows < M only)
             launch(c, s, P_INIT, [&] { return mar::launch_zero(ws.W, (int64_t)slab, s); });
@@ -549,7 +569,7 @@ mar_status run_solve(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds, int nu
                                            &nch, s);
             });
             const int64_t L1 = (int64_t)(last ? 1 : 2) * nk * B;
-            launch(c, s, P_REDUCE, [&] { return mar::launch_reduce(ws.part, nch, L1, ws.red1, ws.h, B, nu, n, s); });
+            launch(c, s, P_REDUCE, [&] { return mar::launch_reduce(ws.part, nch, L1, ws.red1, h, B, nu, n, s); });
             if (last) break;
             const double* c1 = ws.red1 + (size_t)nk * B;
             // CGS pass 1: w -= K c1
@@ -577,15 +597,24 @@ mar_status run_solve(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds, int nu
                                              ws.SK + (size_t)(n + 1) * slab_el, s);
             });
         }
-        double* Kp = (double*)(w + oKp);
-        int32_t* nucp = (int32_t*)(w + oNuCp);
         launch(c, s, P_EIG, [&] {
             return mar::launch_gather<T>(B, ns, seeds, nu, ws.nu_eff, ws.K, stride, c->Hrp, c->Hcol, c->max_row, Kp,
                                          nucp, s);
         });
-        eig_stage<T>(c, s, B, ns, seeds, nu, ws.h, nucp, Kp, ws.K, stride, M, mu, kT, d_rho, e_seed + blk0,
+        hipStream_t se = s;
+        if (eig_ovl && !c->dry) {   // the eigensolve reads only h, the gathered rows and H: off the caller's stream
+            hipEventRecord(c->ev_ready[ep], s);
+            hipStreamWaitEvent(c->stream2, c->ev_ready[ep], 0);
+            se = c->stream2;
+        }
+        eig_stage<T>(c, se, B, ns, seeds, nu, h, nucp, Kp, ws.K, stride, M, mu, kT, d_rho, e_seed + blk0,
                      n_seed + blk0, nu_out + blk0, d_eps ? d_eps + blk0 * nu : nullptr,
                      d_w ? d_w + blk0 * nu : nullptr, blk0);
+        if (eig_ovl && !c->dry) hipEventRecord(c->ev_eig[ep], c->stream2);
+    }
+    if (eig_ovl && !c->dry) {   // the caller's stream waits for the second stream's work
+        hipEventRecord(c->ev_join, c->stream2);
+        hipStreamWaitEvent(s, c->ev_join, 0);
     }
     if (!c->zc_defer && !c->es.mode) launch(c, s, P_SUM, [&] { return mar::launch_sum(e_seed, n_seeds, d_e_band, s); });
     if (c->refused) {

@@ -137,6 +137,24 @@ def test_support_profile_bytes(sysm, ctx):
     assert out[False]["support"]["launches"] == 0
 
 
+@pytest.mark.parametrize("prec,form,B", [("fp64", "plain", 0), ("fp32", "plain", 0), ("fp32", "batched", 16)])
+def test_textbook_eig_overlap_bit_equal(sysm, ctx, prec, form, B):
+    """The plain form (and the textbook schedule of the batched form): each block's eigensolve on the second
+    stream gives the same results as everything on one stream."""
+    seeds = np.arange(300, 300 + (9 if form == "plain" else 3 * B + 5), dtype=np.int32)
+    out = []
+    for ovl in (True, False):
+        ctx.set_tuning(seed_block=B, schedule="textbook", two_streams=False, overlap_eig=ovl)
+        try:
+            out.append(ctx.solve(seeds, 30, -0.3, KT, precision=prec, form=form, levels=True))
+        finally:
+            ctx.set_tuning()
+    o, ref = out
+    assert np.array_equal(o.rho, ref.rho) and o.e_band == ref.e_band
+    assert np.array_equal(o.nu_eff, ref.nu_eff) and np.array_equal(o.eps, ref.eps)
+    assert np.array_equal(o.weight, ref.weight) and np.array_equal(o.e_seed, ref.e_seed)
+
+
 @pytest.mark.parametrize("prec,B", [("fp32", 64), ("fp64", 32)])
 def test_two_streams_bit_equal(sysm, ctx, prec, B):
     """Alternating seed blocks between two workspaces and streams, or running each block's eigensolve on
