@@ -14,8 +14,9 @@ What it restates (Sec. 3, Eq. 3, and the Appendix):
         e_j^T phi_k = sum_alpha (e_j^T v_alpha^(j)) int_{eta(k-1)}^{eta(k)} d(eps - eps_alpha^(j)) deps
     with d a smoothed delta function;
   * every subspace eigenvector may be flipped (v -> -v); the inner-product
-    method picks as reference the subspace eigenvector with the largest weight
-    contribution to phi_k and flips each v_alpha^(j) so that v_ref . v_alpha^(j) > 0.
+    method (Appendix) takes as reference the subspace eigenvector that
+    contributes most to phi_k and flips each v_alpha^(j) so that
+    v_ref . v_alpha^(j) > 0.
 Readings where the paper is silent (listed in the design notes):
   * the smoothed delta is the derivative of the logistic step of width sigma,
     so the window integral is F((b - eps)/sigma) - F((a - eps)/sigma) with
@@ -25,8 +26,8 @@ Readings where the paper is silent (listed in the design notes):
     the gap between the k-th and (k+1)-th levels instead of anywhere on the
     plateau of the sharp count (sigma = 0: the sharp step, 1/2 at 0);
   * eta(n) is found by 200 bisection halvings of [min eps - 1 eV, max eps + 1 eV];
-  * "largest weight contribution" is the largest |(e_j^T v_alpha^(j)) x window|;
-    a zero inner product counts as positive.
+  * the subspace eigenvector that contributes most is the one with the largest
+    |(e_j^T v_alpha^(j)) x window|; a zero inner product counts as positive.
 Pins (tests/test_oracle_eigenstate.py): at nu = M the subspace eigenvectors are
 exact, so eps_k must equal the k-th generalized eigenvalue and phi_k the
 S-normalized eigenvector up to one global sign; n(eta) is monotone with

@@ -2,11 +2,17 @@
 
 The pins tie the oracle to things other than itself: brute-force distance-2
 reachability by dense matrix powers (validity and greedy minimality of the
-colouring), R recomputed from scratch with sparse products (monotone descent,
-local minimality, tracked residual, the penalty term), and the exact
-eigenvector of LAPACK's generalized solver (sign errors on first-colour rows
-are undone in the first colour).
+colouring), R recomputed from scratch with sparse products (descent at every
+logged flip, with and without the orthogonality penalty; local minimality;
+tracked residual), and the exact eigenvector of LAPACK's generalized solver
+(sign errors on first-colour rows are undone in the first colour). Planted
+mistakes in the penalty term (its sign, a dropped square term, a p frozen at
+the colour's start, a wrong update of p) must each break one of the pins.
 """
+import importlib.util
+import pathlib
+import sys
+
 import numpy as np
 import pytest
 import scipy.linalg
@@ -86,3 +92,111 @@ def test_penalty_tracks_the_definition(cell):
 
 def test_paper_constant():
     assert F.C_PAPER_EV2 == pytest.approx(5.0 * 27.211386245988 ** 2)
+
+
+def _penalised_start(V, k, seed, noise=0.02, frac=0.15):
+    rng = np.random.default_rng(seed)
+    x = V[:, k] + noise * rng.standard_normal(V.shape[0]) * np.abs(V[:, k]).max()
+    x[rng.random(V.shape[0]) < frac] *= -1.0
+    return x
+
+
+def _penalised_checks(Fm, H, S, ev, V, col, cases):
+    """Failed pin names for a flip oracle module on (seed, c) cases with the penalty of V[:, k-1]."""
+    failed = []
+    for seed, cpen in cases:
+        k = H.shape[0] // 2 + seed % 3
+        ref = V[:, k - 1]
+        x = _penalised_start(V, k, seed)
+        log = []
+        try:
+            res = Fm.local_flip(H, S, x, ev[k], phi_ref=ref, c=cpen, max_sweeps=200, colour=col, log=log)
+        except Exception:
+            return ["raised"]
+        # replay the logged flips one at a time, R of the definition from scratch
+        y = x.copy()
+        prev = F.residual_norm(H, S, y, ev[k], ref, cpen)
+        scale = prev
+        rose = False
+        for l in log:
+            y[l] = -y[l]
+            now = F.residual_norm(H, S, y, ev[k], ref, cpen)
+            if now > prev + 1e-12 * scale:
+                failed.append(f"rise seed={seed} c={cpen:.3g}")
+                rose = True
+                break
+            prev = now
+        if not rose and not np.array_equal(y, res.phi):
+            failed.append(f"log seed={seed}")
+        want = F.residual_norm(H, S, res.phi, ev[k], ref, cpen)
+        if not abs(res.R[-1] - want) <= 1e-10 * max(want, 1e-300):
+            failed.append(f"R tracked seed={seed}")
+        if res.sweeps < 200:                           # converged: no single flip lowers R
+            for l in range(H.shape[0]):
+                z = res.phi.copy()
+                z[l] = -z[l]
+                if F.residual_norm(H, S, z, ev[k], ref, cpen) < want * (1.0 - 1e-12):
+                    failed.append(f"not a local minimum seed={seed} row={l}")
+                    break
+    return failed
+
+
+PEN_CASES = [(seed, cpen) for seed in range(6) for cpen in (F.C_PAPER_EV2, 50.0 * F.C_PAPER_EV2)]
+
+
+def test_penalised_descent_per_flip_and_local_minimum(cell):
+    H, S, ev, V, col = cell
+    assert _penalised_checks(F, H, S, ev, V, col, PEN_CASES) == []
+
+
+def test_unpenalised_descent_per_flip(cell):
+    H, S, ev, V, col = cell
+    for seed in range(3):
+        k = H.shape[0] // 2 + seed
+        x = _penalised_start(V, k, seed, noise=0.05, frac=0.3)
+        log = []
+        res = F.local_flip(H, S, x, ev[k], max_sweeps=200, colour=col, log=log)
+        assert len(log) == res.flips
+        y = x.copy()
+        prev = F.residual_norm(H, S, y, ev[k])
+        for l in log:
+            y[l] = -y[l]
+            now = F.residual_norm(H, S, y, ev[k])
+            assert now <= prev + 1e-12 * res.R[0]
+            prev = now
+        assert np.array_equal(y, res.phi)
+
+
+FLIP_SRC = pathlib.Path(__file__).resolve().parent.parent / "oracle" / "mar_flip.py"
+PENALTY_MUTANTS = {
+    "penalty_cross_sign": ("- 4.0 * a * s[l] * p)", "+ 4.0 * a * s[l] * p)"),
+    "penalty_no_square_term": ("d += c * (4.0 * a * a * s[l] * s[l] - 4.0 * a * s[l] * p)",
+                               "d += c * (- 4.0 * a * s[l] * p)"),
+    "penalty_p_update_sign": ("p = p - (2.0 * a) * s[l]", "p = p + (2.0 * a) * s[l]"),
+    "penalty_p_stale_in_colour": (
+        "                for l in rows:                        # index order, p as left by the flips before\n",
+        "                p_start = p\n"
+        "                for l in rows:                        # index order, p as left by the flips before\n"),
+    "penalty_p_never_updated": ("p = p - (2.0 * a) * s[l]", "p = p"),
+}
+
+
+def _load(src, name):
+    spec = importlib.util.spec_from_loader(name, loader=None)
+    mod = importlib.util.module_from_spec(spec)
+    sys.modules[name] = mod
+    exec(compile(src, f"<{name}>", "exec"), mod.__dict__)
+    return mod
+
+
+@pytest.mark.parametrize("name", sorted(PENALTY_MUTANTS))
+def test_penalty_mutant_is_caught(cell, name):
+    H, S, ev, V, col = cell
+    old, new = PENALTY_MUTANTS[name]
+    src = FLIP_SRC.read_text()
+    assert src.count(old) == 1, f"mutation anchor for {name} not unique"
+    src = src.replace(old, new)
+    if name == "penalty_p_stale_in_colour":        # decide on the colour's starting p
+        src = src.replace("- 4.0 * a * s[l] * p)", "- 4.0 * a * s[l] * p_start)")
+    Fm = _load(src, f"flip_mutant_{name}")
+    assert _penalised_checks(Fm, H, S, ev, V, col, PEN_CASES), f"mutant {name} passed every pin"
