@@ -54,7 +54,8 @@ typedef enum {
     MAR_ERR_NOT_SPD = -3,  /* S_jj <= 0 at create, or w^T S w < 0 during a solve */
     MAR_ERR_NOMEM = -4,    /* device allocation failed */
     MAR_ERR_HIP = -5,      /* HIP runtime error (message in mar_last_error) */
-    MAR_ERR_STATE = -6     /* NULL context or use after an unrecoverable error */
+    MAR_ERR_STATE = -6,    /* NULL context or use after an unrecoverable error */
+    MAR_ERR_NOCONV = -7    /* the subspace eigensolve of some seed did not converge (nu_eff = -3) */
 } mar_status;
 
 typedef enum { MAR_FP64 = 0, MAR_FP32 = 1 } mar_precision;
@@ -76,7 +77,10 @@ typedef enum { MAR_FORM_BATCHED = 0, MAR_FORM_PLAIN = 1 } mar_form;
  *   relation H K = K R (R: the Gram-Schmidt coefficients) carries the change
  *   from H u~ to H u_n into A and the coefficients; only K is stored (two basis
  *   passes per step). The breakdown test on the two-pass norm runs one step
- *   later, plus a first-pass test.
+ *   later, plus a first-pass test. The products of the unnormalized residual
+ *   with itself are cubic in the scale of H, so this schedule needs the
+ *   entries of H within about 2^-300 ... 2^300 in magnitude (the textbook
+ *   schedule, whose vectors are normalized every step, about 2^-480 ... 2^480).
  * AUTO: TEXTBOOK for the plain form, DELAYED for the batched form. */
 typedef enum { MAR_SCHED_AUTO = 0, MAR_SCHED_TEXTBOOK = 1, MAR_SCHED_DELAYED = 2 } mar_schedule;
 
@@ -108,6 +112,9 @@ typedef struct {
                               eigen-state passes or inside mar_solve_many's graphs; the caller's stream
                               waits for the second one before the solve's last kernel. The results do
                               not depend on it. */
+    int32_t ql_max_iter;   /* implicit-QL iterations allowed per eigenvalue of the nu x nu subspace
+                              eigensolve (0 = 80). A seed whose eigensolve is still unconverged after
+                              them gets nu_eff = -3 (see mar_solve). */
 } mar_tuning;
 
 /* Create a context from host CSR arrays of H and S (M x M, 0-based, columns
@@ -129,6 +136,11 @@ void mar_destroy(mar_ctx* ctx);
 
 /* Host-side solve (blocking). seeds: n_seeds distinct indices in [0, M)
  * (MAR_ERR_ARG otherwise); 1 <= nu <= M; mu finite; kT >= 0 and finite.
+ * The subspace eigensolve (Sec. 2: the nu x nu standard eigenproblem) is a
+ * Householder reduction and an implicit QL iteration; a seed with an
+ * eigenvalue still unconverged after ql_max_iter iterations (mar_tuning) gets
+ * nu_eff = -3, NaN in its rho slots, E_j, N_j, eps and weight entries (so
+ * e_band is NaN), and the call returns MAR_ERR_NOCONV naming the seed.
  * Outputs (host, caller-allocated):
  *   rho     [nnz(H)]   CSR row j slots of each listed seed j receive rho_ij for
  *                      i in P(j) (slot (j,i) holds rho_ij); all other slots keep
@@ -151,7 +163,8 @@ mar_status mar_solve(mar_ctx* ctx, const int32_t* seeds, int64_t n_seeds, int32_
  * the same meaning and layout as in mar_solve; d_seeds is read on the device,
  * so range and uniqueness are not validated on the host: a seed outside
  * [0, M) gets d_nu_eff = -2 and no other output, a seed that met w^T S w < 0
- * gets d_nu_eff = -1 (d_nu_eff must then be non-NULL to see it). Scalar
+ * gets d_nu_eff = -1, a seed whose subspace eigensolve did not converge
+ * d_nu_eff = -3 and NaN outputs (d_nu_eff must be non-NULL to see these). Scalar
  * arguments are validated as in mar_solve. The device workspace is owned by
  * the context and may be reallocated (hipMalloc) when nu, B, or the precision
  * grows; call once with the largest shapes before capturing. */
@@ -265,12 +278,15 @@ mar_status mar_autotune(mar_ctx* ctx, int32_t nu, mar_precision prec, const int3
  * matrices in eV). A flip changes r only on the rows of P(l), so no matrix
  * product is needed after the first residual. Rows are visited by colour of a
  * greedy distance-2 colouring of H's pattern (row l takes the smallest colour
- * unused by earlier rows within two hops; built on the first call and kept):
- * rows of one colour decide together (their single-flip changes of |r|^2 are
- * independent), row l flipping when
+ * unused by earlier rows within two hops; built on the first call and kept),
+ * and in index order within a colour. Row l flips when its single-flip change
  *     dR_l = sum_{i in P(l)} A_il (4 a_l^2 A_il - 4 a_l r_i)
  *            + c (4 a_l^2 s_l^2 - 4 a_l s_l p) < 0,   A = H - eps S, s = S phi_ref,
- * with p from the start of the colour; a sweep visits every colour; sweeps
+ * is negative, on the current r and p: every accepted flip lowers R. Rows of
+ * one colour have disjoint supports, so the first sum does not depend on the
+ * colour's other flips; without the penalty the colour's rows decide at once,
+ * with it they decide one after the other on the p left by the flips before
+ * (p drops by 2 a_l s_l at each flip). A sweep visits every colour; sweeps
  * repeat until one flips nothing or max_sweeps have run. Sums run in fixed
  * orders with separately rounded products, so the decisions are reproducible.
  *   d_phi     [M] device, FP64, in/out.
@@ -278,8 +294,9 @@ mar_status mar_autotune(mar_ctx* ctx, int32_t nu, mar_precision prec, const int3
  *   d_R       [max_sweeps + 1] device or NULL: R before the first sweep and after
  *             each sweep run (later entries untouched).
  *   d_info    [2] device or NULL: sweeps run, flips made.
- * One workgroup on the caller's stream; asynchronous. MAR_ERR_ARG for a NULL
- * phi, eps or c not finite, c < 0 or max_sweeps < 0. */
+ * One workgroup on the caller's stream; asynchronous. The context keeps a
+ * workspace of 25 M bytes for it (allocated at the first call). MAR_ERR_ARG for
+ * a NULL phi, eps or c not finite, c < 0 or max_sweeps < 0. */
 mar_status mar_local_flip(mar_ctx* ctx, double* d_phi, double eps, const double* d_phi_ref, double c,
                           int32_t max_sweeps, double* d_R, int32_t* d_info, void* hip_stream);
 /* Number of colours of that colouring (built if needed; synchronous); -1 on error. */

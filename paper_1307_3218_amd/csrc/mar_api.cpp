@@ -448,6 +448,7 @@ void eig_stage(mar_ctx* c, hipStream_t s, int B, int ns, const int32_t* seeds, i
                const double* Kp, const T* K, int64_t stride, int64_t Mp, double mu, double kT, double* rho,
                double* e_seed, double* n_seed, int32_t* nu_out, double* eps, double* w, int64_t blk0) {
     mar::EigExtra ex;
+    ex.ql_maxit = c->tune.ql_max_iter > 0 ? c->tune.ql_max_iter : 80;
     if (c->es.mode == 2) {   // v_ref . v_alpha^(j) through K^T v_ref, then the signed Eq. 3 component
         launch(c, s, P_EIG, [&] {
             return mar::launch_es_pdot<T>(B, K, stride, c->M, Mp, nu, c->es.vref, c->es.pdot, c->es.groups, s);
@@ -1000,6 +1001,16 @@ mar_status check_scalars(mar_ctx* c, int64_t n_seeds, int32_t nu, double mu, dou
     return MAR_OK;
 }
 
+// MAR_ERR_NOCONV for the first seed whose subspace eigensolve did not converge.
+mar_status check_noconv(mar_ctx* c, const int32_t* seeds, const std::vector<int32_t>& nuv) {
+    for (size_t i = 0; i < nuv.size(); ++i)
+        if (nuv[i] == mar::NU_NOCONV)
+            return set_err(c, MAR_ERR_NOCONV,
+                           fmt("the subspace eigensolve of seed %d did not converge within %d QL iterations per "
+                               "eigenvalue", seeds[i], c->tune.ql_max_iter > 0 ? c->tune.ql_max_iter : 80));
+    return MAR_OK;
+}
+
 // Validation shared by the device-side entry points.
 mar_status check_request(mar_ctx* c, const mar_request& r) {
     mar_status st = check_scalars(c, r.n_seeds, r.nu, r.mu, r.kT, r.prec, r.form);
@@ -1151,7 +1162,7 @@ mar_status mar_create(int64_t M, const int64_t* H_rowptr, const int32_t* H_col, 
     c->nnzH = H_rowptr[M];
     c->nnzS = S_rowptr[M];
     c->max_row = max_row;
-    c->tune = mar_tuning{0, 0, 0, 0, 0, 0, 0, 0};
+    c->tune = mar_tuning{0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int k = 0; k < MAR_PROF_CLASSES; ++k) {
         std::memset(&c->agg[k], 0, sizeof(mar_prof_entry));
         if (k < P_COUNT) std::snprintf(c->agg[k].name, sizeof c->agg[k].name, "%s", kProfNames[k]);
@@ -1511,7 +1522,7 @@ mar_status mar_eigen_state_async(mar_ctx* c, const int32_t* d_seeds, int64_t n_s
         return mar::launch_dos_search(n_seeds, nu, nu_eff, eps, wt, sigma, k, 200, (double*)(f + oPart),
                                       (double*)(f + oSt), d_levels, s);
     });
-    // the reference subspace eigenvector: largest weight contribution to phi_k (Appendix)
+    // the reference subspace eigenvector: the one contributing most to phi_k (Appendix)
     launch(c, s, P_EIG, [&] {
         return mar::launch_es_reference((int)n_seeds, d_seeds, nu, nu_eff, eps, zc, c->max_row, c->Hrp, c->Hcol,
                                         d_levels, sigma, (double*)(f + oCm), (int32_t*)(f + oAm), ref, refseed, s);
@@ -1657,7 +1668,7 @@ mar_status mar_solve_fermi(mar_ctx* c, const int32_t* seeds, int64_t n_seeds, in
         if (nuv[i] == -1)
             return set_err(c, MAR_ERR_NOT_SPD, fmt("w^T S w < 0 for seed %d: S is not positive definite", seeds[i]));
     }
-    return MAR_OK;
+    return check_noconv(c, seeds, nuv);
 }
 
 mar_status mar_solve(mar_ctx* c, const int32_t* seeds, int64_t n_seeds, int32_t nu, double mu, double kT,
@@ -1720,7 +1731,7 @@ mar_status mar_solve(mar_ctx* c, const int32_t* seeds, int64_t n_seeds, int32_t 
     for (int64_t i = 0; i < n_seeds; ++i)
         if (nuv[i] == -1)
             return set_err(c, MAR_ERR_NOT_SPD, fmt("w^T S w < 0 for seed %d: S is not positive definite", seeds[i]));
-    return MAR_OK;
+    return check_noconv(c, seeds, nuv);
 }
 
 // Greedy distance-2 colouring of H's rows in index order: row l takes the
@@ -1775,14 +1786,15 @@ mar_status mar_local_flip(mar_ctx* c, double* d_phi, double eps, const double* d
     }
     if (!c->flws) {
         void* p = nullptr;
-        HIP_OR(c, hipMalloc(&p, (size_t)c->M * 17 + 16));
+        HIP_OR(c, hipMalloc(&p, (size_t)c->M * 25 + 16));
         c->flws = (char*)p;
     }
-    double* r = (double*)c->flws;
-    double* sv = r + c->M;
-    int8_t* flag = (int8_t*)(sv + c->M);
+    double* r = (double*)c->flws;       // residual (H - eps S) phi
+    double* sv = r + c->M;              // S phi_ref
+    double* drr = sv + c->M;            // per colour entry: |r|^2 change of its single flip
+    int8_t* flag = (int8_t*)(drr + c->M);
     mar::launch_flip(c->M, c->Hrp, c->Hcol, c->Hval, c->SvalH, eps, d_phi, d_phi_ref, cpen, c->fl_ncol, c->fl_coff,
-                     c->fl_crow, max_sweeps, r, sv, flag, d_R, d_info, (hipStream_t)hip_stream);
+                     c->fl_crow, max_sweeps, r, sv, drr, flag, d_R, d_info, (hipStream_t)hip_stream);
     HIP_OR(c, hipGetLastError());
     return MAR_OK;
 }
@@ -1806,7 +1818,7 @@ int32_t mar_local_region(const mar_ctx* c) { return c ? c->loc : -1; }
 mar_status mar_set_tuning(mar_ctx* c, const mar_tuning* t) {
     if (!c) return MAR_ERR_STATE;
     if (!t) {
-        c->tune = mar_tuning{0, 0, 0, 0, 0, 0, 0, 0};
+        c->tune = mar_tuning{0, 0, 0, 0, 0, 0, 0, 0, 0};
         return MAR_OK;
     }
     if (t->seed_block < 0 || t->seed_block > 256 || (t->seed_block & (t->seed_block - 1)) != 0)
@@ -1820,6 +1832,7 @@ mar_status mar_set_tuning(mar_ctx* c, const mar_tuning* t) {
         return set_err(c, MAR_ERR_ARG, "upd_q must be 0, 2, 4 or 8");
     if (t->support_off != 0 && t->support_off != 1) return set_err(c, MAR_ERR_ARG, "support_off must be 0 or 1");
     if (t->two_streams < 0 || t->two_streams > 3) return set_err(c, MAR_ERR_ARG, "two_streams must be 0, 1, 2 or 3");
+    if (t->ql_max_iter < 0) return set_err(c, MAR_ERR_ARG, "ql_max_iter < 0");
     c->tune = *t;
     return MAR_OK;
 }

@@ -73,8 +73,10 @@ __device__ __forceinline__ double lane_value(double x, int t) {
 // recurrence; the plane rotations are logged in cs/sn and then applied by the
 // lanes to their columns l, l + 64, ... of R, carrying the row each rotation
 // passes down. The split point is found by testing 64 subdiagonal entries at once.
-// Returns the number of eigenvalues left unconverged (0 on success).
-__device__ int ql_implicit(double* d, double* e, int m, double* R, int nr, int lane, double* cs, double* sn) {
+// At most maxit iterations per eigenvalue; returns the number of eigenvalues
+// left unconverged (0 on success).
+__device__ int ql_implicit(double* d, double* e, int m, double* R, int nr, int lane, double* cs, double* sn,
+                           int maxit) {
     int fails = 0;
     for (int l = 0; l < m; ++l) {
         int iter = 0;
@@ -92,7 +94,7 @@ __device__ int ql_implicit(double* d, double* e, int m, double* R, int nr, int l
                 }
             }
             if (mm == l) break;
-            if (++iter > 80) {
+            if (++iter > maxit) {
                 ++fails;
                 break;
             }
@@ -374,11 +376,38 @@ __global__ __launch_bounds__(WG) void k_eig(EigExtra ex, int nseeds, const int32
     __syncthreads();
     // v, q are free after the reduction; R is in LDS except in mode 1 (a separate
     // call there, so that the LDS case compiles to LDS instructions)
+    int* failp = tjp + 1;
     if (wave == 0) {
-        if (ex.mode == 1) ql_implicit(d, e, m, R, NR, lane, v, q);
-        else ql_implicit(d, e, m, Rl, NR, lane, v, q);
+        int f;
+        if (ex.mode == 1) f = ql_implicit(d, e, m, R, NR, lane, v, q, ex.ql_maxit);
+        else f = ql_implicit(d, e, m, Rl, NR, lane, v, q, ex.ql_maxit);
+        if (lane == 0) *failp = f;
     }
     __syncthreads();
+    if (*failp != 0) {
+        // an eigenvalue is still unconverged: the seed reports NU_NOCONV and NaN in every output
+        const double nan = __builtin_nan("");
+        if (ex.mode == 1) {
+            for (int idx = tid; idx < m * m; idx += WG) {
+                const int a = idx / m, c = idx - a * m;
+                ex.Y[((int64_t)b * nu + a) * nu + c] = nan;
+            }
+        } else if (ex.mode == 2) {
+            if (tid == 0) ex.phi[b] = nan;
+        } else if (zc == nullptr) {
+            for (int t = tid; t < nP; t += WG) rho[rlo + t] = nan;
+            if (tid == 0) {
+                e_seed[b] = nan;
+                n_seed[b] = nan;
+            }
+        }
+        for (int a = tid; a < nu; a += WG) {
+            if (eps_b) eps_b[a] = nan;
+            if (w_b) w_b[a] = nan;
+        }
+        if (tid == 0) nu_eff_out[b] = NU_NOCONV;
+        return;
+    }
 
     // Fermi-weighted assembly, or (zc != nullptr) keep the rows e_i.v_alpha,
     // i in P(j), for an assembly at a Fermi level found later (k_assemble).
@@ -520,9 +549,13 @@ __global__ __launch_bounds__(WG) void k_assemble(int nseeds, const int32_t* __re
     if (b >= nseeds) return;
     const int m = nu_eff[b];
     if (m <= 0) {
+        // a seed whose subspace eigensolve did not converge gets NaN outputs, as in k_eig
+        const double fill = m == NU_NOCONV ? __builtin_nan("") : 0.0;
+        if (m == NU_NOCONV)
+            for (int t = Hrp[seeds[b]] + tid; t < Hrp[seeds[b] + 1]; t += WG) rho[t] = fill;
         if (tid == 0) {
-            e_seed[b] = 0.0;
-            n_seed[b] = 0.0;
+            e_seed[b] = fill;
+            n_seed[b] = fill;
         }
         return;
     }

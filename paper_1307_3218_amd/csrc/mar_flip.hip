@@ -5,9 +5,13 @@
 // of a_l changes r by -2 a_l (H - eps S) e_l on the rows of P(l) only (H and S
 // are symmetric) and p by -2 a_l s_l, s = S phi_ref, so no product with the
 // matrix is needed after the first residual. The rows are visited by colour of
-// a distance-2 colouring of H's pattern: rows of one colour have disjoint
-// column supports, so their single-flip changes of |r|^2 are independent and
-// all of them decide at once; the penalty uses p from the start of the colour.
+// a distance-2 colouring of H's pattern, and in index order within a colour.
+// Rows of one colour have disjoint column supports, so the |r|^2 part of each
+// row's single-flip change does not depend on the colour's other flips: it is
+// computed for all rows of the colour at once. Without the penalty the rows
+// then decide at once. The penalty couples every row through p, so with it one
+// wave walks the colour's rows in index order, each deciding on the p left by
+// the flips before it: a sequential descent, every accepted flip lowering R.
 // Sweeps repeat until one flips nothing or max_sweeps have run.
 //
 // One workgroup does everything (the refinement is a small cost next to the
@@ -22,12 +26,20 @@ namespace mar {
 
 constexpr int FLIP_WG = 1024;
 
+__device__ __forceinline__ double bcast(double v, int t) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, t);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), t);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 __global__ __launch_bounds__(FLIP_WG) void k_flip(int64_t M, const int32_t* __restrict__ rp,
                                                   const int32_t* __restrict__ col, const double* __restrict__ hv,
                                                   const double* __restrict__ sv, double eps, double* phi,
                                                   const double* __restrict__ phi_ref, double cpen, int ncol,
                                                   const int32_t* __restrict__ coff, const int32_t* __restrict__ crow,
-                                                  int max_sweeps, double* r, double* s, int8_t* flag,
+                                                  int max_sweeps, double* r, double* s, double* drr,
+                                                  int8_t* flag,
                                                   double* __restrict__ Rout, int32_t* __restrict__ info) {
 #pragma clang fp contract(off)
     const int tid = threadIdx.x;
@@ -77,7 +89,7 @@ __global__ __launch_bounds__(FLIP_WG) void k_flip(int64_t M, const int32_t* __re
         __syncthreads();
         for (int k = 0; k < ncol; ++k) {
             const int e0 = coff[k], e1 = coff[k + 1];
-            const double p = p_sh;
+            // the |r|^2 part of each row's single-flip change, summed in the row's column order
             for (int e = e0 + tid; e < e1; e += FLIP_WG) {
                 const int l = crow[e];
                 const double a = phi[l];
@@ -86,8 +98,41 @@ __global__ __launch_bounds__(FLIP_WG) void k_flip(int64_t M, const int32_t* __re
                     const double av = hv[q] - eps * sv[q];
                     d = d + av * ((4.0 * a) * a * av - (4.0 * a) * r[col[q]]);
                 }
-                if (pen) d = d + cpen * ((4.0 * a) * a * s[l] * s[l] - (4.0 * a) * s[l] * p);
-                flag[e] = d < 0.0 ? 1 : 0;
+                if (pen)
+                    drr[e] = d;
+                else
+                    flag[e] = d < 0.0 ? 1 : 0;
+            }
+            __threadfence_block();
+            __syncthreads();
+            if (pen && tid < 64) {
+                // wave 0 walks the colour's rows in index order, 64 at a time: each
+                // lane prepares its row's p-independent terms, then every lane takes
+                // the same decisions on broadcast values, p carried in registers
+                double p = p_sh;
+                for (int base = e0; base < e1; base += 64) {
+                    const int e = base + tid;
+                    const bool in = e < e1;
+                    double dl = 0.0, x = 0.0, y = 0.0, z = 0.0;
+                    if (in) {
+                        const int l = crow[e];
+                        const double a = phi[l], sl = s[l];
+                        dl = drr[e];
+                        x = (4.0 * a) * a * sl * sl;
+                        y = (4.0 * a) * sl;
+                        z = (2.0 * a) * sl;
+                    }
+                    const int n = e1 - base < 64 ? e1 - base : 64;
+                    int8_t mine = 0;
+                    for (int t = 0; t < n; ++t) {
+                        const double d = bcast(dl, t) + cpen * (bcast(x, t) - bcast(y, t) * p);
+                        const bool f = d < 0.0;
+                        if (f) p = p - bcast(z, t);
+                        if (t == tid) mine = f ? 1 : 0;
+                    }
+                    if (in) flag[e] = mine;
+                }
+                if (tid == 0) p_sh = p;
             }
             __threadfence_block();
             __syncthreads();
@@ -105,16 +150,6 @@ __global__ __launch_bounds__(FLIP_WG) void k_flip(int64_t M, const int32_t* __re
             }
             if (mine) atomicAdd(&nflip, mine);
             __threadfence_block();
-            __syncthreads();
-            if (pen && tid == 0) {   // p drops by the flipped rows' 2 a s_l, summed in index order
-                double dp = 0.0;
-                for (int e = e0; e < e1; ++e)
-                    if (flag[e]) {
-                        const int l = crow[e];
-                        dp = dp + (2.0 * (-phi[l])) * s[l];
-                    }
-                p_sh = p - dp;
-            }
             __syncthreads();
         }
         double part = 0.0;
@@ -135,10 +170,10 @@ __global__ __launch_bounds__(FLIP_WG) void k_flip(int64_t M, const int32_t* __re
 
 LaunchInfo launch_flip(int64_t M, const int32_t* rp, const int32_t* col, const double* hv, const double* sv,
                        double eps, double* phi, const double* phi_ref, double cpen, int ncol, const int32_t* coff,
-                       const int32_t* crow, int max_sweeps, double* r, double* s, int8_t* flag, double* Rout,
-                       int32_t* info, hipStream_t st) {
+                       const int32_t* crow, int max_sweeps, double* r, double* s, double* drr, int8_t* flag,
+                       double* Rout, int32_t* info, hipStream_t st) {
     hipLaunchKernelGGL(k_flip, dim3(1), dim3(FLIP_WG), 0, st, M, rp, col, hv, sv, eps, phi, phi_ref, cpen, ncol,
-                       coff, crow, max_sweeps, r, s, flag, Rout, info);
+                       coff, crow, max_sweeps, r, s, drr, flag, Rout, info);
     LaunchInfo li;
     li.wgs = 1;
     return li;

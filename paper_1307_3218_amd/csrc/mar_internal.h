@@ -125,7 +125,10 @@ struct EigExtra {
     const double* win = nullptr;  // mode 2: {eps_k, eta(k-1), eta(k)} on the device
     double sigma = 0.0;           // mode 2: width of the smoothed delta
     double* phi = nullptr;        // mode 2: e_j^T phi_k of each seed
+    int ql_maxit = 80;            // implicit-QL iterations allowed per eigenvalue
 };
+// nu_eff of a seed whose subspace eigensolve did not converge
+constexpr int NU_NOCONV = -3;
 LaunchInfo launch_eig(int nseeds, const int32_t* seeds, int nu, double* h, const int32_t* nu_eff_blk,
                       const double* Kp, const int32_t* Hrp, const int32_t* Hcol, const double* Hval,
                       const double* SvalH, const double* diagS, int max_row, double mu, double kT, double* rho,
@@ -258,8 +261,8 @@ LaunchInfo launch_zero(void* p, int64_t bytes, hipStream_t s);  // bytes: multip
 // coff[k+1]) in index order; r, s [M] and flag [M] workspace; Rout [max_sweeps + 1] and info [2] optional.
 LaunchInfo launch_flip(int64_t M, const int32_t* rp, const int32_t* col, const double* hv, const double* sv,
                        double eps, double* phi, const double* phi_ref, double cpen, int ncol, const int32_t* coff,
-                       const int32_t* crow, int max_sweeps, double* r, double* s, int8_t* flag, double* Rout,
-                       int32_t* info, hipStream_t st);
+                       const int32_t* crow, int max_sweeps, double* r, double* s, double* drr, int8_t* flag,
+                       double* Rout, int32_t* info, hipStream_t st);
 
 // Largest B accepted for an element type (P = B / vector width must fit one wavefront).
 template <typename T>

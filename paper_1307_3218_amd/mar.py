@@ -19,8 +19,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmar.so")
 
 MAR_OK, MAR_ERR_ARG, MAR_ERR_PATTERN, MAR_ERR_NOT_SPD, MAR_ERR_NOMEM, MAR_ERR_HIP, MAR_ERR_STATE = 0, -1, -2, -3, -4, -5, -6
+MAR_ERR_NOCONV = -7
+NU_NOCONV = -3      # nu_eff of a seed whose subspace eigensolve did not converge
 STATUS_NAMES = {0: "MAR_OK", -1: "MAR_ERR_ARG", -2: "MAR_ERR_PATTERN", -3: "MAR_ERR_NOT_SPD",
-                -4: "MAR_ERR_NOMEM", -5: "MAR_ERR_HIP", -6: "MAR_ERR_STATE"}
+                -4: "MAR_ERR_NOMEM", -5: "MAR_ERR_HIP", -6: "MAR_ERR_STATE", -7: "MAR_ERR_NOCONV"}
 PRECISION = {"fp64": 0, "fp32": 1}
 SCHEDULE = {"auto": 0, "textbook": 1, "delayed": 2}
 FORM = {"batched": 0, "plain": 1}
@@ -37,7 +39,7 @@ class MarError(RuntimeError):
 class mar_tuning(C.Structure):
     _fields_ = [("seed_block", C.c_int32), ("schedule", C.c_int32), ("proj_wgs", C.c_int32),
                 ("slab_pad_kb", C.c_int32), ("proj_variant", C.c_int32), ("upd_q", C.c_int32),
-                ("support_off", C.c_int32), ("two_streams", C.c_int32)]
+                ("support_off", C.c_int32), ("two_streams", C.c_int32), ("ql_max_iter", C.c_int32)]
 
 
 class mar_request(C.Structure):
@@ -230,8 +232,10 @@ def mar_autotune(ctx, nu, prec, d_seeds, mu, kT, stream=None) -> tuple:
 
 
 def mar_set_tuning(ctx, seed_block: int = 0, schedule: int = 0, proj_wgs: int = 0, slab_pad_kb: int = 0,
-                   proj_variant: int = 0, upd_q: int = 0, support_off: int = 0, two_streams: int = 0) -> int:
-    t = mar_tuning(seed_block, schedule, proj_wgs, slab_pad_kb, proj_variant, upd_q, support_off, two_streams)
+                   proj_variant: int = 0, upd_q: int = 0, support_off: int = 0, two_streams: int = 0,
+                   ql_max_iter: int = 0) -> int:
+    t = mar_tuning(seed_block, schedule, proj_wgs, slab_pad_kb, proj_variant, upd_q, support_off, two_streams,
+                   ql_max_iter)
     return lib().mar_set_tuning(ctx, C.byref(t))
 
 
@@ -400,14 +404,15 @@ class Context:
 
     def set_tuning(self, seed_block: int = 0, schedule: str = "auto", proj_wgs: int = 0, slab_pad_kb: int = 0,
                    proj_variant: int = 0, upd_q: int = 0, support: bool = True, two_streams: bool | None = None,
-                   overlap_eig: bool = True):
+                   overlap_eig: bool = True, ql_max_iter: int = 0):
         """two_streams: None lets the library choose (two blocks in flight for local regions of 6 hops or
         more, else one block at a time); True alternates two blocks; False runs one block at a time, with
-        each block's eigensolve on the second stream when overlap_eig, else everything on one stream."""
+        each block's eigensolve on the second stream when overlap_eig, else everything on one stream.
+        ql_max_iter: QL iterations allowed per eigenvalue of the subspace eigensolve (0 = 80)."""
         _check(self.handle, mar_set_tuning(self.handle, seed_block, SCHEDULE[schedule], proj_wgs, slab_pad_kb,
                                            proj_variant, upd_q, 0 if support else 1,
                                            (0 if overlap_eig else 2) if two_streams is None else
-                                           1 if two_streams else (3 if overlap_eig else 2)))
+                                           1 if two_streams else (3 if overlap_eig else 2), ql_max_iter))
 
     def autotune(self, d_seeds, nu, mu, kT, precision="fp32", stream=None) -> dict:
         """Pick the seed block and projection tiles for (nu, precision) by timing probe solves."""

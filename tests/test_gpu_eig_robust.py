@@ -1,0 +1,122 @@
+"""The subspace eigensolve (Sec. 2: one nu x nu standard eigenproblem per seed, FP64) on the GPU:
+failure reporting and the plane rotations over the whole exponent range.
+
+* An iteration cap too small for the implicit QL iteration to converge (tuning ql_max_iter = 1 on the
+  subspace matrices of the 64-atom cell) must be reported: nu_eff = -3 and NaN outputs for the seed,
+  MAR_ERR_NOCONV from the host entry points. The cap bounds the QL loop, so every kernel exits normally.
+* The QL rotations form r = sqrt(f^2 + g^2) and 1/(2r) from a reciprocal-square-root estimate refined by
+  two coupled Goldschmidt steps. Scaling H, mu and kT by 2^k leaves rho unchanged and scales the levels and
+  E_band by 2^k (scale covariance), while f^2 + g^2 scales by 4^k. The plain form (textbook schedule,
+  normalized vectors) takes k = +-480, which moves f^2 + g^2 across roughly 2^-950 ... 2^970; the batched
+  form's delayed schedule forms products of the unnormalized residual with itself, cubic in the scale of
+  H, and takes k = +-150, +-300. Every scale is compared with the oracle at that scale to the FP64 bar,
+  and with the unscaled GPU result.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mar_oracle as O
+from paper_1307_3218_amd import mar
+
+pytestmark = pytest.mark.gpu
+
+NU, KT, MU = 30, 0.1, 0.0
+
+
+@pytest.fixture(scope="module")
+def ctx(cell256):
+    c = mar.Context(cell256.H, cell256.S)
+    yield c
+    c.close()
+
+
+def _slots(H, seeds):
+    return np.concatenate([np.arange(H.indptr[j], H.indptr[j + 1]) for j in seeds])
+
+
+def test_iteration_cap_reported_host(cell256, ctx):
+    seeds = np.arange(0, cell256.M, 7)
+    ctx.set_tuning(ql_max_iter=1)
+    try:
+        print("[eig-robust] host solve with ql_max_iter = 1", flush=True)
+        with pytest.raises(mar.MarError) as ei:
+            ctx.solve(seeds, NU, MU, KT, precision="fp64")
+        assert ei.value.status == mar.MAR_ERR_NOCONV
+        with pytest.raises(mar.MarError) as ei:
+            ctx.solve_fermi(seeds, NU, float(len(seeds)), KT, precision="fp32")
+        assert ei.value.status == mar.MAR_ERR_NOCONV
+    finally:
+        ctx.set_tuning()
+    # the default cap converges again, and the result is the oracle's
+    ref = O.solve(cell256.H, cell256.S, seeds, NU, MU, KT)
+    g = ctx.solve(seeds, NU, MU, KT, precision="fp64")
+    assert np.array_equal(g.nu_eff, ref.nu_eff)
+    assert abs(g.e_band - ref.e_band) <= 1e-10 * abs(ref.e_band)
+
+
+@pytest.mark.parametrize("prec,form", [("fp64", "batched"), ("fp32", "batched"), ("fp64", "plain")])
+def test_iteration_cap_reported_async(cell256, ctx, prec, form):
+    import torch
+    dev = torch.device("cuda", 0)
+    H = cell256.H
+    seeds = np.arange(3, cell256.M, 11, dtype=np.int32)
+    n = len(seeds)
+    d_seeds = torch.as_tensor(seeds).to(dev)
+    d_rho = torch.zeros(H.nnz, dtype=torch.float64, device=dev)
+    d_eb = torch.zeros(1, dtype=torch.float64, device=dev)
+    d_e = torch.zeros(n, dtype=torch.float64, device=dev)
+    d_n = torch.zeros(n, dtype=torch.float64, device=dev)
+    d_nu = torch.zeros(n, dtype=torch.int32, device=dev)
+    d_eps = torch.zeros(n * NU, dtype=torch.float64, device=dev)
+    d_w = torch.zeros(n * NU, dtype=torch.float64, device=dev)
+    ctx.set_tuning(ql_max_iter=1)
+    try:
+        print(f"[eig-robust] async solve with ql_max_iter = 1, {prec} {form}", flush=True)
+        ctx.solve_async(d_seeds, NU, MU, KT, precision=prec, form=form, d_rho=d_rho, d_e_band=d_eb, d_e_seed=d_e,
+                        d_n_seed=d_n, d_nu_eff=d_nu, d_eps=d_eps, d_weight=d_w)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_tuning()
+    nu_eff = d_nu.cpu().numpy()
+    assert np.all(nu_eff == mar.NU_NOCONV), nu_eff
+    rho = d_rho.cpu().numpy()
+    assert np.all(np.isnan(rho[_slots(H, seeds)]))
+    others = np.setdiff1d(np.arange(H.nnz), _slots(H, seeds))
+    assert np.all(rho[others] == 0.0)                   # rows of unlisted seeds untouched
+    assert np.all(np.isnan(d_e.cpu().numpy())) and np.all(np.isnan(d_n.cpu().numpy()))
+    assert np.all(np.isnan(d_eps.cpu().numpy())) and np.all(np.isnan(d_w.cpu().numpy()))
+    assert math.isnan(float(d_eb.cpu()[0]))
+
+
+@pytest.mark.parametrize("form,k", [("plain", -480), ("plain", 480), ("batched", -300), ("batched", -150),
+                                    ("batched", 150), ("batched", 300)])
+def test_rotations_over_exponent_range(cell256, ctx, form, k):
+    H, S = cell256.H, cell256.S
+    a = math.ldexp(1.0, k)
+    seeds = np.arange(1, cell256.M, 9)
+    base = ctx.solve(seeds, NU, MU, KT, precision="fp64", form=form, levels=True)
+    Hs = H.copy()
+    Hs.data = Hs.data * a                                   # exact: a power of two
+    cs = mar.Context(Hs, S)
+    try:
+        print(f"[eig-robust] H scaled by 2^{k}, {form}", flush=True)
+        g = cs.solve(seeds, NU, MU * a, KT * a, precision="fp64", form=form, levels=True)
+    finally:
+        cs.close()
+    ref = O.solve(Hs, S, seeds, NU, MU * a, KT * a)
+    idx = _slots(H, seeds)
+    assert np.array_equal(g.nu_eff, ref.nu_eff)
+    rho_rel = np.linalg.norm(g.rho[idx] - ref.rho[idx]) / np.linalg.norm(ref.rho[idx])
+    e_rel = abs(g.e_band - ref.e_band) / abs(ref.e_band)
+    print(f"[eig-robust 2^{k}] rho {rho_rel:.2e} E_band {e_rel:.2e}", flush=True)
+    assert rho_rel <= 1e-10 and e_rel <= 1e-10
+    for s in range(len(seeds)):
+        m = g.nu_eff[s]
+        lv = np.sort(g.eps[s, :m]) / a
+        assert np.abs(lv - np.sort(ref.eps[s]) / a).max() <= 1e-10 * 20.0
+    # against the unscaled GPU solve: rho unchanged, levels and E_band scaled
+    np.testing.assert_allclose(g.rho[idx], base.rho[idx], rtol=0, atol=1e-12 * np.abs(base.rho[idx]).max())
+    assert abs(g.e_band / a - base.e_band) <= 1e-12 * abs(base.e_band)
+    np.testing.assert_allclose(g.eps / a, base.eps, rtol=0, atol=1e-12 * np.abs(base.eps).max())

@@ -2,7 +2,9 @@
 
 The decisions are comparisons of FP64 sums taken in the same order on both
 sides with separately rounded products, so the refined vector, the sweep and
-flip counts must agree exactly and the residual history to rounding.
+flip counts must agree exactly and the residual history to rounding. With the
+orthogonality penalty the rows of a colour decide one after the other on the
+current p, so the penalised R never rises from sweep to sweep.
 """
 import numpy as np
 import pytest
@@ -51,15 +53,23 @@ def test_flip_matches_oracle(case, seed):
     assert g["R"][-1] < g["R"][0]
 
 
-def test_flip_with_penalty_matches_oracle(case):
+@pytest.mark.parametrize("seed,cscale", [(5, 1.0), (2, 50.0), (7, 50.0)])
+def test_flip_with_penalty_matches_oracle(case, seed, cscale):
+    """With the orthogonality penalty every row decides on the p left by the flips before it (a sequential
+    descent): the penalised R never rises, on the device as in the oracle."""
     H, S, ev, V, ctx = case
     k = H.shape[0] // 2
-    x = _start(V, k, 5, noise=0.02, frac=0.1)
-    ref = OF.local_flip(H, S, x, ev[k], phi_ref=V[:, k - 1], c=OF.C_PAPER_EV2, max_sweeps=60)
-    g = ctx.local_flip(x, ev[k], phi_ref=V[:, k - 1], c=OF.C_PAPER_EV2, max_sweeps=60)
+    x = _start(V, k, seed, noise=0.02, frac=0.1 if seed == 5 else 0.2)
+    c = cscale * OF.C_PAPER_EV2
+    ref = OF.local_flip(H, S, x, ev[k], phi_ref=V[:, k - 1], c=c, max_sweeps=60)
+    g = ctx.local_flip(x, ev[k], phi_ref=V[:, k - 1], c=c, max_sweeps=60)
+    print(f"[flip penalty M={H.shape[0]} c={c:.3g}] sweeps {g['sweeps']} flips {g['flips']} "
+          f"R {g['R'][0]:.3e} -> {g['R'][-1]:.3e}", flush=True)
     assert g["sweeps"] == ref.sweeps and g["flips"] == ref.flips
     assert np.array_equal(g["phi"], ref.phi)
     np.testing.assert_allclose(g["R"], ref.R, rtol=1e-10)
+    assert all(b <= a * (1.0 + 1e-12) for a, b in zip(g["R"], g["R"][1:]))
+    assert g["R"][-1] == pytest.approx(OF.residual_norm(H, S, g["phi"], ev[k], V[:, k - 1], c), rel=1e-10)
 
 
 def test_first_colour_errors_undone(case):
