@@ -173,6 +173,29 @@ mar_status mar_solve_async(mar_ctx* ctx, const int32_t* d_seeds, int64_t n_seeds
                            double* d_rho, double* d_e_band, double* d_e_seed, double* d_n_seed,
                            int32_t* d_nu_eff, double* d_eps, double* d_weight, void* hip_stream);
 
+/* ---- the solve without device allocation ----
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc. Same
+ * arguments, outputs and errors as mar_solve_async, but the solve runs on a
+ * static device array of MAR_NOALLOC_SCRATCH_BYTES instead of the context's
+ * workspace, and the call allocates nothing (no hipMalloc, hipFree or
+ * allocating library routine; per-kernel timing is suspended for the call).
+ * Every GPU the library runs on holds the array until the process ends; its
+ * address is looked up at the first call on each device. With the batched
+ * form and no seed block fixed by mar_set_tuning, the planned block is halved
+ * until the solve's workspace fits the array; a solve that does not fit even
+ * then (or with the block fixed) is refused with MAR_ERR_ARG and the needed
+ * size in mar_last_error (about nu * M * B * 4 bytes of FP32 basis for blocks
+ * of B seeds: M = 16384, nu = 30 runs FP32 blocks of up to 16-32 seeds). All
+ * calls on one GPU share the array and it keeps the last call's contents:
+ * calls that overlap on one GPU (other streams, other threads, other
+ * contexts) race and must be serialized by the caller. */
+#define MAR_NOALLOC_SCRATCH_BYTES (64ull << 20)
+mar_status mar_solve_async_noalloc(mar_ctx* ctx, const int32_t* d_seeds, int64_t n_seeds, int32_t nu, double mu,
+                                   double kT, mar_precision prec, mar_form form, double* d_rho, double* d_e_band,
+                                   double* d_e_seed, double* d_n_seed, int32_t* d_nu_eff, double* d_eps,
+                                   double* d_weight, void* hip_stream);
+
 /* ---- Fermi level found on the device ----
  * The method takes the chemical potential mu as given (Sec. 2: the subspace
  * levels give the Green's function, and from it the energy at mu). These

@@ -21,7 +21,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libmar.so")
 
 SOURCES = ["mar_api.cpp", "mar_common.hip", "mar_support.hip", "mar_flip.hip", "mar_launch_f32.hip",
-           "mar_launch_f64.hip", "mar_eig.hip"]
+           "mar_launch_f64.hip", "mar_eig.hip", "mar_noalloc.hip"]
 ARCH = "gfx950"
 FLAGS = [
     "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",

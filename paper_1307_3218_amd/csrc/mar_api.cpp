@@ -100,6 +100,10 @@ struct mar_ctx {
     int32_t loc = -1;             // local-region hops of later solves (< 0: the full system)
     char* ws = nullptr;
     size_t ws_bytes = 0;
+    char* ext_ws = nullptr;       // a caller's workspace for the current solve (nothing is allocated then)
+    size_t ext_bytes = 0;
+    bool ext_short = false;       // the current solve needs more than ext_bytes
+    char* ws_act = nullptr;       // the workspace the current solve runs on (ws or ext_ws)
     char* io = nullptr;
     size_t io_bytes = 0;
     hipStream_t stream = nullptr;
@@ -426,6 +430,15 @@ int64_t slab_stride(const mar_ctx* c, int64_t Mp, int B, size_t elem) {
 void drop_graphs_of(mar_ctx* c);
 
 mar_status ensure_ws(mar_ctx* c, size_t bytes) {
+    if (c->ext_ws) {   // the caller's workspace: never allocate, refuse what does not fit
+        c->ws_act = c->ext_ws;
+        if (bytes <= c->ext_bytes) return MAR_OK;
+        c->ext_short = true;
+        return set_err(c, MAR_ERR_ARG,
+                       fmt("the solve needs %zu bytes of workspace, more than the %zu bytes of the static scratch",
+                           bytes, c->ext_bytes));
+    }
+    c->ws_act = c->ws;
     if (bytes <= c->ws_bytes) return MAR_OK;
     if (c->ws) {
         HIP_OR(c, hipDeviceSynchronize());
@@ -438,6 +451,7 @@ mar_status ensure_ws(mar_ctx* c, size_t bytes) {
     HIP_OR(c, hipMalloc(&p, bytes));
     c->ws = (char*)p;
     c->ws_bytes = bytes;
+    c->ws_act = c->ws;
     return MAR_OK;
 }
 
@@ -527,7 +541,7 @@ mar_status run_solve(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds, int nu
     const size_t oNc2 = take(eig_ovl ? (size_t)B * 4 : 0);
     mar_status st = ensure_ws(c, off);
     if (st != MAR_OK) return st;
-    char* w = c->ws;
+    char* w = c->ws_act;
     mar::BlockWS<T> ws{(T*)(w + oK), (T*)(w + oSK), (T*)(w + oW), (T*)(w + oZ), (double*)(w + oPart),
                        (double*)(w + oRed1), (double*)(w + oRed2), (double*)(w + oRedb), (double*)(w + oH),
                        (double*)(w + oBeta), (int32_t*)(w + oAct), (int32_t*)(w + oNu)};
@@ -722,7 +736,7 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     constexpr int kTwoSetMinHops = 6;
     const int tsm = c->tune.two_streams != 0 ? c->tune.two_streams : (local && c->loc >= kTwoSetMinHops ? 1 : 3);
     bool two_fit = 2.0 * (double)set_bytes <= kTwoSetBytes;
-    if (two_fit && tsm == 1 && c->tune.two_streams == 0 && !c->dry && 2 * set_bytes > c->ws_bytes) {
+    if (two_fit && tsm == 1 && c->tune.two_streams == 0 && !c->dry && !c->ext_ws && 2 * set_bytes > c->ws_bytes) {
         // the default takes a second workspace only when the device has room for it (the current
         // workspace is given back first); else it runs one block at a time
         size_t fr = 0, tot = 0;
@@ -749,7 +763,7 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     const size_t oNuOut = take(own_nu ? (size_t)n_seeds * 4 : 0);
     mar_status st = ensure_ws(c, off);
     if (st != MAR_OK) return st;
-    char* w = c->ws;
+    char* w = c->ws_act;
     // profiled solve: each block's tile counts are kept for the restricted byte counts
     int32_t* plog = nullptr;
     if (sparse && c->prof && !c->dry) {
@@ -1915,3 +1929,55 @@ int32_t mar_ctx_info(const mar_ctx* c, int64_t* M, int64_t* nnz_H, int64_t* nnz_
 }
 
 }  // extern "C"
+
+// --------------------------------------------------- solve on a caller's workspace
+namespace mar {
+
+int ctx_device(const mar_ctx* c) { return c ? c->device : -1; }
+
+mar_status ctx_error(mar_ctx* c, mar_status st, const char* msg) { return set_err(c, st, msg); }
+
+// mar_solve_async on the workspace ws[0, ws_bytes) instead of the context's own:
+// nothing is allocated on the device. With the batched form and no block size
+// fixed by the tuning, the planned seed block is halved until the solve's
+// workspace fits (a dry run sizes it); per-kernel timing is suspended for the
+// call (its events and tile logs would be created on demand).
+mar_status solve_async_ext(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds, int32_t nu, double mu, double kT,
+                           mar_precision prec, mar_form form, double* d_rho, double* d_e_band, double* d_e_seed,
+                           double* d_n_seed, int32_t* d_nu_eff, double* d_eps, double* d_weight, void* ws,
+                           size_t ws_bytes, void* hip_stream) {
+    if (!c) return MAR_ERR_STATE;
+    mar_status st = check_scalars(c, n_seeds, nu, mu, kT, prec, form);
+    if (st != MAR_OK) return st;
+    if (!d_e_band) return set_err(c, MAR_ERR_ARG, "e_band output is NULL");
+    if (n_seeds > 0 && (!d_seeds || !d_rho)) return set_err(c, MAR_ERR_ARG, "seeds or rho is NULL");
+    if (!ws) return set_err(c, MAR_ERR_STATE, "no workspace");
+    HIP_OR(c, hipSetDevice(c->device));
+    const mar_request r{d_seeds, n_seeds, nu, mu, kT, prec, form, d_rho, d_e_band, d_e_seed, d_n_seed, d_nu_eff,
+                        d_eps, d_weight};
+    hipStream_t s = (hipStream_t)hip_stream;
+    Plan pl = plan_solve(c, nu, prec, form, n_seeds);
+    const int min_b = c->loc >= 0 ? (prec == MAR_FP32 ? 4 : 2) : 1;
+    const bool shrink = form == MAR_FORM_BATCHED && c->tune.seed_block == 0;
+    const bool prof = c->prof;
+    c->prof = false;
+    c->ext_ws = (char*)ws;
+    c->ext_bytes = ws_bytes;
+    for (;;) {
+        c->ext_short = false;
+        c->dry = true;
+        st = dispatch_solve(c, r, pl, s);
+        c->dry = false;
+        if (st == MAR_OK || !c->ext_short || !shrink || pl.B / 2 < min_b) break;
+        pl.B /= 2;
+    }
+    if (st == MAR_OK) st = dispatch_solve(c, r, pl, s);
+    c->ext_ws = nullptr;
+    c->ext_bytes = 0;
+    c->ext_short = false;
+    c->ws_act = c->ws;
+    c->prof = prof;
+    return st;
+}
+
+}  // namespace mar

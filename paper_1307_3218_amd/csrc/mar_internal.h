@@ -2,7 +2,10 @@
 #pragma once
 
 #include <hip/hip_runtime_api.h>
+#include <stddef.h>
 #include <stdint.h>
+
+#include "mar.h"
 
 namespace mar {
 
@@ -270,5 +273,17 @@ constexpr int max_block() { return sizeof(T) == 4 ? 256 : 128; }
 
 size_t eig_lds_bytes(int nu, int max_row, bool a_in_lds);
 bool eig_a_fits_lds(int nu, int max_row);
+
+// The device a context lives on (-1 for NULL).
+int ctx_device(const mar_ctx* c);
+// Record msg as the context's last error and return st.
+mar_status ctx_error(mar_ctx* c, mar_status st, const char* msg);
+// mar_solve_async on the caller's workspace ws[0, ws_bytes): no device allocation. The batched form's
+// planned seed block (when the tuning fixes none) is halved until the workspace fits; MAR_ERR_ARG when
+// even the smallest block does not fit.
+mar_status solve_async_ext(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds, int32_t nu, double mu, double kT,
+                           mar_precision prec, mar_form form, double* d_rho, double* d_e_band, double* d_e_seed,
+                           double* d_n_seed, int32_t* d_nu_eff, double* d_eps, double* d_weight, void* ws,
+                           size_t ws_bytes, void* hip_stream);
 
 }  // namespace mar

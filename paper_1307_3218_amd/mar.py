@@ -81,6 +81,8 @@ def lib() -> C.CDLL:
     L.mar_solve.restype = C.c_int
     L.mar_solve_async.argtypes = [_P, _P, i64, i32, f64, f64, C.c_int, C.c_int, _P, _P, _P, _P, _P, _P, _P, _P]
     L.mar_solve_async.restype = C.c_int
+    L.mar_solve_async_noalloc.argtypes = L.mar_solve_async.argtypes
+    L.mar_solve_async_noalloc.restype = C.c_int
     L.mar_solve_fermi.argtypes = [_P, _P, i64, i32, f64, f64, C.c_int, C.c_int, _P, _P, _P, _P, _P, _P, _P, _P]
     L.mar_solve_fermi.restype = C.c_int
     L.mar_solve_fermi_async.argtypes = [_P, _P, i64, i32, f64, f64, C.c_int, C.c_int, _P, _P, _P, _P, _P, _P, _P,
@@ -177,6 +179,14 @@ def mar_solve_async(ctx, d_seeds, n_seeds, nu, mu, kT, prec, form, d_rho, d_e_ba
     return lib().mar_solve_async(ctx, _tptr(d_seeds), int(n_seeds), int(nu), float(mu), float(kT), int(prec),
                                  int(form), _tptr(d_rho), _tptr(d_e_band), _tptr(d_e_seed), _tptr(d_n_seed),
                                  _tptr(d_nu_eff), _tptr(d_eps), _tptr(d_weight), stream)
+
+
+def mar_solve_async_noalloc(ctx, d_seeds, n_seeds, nu, mu, kT, prec, form, d_rho, d_e_band, d_e_seed=None,
+                            d_n_seed=None, d_nu_eff=None, d_eps=None, d_weight=None, stream=None) -> int:
+    """As mar_solve_async, on the library's static scratch array: no device allocation."""
+    return lib().mar_solve_async_noalloc(ctx, _tptr(d_seeds), int(n_seeds), int(nu), float(mu), float(kT),
+                                         int(prec), int(form), _tptr(d_rho), _tptr(d_e_band), _tptr(d_e_seed),
+                                         _tptr(d_n_seed), _tptr(d_nu_eff), _tptr(d_eps), _tptr(d_weight), stream)
 
 
 def mar_solve_fermi(ctx, seeds, nu, n_target, kT, prec, form, rho, e_band, mu, e_seed=None, n_seed=None,
