@@ -107,14 +107,14 @@ def errors_vs_oracle(ctx, system, seeds, ref, nu, mu):
     """Per-result error of the device forms against the oracle on the oracle's seeds."""
     H = system.H
     idx = np.concatenate([np.arange(H.indptr[j], H.indptr[j + 1]) for j in seeds])
-    from paper_1307_3218_amd import fermi
+    from oracle import mar_oracle as O
     out = {}
     for prec, form in (("fp32", "batched"), ("fp64", "batched"), ("fp64", "plain")):
         g = ctx.solve(np.asarray(seeds, dtype=np.int32), nu, mu, KT, precision=prec, form=form, levels=True)
         # invariants of the device outputs alone: sum_a w_a = 1, N_j = 2 sum f w, E_j = 2 sum f eps w
         mask = np.arange(nu)[None, :] < g.nu_eff[:, None]
         w = np.where(mask, g.weight, 0.0)
-        fw = np.where(mask, fermi.occupation(g.eps, mu, KT), 0.0) * w
+        fw = np.where(mask, O.fermi(g.eps, mu, KT), 0.0) * w
         out[f"{prec}_{form}"] = dict(
             e_band_rel=float(abs(g.e_band - ref.e_band) / abs(ref.e_band)),
             rho_rel=float(np.linalg.norm(g.rho[idx] - ref.rho[idx]) / np.linalg.norm(ref.rho[idx])),
@@ -343,7 +343,8 @@ def main() -> int:
         return run_uneven(args)
     if args.workload == "eigenstate":
         return run_eigenstate(args)
-    from paper_1307_3218_amd import fermi, lattice, mar
+    from oracle import mar_oracle as O
+    from paper_1307_3218_amd import lattice, mar
     t = time.perf_counter()
     system = lattice.workload(args.workload)
     M, nu = system.M, args.nu
@@ -413,9 +414,13 @@ def main() -> int:
             ctx.profile(False)
             mu = float(d_mu.cpu()[0])
             nue = d_nu.cpu().numpy()
-            mu_host = fermi.fermi_level(d_eps.cpu().numpy(), d_w.cpu().numpy(), nue, float(S_step), KT)
+            # the oracle's bisection on the device's levels and weights, as a check of the device search
+            h_eps, h_w = d_eps.cpu().numpy(), d_w.cpu().numpy()
+            eps_l = [h_eps[i, :m] for i, m in enumerate(nue) if m > 0]
+            w_l = [h_w[i, :m] for i, m in enumerate(nue) if m > 0]
+            mu_host = O.fermi_level(eps_l, w_l, float(S_step), KT)
             # sum rule: the seeds' electron count at the device's mu equals the target (half filling)
-            n_at_mu = fermi.electron_count(d_eps.cpu().numpy(), d_w.cpu().numpy(), nue, mu, KT)
+            n_at_mu = O.electron_count(eps_l, w_l, mu, KT)
             fermi_info = dict(mu=mu, seeds=S_step, search_ms=round(fs["ms"], 3) if fs else None,
                               host_bisection_mu=mu_host, electron_count_at_mu=n_at_mu,
                               electron_count_rel_error=abs(n_at_mu - float(S_step)) / float(S_step))

@@ -342,7 +342,11 @@ mar_status mar_set_local_region(mar_ctx* ctx, int32_t hops);
 /* Current local-region hops of ctx (-1: the full system, or ctx NULL). */
 int32_t mar_local_region(const mar_ctx* ctx);
 
-/* Set the tuning used by later solves (NULL restores the defaults). */
+/* Set the tuning used by later solves. NULL restores the defaults (every
+ * field 0): later batched solves then use the (B, projection variant) that
+ * mar_autotune kept for their (nu, precision) on this context, when it ran,
+ * else the widest block whose basis fits in 128 GB. A nonzero seed_block or
+ * proj_variant overrides the autotuned choice. */
 mar_status mar_set_tuning(mar_ctx* ctx, const mar_tuning* t);
 mar_status mar_get_tuning(const mar_ctx* ctx, mar_tuning* t);
 
@@ -372,6 +376,11 @@ mar_status mar_profile_enable(mar_ctx* ctx, int32_t on);
 mar_status mar_profile_reset(mar_ctx* ctx);
 mar_status mar_profile_collect(mar_ctx* ctx, mar_prof_entry* out /* [MAR_PROF_CLASSES] */,
                                int32_t* n_out);
+
+/* Identity of the build: the first 16 hex digits of the SHA-256 over the
+ * library's source files and this header, as the build script computed them
+ * (static string, never NULL). */
+const char* mar_build_id(void);
 
 /* Library description: matrix storage actually used (1 = BSR 4x4 for H, 2 = for S). */
 int32_t mar_ctx_info(const mar_ctx* ctx, int64_t* M, int64_t* nnz_H, int64_t* nnz_S);

@@ -3,11 +3,14 @@
     python -m paper_1307_3218_amd.build_lib [-v]
 
 Objects go to <repo>/_build/, the library to paper_1307_3218_amd/libmar.so.
-Every call recompiles every source.
+Every call recompiles every source. The library's mar_build_id() returns
+source_hash() of the sources it was built from, so that a test can tell a
+library built from other sources.
 """
 from __future__ import annotations
 
 import concurrent.futures as cf
+import hashlib
 import os
 import shutil
 import subprocess
@@ -31,6 +34,17 @@ FLAGS = [
 ]
 
 
+def source_hash() -> str:
+    """First 16 hex digits of the SHA-256 over every source and header the library is built from."""
+    h = hashlib.sha256()
+    files = sorted(f for f in os.listdir(CSRC) if f.endswith((".cpp", ".hip", ".h")))
+    for name, path in [(f, os.path.join(CSRC, f)) for f in files] + [("mar.h", os.path.join(INCLUDE, "mar.h"))]:
+        h.update(name.encode())
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def hipcc() -> str:
     for c in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
         if c and os.path.exists(c):
@@ -38,9 +52,9 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def _compile(src: str, verbose: bool) -> str:
+def _compile(src: str, verbose: bool, build_id: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), *FLAGS]
+    cmd = [hipcc(), *FLAGS, f'-DMAR_BUILD_ID="{build_id}"']
     if src.endswith(".hip"):
         cmd += ["-x", "hip"]
     cmd += ["-c", os.path.join(CSRC, src), "-o", obj]
@@ -57,8 +71,9 @@ def _compile(src: str, verbose: bool) -> str:
 def build(verbose: bool = False, jobs: int | None = None) -> str:
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or min(len(SOURCES), max(1, (os.cpu_count() or 2)))
+    build_id = source_hash()
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+        objs = list(ex.map(lambda s: _compile(s, verbose, build_id), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     if verbose:

@@ -1920,6 +1920,11 @@ mar_status mar_profile_collect(mar_ctx* c, mar_prof_entry* out, int32_t* n_out) 
     return MAR_OK;
 }
 
+#ifndef MAR_BUILD_ID
+#define MAR_BUILD_ID "unknown"
+#endif
+const char* mar_build_id(void) { return MAR_BUILD_ID; }
+
 int32_t mar_ctx_info(const mar_ctx* c, int64_t* M, int64_t* nnz_H, int64_t* nnz_S) {
     if (!c) return -1;
     if (M) *M = c->M;

@@ -121,6 +121,8 @@ def lib() -> C.CDLL:
     L.mar_profile_collect.restype = C.c_int
     L.mar_ctx_info.argtypes = [_P, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
     L.mar_ctx_info.restype = i32
+    L.mar_build_id.argtypes = []
+    L.mar_build_id.restype = C.c_char_p
     _lib = L
     return L
 
@@ -284,6 +286,11 @@ def mar_profile_collect(ctx) -> dict:
     _check(ctx, lib().mar_profile_collect(ctx, arr, C.byref(n)))
     return {arr[k].name.decode(): dict(launches=arr[k].launches, ms=arr[k].ms, bytes=arr[k].bytes,
                                        flops=arr[k].flops) for k in range(n.value)}
+
+
+def mar_build_id() -> str:
+    """The source hash the loaded library was built from (build_lib.source_hash() at build time)."""
+    return lib().mar_build_id().decode()
 
 
 def mar_ctx_info(ctx) -> dict:

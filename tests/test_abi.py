@@ -164,3 +164,35 @@ def test_null_context_calls():
     assert L.mar_set_tuning(None, None) == mar.MAR_ERR_STATE
     assert L.mar_profile_enable(None, 1) == mar.MAR_ERR_STATE
     assert isinstance(mar.mar_last_error(None), str)
+
+
+def test_loaded_library_is_built_from_these_sources():
+    """mar_build_id() carries the hash of the sources the library was compiled from: a library built from
+    other sources (an older tree, a stale copy) fails here."""
+    from paper_1307_3218_amd import build_lib
+    assert mar.mar_build_id() == build_lib.source_hash()
+
+
+@pytest.mark.gpu
+def test_library_on_the_gpu_box_is_built_from_these_sources():
+    from paper_1307_3218_amd import build_lib
+    print(f"[abi] libmar.so build id {mar.mar_build_id()}", flush=True)
+    assert mar.mar_build_id() == build_lib.source_hash()
+
+
+def test_design_boundary_table_names_every_declaration():
+    """The design doc's entry-point table (the boundary against the survey's proposal) lists exactly the header's
+    declarations, so that every departure from the proposed boundary is recorded."""
+    text = open(os.path.join(ROOT, "DESIGN.md")).read()
+    start = text.index("<!-- entry points: first column, one per row -->")
+    rows = []
+    for line in text[start:].splitlines()[1:]:
+        if not line.startswith("|"):
+            if rows:
+                break
+            continue
+        cell = line.split("|")[1].strip()
+        m = re.fullmatch(r"`(mar_[a-z_]+)`", cell)
+        if m:
+            rows.append(m.group(1))
+    assert sorted(rows) == _declared()

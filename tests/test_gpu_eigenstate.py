@@ -3,7 +3,13 @@ and the components e_j^T phi_k of Eq. 3 with the inner-product sign method.
 
 At nu = M (every subspace is the whole space) the result must be the exact
 generalized eigenpair (LAPACK) up to one global sign; at nu < M it must match the
-eigen-state oracle (oracle/mar_eigenstate.py) on the same seeds.
+eigen-state oracle (oracle/mar_eigenstate.py) on the same seeds, at the bars of the
+two forms (FP64 1e-10, FP32 1e-5): phi relative to its norm (up to one global sign),
+the level eps_k relative to the spectral scale max |eps|. The bisection points
+eta(k - 1) and eta(k) lie in gaps of the integrated density of states, where it is
+flat to within the smoothing, so they are compared with the oracle's to 1e-3 of the
+spectral scale in FP32 (FP64: 1e-10); they enter phi only through the window, which
+is flat there too.
 """
 import numpy as np
 import pytest
@@ -51,14 +57,16 @@ def test_cell256_state_against_oracle(cell256, cell256_states, k):
     ref = ES.eigen_state(cell256_states, k, sigma)
     ctx = mar.Context(cell256.H, cell256.S)
     try:
-        for prec, bar in (("fp64", 1e-8), ("fp32", 1e-3)):
+        scale = max(np.abs(st.eps).max() for st in cell256_states)
+        for prec, bar in (("fp64", 1e-10), ("fp32", 1e-5)):
             out = ctx.eigen_state(np.arange(cell256.M, dtype=np.int32), 30, k, sigma, prec, "batched")
             err = _sign_free(out["phi"], ref.phi)
             print(f"[es cell256 k={k} {prec}] eps_k {out['eps_k']:.10f} oracle {ref.eps_k:.10f} phi err {err:.2e} "
                   f"ref {out['ref'][:2]} oracle ref {ref.ref}", flush=True)
-            assert abs(out["eps_k"] - ref.eps_k) <= (1e-9 if prec == "fp64" else 1e-4)
-            assert abs(out["eta_lo"] - ref.eta_lo) <= (1e-9 if prec == "fp64" else 1e-3)
-            assert abs(out["eta_hi"] - ref.eta_hi) <= (1e-9 if prec == "fp64" else 1e-3)
+            gap_bar = 1e-10 if prec == "fp64" else 1e-3
+            assert abs(out["eps_k"] - ref.eps_k) <= bar * scale
+            assert abs(out["eta_lo"] - ref.eta_lo) <= gap_bar * scale
+            assert abs(out["eta_hi"] - ref.eta_hi) <= gap_bar * scale
             assert err <= bar
     finally:
         ctx.close()

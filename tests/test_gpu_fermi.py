@@ -2,10 +2,13 @@
 
 The GPU keeps every seed's subspace levels, weights and rows e_i.v_alpha,
 bisects mu on the device so that N(mu) = n_target, and assembles rho, E_j, N_j
-at that mu. Checks: mu against the oracle's bisection on the oracle's own
-levels; rho and E against the oracle solved at the oracle's mu; bit-equality
-with the ordinary solve at the returned mu; the electron-count sum rule; kT = 0;
-the device-pointer entry point; argument errors.
+at that mu. Checks, at the bars of the two forms (FP64 1e-10, FP32 1e-5): mu
+against the oracle's bisection on the oracle's own levels, relative to the
+spectral scale max |eps| (mu is an energy, compared as the levels are); rho and
+E against the oracle solved at the returned mu (the solve's own error, apart
+from the error of mu); bit-equality with the ordinary solve at the returned mu;
+the electron-count sum rule (each N_j within the bar of the full occupation 2);
+kT = 0; the device-pointer entry point; argument errors.
 """
 import numpy as np
 import pytest
@@ -27,8 +30,9 @@ def ctx1(cell256):
 
 
 def _oracle_mu(H, S, seeds, nu, n_target, kT):
+    """The oracle's Fermi level and the spectral scale max |eps| of its levels."""
     ref = O.solve(H, S, seeds, nu, 0.0, kT, workers=4)
-    return O.fermi_level(ref.eps, ref.weight, n_target, kT)
+    return O.fermi_level(ref.eps, ref.weight, n_target, kT), max(float(np.abs(e).max()) for e in ref.eps)
 
 
 def _rows(H, seeds):
@@ -40,32 +44,31 @@ def test_cell256_fermi_all_seeds(cell256, ctx1, prec, form):
     seeds = np.arange(cell256.M, dtype=np.int32)
     nu = 30
     out, mu = ctx1.solve_fermi(seeds, nu, float(cell256.M), KT, prec, form, levels=True)
-    mu_ref = _oracle_mu(cell256.H, cell256.S, seeds, nu, float(cell256.M), KT)
+    mu_ref, scale = _oracle_mu(cell256.H, cell256.S, seeds, nu, float(cell256.M), KT)
     print(f"[fermi cell256 {prec} {form}] mu {mu:.15f} oracle {mu_ref:.15f}", flush=True)
     tol = TOL[prec]
-    assert abs(mu - mu_ref) <= (1e-10 if prec == "fp64" else 1e-4) * max(1.0, abs(mu_ref))
+    assert abs(mu - mu_ref) <= tol * scale
     # sum rule at the returned level
-    assert abs(out.n_seed.sum() - cell256.M) <= 100 * tol * cell256.M
+    assert abs(out.n_seed.sum() - cell256.M) <= 2.0 * tol * cell256.M
     # the ordinary solve at the same mu gives the same bits
     plain = ctx1.solve(seeds, nu, mu, KT, prec, form)
     assert np.array_equal(plain.rho, out.rho) and plain.e_band == out.e_band
-    # against the oracle solved at the oracle's level
-    ref = O.solve(cell256.H, cell256.S, seeds, nu, mu_ref, KT, workers=4)
+    # against the oracle solved at the returned level
+    ref = O.solve(cell256.H, cell256.S, seeds, nu, mu, KT, workers=4)
     idx = _rows(cell256.H, seeds)
     rho_rel = np.linalg.norm(out.rho[idx] - ref.rho[idx]) / np.linalg.norm(ref.rho[idx])
     e_rel = abs(out.e_band - ref.e_band) / abs(ref.e_band)
     print(f"[fermi cell256 {prec} {form}] rho {rho_rel:.2e} E {e_rel:.2e}", flush=True)
-    bar = tol if prec == "fp64" else 10 * tol   # mu itself carries the FP32 level error into rho
-    assert rho_rel <= bar and e_rel <= bar
+    assert rho_rel <= tol and e_rel <= tol
 
 
 def test_cell256_fermi_zero_temperature(cell256, ctx1):
     seeds = np.arange(0, cell256.M, 3, dtype=np.int32)
     nu = 30
     out, mu = ctx1.solve_fermi(seeds, nu, float(len(seeds)), 0.0, "fp64", "batched")
-    mu_ref = _oracle_mu(cell256.H, cell256.S, seeds, nu, float(len(seeds)), 0.0)
+    mu_ref, scale = _oracle_mu(cell256.H, cell256.S, seeds, nu, float(len(seeds)), 0.0)
     print(f"[fermi kT=0] mu {mu:.15f} oracle {mu_ref:.15f}", flush=True)
-    assert abs(mu - mu_ref) <= 1e-9 * max(1.0, abs(mu_ref))
+    assert abs(mu - mu_ref) <= 1e-10 * scale
     plain = ctx1.solve(seeds, nu, mu, 0.0, "fp64", "batched")
     assert np.array_equal(plain.rho, out.rho)
 
@@ -79,11 +82,12 @@ def test_cell16k_fermi_sample_fp32():
         out, mu = ctx.solve_fermi(seeds, nu, float(len(seeds)), KT, "fp32", "batched")
         ref = O.solve(s.H, s.S, seeds, nu, 0.0, KT, workers=8)
         mu_ref = O.fermi_level(ref.eps, ref.weight, float(len(seeds)), KT)
+        scale = max(float(np.abs(e).max()) for e in ref.eps)
         print(f"[fermi cell16k fp32] mu {mu:.10f} oracle {mu_ref:.10f}", flush=True)
-        assert abs(mu - mu_ref) <= 1e-4 * max(1.0, abs(mu_ref))
-        assert abs(out.n_seed.sum() - len(seeds)) <= 1e-3
+        assert abs(mu - mu_ref) <= TOL["fp32"] * scale
+        assert abs(out.n_seed.sum() - len(seeds)) <= 2.0 * TOL["fp32"] * len(seeds)
         out64, mu64 = ctx.solve_fermi(seeds, nu, float(len(seeds)), KT, "fp64", "batched")
-        assert abs(mu64 - mu_ref) <= 1e-10 * max(1.0, abs(mu_ref))
+        assert abs(mu64 - mu_ref) <= TOL["fp64"] * scale
     finally:
         ctx.close()
 

@@ -4,9 +4,11 @@ nu alternating 30 / 100, FP32 batched).
 
 Checks: the graph result equals the eager per-system result bit for bit (same
 kernels, same block sizes), on the first launch and on replays with other
-device work in between; sampled seeds of every system match the FP64 oracle
-to the FP32 bar; cached graphs are rebuilt after a workspace grows; argument
-errors are reported on the right context.
+device work in between; eight seeds of every system, the first and the last
+of its list among them, match the FP64 oracle to the FP32 bar (1e-5: each rho
+column relative to its norm, each E_j and N_j relative to its size with the
+floors of the parity tests); cached graphs are rebuilt after a workspace
+grows; argument errors are reported on the right context.
 """
 import types
 
@@ -80,6 +82,26 @@ def _eager(torch, ctx, req):
     return _snapshot(req)
 
 
+def _check_seeds(s, nu, r, seeds, pick, label):
+    """The listed seeds' outputs of request r against the FP64 oracle, each at the FP32 bar."""
+    js = seeds[pick]
+    ref = O.solve(s.H, s.S, js, nu, MU, KT, workers=min(8, O.default_workers()))
+    rho = r["d_rho"].cpu().numpy()
+    e_seed = r["d_e_seed"].cpu().numpy()[pick]
+    n_seed = r["d_n_seed"].cpu().numpy()[pick]
+    nu_eff = r["d_nu_eff"].cpu().numpy()[pick]
+    assert np.array_equal(nu_eff, ref.nu_eff)
+    worst = 0.0
+    for j in js:
+        sl = slice(s.H.indptr[j], s.H.indptr[j + 1])
+        worst = max(worst, np.linalg.norm(rho[sl] - ref.rho[sl]) / np.linalg.norm(ref.rho[sl]))
+    e_floor = 1e-2 * np.abs(ref.e_seed).max()
+    e_err = (np.abs(e_seed - ref.e_seed) / np.maximum(np.abs(ref.e_seed), e_floor)).max()
+    n_err = (np.abs(n_seed - ref.n_seed) / np.maximum(np.abs(ref.n_seed), 2e-2)).max()
+    print(f"[{label}] M={s.M} nu={nu}: worst column {worst:.2e}, E_j {e_err:.2e}, N_j {n_err:.2e}", flush=True)
+    assert worst <= TOL and e_err <= TOL and n_err <= TOL, (s.M, worst, e_err, n_err)
+
+
 def _same(a, b):
     for k in a:
         assert np.array_equal(a[k], b[k]), k
@@ -107,21 +129,9 @@ def test_many_against_oracle(torch, systems, contexts):
     mar.solve_many(contexts, list(reqs))
     torch.cuda.synchronize()
     for (s, nu), r, seeds in zip(systems, reqs, seed_lists):
-        pick = [0, len(seeds) - 1]
-        js = seeds[pick]
-        ref = O.solve(s.H, s.S, js, nu, MU, KT, workers=2)
-        rho = r["d_rho"].cpu().numpy()
-        e_seed = r["d_e_seed"].cpu().numpy()[pick]
-        n_seed = r["d_n_seed"].cpu().numpy()[pick]
-        nu_eff = r["d_nu_eff"].cpu().numpy()[pick]
-        assert np.array_equal(nu_eff, ref.nu_eff)
-        for j in js:
-            sl = slice(s.H.indptr[j], s.H.indptr[j + 1])
-            rel = np.linalg.norm(rho[sl] - ref.rho[sl]) / np.linalg.norm(ref.rho[sl])
-            assert rel <= 100 * TOL, (s.M, j, rel)
-        assert np.all(np.abs(e_seed - ref.e_seed) <= 100 * TOL * np.maximum(np.abs(ref.e_seed), 1e-3))
-        assert np.all(np.abs(n_seed - ref.n_seed) <= 100 * TOL)
-        print(f"[many oracle] M={s.M} nu={nu} ok", flush=True)
+        n = len(seeds)
+        pick = np.array([0, 1, n // 5, (2 * n) // 5, (3 * n) // 5, (4 * n) // 5, n - 2, n - 1])
+        _check_seeds(s, nu, r, seeds, pick, "many oracle")
 
 
 def test_many_rebuilds_after_workspace_growth(torch, systems, contexts):
@@ -164,12 +174,14 @@ def test_autotune_then_solve(torch, systems):
         print(f"[autotune] M={s.M} nu={nu}: {t}", flush=True)
         assert t["seed_block"] in (16, 32, 64, 128, 256) and t["proj_variant"] in (0, 3) and t["probe_rate"] > 0
         assert ctx.seed_block(nu, "fp32") == t["seed_block"]
+        # a fixed block overrides the autotuned choice; mar_set_tuning(NULL) restores the defaults, under
+        # which the autotuned (cached) choice applies again
+        other = 64 if t["seed_block"] != 64 else 32
+        ctx.set_tuning(seed_block=other)
+        assert ctx.seed_block(nu, "fp32") == other
+        assert mar.lib().mar_set_tuning(ctx.handle, None) == mar.MAR_OK
+        assert ctx.seed_block(nu, "fp32") == t["seed_block"]
         _eager(torch, ctx, req)
-        js = seeds[:2]
-        ref = O.solve(s.H, s.S, js, nu, MU, KT, workers=2)
-        rho = req["d_rho"].cpu().numpy()
-        for j in js:
-            sl = slice(s.H.indptr[j], s.H.indptr[j + 1])
-            assert np.linalg.norm(rho[sl] - ref.rho[sl]) <= 100 * TOL * np.linalg.norm(ref.rho[sl])
+        _check_seeds(s, nu, req, seeds, np.array([0, 1, len(seeds) - 1]), "autotuned")
     finally:
         ctx.close()
