@@ -307,7 +307,7 @@ def main() -> int:
     ap.add_argument("--workload", default="mixed_16x16x16")
     ap.add_argument("--nu", type=int, default=100)
     ap.add_argument("--seeds-per-step", type=int, default=1024)
-    ap.add_argument("--plain-seeds", type=int, default=16)
+    ap.add_argument("--plain-seeds", type=int, default=256)
     ap.add_argument("--fp64-batched-seeds", type=int, default=256)
     ap.add_argument("--cpu-seeds", type=int, default=0, help="oracle sample size (0 = about 20 s of CPU work)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -278,7 +278,12 @@ typedef struct {
  * without capture, so a caller that refills the same seed buffers pays one
  * capture. Workspaces are sized (and allocated) before the capture. Errors are
  * reported on the context of the failing request (on ctx[0] for errors of the
- * call itself). Cached graphs of a context are released by mar_destroy. */
+ * call itself). Cached graphs of a context are released by mar_destroy.
+ * A context that has run any solve with two seed blocks in flight (two_streams
+ * 1, or the default for local regions of 6 hops or more) is refused with
+ * MAR_ERR_STATE for the rest of its life: host crashes followed a capture
+ * after such solves, and their cause is not known. Contexts meant for graphs
+ * keep two_streams 3 or 2 from their creation on. */
 mar_status mar_solve_many(int32_t n_sys, mar_ctx* const* ctx, const mar_request* req, void* hip_stream);
 
 /* Autotuner: time the batched form on the first min(n_seeds, 256) of d_seeds

@@ -74,6 +74,7 @@ struct mar_ctx {
     int n_cu = 1;             // compute units of the device
     bool dry = false;         // size and allocate the workspace only; launch nothing
     bool in_graph = false;    // sizing or capturing a mar_solve_many graph (one stream per system there)
+    bool ran_two_sets = false;    // a solve ran two seed blocks in flight (mar_solve_many refuses the context)
     // projection workgroups per compute unit, by (element bytes, B, variant)
     std::map<std::tuple<int, int, int>, int> occ;
     // autotuned (B, projection variant) by (nu, precision)
@@ -749,6 +750,7 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
                          ? 2
                          : 1;
     off = (size_t)nset * set_bytes;
+    if (!c->dry && nset == 2) c->ran_two_sets = true;
     // One block at a time (two_streams 3, or 0 when it does not pick two blocks or they do not fit): each
     // block's eigensolve runs on the second stream while the next block's sweeps run on the caller's; the
     // subspace matrix and the gathered rows alternate between two copies. Not while profiling, inside graphs
@@ -1232,6 +1234,12 @@ mar_status mar_solve_many(int32_t n_sys, mar_ctx* const* ctx, const mar_request*
             return set_err(ctx[0], MAR_ERR_ARG, fmt("ctx[%d] is on another device", i));
         mar_status st = check_request(ctx[i], req[i]);
         if (st != MAR_OK) return st;
+        // Two host crashes (segmentation faults, no GPU fault) followed a graph capture on contexts whose
+        // earlier solves ran two seed blocks in flight; the cause is not known, so that sequence is refused.
+        if (ctx[i]->ran_two_sets)
+            return set_err(ctx[i], MAR_ERR_STATE,
+                           fmt("ctx[%d] has run solves with two seed blocks in flight; mar_solve_many refuses such a "
+                               "context (use another context, or two_streams 3 or 2 from its creation on)", i));
     }
     mar_ctx* c0 = ctx[0];
     HIP_OR(c0, hipSetDevice(c0->device));

@@ -101,9 +101,12 @@ def test_local_independent_of_blocking(sysm, ctx):
     assert np.abs(a.e_seed - b.e_seed[inv]).max() <= 1e-12 * np.abs(a.e_seed).max()
 
 
-def test_local_graph_launch(sysm, ctx):
+def test_local_graph_launch(sysm):
+    """Two local radii through one graph launch, on fresh contexts (mar_solve_many refuses a context that
+    ran two seed blocks in flight, as the module's context has at 6 and 7 hops)."""
     import torch
     dev = torch.device("cuda:0")
+    ctx = mar.Context(sysm.H, sysm.S)
     other = mar.Context(sysm.H, sysm.S)
     try:
         ctx.set_local_region(2)
@@ -126,7 +129,7 @@ def test_local_graph_launch(sysm, ctx):
         ref = OL.solve_local(sysm.H, sysm.S, np.arange(300), 20, 2, MU, KT)
         assert abs(out[0][0] - ref.e_band) <= TOL["fp32"] * abs(ref.e_band)
     finally:
-        ctx.set_local_region(None)
+        ctx.close()
         other.close()
 
 
@@ -176,5 +179,30 @@ def test_local_refusals(sysm, ctx):
     try:
         with pytest.raises(mar.MarError):
             c.set_local_region(1)
+    finally:
+        c.close()
+
+
+def test_solve_many_refuses_after_two_blocks_in_flight(sysm):
+    """A context that ran two seed blocks in flight (the default at 6 hops) is refused by mar_solve_many before
+    any capture: host crashes followed that sequence and their cause is not known."""
+    import torch
+    dev = torch.device("cuda:0")
+    c = mar.Context(sysm.H, sysm.S)
+    try:
+        c.set_local_region(6)
+        c.set_tuning(seed_block=32)
+        seeds = np.arange(40, 40 + 3 * 32, dtype=np.int32)
+        c.solve(seeds, 24, MU, KT, precision="fp32")                 # three blocks: two in flight
+        req = dict(d_seeds=torch.from_numpy(seeds).to(dev), nu=24, mu=MU, kT=KT, precision="fp32",
+                   form="batched", d_rho=torch.zeros(sysm.H.nnz, dtype=torch.float64, device=dev),
+                   d_e_band=torch.zeros(1, dtype=torch.float64, device=dev))
+        with pytest.raises(mar.MarError) as e:
+            mar.solve_many([c], [req])
+        assert e.value.status == mar.MAR_ERR_STATE
+        assert "two seed blocks in flight" in mar.mar_last_error(c.handle)
+        c.set_tuning(seed_block=32, two_streams=False)                # still refused: the context ran them
+        with pytest.raises(mar.MarError):
+            mar.solve_many([c], [req])
     finally:
         c.close()
