@@ -3,12 +3,23 @@
 sampled seeds (stored by tests/golden/make_mixed1m_oracle.py, which calls only the
 oracle; mu = -0.45 eV, kT = 0.1 eV).
 
-Bars: FP64 form 1e-10 (relative, on the listed rows of rho and on the summed
-E); FP32 form 1e-5 on the summed E. For rho in the FP32 form at this size the
-rounding of the FP32 basis itself decides the error: equivalent launch
-configurations (seed block 8 ... 64, either CGS2 schedule, any projection grid)
-measured 2.9e-6 ... 1.5e-5 on these seeds, so rho is held to RHO32 = 3e-5 (twice
-the largest measured) and the value is printed per run. nu_eff equal.
+Bars: FP64 form 1e-10, FP32 form 1e-5, on rho (Frobenius norm over the listed
+rows), on the summed E, on every E_j and N_j (floors as in the other parity
+tests), and on every rho column in the FP64 form; nu_eff equal.
+
+Every rho column in the FP32 form at 1e-5 is an expected failure here
+(xfail, strict): the columns of seeds 14 and 786929 reach 1.8e-5 and 1.4e-5,
+the others 5.4e-6 and below (the Frobenius norm, 7.4e-6, meets the bar). A numpy
+emulation of the textbook CGS2 with every step in FP32 arithmetic and FP32
+storage (the FP32 form) gives, seed by seed, 1.6e-5, 3.5e-6 and 1.9e-7 for
+seeds 14, 391606 and 656200, where the device gives 1.8e-5, 5.4e-6 and 2.7e-7.
+Keeping the steps in FP64 one at a time (seed 14) shows that the FP32 storage
+of the basis alone accounts for 9e-7 and the FP32 matrix values for 2e-8,
+while the FP32 sums do the rest (the sparse products' sums alone 1.5e-5, the
+updates alone 4.6e-6). Summing the device's sparse products in FP64 moved its
+Frobenius error only from 7.4e-6 to 6.5e-6. So the FP32 form's own arithmetic,
+not a flaw of the device code, puts these columns above the bar at nu = 300
+on this lattice.
 """
 import json
 import os
@@ -22,7 +33,6 @@ pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "mixed1m_oracle_nu300.json")
 TOL = {"fp64": 1e-10, "fp32": 1e-5}
-RHO32 = 3e-5
 
 
 @pytest.fixture(scope="module")
@@ -45,32 +55,39 @@ def mixed1m_ctx(mixed1m):
     ctx.close()
 
 
-def _check(g, out, prec, label):
+def _check(g, out, prec, label, columns=True):
+    """Assert the stated bars (every rho column too when columns is set) and print the errors."""
     tol = TOL[prec]
     seeds = g["seeds"]
     assert list(out.nu_eff) == g["nu_eff"], label
     num = den = 0.0
-    worst = 0.0
+    cols = []
     for j in seeds:
         row = g["rho_rows"][str(j)]
         ref = np.array(row["rho"])
         got = out.rho_rows[j]
         num += float(np.sum((got - ref) ** 2))
         den += float(np.sum(ref ** 2))
-        worst = max(worst, np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        cols.append(np.linalg.norm(got - ref) / np.linalg.norm(ref))
     rho_rel = (num / den) ** 0.5
     e_ref = float(np.sum(g["e_seed"]))
     e_rel = abs(float(np.sum(out.e_seed)) - e_ref) / abs(e_ref)
-    print(f"[mixed1m {label} {prec}] rho {rho_rel:.2e} E {e_rel:.2e} worst column {worst:.2e}", flush=True)
-    rho_tol = RHO32 if prec == "fp32" else tol
-    assert rho_rel <= rho_tol and e_rel <= tol and worst <= 100 * rho_tol
-    assert np.abs(np.array(out.n_seed) - np.array(g["n_seed"])).max() <= 100 * tol
+    worst = max(cols)
+    print(f"[mixed1m {label} {prec}] rho {rho_rel:.2e} E {e_rel:.2e} worst column {worst:.2e}; columns "
+          + " ".join(f"{j}:{c:.1e}" for j, c in zip(seeds, cols)), flush=True)
+    assert rho_rel <= tol and e_rel <= tol
+    if columns:
+        assert worst <= tol
+    e_ref_j, n_ref_j = np.array(g["e_seed"]), np.array(g["n_seed"])
+    e_err = np.abs(np.array(out.e_seed) - e_ref_j) / np.maximum(np.abs(e_ref_j), 1e-2 * np.abs(e_ref_j).max())
+    n_err = np.abs(np.array(out.n_seed) - n_ref_j) / np.maximum(np.abs(n_ref_j), 2e-2)
+    assert e_err.max() <= tol and n_err.max() <= tol, (e_err.max(), n_err.max())
     # individual Ritz levels at nu = 300 are ill-conditioned (interior, unconverged,
     # near-degenerate: they move by ~1e-8 eV in FP64 and ~1e-2 eV in FP32 with the
     # rounding order), so the levels are compared through their weighted moments
     # sum_a w_a eps_a^k, k = 0..3 (the quadrature of the seed's local spectrum)
     scale = max(max(abs(v) for v in e) for e in g["eps"])
-    mtol = (10 if prec == "fp64" else 100) * tol
+    mtol = tol
     for s in range(len(seeds)):
         m = out.nu_eff[s]
         ge, gw = out.eps[s, :m], out.weight[s, :m]
@@ -100,8 +117,20 @@ def test_mixed1m_block_size(mixed1m_ctx, golden):
     assert mixed1m_ctx.seed_block(golden["nu"], "fp32") == 64
 
 
-def test_mixed1m_fp32_batched(mixed1m_ctx, mixed1m, golden):
-    _check(golden, _solve(mixed1m_ctx, mixed1m, golden, "fp32", "batched", block=64), "fp32", "batched B=64")
+@pytest.fixture(scope="module")
+def fp32_batched(mixed1m_ctx, mixed1m, golden):
+    return _solve(mixed1m_ctx, mixed1m, golden, "fp32", "batched", block=64)
+
+
+def test_mixed1m_fp32_batched(fp32_batched, golden):
+    _check(golden, fp32_batched, "fp32", "batched B=64", columns=False)
+
+
+@pytest.mark.xfail(strict=True, reason="FP32 arithmetic of the FP32 form: the rho columns of two seeds reach 1.8e-5 "
+                                       "and 1.4e-5 at nu = 300 on this lattice (emulated seed by seed, e.g. 1.6e-5 "
+                                       "for the worst); see the module docstring")
+def test_mixed1m_fp32_batched_every_column(fp32_batched, golden):
+    _check(golden, fp32_batched, "fp32", "batched B=64 per column", columns=True)
 
 
 def test_mixed1m_fp64_plain(mixed1m_ctx, mixed1m, golden):
