@@ -112,9 +112,9 @@ typedef struct {
                               eigen-state passes or inside mar_solve_many's graphs; the caller's stream
                               waits for the second one before the solve's last kernel. The results do
                               not depend on it. */
-    int32_t ql_max_iter;   /* implicit-QL iterations allowed per eigenvalue of the nu x nu subspace
-                              eigensolve (0 = 80). A seed whose eigensolve is still unconverged after
-                              them gets nu_eff = -3 (see mar_solve). */
+    int32_t eig_max_sweeps; /* Jacobi sweeps allowed to the nu x nu subspace eigensolve (0 = 40; about
+                              ten are needed at nu = 100). A seed whose eigensolve has not converged
+                              after them gets nu_eff = -3 (see mar_solve). */
 } mar_tuning;
 
 /* Create a context from host CSR arrays of H and S (M x M, 0-based, columns
@@ -136,11 +136,11 @@ void mar_destroy(mar_ctx* ctx);
 
 /* Host-side solve (blocking). seeds: n_seeds distinct indices in [0, M)
  * (MAR_ERR_ARG otherwise); 1 <= nu <= M; mu finite; kT >= 0 and finite.
- * The subspace eigensolve (Sec. 2: the nu x nu standard eigenproblem) is a
- * Householder reduction and an implicit QL iteration; a seed with an
- * eigenvalue still unconverged after ql_max_iter iterations (mar_tuning) gets
- * nu_eff = -3, NaN in its rho slots, E_j, N_j, eps and weight entries (so
- * e_band is NaN), and the call returns MAR_ERR_NOCONV naming the seed.
+ * The subspace eigensolve (Sec. 2: the nu x nu standard eigenproblem) is the
+ * parallel cyclic Jacobi method; a seed whose eigensolve has not converged
+ * after eig_max_sweeps sweeps (mar_tuning) gets nu_eff = -3, NaN in its rho
+ * slots, E_j, N_j, eps and weight entries (so e_band is NaN), and the call
+ * returns MAR_ERR_NOCONV naming the seed.
  * Outputs (host, caller-allocated):
  *   rho     [nnz(H)]   CSR row j slots of each listed seed j receive rho_ij for
  *                      i in P(j) (slot (j,i) holds rho_ij); all other slots keep

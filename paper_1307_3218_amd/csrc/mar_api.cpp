@@ -463,7 +463,7 @@ void eig_stage(mar_ctx* c, hipStream_t s, int B, int ns, const int32_t* seeds, i
                const double* Kp, const T* K, int64_t stride, int64_t Mp, double mu, double kT, double* rho,
                double* e_seed, double* n_seed, int32_t* nu_out, double* eps, double* w, int64_t blk0) {
     mar::EigExtra ex;
-    ex.ql_maxit = c->tune.ql_max_iter > 0 ? c->tune.ql_max_iter : 80;
+    ex.eig_max_sweeps = c->tune.eig_max_sweeps > 0 ? c->tune.eig_max_sweeps : 40;
     if (c->es.mode == 2) {   // v_ref . v_alpha^(j) through K^T v_ref, then the signed Eq. 3 component
         launch(c, s, P_EIG, [&] {
             return mar::launch_es_pdot<T>(B, K, stride, c->M, Mp, nu, c->es.vref, c->es.pdot, c->es.groups, s);
@@ -1022,8 +1022,8 @@ mar_status check_noconv(mar_ctx* c, const int32_t* seeds, const std::vector<int3
     for (size_t i = 0; i < nuv.size(); ++i)
         if (nuv[i] == mar::NU_NOCONV)
             return set_err(c, MAR_ERR_NOCONV,
-                           fmt("the subspace eigensolve of seed %d did not converge within %d QL iterations per "
-                               "eigenvalue", seeds[i], c->tune.ql_max_iter > 0 ? c->tune.ql_max_iter : 80));
+                           fmt("the subspace eigensolve of seed %d did not converge within %d Jacobi sweeps", seeds[i],
+                               c->tune.eig_max_sweeps > 0 ? c->tune.eig_max_sweeps : 40));
     return MAR_OK;
 }
 
@@ -1854,7 +1854,7 @@ mar_status mar_set_tuning(mar_ctx* c, const mar_tuning* t) {
         return set_err(c, MAR_ERR_ARG, "upd_q must be 0, 2, 4 or 8");
     if (t->support_off != 0 && t->support_off != 1) return set_err(c, MAR_ERR_ARG, "support_off must be 0 or 1");
     if (t->two_streams < 0 || t->two_streams > 3) return set_err(c, MAR_ERR_ARG, "two_streams must be 0, 1, 2 or 3");
-    if (t->ql_max_iter < 0) return set_err(c, MAR_ERR_ARG, "ql_max_iter < 0");
+    if (t->eig_max_sweeps < 0) return set_err(c, MAR_ERR_ARG, "eig_max_sweeps < 0");
     c->tune = *t;
     return MAR_OK;
 }

@@ -1,11 +1,13 @@
 // Subspace eigensolve and Fermi-weighted assembly, one workgroup per seed.
 //
-// For seed j with m = nu_eff vectors, A = K^T H K (m x m, FP64) is reduced to
-// tridiagonal form T = Q^T A Q by Householder reflections; the reflections are
-// applied on the fly to the m x (1 + |P(j)|) matrix R = [e_1 | K[P(j), :]^T],
-// so no m x m eigenvector matrix is ever formed. The implicit QL iteration
-// with Wilkinson shifts then diagonalizes T, applying each plane rotation to
-// the rows of R. At the end row alpha of R holds
+// For seed j with m = nu_eff vectors, A = K^T H K (m x m, FP64) is
+// diagonalized by the parallel cyclic Jacobi method: each step rotates m / 2
+// disjoint index pairs at once (a round-robin tournament, so that every pair
+// meets once per sweep of m - 1 steps or m steps for odd m), A <- J^T A J,
+// and the same rotations are applied to the rows of the m x (1 + |P(j)|)
+// matrix R = [e_1 | K[P(j), :]^T]; sweeps repeat until one rotates nothing.
+// No m x m eigenvector matrix is formed. At the end A's diagonal holds the
+// levels eps_alpha and row alpha of R holds
 //     R[alpha][0]     = y_1alpha            (first component of y_alpha)
 //     R[alpha][1 + t] = e_i . v_alpha,  i = P(j)[t],  v_alpha = K y_alpha
 // which is all the Green's-function assembly needs (Sec. 2):
@@ -56,142 +58,214 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
     return (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// Lane t's double, read by the whole wavefront (t uniform).
-__device__ __forceinline__ double lane_value(double x, int t) {
-    const long long b = __double_as_longlong(x);
-    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)b, t);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), t);
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+// Threads of the eigensolver's workgroup: four waves per SIMD, so that the
+// LDS latencies of the Jacobi steps of one seed hide behind each other.
+constexpr int EIG_WG = 1024;
+constexpr int EIG_WAVES = EIG_WG / 64;
+// Per-thread work lists of a Jacobi step when they are short (at most JB blocks
+// and JR entries of R per thread, fixed for the whole iteration).
+constexpr int JB = 3, JR = 4;
+
+// 1/x and 1/sqrt(x) (x > 0, normal) from the hardware estimates and two Newton steps each (full FP64
+// precision: the estimates carry about 23 bits and each step doubles them).
+__device__ __forceinline__ double recip(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+__device__ __forceinline__ double rsqrt(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-x * y, y, 1.0);
+    return fma(0.5 * y, e, y);
 }
 
-// Implicit QL with Wilkinson shifts on the symmetric tridiagonal (d, e),
-// e[i] coupling d[i] and d[i+1], e[m-1] = 0 (Bowdler, Martin, Reinsch and
-// Wilkinson's tql2 scheme). Run by one wavefront. The (d, e) recurrence is
-// serial: every lane carries it with the same values. A sweep reads only the
-// entries as they were when it began, so they are loaded 64 at a time into
-// lane registers and broadcast with readlane, keeping LDS latency off the
-// recurrence; the plane rotations are logged in cs/sn and then applied by the
-// lanes to their columns l, l + 64, ... of R, carrying the row each rotation
-// passes down. The split point is found by testing 64 subdiagonal entries at once.
-// At most maxit iterations per eigenvalue; returns the number of eigenvalues
-// left unconverged (0 on success).
-__device__ int ql_implicit(double* d, double* e, int m, double* R, int nr, int lane, double* cs, double* sn,
-                           int maxit) {
-    int fails = 0;
-    for (int l = 0; l < m; ++l) {
-        int iter = 0;
-        for (;;) {
-            // first mm >= l with a negligible e[mm]; e[m-1] = 0 ends the search at m-1
-            int mm = m - 1;
-            for (int base = l; base < m - 1; base += 64) {
-                const int t = base + lane;
-                bool small = false;
-                if (t < m - 1) small = fabs(e[t]) <= DBL_EPSILON * (fabs(d[t]) + fabs(d[t + 1]));
-                const unsigned long long hit = __ballot(small);
-                if (hit) {
-                    mm = base + __ffsll(hit) - 1;
-                    break;
-                }
-            }
-            if (mm == l) break;
-            if (++iter > maxit) {
-                ++fails;
-                break;
-            }
-            double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-            double r = hypot(g, 1.0);
-            g = d[mm] - d[l] + e[l] / (g + copysign(r, g));
-            double s = 1.0, c = 1.0, p = 0.0;
-            bool split = false;
-            int nrot = 0;
-            double di1 = d[mm];   // d[i+1] as it was when the sweep began
-            for (int i0 = mm - 1; i0 >= l && !split; i0 -= 64) {
-                const int ii = i0 - lane;   // lane t holds e[i0-t], d[i0-t]
-                const double eR = ii >= l ? e[ii] : 0.0, dR = ii >= l ? d[ii] : 0.0;
-                const int nt = min(64, i0 - l + 1);
-                // wait for these two loads here, so the loop below carries no LDS wait
-                __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0), other counters unchanged
-                for (int t = 0; t < nt; ++t) {
-                    const int i = i0 - t;
-                    const double ei = lane_value(eR, t), di = lane_value(dR, t);
-                    const double f = s * ei, bb = c * ei, bb2 = 2.0 * bb;
-                    const double ss = fma(f, f, g * g);
-                    // r = sqrt(ss) and 1/(2r) by two coupled Goldschmidt steps from the reciprocal
-                    // square root; tiny, huge or zero ss take the careful path below instead
-                    const double y0 = __builtin_amdgcn_rsq(ss);
-                    double gq = ss * y0, hq = 0.5 * y0;
-                    double res = fma(-gq, hq, 0.5);
-                    gq = fma(gq, res, gq);
-                    hq = fma(hq, res, hq);
-                    res = fma(-gq, hq, 0.5);
-                    gq = fma(gq, res, gq);
-                    hq = fma(hq, res, hq);
-                    r = gq;
-                    double rinv = 2.0 * hq;
-                    if (!(ss > DBL_MIN && ss < DBL_MAX)) {
-                        r = hypot(f, g);
-                        rinv = r != 0.0 ? 1.0 / r : 0.0;
-                        if (r == 0.0) {
-                            e[i + 1] = r;
-                            d[i + 1] = di1 - p;
-                            e[mm] = 0.0;
-                            split = true;
-                            break;
-                        }
-                    }
-                    e[i + 1] = r;
-                    s = f * rinv;
-                    c = g * rinv;
-                    g = di1 - p;
-                    r = (di - g) * s + c * bb2;   // c * (2 bb) equals (2 c) * bb exactly
-                    p = s * r;
-                    d[i + 1] = g + p;
-                    g = c * r - bb;
-                    cs[nrot] = c;
-                    sn[nrot] = s;
-                    ++nrot;
-                    di1 = di;
-                }
-            }
-            // rotation t acts on rows (mm-1-t, mm-t); row mm-t is final after it.
-            // Four rotations at a time: their loads (rows not yet written) go out first.
-            for (int col = lane; col < nr; col += 64) {
-                double carry = R[mm * nr + col];
-                int t = 0;
-                for (; t + 4 <= nrot; t += 4) {
-                    const int i = mm - 1 - t;
-                    double a[4], cc[4], sv[4];
+// Parallel cyclic Jacobi on the symmetric m x m matrix A (in LDS or global
+// memory, upper triangle only: a_ij, i <= j, at A[i * ld + j]; an odd ld spreads
+// the column accesses over the LDS banks), each rotation also applied to the
+// rows of the m x nr matrix R (R <- J^T R). Run by the whole workgroup.
+// Step s of a sweep pairs the indices of a round-robin tournament of n = m
+// rounded up to even players (player n - 1 = m is a bye for odd m): position k
+// holds players idx(k) and idx(n - 1 - k), idx(0) = 0, idx(i) = 1 + (i - 1 + s)
+// mod (n - 1). A pair (p, q) rotates when |a_pq| > eps sqrt(|a_pp a_qq|), with
+// the symmetric Schur rotation that zeroes a_pq (tau = (a_qq - a_pp) / (2 a_pq),
+// t = sign(tau) / (|tau| + sqrt(1 + tau^2)), c = 1 / sqrt(1 + t^2), s = t c):
+// a_pp -= t a_pq, a_qq += t a_pq, a_pq = 0. Every other element belongs to one
+// 2 x 2 block of two pairs, J_1^T B J_2, updated in place by one thread (blocks
+// k1 <= k2 of pair positions). When the blocks and R's entries make at most JB
+// and JR per thread, each thread keeps its list for the whole iteration and
+// issues all loads of a step at once; otherwise wave w takes the block rows
+// k1 = w, w + 16, ..., its lanes the block columns. Sweeps repeat until one
+// rotates nothing, at most max_sweeps. Scratch: cs, sn, tt (n / 2 doubles
+// each), cnt (one int). Returns 0 when converged, 1 otherwise. The levels are
+// A's diagonal.
+__device__ __forceinline__ int jacobi_eig(double* A, int ld, int m, double* R, int nr, double* cs, double* sn,
+                                          double* tt, int* cnt, int max_sweeps) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n = m + (m & 1), np = n / 2, n1 = n - 1;
+    auto off = [&](int i, int j) { return i <= j ? i * ld + j : j * ld + i; };   // a_ij in the upper triangle
+    // the pair at position k of step st, p < q (q == m: the bye)
+    auto pair = [&](int k, int st, int& p, int& q) {
+        int a = k - 1 + st, bb = n - 2 - k + st;
+        a = k == 0 ? 0 : 1 + (a >= n1 ? a - n1 : a);
+        bb = 1 + (bb >= n1 ? bb - n1 : bb);
+        p = a < bb ? a : bb;
+        q = a < bb ? bb : a;
+    };
+    // J_1^T B J_2 on the block of positions k1 < k2 (pairs (p1, q1), (p2, q2)); a bye's row or column is
+    // absent (its loads read a_p1p2 again and are dropped)
+    auto block = [&](int p1, int q1, double c1, double s1, int p2, int q2, double c2, double s2) {
+        const bool hq1 = q1 < m, hq2 = q2 < m, hw = hq1 && hq2;
+        const int ox = off(p1, p2);
+        const int oy = hq2 ? off(p1, q2) : ox, oz = hq1 ? off(q1, p2) : ox, ow = hw ? off(q1, q2) : ox;
+        const double x = A[ox];
+        const double y = hq2 ? A[oy] : 0.0, z = hq1 ? A[oz] : 0.0, w = hw ? A[ow] : 0.0;
+        const double xr = c1 * x - s1 * z, yr = c1 * y - s1 * w;   // rows: J_1^T B
+        const double zr = s1 * x + c1 * z, wr = s1 * y + c1 * w;
+        A[ox] = c2 * xr - s2 * yr;                                  // columns: (J_1^T B) J_2
+        if (hq2) A[oy] = s2 * xr + c2 * yr;
+        if (hq1) A[oz] = c2 * zr - s2 * wr;
+        if (hw) A[ow] = s2 * zr + c2 * wr;
+    };
+    // fixed per-thread lists when short: blocks (k1, k2), k1 <= k2, numbered row by row, and R entries (k, col)
+    const int nblk = np * (np + 1) / 2;
+    const bool lists = nblk <= JB * EIG_WG && np * nr <= JR * EIG_WG;
+    int bk1[JB], bk2[JB], rk[JR], rc[JR];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        a[u] = R[(i - u) * nr + col];
-                        cc[u] = cs[t + u];
-                        sv[u] = sn[t + u];
-                    }
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        R[(i - u + 1) * nr + col] = sv[u] * a[u] + cc[u] * carry;
-                        carry = cc[u] * a[u] - sv[u] * carry;
-                    }
-                }
-                for (; t < nrot; ++t) {
-                    const int i = mm - 1 - t;
-                    const double a0 = R[i * nr + col];
-                    R[(i + 1) * nr + col] = sn[t] * a0 + cs[t] * carry;
-                    carry = cs[t] * a0 - sn[t] * carry;
-                }
-                R[(mm - nrot) * nr + col] = carry;
+    for (int i = 0; i < JB; ++i) {
+        int lin = tid + i * EIG_WG, k1 = 0;
+        bk1[i] = -1;
+        bk2[i] = 0;
+        if (lists && lin < nblk) {
+            while (lin >= np - k1) {
+                lin -= np - k1;
+                ++k1;
             }
-            if (split) continue;
-            d[l] -= p;
-            e[l] = g;
-            e[mm] = 0.0;
+            bk1[i] = k1;
+            bk2[i] = k1 + lin;
         }
     }
-    return fails;
+#pragma unroll
+    for (int i = 0; i < JR; ++i) {
+        const int lin = tid + i * EIG_WG;
+        rk[i] = lists && lin < np * nr ? lin / nr : -1;
+        rc[i] = lists && lin < np * nr ? lin - (lin / nr) * nr : 0;
+    }
+    if (tid == 0) *cnt = 0;
+    __syncthreads();
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+        for (int st = 0; st < n1; ++st) {
+            // the rotations of this step, one pair per thread
+            for (int k = tid; k < np; k += EIG_WG) {
+                int p, q;
+                pair(k, st, p, q);
+                double c = 1.0, sv = 0.0, t = 0.0;
+                if (q < m) {
+                    const double apq = A[p * ld + q], app = A[p * ld + p], aqq = A[q * ld + q];   // p < q
+                    if (apq != 0.0 && apq * apq > (DBL_EPSILON * DBL_EPSILON) * fabs(app * aqq)) {
+                        const double tau = (aqq - app) * recip(2.0 * apq);
+                        if (fabs(tau) > 1e150) {
+                            t = 0.5 * recip(tau);
+                        } else {
+                            const double r = 1.0 + tau * tau;
+                            t = copysign(recip(fabs(tau) + r * rsqrt(r)), tau);
+                        }
+                        c = rsqrt(1.0 + t * t);
+                        sv = t * c;
+                        atomicAdd(cnt, 1);
+                    }
+                }
+                cs[k] = c;
+                sn[k] = sv;
+                tt[k] = t;
+            }
+            __syncthreads();
+            if (lists) {
+#pragma unroll
+                for (int i = 0; i < JB; ++i) {
+                    const int k1 = bk1[i], k2 = bk2[i];
+                    if (k1 < 0) continue;
+                    int p1, q1;
+                    pair(k1, st, p1, q1);
+                    const double c1 = cs[k1], s1 = sn[k1];
+                    if (k1 == k2) {
+                        if (s1 != 0.0) {
+                            const double apq = A[p1 * ld + q1], t = tt[k1];
+                            A[p1 * ld + p1] -= t * apq;
+                            A[q1 * ld + q1] += t * apq;
+                            A[p1 * ld + q1] = 0.0;
+                        }
+                        continue;
+                    }
+                    const double c2 = cs[k2], s2 = sn[k2];
+                    if (s1 == 0.0 && s2 == 0.0) continue;
+                    int p2, q2;
+                    pair(k2, st, p2, q2);
+                    block(p1, q1, c1, s1, p2, q2, c2, s2);
+                }
+#pragma unroll
+                for (int i = 0; i < JR; ++i) {
+                    const int k = rk[i], col = rc[i];
+                    if (k < 0) continue;
+                    const double sv = sn[k];
+                    if (sv == 0.0) continue;
+                    int p, q;
+                    pair(k, st, p, q);
+                    const double c = cs[k], rp = R[p * nr + col], rq = R[q * nr + col];
+                    R[p * nr + col] = c * rp - sv * rq;
+                    R[q * nr + col] = sv * rp + c * rq;
+                }
+            } else {
+                for (int k1 = wave; k1 < np; k1 += EIG_WAVES) {
+                    int p1, q1;
+                    pair(k1, st, p1, q1);
+                    const double c1 = cs[k1], s1 = sn[k1];
+                    for (int k2 = k1 + lane; k2 < np; k2 += 64) {
+                        if (k2 == k1) {
+                            if (s1 != 0.0) {
+                                const double apq = A[p1 * ld + q1], t = tt[k1];
+                                A[p1 * ld + p1] -= t * apq;
+                                A[q1 * ld + q1] += t * apq;
+                                A[p1 * ld + q1] = 0.0;
+                            }
+                            continue;
+                        }
+                        const double c2 = cs[k2], s2 = sn[k2];
+                        if (s1 == 0.0 && s2 == 0.0) continue;
+                        int p2, q2;
+                        pair(k2, st, p2, q2);
+                        block(p1, q1, c1, s1, p2, q2, c2, s2);
+                    }
+                }
+                for (int k = wave; k < np; k += EIG_WAVES) {
+                    const double sv = sn[k];
+                    if (sv == 0.0) continue;
+                    int p, q;
+                    pair(k, st, p, q);
+                    const double c = cs[k];
+                    for (int col = lane; col < nr; col += 64) {
+                        const double rp = R[p * nr + col], rq = R[q * nr + col];
+                        R[p * nr + col] = c * rp - sv * rq;
+                        R[q * nr + col] = sv * rp + c * rq;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        const int rotated = *cnt;
+        __syncthreads();
+        if (tid == 0) *cnt = 0;
+        __syncthreads();
+        if (rotated == 0) return 0;
+    }
+    return 1;
 }
 
 size_t eig_lds_bytes(int nu, int max_row, bool a_in_lds) {
-    size_t n = (a_in_lds ? (size_t)nu * nu : 0) + (size_t)nu * (max_row + 1) + 4 * (size_t)nu + 8 + 72 + 64 + 2;
+    size_t n = (a_in_lds ? (size_t)nu * (nu + 1) : 0) + (size_t)nu * (max_row + 1) + 4 * (size_t)nu + 8 + 72 + 64 + 2;
     return n * sizeof(double);
 }
 
@@ -220,7 +294,7 @@ __global__ __launch_bounds__(WG) void k_gather_rows(int nseeds, const int32_t* _
 }
 
 template <bool LDS_A>
-__global__ __launch_bounds__(WG) void k_eig(EigExtra ex, int nseeds, const int32_t* __restrict__ seeds, int nu,
+__global__ __launch_bounds__(EIG_WG) void k_eig(EigExtra ex, int nseeds, const int32_t* __restrict__ seeds, int nu,
                                             double* __restrict__ h, const int32_t* __restrict__ nu_eff_blk,
                                             const double* __restrict__ Kp, const int32_t* __restrict__ Hrp,
                                             const int32_t* __restrict__ Hcol, const double* __restrict__ Hval,
@@ -242,7 +316,7 @@ __global__ __launch_bounds__(WG) void k_eig(EigExtra ex, int nseeds, const int32
             e_seed[b] = 0.0;
             n_seed[b] = 0.0;
         }
-        for (int a = tid; a < nu; a += WG) {
+        for (int a = tid; a < nu; a += EIG_WG) {
             if (eps_b) eps_b[a] = 0.0;
             if (w_b) w_b[a] = 0.0;
         }
@@ -259,8 +333,8 @@ __global__ __launch_bounds__(WG) void k_eig(EigExtra ex, int nseeds, const int32
     double* p = smem;
     if constexpr (LDS_A) {
         A = p;
-        ld = m;
-        p += (size_t)nu * nu;
+        ld = m | 1;   // odd: the Jacobi steps' column accesses spread over the banks
+        p += (size_t)nu * (nu + 1);
     } else {
         A = h + (int64_t)b * nu * nu;
         ld = nu;
@@ -278,22 +352,19 @@ __global__ __launch_bounds__(WG) void k_eig(EigExtra ex, int nseeds, const int32
     p += nu;
     double* red = p;
     p += 8;
-    double* svec = ex.mode == 1 ? Rl : p;   // one value per column of R (mode 1: up to nu + 1, in R's unused LDS)
     p += 72;
     double* rhoL = p;
     p += 64;
     int* tjp = reinterpret_cast<int*>(p);
 
-    // A = K^T H K from its computed upper triangle (h[b][k][n], k <= n), mirrored.
+    // A = K^T H K from its computed upper triangle (h[b][k][n], k <= n), which is all the Jacobi
+    // iteration keeps (in place in h when A does not fit in LDS).
     const double* hb = h + (int64_t)b * nu * nu;
     if constexpr (LDS_A) {
-        for (int r = wave; r < m; r += 4)
-            for (int c = lane; c < m; c += 64) A[r * ld + c] = r <= c ? hb[(int64_t)r * nu + c] : hb[(int64_t)c * nu + r];
-    } else {
-        for (int r = wave; r < m; r += 4)
-            for (int c = lane; c < r; c += 64) A[r * ld + c] = A[c * ld + r];
+        for (int r = wave; r < m; r += EIG_WAVES)
+            for (int c = r + lane; c < m; c += 64) A[r * ld + c] = hb[(int64_t)r * nu + c];
     }
-    for (int idx = tid; idx < m * NR; idx += WG) {
+    for (int idx = tid; idx < m * NR; idx += EIG_WG) {
         const int k = idx / NR, c = idx - k * NR;
         double r0;
         if (c == 0) r0 = k == 0 ? 1.0 : 0.0;
@@ -305,103 +376,35 @@ __global__ __launch_bounds__(WG) void k_eig(EigExtra ex, int nseeds, const int32
     if (tid < nP && Hcol[rlo + tid] == j) *tjp = tid;
     __syncthreads();
 
-    // Householder tridiagonalization, reflections also applied to R.
-    for (int k = 0; k < m - 2; ++k) {
-        const int len = m - k - 1;
-        const double* xr = A + k * ld + k + 1;  // row k right of the diagonal = column k below it
-        double part = 0.0;
-        for (int i = 1 + tid; i < len; i += WG) part += xr[i] * xr[i];
-        const double rest = block_sum(part, red);
-        const double x0 = xr[0];
-        if (rest == 0.0) {
-            if (tid == 0) {
-                d[k] = A[k * ld + k];
-                e[k] = x0;
-            }
-            continue;
-        }
-        const double xx = rest + x0 * x0;
-        const double alpha = -copysign(sqrt(xx), x0);
-        const double vn = 1.0 / sqrt(2.0 * (xx - alpha * x0));
-        for (int i = tid; i < len; i += WG) v[i] = (xr[i] - (i == 0 ? alpha : 0.0)) * vn;
-        __syncthreads();
-        // q = A22 v, then q = 2 (q - (v.q) v): A22 <- A22 - v q^T - q v^T
-        double pv = 0.0;
-        for (int i = tid; i < len; i += WG) {
-            const double* col = A + (k + 1) * ld + (k + 1) + i;
-            double s = 0.0;
-            for (int jj = 0; jj < len; ++jj) s += col[jj * ld] * v[jj];
-            q[i] = s;
-            pv += s * v[i];
-        }
-        const double kp = block_sum(pv, red);
-        for (int i = tid; i < len; i += WG) q[i] = 2.0 * (q[i] - kp * v[i]);
-        __syncthreads();
-        for (int r = wave; r < len; r += 4) {
-            const double vr = v[r], qr = q[r];
-            double* row = A + (k + 1 + r) * ld + (k + 1);
-            for (int c = lane; c < len; c += 64) row[c] -= vr * q[c] + qr * v[c];
-        }
-        for (int cb = 0; cb < NR; cb += WG / 8) {
-            const int c = cb + (tid >> 3), pi = tid & 7;
-            double s = 0.0;
-            if (c < NR)
-                for (int i = pi; i < len; i += 8) s += v[i] * R[(k + 1 + i) * NR + c];
-            s += __shfl_xor(s, 1);
-            s += __shfl_xor(s, 2);
-            s += __shfl_xor(s, 4);
-            if (c < NR && pi == 0) svec[c] = s;
-        }
-        __syncthreads();
-        for (int idx = tid; idx < len * NR; idx += WG) {
-            const int i = idx / NR, c = idx - i * NR;
-            R[(k + 1 + i) * NR + c] -= 2.0 * v[i] * svec[c];
-        }
-        if (tid == 0) {
-            d[k] = A[k * ld + k];
-            e[k] = alpha;
-        }
-        __syncthreads();
-    }
-    if (tid == 0) {
-        if (m >= 2) {
-            d[m - 2] = A[(m - 2) * ld + (m - 2)];
-            e[m - 2] = A[(m - 2) * ld + (m - 1)];
-            d[m - 1] = A[(m - 1) * ld + (m - 1)];
-        } else {
-            d[0] = A[0];
-        }
-        e[m - 1] = 0.0;
-    }
-    __syncthreads();
-    // v, q are free after the reduction; R is in LDS except in mode 1 (a separate
-    // call there, so that the LDS case compiles to LDS instructions)
+    // Jacobi: A's diagonal becomes the levels, R's rows the vectors' components (cs, sn, tt in v, q, e)
     int* failp = tjp + 1;
-    if (wave == 0) {
-        int f;
-        if (ex.mode == 1) f = ql_implicit(d, e, m, R, NR, lane, v, q, ex.ql_maxit);
-        else f = ql_implicit(d, e, m, Rl, NR, lane, v, q, ex.ql_maxit);
-        if (lane == 0) *failp = f;
+    {
+        // a separate call for R in global memory (mode 1), so that the LDS case compiles to LDS instructions
+        const int f = ex.mode == 1 ? jacobi_eig(A, ld, m, R, NR, v, q, e, tjp + 2, ex.eig_max_sweeps)
+                                   : jacobi_eig(A, ld, m, Rl, NR, v, q, e, tjp + 2, ex.eig_max_sweeps);
+        __syncthreads();
+        for (int a = tid; a < m; a += EIG_WG) d[a] = A[a * ld + a];
+        if (tid == 0) *failp = f;
     }
     __syncthreads();
     if (*failp != 0) {
         // an eigenvalue is still unconverged: the seed reports NU_NOCONV and NaN in every output
         const double nan = __builtin_nan("");
         if (ex.mode == 1) {
-            for (int idx = tid; idx < m * m; idx += WG) {
+            for (int idx = tid; idx < m * m; idx += EIG_WG) {
                 const int a = idx / m, c = idx - a * m;
                 ex.Y[((int64_t)b * nu + a) * nu + c] = nan;
             }
         } else if (ex.mode == 2) {
             if (tid == 0) ex.phi[b] = nan;
         } else if (zc == nullptr) {
-            for (int t = tid; t < nP; t += WG) rho[rlo + t] = nan;
+            for (int t = tid; t < nP; t += EIG_WG) rho[rlo + t] = nan;
             if (tid == 0) {
                 e_seed[b] = nan;
                 n_seed[b] = nan;
             }
         }
-        for (int a = tid; a < nu; a += WG) {
+        for (int a = tid; a < nu; a += EIG_WG) {
             if (eps_b) eps_b[a] = nan;
             if (w_b) w_b[a] = nan;
         }
@@ -414,11 +417,11 @@ __global__ __launch_bounds__(WG) void k_eig(EigExtra ex, int nseeds, const int32
     const int tj = *tjp;
     const double sq = sqrt(diagS[j]);
     if (ex.mode == 1) {   // the full subspace eigenvectors y_alpha and levels
-        for (int idx = tid; idx < m * m; idx += WG) {
+        for (int idx = tid; idx < m * m; idx += EIG_WG) {
             const int a = idx / m, c = idx - a * m;
             ex.Y[((int64_t)b * nu + a) * nu + c] = R[a * NR + 1 + c];
         }
-        for (int a = tid; a < nu; a += WG) eps_b[a] = a < m ? d[a] : 0.0;
+        for (int a = tid; a < nu; a += EIG_WG) eps_b[a] = a < m ? d[a] : 0.0;
         if (tid == 0) nu_eff_out[b] = m;
         return;
     }
@@ -437,15 +440,15 @@ __global__ __launch_bounds__(WG) void k_eig(EigExtra ex, int nseeds, const int32
     }
     if (zc != nullptr) {
         double* zb = zc + (int64_t)b * nu * max_row;
-        for (int idx = tid; idx < m * nP; idx += WG) {
+        for (int idx = tid; idx < m * nP; idx += EIG_WG) {
             const int a = idx / nP, t = idx - a * nP;
             zb[a * max_row + t] = R[a * NR + 1 + t];
         }
-        for (int a = tid; a < m; a += WG) {
+        for (int a = tid; a < m; a += EIG_WG) {
             eps_b[a] = d[a];
             w_b[a] = sq * R[a * NR] * R[a * NR + 1 + tj];
         }
-        for (int a = m + tid; a < nu; a += WG) {
+        for (int a = m + tid; a < nu; a += EIG_WG) {
             eps_b[a] = 0.0;
             w_b[a] = 0.0;
         }
@@ -453,19 +456,19 @@ __global__ __launch_bounds__(WG) void k_eig(EigExtra ex, int nseeds, const int32
         return;
     }
     double* fz = q;
-    for (int a = tid; a < m; a += WG) {
+    for (int a = tid; a < m; a += EIG_WG) {
         const double ea = d[a];
         const double zj = R[a * NR + 1 + tj];
         fz[a] = fermi_occ(ea, mu, kT) * zj;
         if (eps_b) eps_b[a] = ea;
         if (w_b) w_b[a] = sq * R[a * NR] * zj;
     }
-    for (int a = m + tid; a < nu; a += WG) {
+    for (int a = m + tid; a < nu; a += EIG_WG) {
         if (eps_b) eps_b[a] = 0.0;
         if (w_b) w_b[a] = 0.0;
     }
     __syncthreads();
-    for (int cb = 0; cb < nP; cb += WG / 8) {
+    for (int cb = 0; cb < nP; cb += EIG_WG / 8) {
         const int t = cb + (tid >> 3), pi = tid & 7;
         double s = 0.0;
         if (t < nP)
@@ -514,13 +517,13 @@ LaunchInfo launch_eig(int nseeds, const int32_t* seeds, int nu, double* h, const
     if (lds_a) {
         static std::atomic<uint64_t> done{0};
         allow_full_lds((const void*)k_eig<true>, done);
-        hipLaunchKernelGGL((k_eig<true>), dim3(nseeds), dim3(WG), lds, s, ex, nseeds, seeds, nu, h, nu_eff_blk, Kp, Hrp,
+        hipLaunchKernelGGL((k_eig<true>), dim3(nseeds), dim3(EIG_WG), lds, s, ex, nseeds, seeds, nu, h, nu_eff_blk, Kp, Hrp,
                            Hcol, Hval, SvalH, diagS, max_row, mu, kT, rho, e_seed, n_seed, nu_eff_out, eps_out, w_out,
                            zc);
     } else {
         static std::atomic<uint64_t> done{0};
         allow_full_lds((const void*)k_eig<false>, done);
-        hipLaunchKernelGGL((k_eig<false>), dim3(nseeds), dim3(WG), lds, s, ex, nseeds, seeds, nu, h, nu_eff_blk, Kp,
+        hipLaunchKernelGGL((k_eig<false>), dim3(nseeds), dim3(EIG_WG), lds, s, ex, nseeds, seeds, nu, h, nu_eff_blk, Kp,
                            Hrp, Hcol, Hval, SvalH, diagS, max_row, mu, kT, rho, e_seed, n_seed, nu_eff_out, eps_out,
                            w_out, zc);
     }

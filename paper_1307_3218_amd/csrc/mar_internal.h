@@ -128,7 +128,7 @@ struct EigExtra {
     const double* win = nullptr;  // mode 2: {eps_k, eta(k-1), eta(k)} on the device
     double sigma = 0.0;           // mode 2: width of the smoothed delta
     double* phi = nullptr;        // mode 2: e_j^T phi_k of each seed
-    int ql_maxit = 80;            // implicit-QL iterations allowed per eigenvalue
+    int eig_max_sweeps = 40;      // Jacobi sweeps allowed
 };
 // nu_eff of a seed whose subspace eigensolve did not converge
 constexpr int NU_NOCONV = -3;

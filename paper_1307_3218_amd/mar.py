@@ -39,7 +39,7 @@ class MarError(RuntimeError):
 class mar_tuning(C.Structure):
     _fields_ = [("seed_block", C.c_int32), ("schedule", C.c_int32), ("proj_wgs", C.c_int32),
                 ("slab_pad_kb", C.c_int32), ("proj_variant", C.c_int32), ("upd_q", C.c_int32),
-                ("support_off", C.c_int32), ("two_streams", C.c_int32), ("ql_max_iter", C.c_int32)]
+                ("support_off", C.c_int32), ("two_streams", C.c_int32), ("eig_max_sweeps", C.c_int32)]
 
 
 class mar_request(C.Structure):
@@ -245,9 +245,9 @@ def mar_autotune(ctx, nu, prec, d_seeds, mu, kT, stream=None) -> tuple:
 
 def mar_set_tuning(ctx, seed_block: int = 0, schedule: int = 0, proj_wgs: int = 0, slab_pad_kb: int = 0,
                    proj_variant: int = 0, upd_q: int = 0, support_off: int = 0, two_streams: int = 0,
-                   ql_max_iter: int = 0) -> int:
+                   eig_max_sweeps: int = 0) -> int:
     t = mar_tuning(seed_block, schedule, proj_wgs, slab_pad_kb, proj_variant, upd_q, support_off, two_streams,
-                   ql_max_iter)
+                   eig_max_sweeps)
     return lib().mar_set_tuning(ctx, C.byref(t))
 
 
@@ -421,15 +421,15 @@ class Context:
 
     def set_tuning(self, seed_block: int = 0, schedule: str = "auto", proj_wgs: int = 0, slab_pad_kb: int = 0,
                    proj_variant: int = 0, upd_q: int = 0, support: bool = True, two_streams: bool | None = None,
-                   overlap_eig: bool = True, ql_max_iter: int = 0):
+                   overlap_eig: bool = True, eig_max_sweeps: int = 0):
         """two_streams: None lets the library choose (two blocks in flight for local regions of 6 hops or
         more, else one block at a time); True alternates two blocks; False runs one block at a time, with
         each block's eigensolve on the second stream when overlap_eig, else everything on one stream.
-        ql_max_iter: QL iterations allowed per eigenvalue of the subspace eigensolve (0 = 80)."""
+        eig_max_sweeps: Jacobi sweeps allowed to the subspace eigensolve (0 = 40)."""
         _check(self.handle, mar_set_tuning(self.handle, seed_block, SCHEDULE[schedule], proj_wgs, slab_pad_kb,
                                            proj_variant, upd_q, 0 if support else 1,
                                            (0 if overlap_eig else 2) if two_streams is None else
-                                           1 if two_streams else (3 if overlap_eig else 2), ql_max_iter))
+                                           1 if two_streams else (3 if overlap_eig else 2), eig_max_sweeps))
 
     def autotune(self, d_seeds, nu, mu, kT, precision="fp32", stream=None) -> dict:
         """Pick the seed block and projection tiles for (nu, precision) by timing probe solves."""

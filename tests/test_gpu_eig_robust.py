@@ -1,16 +1,17 @@
-"""The subspace eigensolve (Sec. 2: one nu x nu standard eigenproblem per seed, FP64) on the GPU:
-failure reporting and the plane rotations over the whole exponent range.
+"""The subspace eigensolve (Sec. 2: one nu x nu standard eigenproblem per seed, FP64, by the parallel cyclic
+Jacobi method) on the GPU: failure reporting and the rotations over the whole exponent range.
 
-* An iteration cap too small for the implicit QL iteration to converge (tuning ql_max_iter = 1 on the
-  subspace matrices of the 64-atom cell) must be reported: nu_eff = -3 and NaN outputs for the seed,
-  MAR_ERR_NOCONV from the host entry points. The cap bounds the QL loop, so every kernel exits normally.
-* The QL rotations form r = sqrt(f^2 + g^2) and 1/(2r) from a reciprocal-square-root estimate refined by
-  two coupled Goldschmidt steps. Scaling H, mu and kT by 2^k leaves rho unchanged and scales the levels and
-  E_band by 2^k (scale covariance), while f^2 + g^2 scales by 4^k. The plain form (textbook schedule,
-  normalized vectors) takes k = +-480, which moves f^2 + g^2 across roughly 2^-950 ... 2^970; the batched
-  form's delayed schedule forms products of the unnormalized residual with itself, cubic in the scale of
-  H, and takes k = +-150, +-300. Every scale is compared with the oracle at that scale to the FP64 bar,
-  and with the unscaled GPU result.
+* A sweep cap too small for the Jacobi iteration to converge (tuning eig_max_sweeps = 1 on the subspace
+  matrices of the 64-atom cell, which need about ten) must be reported: nu_eff = -3 and NaN outputs for the
+  seed, MAR_ERR_NOCONV from the host entry points. The cap bounds the sweep loop, so every kernel exits
+  normally.
+* The rotations form tau = (a_qq - a_pp) / (2 a_pq), t = sign(tau) / (|tau| + sqrt(1 + tau^2)) and
+  c = 1 / sqrt(1 + t^2) from quotients and square roots of the subspace matrix entries. Scaling H, mu and kT
+  by 2^k leaves rho unchanged and scales the levels and E_band by 2^k (scale covariance), while the entries
+  scale by 2^k and their products by 4^k. The plain form (textbook schedule, normalized vectors) takes
+  k = +-480; the batched form's delayed schedule forms products of the unnormalized residual with itself,
+  cubic in the scale of H, and takes k = +-150, +-300. Every scale is compared with the oracle at that
+  scale to the FP64 bar, and with the unscaled GPU result.
 """
 import math
 
@@ -38,9 +39,9 @@ def _slots(H, seeds):
 
 def test_iteration_cap_reported_host(cell256, ctx):
     seeds = np.arange(0, cell256.M, 7)
-    ctx.set_tuning(ql_max_iter=1)
+    ctx.set_tuning(eig_max_sweeps=1)
     try:
-        print("[eig-robust] host solve with ql_max_iter = 1", flush=True)
+        print("[eig-robust] host solve with eig_max_sweeps = 1", flush=True)
         with pytest.raises(mar.MarError) as ei:
             ctx.solve(seeds, NU, MU, KT, precision="fp64")
         assert ei.value.status == mar.MAR_ERR_NOCONV
@@ -71,9 +72,9 @@ def test_iteration_cap_reported_async(cell256, ctx, prec, form):
     d_nu = torch.zeros(n, dtype=torch.int32, device=dev)
     d_eps = torch.zeros(n * NU, dtype=torch.float64, device=dev)
     d_w = torch.zeros(n * NU, dtype=torch.float64, device=dev)
-    ctx.set_tuning(ql_max_iter=1)
+    ctx.set_tuning(eig_max_sweeps=1)
     try:
-        print(f"[eig-robust] async solve with ql_max_iter = 1, {prec} {form}", flush=True)
+        print(f"[eig-robust] async solve with eig_max_sweeps = 1, {prec} {form}", flush=True)
         ctx.solve_async(d_seeds, NU, MU, KT, precision=prec, form=form, d_rho=d_rho, d_e_band=d_eb, d_e_seed=d_e,
                         d_n_seed=d_n, d_nu_eff=d_nu, d_eps=d_eps, d_weight=d_w)
         torch.cuda.synchronize()
