@@ -17,7 +17,10 @@ Keeping the steps in FP64 one at a time (seed 14) shows that the FP32 storage
 of the basis alone accounts for 9e-7 and the FP32 matrix values for 2e-8,
 while the FP32 sums do the rest (the sparse products' sums alone 1.5e-5, the
 updates alone 4.6e-6). Summing the device's sparse products in FP64 moved its
-Frobenius error only from 7.4e-6 to 6.5e-6. So the FP32 form's own arithmetic,
+Frobenius error only from 7.4e-6 to 6.5e-6, and solving the subspace problem
+against the Gram matrix of the FP32 basis summed in FP64 (A y = eps G y instead
+of assuming an S-orthonormal basis) leaves seed 14 at 1.62e-5, unchanged. So the
+FP32 form's own arithmetic,
 not a flaw of the device code, puts these columns above the bar at nu = 300
 on this lattice.
 """
