@@ -318,6 +318,8 @@ def main() -> int:
                     help="natural: consecutive seeds (neighbouring atoms) share a block; random: a permutation of "
                          "all seeds; sampled: a sorted uniform sample of min(M, 16384) seeds")
     ap.add_argument("--no-support", action="store_true", help="stream every row of every slab")
+    ap.add_argument("--proj-variant", type=int, default=0,
+                    help="projection variant of the delayed schedule (0 = the autotuned or default choice)")
     ap.add_argument("--two-streams", action="store_true",
                     help="two seed blocks in flight on two streams (default: the library's choice, which is "
                          "two blocks for local regions of 6 hops or more and one block at a time otherwise)")
@@ -363,7 +365,7 @@ def main() -> int:
         log(f"copy calibration: {args.copy_calibration} MiB read + {args.copy_calibration} MiB written")
         del a, c
     ctx = mar.Context(system.H, system.S)
-    ctx.set_tuning(args.seed_block, support=not args.no_support,
+    ctx.set_tuning(args.seed_block, support=not args.no_support, proj_variant=args.proj_variant,
                    two_streams=True if args.two_streams else (False if args.one_block else None))
     local = args.r_cut >= 0
     if local:
@@ -477,7 +479,7 @@ def main() -> int:
         ach = e["bytes"] / (e["ms"] * 1e-3) / 1e9
         kind, cells = system.name.split("_", 1)          # e.g. mixed, 16x16x16
         wl = f"{kind}{cells.split('x')[0]}_nu{nu}_fp32_b{B}_{args.seed_order}" + ("_full" if args.no_support else "") \
-            + (f"_r{args.r_cut}" if local else "")
+            + (f"_r{args.r_cut}" if local else "") + (f"_v{args.proj_variant}" if args.proj_variant else "")
         traffic = measured_traffic(dom, wl) if S_step % B == 0 else None
         roofline = dict(kernel=dom, bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
                         frac=round(ach / HBM_PEAK_GBPS, 4), traffic=traffic,
@@ -555,7 +557,8 @@ def main() -> int:
                    "M": M, "nnz": int(system.H.nnz), "nu": nu, "seeds_per_step": S_step, "seed_block": B,
                    "precision": "fp32", "form": "batched", "mu": mu, "seed_order": args.seed_order,
                    "support_tracking": not args.no_support, "local_region_hops": args.r_cut if local else None,
-                   "two_streams": True if args.two_streams else (False if args.one_block else "auto")},
+                   "two_streams": True if args.two_streams else (False if args.one_block else "auto"),
+                   "proj_variant": args.proj_variant or "default"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "error_vs_oracle": errors,
