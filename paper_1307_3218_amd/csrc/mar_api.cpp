@@ -9,6 +9,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <type_traits>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -697,6 +698,8 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     if (sparse) part_doubles = std::max<size_t>(part_doubles, (size_t)grid_max * 3 * kg * B);
     // update depth of the full sweep (support tracking runs one tile of 4 * WG vectors per workgroup)
     const int upd_q = c->tune.upd_q > 0 ? c->tune.upd_q : 4;
+    // the FP32 form's update sums in FP64 at large subspace dimensions
+    const bool upd_acc64 = std::is_same<T, float>::value && nu > mar::kUpdAcc64Nu;
     const int64_t part_cap = (int64_t)part_doubles;
 
     size_t off = 0;
@@ -968,9 +971,10 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
                     const bool nt = !local && (double)(n + 2) * (double)slab > mar::kNtSweepBytes;
                     return mar::launch_upd2_list<T>(B, K, M, stride, n, cAT, cBT, gam, Fn, Y, wout, !last, slist,
                                                     sDl, scnt, n + 1, ring ? n + 1 + kg : n + 1,
-                                                    local ? kListWgs : ntiles, nt, s);
+                                                    local ? kListWgs : ntiles, nt, s, upd_acc64);
                 }
-                return mar::launch_upd2<T>(B, K, M, stride, n, cAT, cBT, gam, Fn, Y, wout, !last, upd_q, s);
+                return mar::launch_upd2<T>(B, K, M, stride, n, cAT, cBT, gam, Fn, Y, wout, !last, upd_q, s,
+                                           upd_acc64);
             });
             tag(ru, last ? SP_UPD2_LAST : SP_UPD2, n, bi, (double)ntiles);
             if (last) break;

@@ -190,7 +190,7 @@ template <typename T>
 LaunchInfo launch_upd2_list(int B, T* basis, int64_t M, int64_t stride, int n, const T* cA, const T* cB,
                             const double* gam, const double* Fn, const T* y, T* wout, bool want_w,
                             const int32_t* list, const int32_t* Dl, const int32_t* cnt, int lim, int limz,
-                            int64_t grid, bool nt, hipStream_t s);
+                            int64_t grid, bool nt, hipStream_t s, bool acc64 = false);
 // Zero the row tiles within hmax + 1 hops of a block's seeds (one more BFS level on dist, which holds the levels
 // up to hmax) in nsl slabs of slab_bytes from base and in y; tiles are 4 * WG vectors of 16 bytes, nvec per slab.
 LaunchInfo launch_zero_ring(int64_t nbrow, const int32_t* brp, const int32_t* bcol, int32_t* dist, int hmax,
@@ -210,10 +210,14 @@ constexpr double kNtSweepBytes = 512.0 * 1024 * 1024;
 // cA/cB: [n][B] coefficients in the basis precision T.
 // upd_q: 16-byte vectors per thread (2, 4 or 8; 0 = 4), reduced for small grids. Every row of every slab
 // (with support tracking the update runs over the tile list instead: launch_upd2_list).
+// acc64 (FP32 basis): the running sums over the slabs in FP64, rounded once when stored.
 template <typename T>
 LaunchInfo launch_upd2(int B, T* basis, int64_t M, int64_t stride, int n, const T* cA, const T* cB,
                        const double* gam, const double* Fn, const T* y, T* wout, bool want_w, int upd_q,
-                       hipStream_t s);
+                       hipStream_t s, bool acc64 = false);
+// Subspace dimension above which the FP32 form's update keeps its running sums in FP64 (at nu = 300 on the
+// 1048576-row lattice they halve the form's rho error against the oracle, at 0.7 % of the rate of nu = 100).
+constexpr int kUpdAcc64Nu = 128;
 // cAf/cBf (optional): the update coefficients rounded to FP32 for an FP32 basis.
 // redb (n >= 1): {u~.S u~ [B], u~.u~ [B]} of slab n; the kernel first takes the breakdown test of slab n and
 // sets BT, UU.

@@ -4,6 +4,8 @@
 // Layout (all per seed block of B seeds): vectors are [M][B] with the seed
 // index fastest; the basis K and S*K are [nu][M][B] (slab k = k-th vector of
 // every seed). Each kernel streams whole slabs with 16-byte vector accesses.
+#include <type_traits>
+
 #include "mar_device.h"
 #include "mar_internal.h"
 
@@ -879,7 +881,10 @@ __global__ __launch_bounds__(WG) void k_es_pdot(const T* __restrict__ basis, int
 
 // Q vectors per thread at vbase, vbase + WG, ... (all < nvec), slabs from kst on (the slabs below kst are
 // zero on these rows). The loads of one slab share one base address, so they go out at constant offsets.
-template <typename T, int B, int Q, bool WANT_W, bool NT>
+// ACC64: the running sums u~ - sum K cA and y - sum K cB are kept in FP64 and rounded to the basis
+// precision once, when stored (for an FP32 basis at large nu, where the FP32 rounding of these sums over
+// hundreds of slabs dominates the form's error).
+template <typename T, int B, int Q, bool WANT_W, bool NT, bool ACC64>
 __device__ __forceinline__ void upd2_body(int64_t vbase, int kst, T* __restrict__ basis, int64_t slab, int n,
                                           const T* __restrict__ cA, const T* __restrict__ cB,
                                           const double* __restrict__ gam, const double* __restrict__ Fn,
@@ -887,19 +892,25 @@ __device__ __forceinline__ void upd2_body(int64_t vbase, int kst, T* __restrict_
     using SM = SeedMap<T, B>;
     constexpr int VEC = SM::VEC, P = SM::P;
     using VT = typename Vec16<T>::type;
+    using AT = typename std::conditional<ACC64, double, T>::type;
     const int tid = threadIdx.x;
     const int64_t slabv = slab / VEC;
     const int sb = (B < VEC) ? 0 : (tid % P) * VEC;
     VT* bv = reinterpret_cast<VT*>(basis) + vbase;
     const VT* yv = reinterpret_cast<const VT*>(y) + vbase;
-    T au[Q][VEC], aw[Q][VEC];
+    AT au[Q][VEC], aw[Q][VEC];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        unpack(bv[(int64_t)n * slabv + q * WG], au[q]);
-        if constexpr (WANT_W) unpack(yv[q * WG], aw[q]);
+        T t0[VEC], t1[VEC];
+        unpack(bv[(int64_t)n * slabv + q * WG], t0);
+        if constexpr (WANT_W) unpack(yv[q * WG], t1);
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) {
+            au[q][i] = (AT)t0[i];
+            if constexpr (WANT_W) aw[q][i] = (AT)t1[i];
+        }
     }
-    for (int k = kst; k < n; ++k) {
-        T ca[VEC], cb[VEC];
+    auto coef = [&](int k, T (&ca)[VEC], T (&cb)[VEC]) {
         if constexpr (B >= VEC) {
             unpack(reinterpret_cast<const VT*>(cA + (int64_t)k * B + sb)[0], ca);
             if constexpr (WANT_W) unpack(reinterpret_cast<const VT*>(cB + (int64_t)k * B + sb)[0], cb);
@@ -910,74 +921,104 @@ __device__ __forceinline__ void upd2_body(int64_t vbase, int kst, T* __restrict_
                 if constexpr (WANT_W) cb[i] = cB[(int64_t)k * B + i % B];
             }
         }
-        // NT: the slabs swept exceed the last-level cache and are read once per sweep, so non-temporal loads
-        // keep them from displacing reused lines; a smaller basis stays cached from one sweep to the next
-        const VT* bk = bv + (int64_t)k * slabv;
-        if constexpr (NT) {
-            // Streaming from HBM: one vector at a time, each load used before the next is issued (the
-            // scheduling barrier keeps the compiler from hoisting them). Four loads in flight per wave
-            // made this sweep 20 % slower (5.4 against 6.5 TB/s on the 131072-row workload).
+    };
+    auto step = [&](int q, const T (&a)[VEC], const T (&ca)[VEC], const T (&cb)[VEC]) {
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) {
+            au[q][i] = fma(-(AT)a[i], (AT)ca[i], au[q][i]);
+            if constexpr (WANT_W) aw[q][i] = fma(-(AT)a[i], (AT)cb[i], aw[q][i]);
+        }
+    };
+    if constexpr (NT && ACC64) {
+        // Streaming from HBM with FP64 sums: the next vector's load is issued before this one's sums, so the
+        // longer FP64 arithmetic runs under a load in flight (one load at a time left it exposed: 5.5 against
+        // 6.1 TB/s on the 131072-row workload; with FP32 sums the same look-ahead was slower, 5.6 against 6.2)
+        T an[VEC];
+        if (kst < n) unpack_nt(bv + (int64_t)kst * slabv, an);
+        for (int k = kst; k < n; ++k) {
+            T ca[VEC], cb[VEC];
+            coef(k, ca, cb);
+            const VT* bk = bv + (int64_t)k * slabv;
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 T a[VEC];
-                unpack_nt(bk + q * WG, a);
 #pragma unroll
-                for (int i = 0; i < VEC; ++i) {
-                    au[q][i] = fma(-a[i], ca[i], au[q][i]);
-                    if constexpr (WANT_W) aw[q][i] = fma(-a[i], cb[i], aw[q][i]);
-                }
+                for (int i = 0; i < VEC; ++i) a[i] = an[i];
+                if (q + 1 < Q) unpack_nt(bk + (q + 1) * WG, an);
+                else if (k + 1 < n) unpack_nt(bk + slabv, an);
+                step(q, a, ca, cb);
                 __builtin_amdgcn_sched_barrier(0);
             }
-        } else {
-            // cached slabs (a basis within the last-level cache, local regions): all loads in flight
-            T a[Q][VEC];
+        }
+    } else {
+        for (int k = kst; k < n; ++k) {
+            T ca[VEC], cb[VEC];
+            coef(k, ca, cb);
+            // NT: the slabs swept exceed the last-level cache and are read once per sweep, so non-temporal
+            // loads keep them from displacing reused lines; a smaller basis stays cached from one sweep to the
+            // next
+            const VT* bk = bv + (int64_t)k * slabv;
+            if constexpr (NT) {
+                // Streaming from HBM: one vector at a time, each load used before the next is issued (the
+                // scheduling barrier keeps the compiler from hoisting them). Four loads in flight per wave
+                // made this sweep 20 % slower (5.4 against 6.5 TB/s on the 131072-row workload).
 #pragma unroll
-            for (int q = 0; q < Q; ++q) unpack(bk[q * WG], a[q]);
-#pragma unroll
-            for (int q = 0; q < Q; ++q)
-#pragma unroll
-                for (int i = 0; i < VEC; ++i) {
-                    au[q][i] = fma(-a[q][i], ca[i], au[q][i]);
-                    if constexpr (WANT_W) aw[q][i] = fma(-a[q][i], cb[i], aw[q][i]);
+                for (int q = 0; q < Q; ++q) {
+                    T a[VEC];
+                    unpack_nt(bk + q * WG, a);
+                    step(q, a, ca, cb);
+                    __builtin_amdgcn_sched_barrier(0);
                 }
+            } else {
+                // cached slabs (a basis within the last-level cache, local regions): all loads in flight
+                T a[Q][VEC];
+#pragma unroll
+                for (int q = 0; q < Q; ++q) unpack(bk[q * WG], a[q]);
+#pragma unroll
+                for (int q = 0; q < Q; ++q) step(q, a[q], ca, cb);
+            }
         }
     }
     // 1 / gamma in FP64, rounded once: a multiply per element instead of a division, whose expansion held
     // registers enough to lower the sweep's occupancy
-    T rg[VEC], fn[VEC];
+    AT rg[VEC], fn[VEC];
 #pragma unroll
     for (int i = 0; i < VEC; ++i) {
         const int b = (B < VEC) ? (i % B) : (sb + i);
-        rg[i] = (T)(1.0 / gam[b]);
-        fn[i] = (T)Fn[b];
+        rg[i] = (AT)(1.0 / gam[b]);
+        fn[i] = (AT)Fn[b];
     }
     VT* wv = reinterpret_cast<VT*>(wout) + vbase;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
+        T ou[VEC], ow[VEC];
 #pragma unroll
         for (int i = 0; i < VEC; ++i) {
             au[q][i] = au[q][i] * rg[i];
             if constexpr (WANT_W) aw[q][i] = (aw[q][i] - au[q][i] * fn[i]) * rg[i];
+            ou[i] = (T)au[q][i];
+            ow[i] = (T)aw[q][i];
         }
-        bv[(int64_t)n * slabv + q * WG] = pack(au[q]);
-        if constexpr (WANT_W) wv[q * WG] = pack(aw[q]);
+        bv[(int64_t)n * slabv + q * WG] = pack(ou);
+        if constexpr (WANT_W) wv[q * WG] = pack(ow);
     }
 }
 
 // One chunk of WG * Q vectors starting at v0, slabs from kst on. A whole chunk runs the branch-free body;
 // the one chunk that reaches past nvec runs it vector by vector, for the lanes still inside.
-template <typename T, int B, int Q, bool WANT_W, bool NT>
+template <typename T, int B, int Q, bool WANT_W, bool NT, bool ACC64>
 __device__ __forceinline__ void upd2_chunk(int64_t v0, int kst, T* __restrict__ basis, int64_t slab, int n,
                                            const T* __restrict__ cA, const T* __restrict__ cB,
                                            const double* __restrict__ gam, const double* __restrict__ Fn,
                                            const T* __restrict__ y, T* __restrict__ wout, int64_t nvec) {
     const int64_t vbase = v0 + threadIdx.x;
     if (v0 + (int64_t)Q * WG <= nvec) {
-        upd2_body<T, B, Q, WANT_W, NT>(vbase, kst, basis, slab, n, cA, cB, gam, Fn, y, wout);
+        upd2_body<T, B, Q, WANT_W, NT, ACC64>(vbase, kst, basis, slab, n, cA, cB, gam, Fn, y, wout);
     } else {
         for (int q = 0; q < Q; ++q)
             if (vbase + (int64_t)q * WG < nvec)
-                upd2_body<T, B, 1, WANT_W, NT>(vbase + (int64_t)q * WG, kst, basis, slab, n, cA, cB, gam, Fn, y, wout);
+                upd2_body<T, B, 1, WANT_W, NT, ACC64>(vbase + (int64_t)q * WG, kst, basis, slab, n, cA, cB, gam, Fn,
+                                                      y, wout);
     }
 }
 
@@ -990,14 +1031,14 @@ __device__ __forceinline__ void upd2_chunk(int64_t v0, int kst, T* __restrict__ 
 // The coefficients are [k][B] in the basis precision: one 16-byte load per
 // lane and slab for each of cA, cB when B >= VEC. One chunk of WG * Q
 // vectors per workgroup; NT: non-temporal slab loads.
-template <typename T, int B, int Q, bool WANT_W, bool NT>
+template <typename T, int B, int Q, bool WANT_W, bool NT, bool ACC64>
 __global__ __launch_bounds__(WG) void k_upd2(T* __restrict__ basis, int64_t slab, int n, const T* __restrict__ cA,
                                              const T* __restrict__ cB, const double* __restrict__ gam,
                                              const double* __restrict__ Fn, const T* __restrict__ y,
                                              T* __restrict__ wout, int64_t nvec) {
     const int64_t v0 = (int64_t)blockIdx.x * (WG * Q);
     const int kst = 0;
-    upd2_chunk<T, B, Q, WANT_W, NT>(v0, kst, basis, slab, n, cA, cB, gam, Fn, y, wout, nvec);
+    upd2_chunk<T, B, Q, WANT_W, NT, ACC64>(v0, kst, basis, slab, n, cA, cB, gam, Fn, y, wout, nvec);
 }
 
 // The same update over the row tiles of the support list, sorted by distance
@@ -1012,7 +1053,7 @@ __global__ __launch_bounds__(WG) void k_upd2(T* __restrict__ basis, int64_t slab
 // its support find the zeros it has there (slabs are not cleared per block).
 // STRIDE = false: one entry per workgroup (the grid covers every tile); a grid-stride loop held registers
 // enough to lower the sweep's occupancy.
-template <typename T, int B, bool WANT_W, bool NT, bool STRIDE>
+template <typename T, int B, bool WANT_W, bool NT, bool STRIDE, bool ACC64>
 __global__ __launch_bounds__(WG) void k_upd2_list(T* __restrict__ basis, int64_t slab, int n,
                                                   const T* __restrict__ cA, const T* __restrict__ cB,
                                                   const double* __restrict__ gam, const double* __restrict__ Fn,
@@ -1025,8 +1066,8 @@ __global__ __launch_bounds__(WG) void k_upd2_list(T* __restrict__ basis, int64_t
     for (int64_t e = blockIdx.x; e < cz; e += STRIDE ? (int64_t)gridDim.x : cz) {
         const int64_t t = list[e];
         if (e < ce) {
-            upd2_chunk<T, B, 4, WANT_W, NT>(t * (4 * WG), min(Dl[e], n), basis, slab, n, cA, cB, gam, Fn, y, wout,
-                                            nvec);
+            upd2_chunk<T, B, 4, WANT_W, NT, ACC64>(t * (4 * WG), min(Dl[e], n), basis, slab, n, cA, cB, gam, Fn, y,
+                                                   wout, nvec);
         } else if constexpr (WANT_W) {
             T z[Vec16<T>::n];
 #pragma unroll
@@ -1358,8 +1399,9 @@ template <>
 LaunchInfo launch_upd2_list<MAR_T>(int B, MAR_T* basis, int64_t M, int64_t stride, int n, const MAR_T* cA,
                                    const MAR_T* cB, const double* gam, const double* Fn, const MAR_T* y, MAR_T* wout,
                                    bool want_w, const int32_t* list, const int32_t* Dl, const int32_t* cnt, int lim,
-                                   int limz, int64_t grid, bool nt, hipStream_t s) {
+                                   int limz, int64_t grid, bool nt, hipStream_t s, bool acc64) {
     constexpr int VEC = Vec16<MAR_T>::n;
+    constexpr bool F32 = std::is_same<MAR_T, float>::value;
     const int64_t nvec = M * B / VEC;
     LaunchInfo li;
     if (B < VEC) {
@@ -1368,8 +1410,11 @@ LaunchInfo launch_upd2_list<MAR_T>(int B, MAR_T* basis, int64_t M, int64_t strid
     }
     // a grid of one workgroup per tile takes one entry each; a smaller grid loops over the entries
     const bool stride_loop = grid < (nvec + 4 * WG - 1) / (4 * WG);
+#define MAR_UPD2L_(WW, NTT, SS, AA) \
+    MAR_DISPATCH_B(B, if constexpr (BB >= VEC) hipLaunchKernelGGL((k_upd2_list<MAR_T, BB, WW, NTT, SS, AA>), dim3((unsigned)grid), dim3(WG), 0, s, basis, stride, n, cA, cB, gam, Fn, y, wout, nvec, list, Dl, cnt, lim, limz))
+    // FP64 sums only for an FP32 basis (an FP64 basis sums in FP64 anyway)
 #define MAR_UPD2L(WW, NTT, SS) \
-    MAR_DISPATCH_B(B, if constexpr (BB >= VEC) hipLaunchKernelGGL((k_upd2_list<MAR_T, BB, WW, NTT, SS>), dim3((unsigned)grid), dim3(WG), 0, s, basis, stride, n, cA, cB, gam, Fn, y, wout, nvec, list, Dl, cnt, lim, limz))
+    if (F32 && acc64) { MAR_UPD2L_(WW, NTT, SS, F32); } else { MAR_UPD2L_(WW, NTT, SS, false); }
     if (stride_loop) {   // local regions: few tiles, cached loads
         if (want_w) { MAR_UPD2L(true, false, true); } else { MAR_UPD2L(false, false, true); }
     } else if (nt) {
@@ -1378,6 +1423,7 @@ LaunchInfo launch_upd2_list<MAR_T>(int B, MAR_T* basis, int64_t M, int64_t strid
         if (want_w) { MAR_UPD2L(true, false, false); } else { MAR_UPD2L(false, false, false); }
     }
 #undef MAR_UPD2L
+#undef MAR_UPD2L_
     li.wgs = grid;
     const double slabs_read = (double)n + (want_w ? 2.0 : 1.0), slabs_written = want_w ? 2.0 : 1.0;
     li.bytes = (slabs_read + slabs_written) * (double)(M * B) * sizeof(MAR_T);
@@ -1388,8 +1434,9 @@ LaunchInfo launch_upd2_list<MAR_T>(int B, MAR_T* basis, int64_t M, int64_t strid
 template <>
 LaunchInfo launch_upd2<MAR_T>(int B, MAR_T* basis, int64_t M, int64_t stride, int n, const MAR_T* cA,
                               const MAR_T* cB, const double* gam, const double* Fn, const MAR_T* y, MAR_T* wout,
-                              bool want_w, int upd_q, hipStream_t s) {
+                              bool want_w, int upd_q, hipStream_t s, bool acc64) {
     constexpr int VEC = Vec16<MAR_T>::n;
+    constexpr bool F32 = std::is_same<MAR_T, float>::value;
     const int64_t nvec = M * B / VEC;
     // vectors per thread: the requested depth when the grid still has >= 1024 workgroups
     int Q = upd_q == 2 || upd_q == 4 || upd_q == 8 ? upd_q : 4;
@@ -1398,8 +1445,10 @@ LaunchInfo launch_upd2<MAR_T>(int B, MAR_T* basis, int64_t M, int64_t stride, in
     // non-temporal slab loads once the slabs swept are well beyond the 256 MB last-level cache (a smaller basis
     // is served from it sweep after sweep); the small-grid depths (Q < 4) always load through the caches
     const bool nt = (double)(n + 2) * (double)(M * B) * sizeof(MAR_T) > kNtSweepBytes;
+#define MAR_UPD2_(QQ, WW, NTT, AA) \
+    MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_upd2<MAR_T, BB, QQ, WW, NTT, AA>), dim3(wgs), dim3(WG), 0, s, basis, stride, n, cA, cB, gam, Fn, y, wout, nvec))
 #define MAR_UPD2(QQ, WW, NTT) \
-    MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_upd2<MAR_T, BB, QQ, WW, NTT>), dim3(wgs), dim3(WG), 0, s, basis, stride, n, cA, cB, gam, Fn, y, wout, nvec))
+    if (F32 && acc64) { MAR_UPD2_(QQ, WW, NTT, F32); } else { MAR_UPD2_(QQ, WW, NTT, false); }
 #define MAR_UPD2W(QQ, NTT) \
     if (want_w) { MAR_UPD2(QQ, true, NTT); } else { MAR_UPD2(QQ, false, NTT); }
     if (Q == 8) { if (nt) { MAR_UPD2W(8, true) } else { MAR_UPD2W(8, false) } }
@@ -1408,6 +1457,7 @@ LaunchInfo launch_upd2<MAR_T>(int B, MAR_T* basis, int64_t M, int64_t stride, in
     else { MAR_UPD2W(1, false) }
 #undef MAR_UPD2W
 #undef MAR_UPD2
+#undef MAR_UPD2_
     LaunchInfo li;
     li.wgs = wgs;
     const double slabs_read = (double)n + (want_w ? 2.0 : 1.0), slabs_written = want_w ? 2.0 : 1.0;

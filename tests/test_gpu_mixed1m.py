@@ -4,25 +4,19 @@ sampled seeds (stored by tests/golden/make_mixed1m_oracle.py, which calls only t
 oracle; mu = -0.45 eV, kT = 0.1 eV).
 
 Bars: FP64 form 1e-10, FP32 form 1e-5, on rho (Frobenius norm over the listed
-rows), on the summed E, on every E_j and N_j (floors as in the other parity
-tests), and on every rho column in the FP64 form; nu_eff equal.
+rows and every listed rho column), on the summed E, on every E_j and N_j (floors
+as in the other parity tests); nu_eff equal.
 
-Every rho column in the FP32 form at 1e-5 is an expected failure here
-(xfail, strict): the columns of seeds 14 and 786929 reach 1.8e-5 and 1.4e-5,
-the others 5.4e-6 and below (the Frobenius norm, 7.4e-6, meets the bar). A numpy
-emulation of the textbook CGS2 with every step in FP32 arithmetic and FP32
-storage (the FP32 form) gives, seed by seed, 1.6e-5, 3.5e-6 and 1.9e-7 for
-seeds 14, 391606 and 656200, where the device gives 1.8e-5, 5.4e-6 and 2.7e-7.
-Keeping the steps in FP64 one at a time (seed 14) shows that the FP32 storage
-of the basis alone accounts for 9e-7 and the FP32 matrix values for 2e-8,
-while the FP32 sums do the rest (the sparse products' sums alone 1.5e-5, the
-updates alone 4.6e-6). Summing the device's sparse products in FP64 moved its
-Frobenius error only from 7.4e-6 to 6.5e-6, and solving the subspace problem
-against the Gram matrix of the FP32 basis summed in FP64 (A y = eps G y instead
-of assuming an S-orthonormal basis) leaves seed 14 at 1.62e-5, unchanged. So the
-FP32 form's own arithmetic,
-not a flaw of the device code, puts these columns above the bar at nu = 300
-on this lattice.
+At this size the FP32 form's update keeps its running sums over the slabs in
+FP64 (nu > 128). With FP32 sums the worst columns (seeds 14 and 786929) sat at
+1.7e-5 to 3.3e-5 over seven block sizes and projection variants, and the
+Frobenius norm at 5.7e-6 to 1.2e-5; with FP64 sums the same seven give a worst
+column of 4.8e-6 to 1.0e-5 and a Frobenius norm of 2.2e-6 to 4.2e-6 (9.55e-6 and
+4.2e-6 in the configuration tested here). The remaining error is that of the FP32
+basis and the FP32 sparse products and projections: a numpy emulation of the
+textbook CGS2 in FP32 puts seed 14 at 1.6e-5, of which FP32 storage alone is 9e-7,
+and a Rayleigh-Ritz step against the FP64 Gram matrix of the FP32 basis does not
+change it (the FP32 sums perturb the subspace itself).
 """
 import json
 import os
@@ -129,9 +123,6 @@ def test_mixed1m_fp32_batched(fp32_batched, golden):
     _check(golden, fp32_batched, "fp32", "batched B=64", columns=False)
 
 
-@pytest.mark.xfail(strict=True, reason="FP32 arithmetic of the FP32 form: the rho columns of two seeds reach 1.8e-5 "
-                                       "and 1.4e-5 at nu = 300 on this lattice (emulated seed by seed, e.g. 1.6e-5 "
-                                       "for the worst); see the module docstring")
 def test_mixed1m_fp32_batched_every_column(fp32_batched, golden):
     _check(golden, fp32_batched, "fp32", "batched B=64 per column", columns=True)
 

@@ -89,6 +89,25 @@ def test_support_projection_variants(sysm, ctx, variant):
     assert _rel(a.rho[idx], b.rho[idx]) <= TOL["fp32"]
 
 
+@pytest.mark.parametrize("support", [True, False])
+def test_fp32_update_fp64_sums_against_oracle(sysm, ctx, support):
+    """nu = 140 (> 128): the FP32 form's update keeps its running sums in FP64, over the tile list with support
+    tracking and over whole slabs without; every rho column, E_j and N_j against the oracle at 1e-5."""
+    seeds = np.arange(2500, 2500 + 40, dtype=np.int32)
+    ref = O.solve(sysm.H, sysm.S, seeds, 140, -0.3, KT, workers=max(1, min(16, O.default_workers())))
+    g = _solve(ctx, seeds, 140, "fp32", support, 64)
+    assert np.array_equal(g.nu_eff, ref.nu_eff)
+    worst = 0.0
+    for j in seeds:
+        lo, hi = sysm.H.indptr[j], sysm.H.indptr[j + 1]
+        worst = max(worst, _rel(g.rho[lo:hi], ref.rho[lo:hi]))
+    e_err = np.abs(g.e_seed - ref.e_seed) / np.maximum(np.abs(ref.e_seed), 1e-2 * np.abs(ref.e_seed).max())
+    n_err = np.abs(g.n_seed - ref.n_seed) / np.maximum(np.abs(ref.n_seed), 2e-2)
+    print(f"[fp64 update sums, support={support}] worst rho column {worst:.2e} E_j {e_err.max():.2e} "
+          f"N_j {n_err.max():.2e}", flush=True)
+    assert worst <= TOL["fp32"] and e_err.max() <= TOL["fp32"] and n_err.max() <= TOL["fp32"]
+
+
 @pytest.mark.parametrize("nu", [1, 2, 3])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_support_short_subspaces(sysm, ctx, prec, nu):
