@@ -108,6 +108,20 @@ def test_fp32_update_fp64_sums_against_oracle(sysm, ctx, support):
     assert worst <= TOL["fp32"] and e_err.max() <= TOL["fp32"] and n_err.max() <= TOL["fp32"]
 
 
+@pytest.mark.parametrize("B", [2, 4])
+def test_fp32_update_fp64_sums_narrow_blocks(sysm, ctx, B):
+    """The FP64 update sums with blocks narrower than a 16-byte vector (B = 2: whole-slab update, scalar
+    coefficient loads) and exactly one vector wide (B = 4), nu = 140, against the oracle per rho column."""
+    seeds = np.array([5, 900, 1801, 3333, 5000, 6911, 77], dtype=np.int32)   # ragged last block
+    ref = O.solve(sysm.H, sysm.S, seeds, 140, -0.3, KT, workers=max(1, min(16, O.default_workers())))
+    g = _solve(ctx, seeds, 140, "fp32", True, B)
+    assert np.array_equal(g.nu_eff, ref.nu_eff)
+    worst = max(_rel(g.rho[sysm.H.indptr[j]:sysm.H.indptr[j + 1]], ref.rho[sysm.H.indptr[j]:sysm.H.indptr[j + 1]])
+                for j in seeds)
+    print(f"[fp64 update sums, B={B}] worst rho column {worst:.2e}", flush=True)
+    assert worst <= TOL["fp32"]
+
+
 @pytest.mark.parametrize("nu", [1, 2, 3])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_support_short_subspaces(sysm, ctx, prec, nu):
