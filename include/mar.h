@@ -58,6 +58,12 @@ typedef enum {
     MAR_ERR_NOCONV = -7    /* the subspace eigensolve of some seed did not converge (nu_eff = -3) */
 } mar_status;
 
+/* MAR_FP64: every step in FP64.
+ * MAR_FP32: the Krylov basis is stored in FP32, and the sparse products and both Gram-Schmidt sweeps run in
+ * FP32 with FP32 sums in registers and FP64 partial sums across workgroups; in the delayed schedule with
+ * nu > 128 the update sweep keeps its running sums over the slabs in FP64 and rounds them once when stored.
+ * Coefficients, norms, breakdown tests, the subspace eigensolve, the Fermi weighting and the energy sums
+ * are FP64 in both. */
 typedef enum { MAR_FP64 = 0, MAR_FP32 = 1 } mar_precision;
 
 /* MAR_FORM_PLAIN: one seed at a time (B = 1), one kernel launch per phase.
