@@ -181,8 +181,8 @@ def test_library_on_the_gpu_box_is_built_from_these_sources():
 
 
 def test_design_boundary_table_names_every_declaration():
-    """The design doc's entry-point table (the boundary against the survey's proposal) lists exactly the header's
-    declarations, so that every departure from the proposed boundary is recorded."""
+    """The design notes' entry-point table (each entry point against the originally proposed boundary) lists
+    exactly the header's declarations, so that every departure from that boundary is recorded there."""
     text = open(os.path.join(ROOT, "DESIGN.md")).read()
     start = text.index("<!-- entry points: first column, one per row -->")
     rows = []
