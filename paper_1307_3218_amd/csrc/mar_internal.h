@@ -215,8 +215,9 @@ template <typename T>
 LaunchInfo launch_upd2(int B, T* basis, int64_t M, int64_t stride, int n, const T* cA, const T* cB,
                        const double* gam, const double* Fn, const T* y, T* wout, bool want_w, int upd_q,
                        hipStream_t s, bool acc64 = false);
-// Subspace dimension above which the FP32 form's update keeps its running sums in FP64 (at nu = 300 on the
-// 1048576-row lattice they halve the form's rho error against the oracle, at 0.7 % of the rate of nu = 100).
+// Subspace dimension above which the FP32 form's update keeps its running sums in FP64. At nu = 300 on the
+// 1048576-row lattice they halve the form's rho error against the oracle; switched on at nu = 100 on the
+// 131072-row lattice, where FP32 sums already meet the form's bar with room, they cost 0.7 % of the rate.
 constexpr int kUpdAcc64Nu = 128;
 // cAf/cBf (optional): the update coefficients rounded to FP32 for an FP32 basis.
 // redb (n >= 1): {u~.S u~ [B], u~.u~ [B]} of slab n; the kernel first takes the breakdown test of slab n and
