@@ -2,7 +2,9 @@
 and the components e_j^T phi_k of Eq. 3 with the inner-product sign method.
 
 At nu = M (every subspace is the whole space) the result must be the exact
-generalized eigenpair (LAPACK) up to one global sign; at nu < M it must match the
+generalized eigenpair (LAPACK) up to one global sign, the vector at the FP64 bar
+(the levels tested lie 0.5-9 % of the spectral scale from their neighbours, so two
+eigensolvers agree on the vector to about 1e-13); at nu < M it must match the
 eigen-state oracle (oracle/mar_eigenstate.py) on the same seeds, at the bars of the
 two forms (FP64 1e-10, FP32 1e-5): phi relative to its norm (up to one global sign),
 the level eps_k relative to the spectral scale max |eps|. The bisection points
@@ -40,10 +42,12 @@ def test_exact_state_at_nu_M(small, form, k):
     s, ev, V, ctx = small
     seeds = np.arange(s.M, dtype=np.int32)
     out = ctx.eigen_state(seeds, s.M, k, 1e-6, "fp64", form)
-    print(f"[es exact {form} k={k}] eps_k {out['eps_k']:.12f} exact {ev[k - 1]:.12f} ref {out['ref']}", flush=True)
+    err = _sign_free(out["phi"], V[:, k - 1])
+    print(f"[es exact {form} k={k}] eps_k {out['eps_k']:.12f} exact {ev[k - 1]:.12f} phi err {err:.2e} "
+          f"ref {out['ref']}", flush=True)
     assert abs(out["eps_k"] - ev[k - 1]) <= 1e-9
     assert out["eta_lo"] < out["eps_k"] < out["eta_hi"]
-    assert _sign_free(out["phi"], V[:, k - 1]) <= 1e-8
+    assert err <= 1e-10
 
 
 @pytest.fixture(scope="module")

@@ -36,7 +36,7 @@ def test_exact_level_and_vector_at_nu_M(small, k):
     assert ev[k - 2] < st.eta_lo < ev[k - 1] < st.eta_hi if k > 1 else st.eta_lo < ev[0] < st.eta_hi
     exact = V[:, k - 1]          # S-normalized by the solver
     err = min(np.linalg.norm(st.phi - exact), np.linalg.norm(st.phi + exact))
-    assert err <= 1e-8, err
+    assert err <= 1e-12, err
 
 
 def test_integrated_dos_counts_exact_levels(small):
@@ -112,5 +112,5 @@ def test_mutant_without_sign_method_misses_the_vector(small):
     good = ES.eigen_state(flipped, k, SIGMA)
     bad = ES.eigen_state(flipped, k, SIGMA, sign_method=False)
     err = lambda phi: min(np.linalg.norm(phi - exact), np.linalg.norm(phi + exact))
-    assert err(good.phi) <= 1e-8
+    assert err(good.phi) <= 1e-12
     assert err(bad.phi) > 0.1
