@@ -5,11 +5,12 @@ the smoke check and the bench's CPU-baseline leg may import or run it. It shares
 no code with the HIP library.
 
 What it restates (Sec. 3, Eq. 3, and the Appendix):
-  * the Green's function of all seeds gives the integrated density of states
+  * summed over all seeds, the projected Green's functions count the states
+    below an energy eta:
     n(eta) = sum_j sum_alpha w_alpha^(j) theta(eta - eps_alpha^(j)), with the
     weights w_alpha^(j) = (e_j^T S v_alpha^(j)) (v_alpha^(j)^T e_j) of the
-    projected Green's function, and its inverse eta(n);
-  * the k-th eigen level is eps_k = eta(k - 1/2) (k = 1, 2, ...);
+    projected Green's function; eta(n) inverts that count;
+  * level k (k = 1, 2, ...) sits where the count is k - 1/2: eps_k = eta(k - 1/2);
   * the j-th component of the k-th eigenvector is Eq. 3:
         e_j^T phi_k = sum_alpha (e_j^T v_alpha^(j)) int_{eta(k-1)}^{eta(k)} d(eps - eps_alpha^(j)) deps
     with d a smoothed delta function;
