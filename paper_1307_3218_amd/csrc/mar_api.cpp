@@ -672,6 +672,12 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     // tracking on, the products and the update then run over the support list (a small grid of kListWgs
     // workgroups in a grid-stride loop) instead of a workgroup per row tile of the whole cell.
     const bool local = c->loc >= 0 && dual;
+    // Variant 0 loads the basis non-temporally when the solve's widest sweep (nu + 3 slabs) exceeds the
+    // last-level cache: each slab is read once per sweep, and cached loads would only displace the lines
+    // that are reused (the right-hand sides, the vectors just written). Decided once per solve, so that
+    // every projection of a solve runs one kernel; variant 2's instance has the same tile shape, plan and
+    // grid. Local regions sweep few tiles, which stay cached.
+    const int pvar = variant == 0 && !local && (double)(nu + 3) * (double)slab > mar::kNtSweepBytes ? 2 : variant;
     // grid of the list kernels (local regions): each workgroup also leaves a row of S-norm partials, so small
     // regions run best on few workgroups (512: +2-7 % against 2048 at 4-10 hops, equal at 16, -2 % at 24)
     const int64_t kListWgs = c->loc >= 0 && c->loc <= 16 ? 512 : 2048;
@@ -941,7 +947,7 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
                 int32_t* plan_n = splan + (int64_t)n * pstride;
                 const bool rp = launch(c, s, P_PROJR, [&] {
                     return mar::launch_projr_sp<T>(B, K, M, stride, n, ZT, SY, Y, slist, scnt, plan_n, grid, part,
-                                                   part_cap, variant, s);
+                                                   part_cap, pvar, s);
                 });
                 tag(rp, SP_PROJR, n, bi, (double)ntiles);
                 launch(c, s, P_REDUCE, [&] { return mar::launch_reduce_sp(part, plan_n, grid, kg, nk, B, red, s); });
@@ -953,7 +959,7 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
                 int64_t ngroups = 0;
                 launch(c, s, P_PROJR, [&] {
                     return mar::launch_projr<T>(B, K, M, stride, nk, ZT, SY, Y, part, part_cap, &ngroups, target,
-                                                variant, s);
+                                                pvar, s);
                 });
                 const int64_t L = (int64_t)3 * nk * B;
                 launch(c, s, P_REDUCE, [&] { return mar::launch_reduce(part, ngroups, L, red, nullptr, B, nu, n, s); });

@@ -28,6 +28,17 @@ __device__ __forceinline__ void unpack_nt(const double2* p, double (&a)[2]) {
     a[0] = v.x; a[1] = v.y;
 }
 
+// Non-temporal 16-byte stores: results that only later kernels read, kept from displacing the lines
+// that the storing kernel still reuses from L2.
+__device__ __forceinline__ void store_nt(float4* p, const float (&a)[4]) {
+    const nf4 v = {a[0], a[1], a[2], a[3]};
+    __builtin_nontemporal_store(v, reinterpret_cast<nf4*>(p));
+}
+__device__ __forceinline__ void store_nt(double2* p, const double (&a)[2]) {
+    const nd2 v = {a[0], a[1]};
+    __builtin_nontemporal_store(v, reinterpret_cast<nd2*>(p));
+}
+
 // Seed-interleaved vectors: element e of an [M][B] array belongs to row e / B
 // and seed e % B. A lane owns one 16-byte vector of VEC elements:
 //   B >= VEC: the vector covers seeds (lane_vector_index % P) * VEC + [0, VEC),

@@ -164,9 +164,10 @@ __global__ __launch_bounds__(WG) void k_spmm_bsr4(int64_t nbrow, const int32_t* 
             // neighbours may lie in tiles no sweep of this seed block has written)
             spmm_row_vec<T, B, CH>(Iu, s0, brp, bcol, bval, Xv, acc, rdist != nullptr && rdist[Iu] > lim);
             if (mask != nullptr) region_mask<T, SW>(mask, W, Iu, s0, acc);   // local regions
+            // non-temporal: later kernels read Y; this one reuses X (neighbour rows) from L2
             VT* Yv = reinterpret_cast<VT*>(Y);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) Yv[((4 * Iu + r) * B + s0) / VEC] = pack(acc[r]);
+            for (int r = 0; r < 4; ++r) store_nt(Yv + ((4 * Iu + r) * B + s0) / VEC, acc[r]);
         }
     } else if (I < nbrow) {
         const int lo = brp[I], hi = brp[I + 1];
@@ -246,9 +247,11 @@ __global__ __launch_bounds__(WG) void k_spmm_bsr4(int64_t nbrow, const int32_t* 
 }
 
 // Block row Iu of Y = H X and Z = S X for the seeds s0 .. s0 + VEC - 1,
-// masked to the seeds' regions when mask != nullptr, stored; the S-norm
-// partials X.(S X) and X.X of the row are added to d (NDOT > 0).
-template <typename T, int B, int NDOT>
+// masked to the seeds' regions when mask != nullptr, stored (non-temporally
+// when NTS: a whole-cell sweep, whose X rows are worth keeping in L2 rather
+// than the results); the S-norm partials X.(S X) and X.X of the row are added
+// to d (NDOT > 0).
+template <typename T, int B, int NDOT, bool NTS>
 __device__ __forceinline__ void spmm2_row(int64_t Iu, int s0, const int32_t* __restrict__ brp,
                                           const int32_t* __restrict__ bcol, const T* __restrict__ hval,
                                           const T* __restrict__ sval, const typename Vec16<T>::type* __restrict__ Xv,
@@ -322,8 +325,13 @@ __device__ __forceinline__ void spmm2_row(int64_t Iu, int s0, const int32_t* __r
     VT* Zv = reinterpret_cast<VT*>(Z);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        Yv[((4 * Iu + r) * B + s0) / VEC] = pack(ah[r]);
-        Zv[((4 * Iu + r) * B + s0) / VEC] = pack(as[r]);
+        if constexpr (NTS) {
+            store_nt(Yv + ((4 * Iu + r) * B + s0) / VEC, ah[r]);
+            store_nt(Zv + ((4 * Iu + r) * B + s0) / VEC, as[r]);
+        } else {
+            Yv[((4 * Iu + r) * B + s0) / VEC] = pack(ah[r]);
+            Zv[((4 * Iu + r) * B + s0) / VEC] = pack(as[r]);
+        }
     }
     if constexpr (NDOT > 0) {
 #pragma unroll
@@ -372,8 +380,8 @@ __global__ __launch_bounds__(WG) void k_spmm2_bsr4(int64_t nbrow, const int32_t*
     int64_t Iu = (bid * WG + threadIdx.x) / P;
     if constexpr (P == 64) Iu = __builtin_amdgcn_readfirstlane((int)Iu);   // one row per wavefront
     if (Iu < nbrow)
-        spmm2_row<T, B, NDOT>(Iu, s0, brp, bcol, hval, sval, Xv, Y, Z, mask, W, d,
-                              rdist != nullptr && rdist[Iu] > lim);
+        spmm2_row<T, B, NDOT, true>(Iu, s0, brp, bcol, hval, sval, Xv, Y, Z, mask, W, d,
+                                    rdist != nullptr && rdist[Iu] > lim);
     if constexpr (NDOT > 0) {
         __shared__ double lds[SeedReduce<P, SW, NDOT>::LDS];
         wg_seed_reduce<P, SW, NDOT>(d, lds, [&](int v, int b, double sdot) { part[(bid * NDOT + v) * B + b] = sdot; });
@@ -404,7 +412,7 @@ __global__ __launch_bounds__(WG) void k_spmm2_list(int64_t nbrow, const int32_t*
     for (int64_t e = blockIdx.x; e < ce; e += gridDim.x) {
         int64_t Iu = ((int64_t)list[e] * WG + threadIdx.x) / P;
         if constexpr (P == 64) Iu = __builtin_amdgcn_readfirstlane((int)Iu);
-        if (Iu < nbrow) spmm2_row<T, B, NDOT>(Iu, s0, brp, bcol, hval, sval, Xv, Y, Z, mask, W, d);
+        if (Iu < nbrow) spmm2_row<T, B, NDOT, false>(Iu, s0, brp, bcol, hval, sval, Xv, Y, Z, mask, W, d);
     }
     if constexpr (NDOT > 0) {
         __shared__ double lds[SeedReduce<P, SW, NDOT>::LDS];
@@ -999,8 +1007,13 @@ __device__ __forceinline__ void upd2_body(int64_t vbase, int kst, T* __restrict_
             ou[i] = (T)au[q][i];
             ow[i] = (T)aw[q][i];
         }
-        bv[(int64_t)n * slabv + q * WG] = pack(ou);
-        if constexpr (WANT_W) wv[q * WG] = pack(ow);
+        if constexpr (NT) {   // a sweep beyond the last-level cache: the results too bypass it
+            store_nt(bv + (int64_t)n * slabv + q * WG, ou);
+            if constexpr (WANT_W) store_nt(wv + q * WG, ow);
+        } else {
+            bv[(int64_t)n * slabv + q * WG] = pack(ou);
+            if constexpr (WANT_W) wv[q * WG] = pack(ow);
+        }
     }
 }
 
