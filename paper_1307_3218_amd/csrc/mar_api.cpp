@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -260,6 +261,16 @@ mar_status build_devmat(mar_ctx* c, int64_t M, const int64_t* rp, const int32_t*
         D.bsr = true;
         D.n = nb;
         D.nnz = nblk;
+        std::vector<int64_t> off;
+        off.reserve((size_t)nblk);
+        for (int64_t I = 0; I < nb; ++I)
+            for (int64_t b = brp[I]; b < brp[I + 1]; ++b)
+                if (bcol[b] != I) off.push_back(std::llabs((int64_t)bcol[b] - I));
+        if (!off.empty()) {
+            auto q = off.begin() + (ptrdiff_t)(off.size() * 9 / 10);
+            std::nth_element(off.begin(), q, off.end());
+            D.span = *q;
+        }
         if ((st = upload(c, &D.ptr, brp.data(), brp.size())) != MAR_OK) return st;
         if ((st = upload(c, &D.idx, bcol.data(), bcol.size())) != MAR_OK) return st;
         if ((st = upload(c, &D.v64, v64.data(), v64.size())) != MAR_OK) return st;

@@ -62,6 +62,17 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t n) {
     return x * per + (x < rem ? x : rem) + local;
 }
 
+// Chunk-interleaved order: the dispatcher deals workgroup ids round-robin over the 8 XCDs, and XCD x takes
+// the x-th chunk of each run of 8 chunks of `chunk` consecutive tiles, in order. When a run of 8 chunks
+// spans the distance to a row's far neighbours (the next plane of cells of a lattice), those neighbours
+// were read by the same XCD one chunk earlier instead of a whole contiguous range away. Bijective on
+// [0, 8 * chunk * k); ids past the real tiles are skipped by the caller.
+__device__ __forceinline__ int64_t xcd_chunk(int64_t bid, int64_t chunk) {
+    constexpr int NX = 8;
+    const int64_t x = bid % NX, l = bid / NX;
+    return ((l / chunk) * NX + x) * chunk + l % chunk;
+}
+
 // Workgroup reduction of per-seed partial sums (fixed order, deterministic).
 // Thread t holds vals[v][i] for seed (t % P) * SW + i. For every v and every
 // seed b in [0, P*SW) the sum over the workgroup's 256 threads is passed to

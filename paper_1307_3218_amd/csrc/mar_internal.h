@@ -58,10 +58,19 @@ struct DevMat {
     int32_t* idx = nullptr; // nnz
     double* v64 = nullptr;  // nnz * (bsr ? 16 : 1)
     float* v32 = nullptr;
+    int64_t span = 0;       // BSR: 90th percentile of |I - J| over the off-diagonal blocks (in a lattice, the
+                            // distance to the neighbours in the next plane of cells; periodic wraps excluded)
     double bytes_per_pass(size_t p) const {  // values + indices read once
         return (double)nnz * ((bsr ? 16.0 : 1.0) * (double)p + 4.0) + (double)(n + 1) * 4.0;
     }
 };
+
+// Row tiles per chunk of the whole-cell block products' chunk-interleaved order (see xcd_chunk): 8 chunks
+// span the matrix's typical far-neighbour distance; 0 (contiguous ranges per XCD) below 4 tiles.
+inline int64_t spmm_chunk(int64_t span, int64_t tile_rows) {
+    const int64_t c = span / (8 * tile_rows);
+    return c >= 4 ? c : 0;
+}
 
 // Pointers of one seed block's device workspace.
 template <typename T>

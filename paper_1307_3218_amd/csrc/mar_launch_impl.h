@@ -135,11 +135,12 @@ __global__ __launch_bounds__(WG) void k_spmm_bsr4(int64_t nbrow, const int32_t* 
                                                   const T* __restrict__ X, T* __restrict__ Y,
                                                   double* __restrict__ part, const int32_t* __restrict__ tdist,
                                                   int lim, const uint32_t* __restrict__ mask, int W,
-                                                  const int32_t* __restrict__ rdist) {
+                                                  const int32_t* __restrict__ rdist, int64_t ntile, int64_t chunk) {
     using SM = SeedMap<T, B>;
     constexpr int VEC = SM::VEC, SW = SM::SW, P = SM::P;
     using VT = typename Vec16<T>::type;
-    const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t bid = chunk > 0 ? xcd_chunk(blockIdx.x, chunk) : xcd_remap(blockIdx.x, gridDim.x);
+    if (bid >= ntile) return;
     if (tdist != nullptr && tdist[bid] > lim) {   // a tile outside the support (B >= VEC: one tile per workgroup)
         if constexpr (NDOT > 0)
             for (int i = threadIdx.x; i < NDOT * B; i += WG) part[bid * NDOT * B + i] = 0.0;
@@ -359,12 +360,14 @@ __global__ __launch_bounds__(WG) void k_spmm2_bsr4(int64_t nbrow, const int32_t*
                                                    T* __restrict__ Y, T* __restrict__ Z, double* __restrict__ part,
                                                    const int32_t* __restrict__ tdist, int lim,
                                                    const uint32_t* __restrict__ mask, int W,
-                                                   const int32_t* __restrict__ rdist) {
+                                                   const int32_t* __restrict__ rdist, int64_t ntile,
+                                                   int64_t chunk) {
     using SM = SeedMap<T, B>;
     constexpr int VEC = SM::VEC, SW = SM::SW, P = SM::P;
     static_assert(B >= VEC, "dual product needs one seed group per lane");
     using VT = typename Vec16<T>::type;
-    const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t bid = chunk > 0 ? xcd_chunk(blockIdx.x, chunk) : xcd_remap(blockIdx.x, gridDim.x);
+    if (bid >= ntile) return;
     if (tdist != nullptr && tdist[bid] > lim) {   // a tile outside the support
         if constexpr (NDOT > 0)
             for (int i = threadIdx.x; i < NDOT * B; i += WG) part[bid * NDOT * B + i] = 0.0;
@@ -1139,8 +1142,11 @@ LaunchInfo launch_spmm<MAR_T>(int B, const DevMat& A, const MAR_T* X, MAR_T* Y, 
     const MAR_T* val = std::is_same<MAR_T, float>::value ? (const MAR_T*)A.v32 : (const MAR_T*)A.v64;
 #define MAR_SPMM_LAUNCH(KERNEL, ND) \
     MAR_DISPATCH_B(B, hipLaunchKernelGGL((KERNEL<MAR_T, BB, ND>), dim3(wgs), dim3(WG), 0, s, A.n, A.ptr, A.idx, val, X, Y, part))
+    // whole-cell products: chunk-interleaved tile order when the pattern's far neighbours are far enough
+    const int64_t chunk = A.bsr ? spmm_chunk(A.span, WG / P) : 0;
+    const int64_t grid = chunk > 0 ? (wgs + 8 * chunk - 1) / (8 * chunk) * (8 * chunk) : wgs;
 #define MAR_SPMM_BSR(ND) \
-    MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_spmm_bsr4<MAR_T, BB, ND>), dim3(wgs), dim3(WG), 0, s, A.n, A.ptr, A.idx, val, X, Y, part, tdist, lim, mask, W, rdist))
+    MAR_DISPATCH_B(B, hipLaunchKernelGGL((k_spmm_bsr4<MAR_T, BB, ND>), dim3((unsigned)grid), dim3(WG), 0, s, A.n, A.ptr, A.idx, val, X, Y, part, tdist, lim, mask, W, rdist, wgs, chunk))
     if (A.bsr) {
         if (ndot == 2) { MAR_SPMM_BSR(2); }
         else if (ndot == 1) { MAR_SPMM_BSR(1); }
@@ -1179,8 +1185,10 @@ LaunchInfo launch_spmm2<MAR_T>(int B, const DevMat& H, const DevMat& SH, const M
     const bool f32 = std::is_same<MAR_T, float>::value;
     const MAR_T* hv = f32 ? (const MAR_T*)H.v32 : (const MAR_T*)H.v64;
     const MAR_T* sv = f32 ? (const MAR_T*)SH.v32 : (const MAR_T*)SH.v64;
+    const int64_t chunk = spmm_chunk(H.span, WG / P);
+    const int64_t grid = chunk > 0 ? (wgs + 8 * chunk - 1) / (8 * chunk) * (8 * chunk) : wgs;
 #define MAR_SPMM2(ND) \
-    MAR_DISPATCH_B(B, if constexpr (BB >= VEC) hipLaunchKernelGGL((k_spmm2_bsr4<MAR_T, BB, ND>), dim3(wgs), dim3(WG), 0, s, H.n, H.ptr, H.idx, hv, sv, X, Y, Z, part, tdist, lim, mask, W, rdist))
+    MAR_DISPATCH_B(B, if constexpr (BB >= VEC) hipLaunchKernelGGL((k_spmm2_bsr4<MAR_T, BB, ND>), dim3((unsigned)grid), dim3(WG), 0, s, H.n, H.ptr, H.idx, hv, sv, X, Y, Z, part, tdist, lim, mask, W, rdist, wgs, chunk))
     if (ndot == 2) { MAR_SPMM2(2); }
     else if (ndot == 1) { MAR_SPMM2(1); }
     else { MAR_SPMM2(0); }
