@@ -666,9 +666,6 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     const int64_t M = (c->M + 3) / 4 * 4;
     const int64_t nvec = M * B / VEC;
     const int P = B < VEC ? 1 : B / VEC;
-    // default projection grid: the workgroups the device holds at once (one round, few partial sums)
-    const int64_t target = c->tune.proj_wgs > 0 ? (int64_t)c->tune.proj_wgs
-                                                 : (int64_t)projr_occupancy<T>(c, B, variant) * c->n_cu;
     const int64_t spmm_wgs = std::max((c->S.n * P + mar::WG - 1) / mar::WG, (c->H.n * P + mar::WG - 1) / mar::WG);
     const size_t slab = (size_t)M * B * sizeof(T);
     const int64_t stride = slab_stride(c, M, B, sizeof(T));
@@ -686,9 +683,12 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     // Variant 0 loads the basis non-temporally when the solve's widest sweep (nu + 3 slabs) exceeds the
     // last-level cache: each slab is read once per sweep, and cached loads would only displace the lines
     // that are reused (the right-hand sides, the vectors just written). Decided once per solve, so that
-    // every projection of a solve runs one kernel; variant 2's instance has the same tile shape, plan and
-    // grid. Local regions sweep few tiles, which stay cached.
+    // every projection of a solve runs one kernel; variant 2's instance has the same tile shape and plan.
+    // Local regions sweep few tiles, which stay cached.
     const int pvar = variant == 0 && !local && (double)(nu + 3) * (double)slab > mar::kNtSweepBytes ? 2 : variant;
+    // default projection grid: the workgroups the device holds at once (one round, few partial sums)
+    const int64_t target = c->tune.proj_wgs > 0 ? (int64_t)c->tune.proj_wgs
+                                                 : (int64_t)projr_occupancy<T>(c, B, pvar) * c->n_cu;
     // grid of the list kernels (local regions): each workgroup also leaves a row of S-norm partials, so small
     // regions run best on few workgroups (512: +2-7 % against 2048 at 4-10 hops, equal at 16, -2 % at 24)
     const int64_t kListWgs = c->loc >= 0 && c->loc <= 16 ? 512 : 2048;

@@ -804,13 +804,30 @@ __global__ __launch_bounds__(WG) void k_projr_sp(const T* __restrict__ basis, in
         for (int kk = 0; kk < KG; ++kk)
 #pragma unroll
             for (int i = 0; i < VEC; ++i) raw[r][kk][i] = (T)0;
+    // Slab k0 + kk can be nonzero only on the first cnt[k0 + kk] entries of the distance-sorted list. With
+    // the basis streamed from HBM (NT), on the later entries of the chunk it reads slab k0 + nkl - 1 again
+    // (whose lines are loaded in the same step: no further HBM traffic) and multiplies by +0, the value
+    // those rows hold. Cached sweeps fit the last-level cache and read the chunk's slabs on all its entries.
+    int64_t klim[KG];
+    bool act[KG];
     int koff[KG];
 #pragma unroll
-    for (int kk = 0; kk < KG; ++kk) koff[kk] = kk < nkl ? kk : nkl - 1;
+    for (int kk = 0; kk < KG; ++kk) {
+        klim[kk] = kk < nkl ? cnt[k0 + kk] : 0;
+        act[kk] = true;
+        koff[kk] = kk < nkl ? kk : nkl - 1;
+    }
     // the next tile's index is fetched one tile ahead, so its loads need not wait for it
     int64_t t = e0 < e1 ? list[e0] : 0;
     for (int64_t e = e0; e < e1; ++e) {
         const int64_t tn = e + 1 < e1 ? list[e + 1] : 0;
+        if constexpr (NT) {
+#pragma unroll
+            for (int kk = 0; kk < KG; ++kk) {
+                act[kk] = e < klim[kk];
+                koff[kk] = act[kk] ? kk : nkl - 1;
+            }
+        }
 #pragma unroll
         for (int sub = 0; sub < SUB; ++sub) {
             const int64_t tbase = t * (int64_t)(4 * WG) + (int64_t)sub * (WG * Q);
@@ -831,6 +848,10 @@ __global__ __launch_bounds__(WG) void k_projr_sp(const T* __restrict__ basis, in
                 for (int kk = 0; kk < KG; ++kk) {
                     if constexpr (NT) unpack_nt(bv + (int64_t)koff[kk] * slabv + vs, a[kk]);
                     else unpack(bv[(int64_t)koff[kk] * slabv + vs], a[kk]);
+                    if constexpr (NT) {
+#pragma unroll
+                        for (int i = 0; i < VEC; ++i) a[kk][i] = act[kk] ? a[kk][i] : (T)0;
+                    }
                 }
 #pragma unroll
                 for (int kk = 0; kk < KG; ++kk)
