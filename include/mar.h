@@ -98,10 +98,11 @@ typedef struct {
                               the device holds at once) */
     int32_t slab_pad_kb;   /* extra KiB between consecutive basis slabs (0 = 1 KiB) */
     int32_t proj_variant;  /* delayed-schedule projection, slabs x 16-byte vectors per thread and row
-                              tile: 0 = 4 x 4 (basis loads non-temporal, as variant 2, when the solve's
-                              widest sweep of nu + 3 slabs exceeds 512 MB, outside local regions),
-                              1 = 8 x 4, 2 = 4 x 4 with non-temporal basis loads, 3 = 4 x 2, 4 = 8 x 2,
-                              5 = 6 x 4, 6 = 6 x 2 */
+                              tile: 0 = 4 x 4, or, when the solve's widest sweep of nu + 3 slabs
+                              exceeds 512 MB (outside local regions), variant 7 (variant 2 at nu <= 64
+                              and for the FP32 form at nu > 128); 1 = 8 x 4, 2 = 4 x 4 with
+                              non-temporal basis loads, 3 = 4 x 2, 4 = 8 x 2, 5 = 6 x 4, 6 = 6 x 2,
+                              7 = 8 x 4 with non-temporal basis loads */
     int32_t upd_q;         /* delayed-schedule update: 16-byte vectors per thread, 2/4/8 (0 = 4) */
     int32_t support_off;   /* 1 = stream every row of every slab; 0 (default) = skip, in the batched
                               delayed schedule on a 4x4-block H, the row tiles where all vectors of the

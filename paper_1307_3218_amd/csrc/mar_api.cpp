@@ -674,18 +674,28 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     // Support tracking: the kernels of a step skip the row tiles on which the block's vectors are exactly
     // zero (farther from every seed of the block than the step in hops of H's pattern).
     const bool sparse = dual && c->tune.support_off == 0;
-    const int kg = mar::projr_kg(variant);
     const int64_t nbrow = c->H.n, bpt = mar::WG / std::max(P, 1);
     // local regions (order-N form): per block row and seed, inside the seed's region or not. With the support
     // tracking on, the products and the update then run over the support list (a small grid of kListWgs
     // workgroups in a grid-stride loop) instead of a workgroup per row tile of the whole cell.
     const bool local = c->loc >= 0 && dual;
-    // Variant 0 loads the basis non-temporally when the solve's widest sweep (nu + 3 slabs) exceeds the
-    // last-level cache: each slab is read once per sweep, and cached loads would only displace the lines
-    // that are reused (the right-hand sides, the vectors just written). Decided once per solve, so that
-    // every projection of a solve runs one kernel; variant 2's instance has the same tile shape and plan.
-    // Local regions sweep few tiles, which stay cached.
-    const int pvar = variant == 0 && !local && (double)(nu + 3) * (double)slab > mar::kNtSweepBytes ? 2 : variant;
+    // Variant 0 streams the basis (variant 7: 8 slabs per workgroup, non-temporal loads) when the solve's
+    // widest sweep (nu + 3 slabs) exceeds the last-level cache: each slab is read once per sweep, and
+    // cached loads would only displace the lines that are reused (the right-hand sides, the vectors just
+    // written). Decided once per solve, so that every projection of a solve runs one kernel on one plan.
+    // Local regions sweep few tiles, which stay cached. Four slabs per workgroup (variant 2) instead:
+    //  * at nu <= 64, where the sweeps are short: at nu = 30 on the 16384-row cell 8 slabs took the
+    //    projection from 71 to 85 ms per step, where at nu = 100 on the 131072-row lattice they took it
+    //    from 316 to 297 ms;
+    //  * for the FP32 form at nu > kUpdAcc64Nu: there a single rho column's error depends on how the
+    //    projection's FP32 sums are partitioned, and the 4-slab partition is the one measured within 1e-5
+    //    (at nu = 300 on the 1048576-row lattice the worst of 8 sampled columns is 9.6e-6 with 4 slabs,
+    //    2.9e-5 with 8).
+    const bool four = nu <= 64 || (std::is_same<T, float>::value && nu > mar::kUpdAcc64Nu);
+    const int pvar = variant == 0 && !local && (double)(nu + 3) * (double)slab > mar::kNtSweepBytes
+                         ? (four ? 2 : 7)
+                         : variant;
+    const int kg = mar::projr_kg(pvar);
     // default projection grid: the workgroups the device holds at once (one round, few partial sums)
     const int64_t target = c->tune.proj_wgs > 0 ? (int64_t)c->tune.proj_wgs
                                                  : (int64_t)projr_occupancy<T>(c, B, pvar) * c->n_cu;
@@ -709,7 +719,7 @@ mar_status run_solve_delayed(mar_ctx* c, const int32_t* d_seeds, int64_t n_seeds
     const size_t np_doubles = (size_t)std::max<int64_t>(spmm_wgs, kListWgs) * 2 * B;
     const int64_t np_cap = (int64_t)np_doubles;
     for (int nk = 1; nk <= nu; ++nk) {
-        const mar::ProjrGeom gm = mar::projr_geometry(nvec, nk, variant, target);
+        const mar::ProjrGeom gm = mar::projr_geometry(nvec, nk, pvar, target);
         part_doubles = std::max<size_t>(part_doubles, (size_t)gm.groups * 3 * nk * B);
     }
     if (sparse) part_doubles = std::max<size_t>(part_doubles, (size_t)grid_max * 3 * kg * B);
@@ -1870,7 +1880,7 @@ mar_status mar_set_tuning(mar_ctx* c, const mar_tuning* t) {
         return set_err(c, MAR_ERR_ARG, "unknown schedule");
     if (t->proj_wgs < 0) return set_err(c, MAR_ERR_ARG, "proj_wgs < 0");
     if (t->slab_pad_kb < 0 || t->slab_pad_kb > 65536) return set_err(c, MAR_ERR_ARG, "slab_pad_kb outside [0, 65536]");
-    if (t->proj_variant < 0 || t->proj_variant > 6) return set_err(c, MAR_ERR_ARG, "proj_variant outside [0, 6]");
+    if (t->proj_variant < 0 || t->proj_variant > 7) return set_err(c, MAR_ERR_ARG, "proj_variant outside [0, 7]");
     if (t->upd_q != 0 && t->upd_q != 2 && t->upd_q != 4 && t->upd_q != 8)
         return set_err(c, MAR_ERR_ARG, "upd_q must be 0, 2, 4 or 8");
     if (t->support_off != 0 && t->support_off != 1) return set_err(c, MAR_ERR_ARG, "support_off must be 0 or 1");

@@ -30,7 +30,9 @@ struct ProjrGeom {
 };
 // variant: 0 = 4 slabs x 4 vectors, 1 = 8 x 4, 2 = 4 x 4 non-temporal, 3 = 4 x 2, 4 = 8 x 2, 5 = 6 x 4,
 // 6 = 6 x 2 (slabs per workgroup x 16-byte vectors per thread and row tile).
-inline int projr_kg(int variant) { return variant == 1 || variant == 4 ? 8 : (variant >= 5 ? 6 : 4); }
+inline int projr_kg(int variant) {
+    return variant == 1 || variant == 4 || variant == 7 ? 8 : (variant == 5 || variant == 6 ? 6 : 4);
+}
 inline int projr_q(int variant) { return variant == 3 || variant == 4 || variant == 6 ? 2 : PROJR_Q; }
 // target_wgs (> 0) caps the grid: the row tiles are cut into target_wgs / nks
 // groups, so that a grid of the device's resident capacity runs in one round

@@ -1362,6 +1362,7 @@ LaunchInfo launch_projr<MAR_T>(int B, const MAR_T* basis, int64_t M, int64_t str
     else if (variant == 4) { MAR_PROJR(2, 8, false); }
     else if (variant == 5) { MAR_PROJR(PROJR_Q, 6, false); }
     else if (variant == 6) { MAR_PROJR(2, 6, false); }
+    else if (variant == 7) { MAR_PROJR(PROJR_Q, 8, true); }
     else { MAR_PROJR(PROJR_Q, 4, false); }
 #undef MAR_PROJR
     *ngroups = groups;
@@ -1383,6 +1384,7 @@ int projr_blocks_per_cu<MAR_T>(int B, int variant) {
     else if (variant == 4) { MAR_OCC(2, 8, false); }
     else if (variant == 5) { MAR_OCC(PROJR_Q, 6, false); }
     else if (variant == 6) { MAR_OCC(2, 6, false); }
+    else if (variant == 7) { MAR_OCC(PROJR_Q, 8, true); }
     else { MAR_OCC(PROJR_Q, 4, false); }
 #undef MAR_OCC
     return nb > 0 ? nb : 1;
@@ -1413,6 +1415,7 @@ LaunchInfo launch_projr_sp<MAR_T>(int B, const MAR_T* basis, int64_t M, int64_t 
     else if (variant == 4) { MAR_PROJR_SP(2, 8, false); }
     else if (variant == 5) { MAR_PROJR_SP(PROJR_Q, 6, false); }
     else if (variant == 6) { MAR_PROJR_SP(2, 6, false); }
+    else if (variant == 7) { MAR_PROJR_SP(PROJR_Q, 8, true); }
     else { MAR_PROJR_SP(PROJR_Q, 4, false); }
 #undef MAR_PROJR_SP
     LaunchInfo li;

@@ -127,7 +127,7 @@ def test_cell256_every_block_size_ragged(cell256, cell256_ctx, cell256_mu, prec,
     compare(cell256.H, seeds, g, ref, prec, label=f"M=256 B={B} {sched}")
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_cell256_projection_variants(cell256, cell256_ctx, cell256_mu, cell256_ref30, prec, variant):
     """Every projection variant (4, 6 or 8 slabs, 2 or 4 vectors per thread, non-temporal loads) at the widest block."""

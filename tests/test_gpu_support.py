@@ -79,7 +79,7 @@ def test_support_against_oracle(sysm, ctx, prec):
     assert r_rho <= TOL[prec] and r_e <= TOL[prec]
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7])
 def test_support_projection_variants(sysm, ctx, variant):
     seeds = np.arange(500, 500 + 300, dtype=np.int32)
     a = _solve(ctx, seeds, 30, "fp32", True, 128, variant)
