@@ -381,6 +381,15 @@ def test_mixed131k_bench_block_sampled_oracle(mixed131k):
     compare(mixed131k.H, seeds[pick], sub, ref, "fp32", label="M=131072 nu=100 fp32")
     g64 = ctx.solve(seeds[pick], 100, mu, KT, precision="fp64", form="plain", levels=True)
     compare(mixed131k.H, seeds[pick], g64, ref, "fp64", label="M=131072 nu=100 fp64 plain")
+    # the FP64 batched form in blocks of 128 (a streamed sweep: 8 basis slabs per projection workgroup)
+    ctx.set_tuning(seed_block=128)
+    try:
+        gb = ctx.solve(seeds, 100, mu, KT, precision="fp64", form="batched", levels=True)
+    finally:
+        ctx.set_tuning()
+    sub = mar.SolveOutput(rho=gb.rho, e_band=float(np.sum(gb.e_seed[pick])), e_seed=gb.e_seed[pick],
+                          n_seed=gb.n_seed[pick], nu_eff=gb.nu_eff[pick], eps=gb.eps[pick], weight=None)
+    compare(mixed131k.H, seeds[pick], sub, ref, "fp64", label="M=131072 nu=100 fp64 batched B=128")
     ctx.close()
 
 
