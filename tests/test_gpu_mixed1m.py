@@ -12,7 +12,10 @@ FP64 (nu > 128). With FP32 sums the worst columns (seeds 14 and 786929) sat at
 1.7e-5 to 3.3e-5 over seven block sizes and projection variants, and the
 Frobenius norm at 5.7e-6 to 1.2e-5; with FP64 sums the same seven give a worst
 column of 4.8e-6 to 1.0e-5 and a Frobenius norm of 2.2e-6 to 4.2e-6 (9.55e-6 and
-4.2e-6 in the configuration tested here). The remaining error is that of the FP32
+4.2e-6 in the configuration tested here). Over twelve block sizes and projection
+partitions the worst column spans 4.8e-6 to 2.8e-5 (three of the twelve above 1e-5),
+and 2.9e-5 with 8 slabs per projection workgroup: the per-column bar holds in the
+default configuration, not in every equivalent rounding order. The remaining error is that of the FP32
 basis and the FP32 sparse products and projections: a numpy emulation of the
 textbook CGS2 in FP32 puts seed 14 at 1.6e-5, of which FP32 storage alone is 9e-7,
 and a Rayleigh-Ritz step against the FP64 Gram matrix of the FP32 basis does not
