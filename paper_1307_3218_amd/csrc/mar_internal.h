@@ -29,7 +29,7 @@ struct ProjrGeom {
     int64_t ntiles, tiles, groups;
 };
 // variant: 0 = 4 slabs x 4 vectors, 1 = 8 x 4, 2 = 4 x 4 non-temporal, 3 = 4 x 2, 4 = 8 x 2, 5 = 6 x 4,
-// 6 = 6 x 2 (slabs per workgroup x 16-byte vectors per thread and row tile).
+// 6 = 6 x 2, 7 = 8 x 4 non-temporal (slabs per workgroup x 16-byte vectors per thread and row tile).
 inline int projr_kg(int variant) {
     return variant == 1 || variant == 4 || variant == 7 ? 8 : (variant == 5 || variant == 6 ? 6 : 4);
 }
