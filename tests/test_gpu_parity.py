@@ -243,6 +243,14 @@ def test_argument_errors(cell256, cell256_ctx):
         cell256_ctx.solve(np.array([0], np.int32), 5, 0.0, -1.0)
     with pytest.raises(mar.MarError):
         cell256_ctx.solve(np.array([0], np.int32), 5, float("nan"), KT)
+    # projection variants are 0..7
+    with pytest.raises(mar.MarError) as e:
+        cell256_ctx.set_tuning(proj_variant=8)
+    assert e.value.status == mar.MAR_ERR_ARG
+    with pytest.raises(mar.MarError):
+        cell256_ctx.set_tuning(proj_variant=-1)
+    cell256_ctx.set_tuning(proj_variant=7)
+    cell256_ctx.set_tuning()
 
 
 def test_async_device_buffers_and_invalid_seed(cell256, cell256_ctx, cell256_mu, cell256_ref30):
